@@ -1,0 +1,159 @@
+"""Pins of the oracle's particle sums against invariants of the method.
+
+* A full uniform lattice whose boundary layers continue the lattice has, at
+  every fluid particle, the density rho0 times the lattice sum of a
+  normalised kernel, which is 1 to ~1e-4 at h = 1.3 dx (eqs. density_update,
+  normkernel).
+* Interior particles of that lattice feel no force (symmetric neighbourhoods).
+* The symmetric pressure force and the artificial viscosity are pairwise
+  antisymmetric and central (eqs. momentum, viscous): net force and net torque
+  of the fluid-fluid accelerations vanish.
+* Artificial viscosity dissipates: its power sum_i m w_i . a_i^visc <= 0.
+* Compressed particles (P > 0) repel each other and are pushed off the wall.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sph as O
+
+
+def _full_lattice(width=0.2, height=0.1, dx=0.0125, h_ratio=1.3):
+    fluid, ghosts = W.rect_tank(width, height, dx, int(round(height / dx)), 3, None, 0.0)
+    p = W._fluid_params(dx, h_ratio=h_ratio)
+    pad = 4 * dx
+    p.domain_min = (-width / 2 - pad, -height / 2 - pad)
+    p.domain_max = (width / 2 + pad, height / 2 + pad)
+    st = O.State(fluid.astype(np.float64), np.zeros_like(fluid), np.zeros(6))
+    return p, st, ghosts
+
+
+@pytest.mark.parametrize("h_ratio,tol", [(1.3, 1e-4), (1.5, 5e-3), (2.0, 1e-4)])
+def test_full_lattice_density_is_rest_density(h_ratio, tol):
+    # the lattice (Riemann) sum of a normalised kernel is 1 up to a quadrature
+    # error that is not monotonic in h/dx: 5.3e-5 at 1.3, 3.4e-3 at 1.5
+    p, st, g = _full_lattice(h_ratio=h_ratio)
+    r = O.rhs(p, st, g)
+    err = np.abs(r["rho"] / p.rho0 - 1.0).max()
+    assert err < tol, err
+    # every particle, wall-adjacent ones included, sees the same lattice sum
+    assert np.ptp(r["rho"]) < 1e-9 * p.rho0
+
+
+def test_full_lattice_density_needs_the_ghost_term():
+    p, st, g = _full_lattice()
+    p.gamma1 = 0.5
+    r = O.rhs(p, st, g)
+    # particles next to the wall lose a visible part of their support
+    assert (r["rho"] / p.rho0).min() < 0.9
+
+
+def test_printed_kernel_constant_triples_the_density():
+    p, st, g = _full_lattice()
+    p.kernel_norm = W.KNORM_PRINTED
+    r = O.rhs(p, st, g)
+    assert np.abs(r["rho"] / p.rho0 - 3.0).max() < 3e-4
+
+
+def test_interior_of_full_lattice_is_force_free():
+    p, st, g = _full_lattice(width=0.3, height=0.2)
+    r = O.rhs(p, st, g)
+    s = st.s
+    inner = (np.abs(s[:, 0]) < 0.15 - 2.5 * p.h) & (np.abs(s[:, 1]) < 0.1 - 2.5 * p.h)
+    assert inner.sum() > 20
+    # scale: one pair's pressure acceleration at this pressure level
+    scale = np.abs(r["a_sph"]).max() + 1e-30
+    assert np.abs(r["a_sph"][inner]).max() < 1e-9 * max(scale, 1.0)
+
+
+def _random_cloud(seed=3, n_side=12, dx=0.01):
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(n_side), np.arange(n_side))
+    s = np.stack([i.ravel() * dx, j.ravel() * dx], 1) + rng.uniform(-0.3 * dx, 0.3 * dx, (n_side * n_side, 2))
+    w = rng.normal(0, 0.5, s.shape)
+    p = W._fluid_params(dx)
+    p.domain_min = (-0.1, -0.1)
+    p.domain_max = (n_side * dx + 0.1, n_side * dx + 0.1)
+    return p, O.State(s, w, np.zeros(6)), np.zeros((0, 2))
+
+
+def test_fluid_forces_conserve_linear_momentum():
+    p, st, g = _random_cloud()
+    r = O.rhs(p, st, g)
+    F = p.mass * r["a_sph"]
+    assert np.abs(F.sum(0)).max() < 1e-12 * np.abs(F).sum()
+
+
+def test_fluid_forces_conserve_angular_momentum():
+    p, st, g = _random_cloud()
+    r = O.rhs(p, st, g)
+    F = p.mass * r["a_sph"]
+    torque = st.s[:, 0] * F[:, 1] - st.s[:, 1] * F[:, 0]
+    assert abs(torque.sum()) < 1e-12 * np.abs(torque).sum()
+
+
+def test_viscosity_dissipates_and_vanishes_for_rigid_motion():
+    p, st, g = _random_cloud()
+    r1 = O.rhs(p, st, g)
+    p0 = W._fluid_params(0.01)
+    p0.domain_min, p0.domain_max = p.domain_min, p.domain_max
+    p0.visc_alpha = 0.0
+    r0 = O.rhs(p0, st, g)
+    a_visc = r1["a_sph"] - r0["a_sph"]
+    power = (p.mass * (st.w * a_visc).sum(1)).sum()
+    assert power < 0.0
+    # uniform translation plus rigid rotation: w_ij . s_ij = 0 for every pair
+    st2 = st.copy()
+    st2.w = np.array([0.3, -0.2]) + 1.7 * np.stack([-st.s[:, 1], st.s[:, 0]], 1)
+    ra = O.rhs(p, st2, g)
+    rb = O.rhs(p0, st2, g)
+    assert np.abs(ra["a_sph"] - rb["a_sph"]).max() < 1e-10 * np.abs(ra["a_sph"]).max()
+
+
+def _linear_positive_pressure(dx=0.01):
+    p = W._fluid_params(dx)
+    p.eos = W.EOS_LINEAR
+    p.k_lin = 100.0
+    p.rho0 = 1.0          # any realistic density is then far above rest: P > 0
+    p.mass = 1000.0 * dx * dx
+    p.visc_alpha = p.visc_beta = 0.0
+    p.domain_min, p.domain_max = (-0.5, -0.5), (0.5, 0.5)
+    return p
+
+
+def test_compressed_pair_repels():
+    p = _linear_positive_pressure()
+    s = np.array([[0.0, 0.0], [0.6 * 0.01, 0.2 * 0.01]])
+    r = O.rhs(p, O.State(s, np.zeros_like(s), np.zeros(6)), np.zeros((0, 2)))
+    assert np.all(r["P"] > 0)
+    d = s[0] - s[1]
+    assert np.dot(r["a_sph"][0], d) > 0 and np.dot(r["a_sph"][1], -d) > 0
+
+
+def test_wall_pushes_compressed_fluid_away_and_tank_feels_reaction():
+    p = _linear_positive_pressure()
+    g = np.stack([np.linspace(-0.05, 0.05, 21), np.zeros(21)], 1)      # wall along y = 0
+    s = np.array([[0.0013, 0.4 * p.h]])                                 # just above the wall
+    r = O.rhs(p, O.State(s, np.zeros_like(s), np.zeros(6)), g)
+    assert r["P"][0] > 0
+    assert r["a_sph"][0, 1] > 0                 # pushed up, away from the wall
+    assert r["wrench"][1] < 0                   # the tank is pushed down
+    # action = -reaction: the wall force on the fluid balances the wrench force
+    assert np.allclose(p.mass * r["a_sph"][0], -r["wrench"][:2], rtol=1e-12, atol=0)
+
+
+def test_wall_viscosity_only_resists_approach():
+    p = W._fluid_params(0.01)
+    p.domain_min, p.domain_max = (-0.5, -0.5), (0.5, 0.5)
+    g = np.stack([np.linspace(-0.05, 0.05, 21), np.zeros(21)], 1)
+    s = np.array([[0.0013, 0.4 * p.h]])
+    p0 = W._fluid_params(0.01)
+    p0.domain_min, p0.domain_max = p.domain_min, p.domain_max
+    p0.visc_beta = 0.0
+    def visc(w):
+        st = O.State(s, np.array([w], float), np.zeros(6))
+        return O.rhs(p, st, g)["a_sph"][0] - O.rhs(p0, st, g)["a_sph"][0]
+    a_in = visc([0.0, -0.5])      # moving into the wall: decelerated
+    assert a_in[1] > 0
+    a_out = visc([0.0, 0.5])      # moving away: min(v.r, 0) = 0
+    assert np.abs(a_out).max() == 0.0
