@@ -1,0 +1,212 @@
+/*
+ * slosh.h -- C ABI of the MI355X (gfx950) sloshing simulator.
+ *
+ * The library steps a 2D weakly compressible SPH fluid in a partially filled
+ * tank, in the tank's body frame, coupled to the planar rigid-body dynamics of
+ * the spacecraft that carries it, and evaluates a small MLP surrogate of the
+ * slosh wrench.  The operations follow the paper's problem statement
+ * (Section 2: input u = [u_x, u_y, tau] at the centre of mass, output
+ * y = [r_x, r_y, theta, rdot_x, rdot_y, thetadot]) and its simulator
+ * (Section 3: eqs. density_update, EOS, momentum, viscous, pressure_b2f,
+ * viscous_b2f, tankdynamics, cubicspline, spiky3; Algorithm "state transition
+ * function"; first-order symplectic Euler).
+ *
+ * Conventions for every call:
+ *   - "dev" pointers are device (HBM) pointers on the current HIP device;
+ *     "host" pointers are ordinary host memory.  All float arrays are
+ *     little-endian IEEE binary32, row-major, with no padding.
+ *   - The caller owns all device memory: particle arrays, logs and a
+ *     workspace sized by sph_workspace_bytes / mlp_workspace_bytes.  The
+ *     library never allocates device memory; it allocates only its opaque
+ *     host handle (freed by *_destroy) and, for rollouts, HIP graphs.
+ *   - Work is enqueued on the stream given at init (a hipStream_t passed as
+ *     void*; NULL = the legacy default stream) and is asynchronous unless a
+ *     call says it synchronises.  One handle per stream; no internal locking.
+ *   - Every call returns 0 on success or a negative SPH_E_* code; no C++
+ *     exception crosses the ABI.  sph_strerror gives a message.
+ *   - Particle outputs are in the caller's particle order (the order of the
+ *     arrays given to sph_init); the library reorders particles internally.
+ */
+#ifndef SLOSH_H
+#define SLOSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define SPH_OK 0
+#define SPH_E_INVAL (-1)      /* bad argument, size or parameter */
+#define SPH_E_HIP (-2)        /* a HIP runtime call failed; see sph_strerror */
+#define SPH_E_CAPACITY (-3)   /* workspace too small / grid too large */
+#define SPH_E_STATE (-4)      /* device status word non-zero (see sph_status) */
+
+/* ---- device status bits (latched on device, read by sph_status) -------- */
+#define SPH_ST_ESCAPED 1u     /* a fluid particle left the domain box */
+#define SPH_ST_NONFINITE 2u   /* a NaN or Inf position or velocity appeared */
+#define SPH_ST_SORT 4u        /* a particle moved more than one cell in a step */
+
+/* ---- method options ----------------------------------------------------- */
+#define SPH_EOS_TAIT 0        /* P = B((rho/rho0)^gamma - 1), B = rho0 c0^2/gamma */
+#define SPH_EOS_LINEAR 1      /* P = k (rho - rho0)  (eq. EOS) */
+#define SPH_MOTION_FREE 0     /* Newton-Euler rigid body (eq. tankdynamics) */
+#define SPH_MOTION_SINE 1     /* prescribed theta = A sin(2 pi f t), r = 0 */
+#define SPH_CTRL_NONE 0
+#define SPH_CTRL_PD_ZOH 1     /* tau = kp (ref_k - theta) - kd thetadot, held (Section 5.1) */
+#define SPH_KNORM_UNIT 0      /* cubic spline constant 5/(14 pi h^2): unit integral */
+#define SPH_KNORM_PRINTED 1   /* constant 15/(14 pi h^2) as printed in eq. cubicspline */
+#define SPH_FRAME_BODY 0
+#define SPH_FRAME_WORLD 1
+
+/* Scenario constants.  SI units; masses per unit depth (2D). */
+typedef struct sph_params {
+  int32_t eos, motion, ctrl, kernel_norm;
+  double h;            /* smoothing length; cubic-spline support is 2h */
+  double h_spiky;      /* support of the spiky kernel used for wall forces */
+  double rho0;         /* rest density */
+  double mass;         /* particle mass (fluid and ghost) */
+  double c0;           /* Tait sound speed */
+  double tait_gamma;   /* Tait exponent */
+  double k_lin;        /* linear EOS stiffness */
+  double visc_alpha;   /* fluid artificial-viscosity coefficient (eq. viscous) */
+  double visc_beta;    /* fluid-wall viscosity coefficient (eq. viscous_b2f) */
+  double eps;          /* singularity guard, eps h^2 */
+  double gamma1;       /* ghost density correction (eq. density_update) */
+  double dt;           /* fixed time step */
+  double body_mass, body_inertia;
+  double kp, kd;       /* PD gains */
+  int32_t ctrl_period; /* zero-order-hold period in steps */
+  int32_t reserved;
+  double sine_amp, sine_freq;
+  double domain_min[2], domain_max[2];  /* body-frame box holding every particle */
+} sph_params;
+
+typedef struct sph_handle sph_handle;
+
+/* Device bytes of the workspace for N fluid and G ghost particles, or
+ * SPH_E_INVAL for bad parameters (non-positive h, dt, mass; empty domain;
+ * a cell grid above 2^26 cells). */
+int sph_workspace_bytes(const sph_params* p, int32_t n_fluid, int32_t n_ghost, size_t* bytes);
+
+/* Creates a simulator.  s0_dev, w0_dev: [n_fluid][2] body-frame positions and
+ * velocities; g_dev: [n_ghost][2] static body-frame ghost positions; rigid0:
+ * host [6] = r_x, r_y, theta, rdot_x, rdot_y, thetadot (world frame, double).
+ * ws_dev: workspace of at least sph_workspace_bytes, 256-byte aligned, which
+ * the caller keeps alive until sph_destroy.  Input arrays are copied and may
+ * be freed after the call returns (the call synchronises the stream).
+ * Builds the static ghost cell list and sorts the fluid into cells.
+ * Returns SPH_E_INVAL on bad sizes/pointers or a particle outside the
+ * domain box, SPH_E_CAPACITY if ws_bytes is too small. */
+int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const float* w0_dev,
+             int32_t n_ghost, const float* g_dev, const double* rigid0, void* ws_dev,
+             size_t ws_bytes, void* stream, sph_handle** out);
+
+/* Frees the host handle and its graphs (the workspace stays the caller's). */
+int sph_destroy(sph_handle* h);
+
+/* One symplectic-Euler step of the coupled system (Algorithm "state
+ * transition function" + Section 3.4 integrator): cell-list build, density and
+ * EOS, fluid and wall forces, slosh wrench, controller, rigid body, fictitious
+ * accelerations and fluid update.  u_dev: device [3] = F_x, F_y (world frame)
+ * and torque, or NULL for zero.  Asynchronous. */
+int sph_step(sph_handle* h, const float* u_dev);
+
+/* n_steps steps replayed from captured HIP graphs.  u_seq_dev: [n_steps][3]
+ * inputs or NULL (zero); theta_ref_dev: [n_ref] double angle references at the
+ * control instants (global step / ctrl_period) or NULL (zero), used by
+ * SPH_CTRL_PD_ZOH.  Every log_stride steps (log_stride > 0) entry k receives
+ * the state at local step k*log_stride and the wrench evaluated there:
+ * y_log_dev [n_log][6] = r, theta, rdot, thetadot; wrench_log_dev [n_log][3]
+ * = body-frame slosh force and torque; u_log_dev [n_log][3] = applied F_x,
+ * F_y and total torque (input + controller); wmean_log_dev [n_log][3] = mean
+ * body-frame wrench over the steps of the log interval.  n_log =
+ * ceil(n_steps / log_stride); any log pointer may be NULL.  Asynchronous;
+ * inputs and logs must stay valid until the stream reaches the end. */
+int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
+                const double* theta_ref_dev, int32_t n_ref, int32_t log_stride,
+                float* y_log_dev, float* wrench_log_dev, float* u_log_dev,
+                float* wmean_log_dev);
+
+/* The slosh wrench (F_x, F_y, torque) of the fluid on the tank (the reaction
+ * sums of eq. tankdynamics, torque about the centre of mass) at the last
+ * evaluated state, in SPH_FRAME_BODY or SPH_FRAME_WORLD.  out_dev: device [3]. */
+int sph_slosh_wrench(sph_handle* h, int32_t frame, float* out_dev);
+
+/* Evaluates x_dot = f(x, u) at the current state without advancing it, with
+ * the controller torque held as it is.  u_dev: device [3] or NULL.  Outputs
+ * (device, caller order, any may be NULL): rho_dev [N], p_dev [N] pressure,
+ * a_sph_dev [N][2] SPH acceleration, wdot_dev [N][2] body-frame fluid
+ * acceleration including fictitious terms, wrench_dev [3] body frame,
+ * acc_dev [3] = r''_x, r''_y, theta''.  Reorders particles internally. */
+int sph_rhs(sph_handle* h, const float* u_dev, float* rho_dev, float* p_dev, float* a_sph_dev,
+            float* wdot_dev, float* wrench_dev, float* acc_dev);
+
+/* Copies the state out: s_dev, w_dev [N][2] (caller order, may be NULL);
+ * rigid: host [6] (may be NULL); tau_ctrl, step: host (may be NULL).
+ * Synchronises the stream. */
+int sph_get_state(sph_handle* h, float* s_dev, float* w_dev, double* rigid, double* tau_ctrl,
+                  int64_t* step);
+
+/* Replaces the state (checkpoint restore): s_dev, w_dev [N][2] in caller
+ * order; rigid host [6]; held controller torque; global step counter.
+ * Clears the status word.  Synchronises the stream. */
+int sph_set_state(sph_handle* h, const float* s_dev, const float* w_dev, const double* rigid,
+                  double tau_ctrl, int64_t step);
+
+/* Synchronises the stream and returns the latched SPH_ST_* bits in *flags;
+ * returns SPH_E_STATE if any bit is set, else SPH_OK. */
+int sph_status(sph_handle* h, uint32_t* flags);
+
+/* Test hook of the cell-list traversal that every particle sum uses: for each
+ * fluid particle (caller order) the caller-order indices of the fluid
+ * particles j != i with fmaf(dy, dy, dx*dx) < (2h)^2 in binary32, ascending,
+ * in nbr_dev [N][max_nbr], and their number in count_dev [N] (counts above
+ * max_nbr are reported but only max_nbr indices stored).  Reorders particles
+ * internally like a step does. */
+int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* count_dev);
+
+/* Message for an error code (static storage). */
+const char* sph_strerror(int code);
+
+/* ---- slosh-wrench surrogate (an MLP, trained on rollouts) -------------- */
+/*
+ * Network: x [B][128] (32 samples x 4 channels) -> 4 x (Linear 256 + GELU,
+ * tanh form) -> Linear 3.  Weights are BF16 on the MFMA path with FP32
+ * accumulation, FP32 master weights for Adam.  Parameter packing, used by
+ * every weights argument: for l = 0..4, W_l [out_l][in_l] then b_l [out_l],
+ * concatenated, FP32; dims 128, 256, 256, 256, 256, 3 (231,171 values).
+ */
+typedef struct mlp_handle mlp_handle;
+
+#define MLP_N_PARAMS 231171
+
+/* Workspace bytes for batches of up to max_batch rows. */
+int mlp_workspace_bytes(int32_t max_batch, size_t* bytes);
+
+/* Creates a network with FP32 master weights copied from params_dev [231171]. */
+int mlp_init(const float* params_dev, int32_t max_batch, void* ws_dev, size_t ws_bytes,
+             void* stream, mlp_handle** out);
+
+int mlp_destroy(mlp_handle* h);
+
+/* y_dev [B][3] FP32 = net(x_dev [B][128] FP32), inputs rounded to BF16. */
+int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev);
+
+/* One training step on the mean squared error: forward, backward (gradients
+ * in FP32, written to grad_dev [231171] if non-NULL), then Adam with bias
+ * correction (step counter kept in the handle).  target_dev [B][3].  The
+ * batch loss is written to loss_dev [1] if non-NULL. */
+int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, int32_t batch,
+                   float lr, float beta1, float beta2, float eps, float* grad_dev,
+                   float* loss_dev);
+
+/* Copies the FP32 master weights to params_dev [231171]. */
+int mlp_get_params(mlp_handle* h, float* params_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLOSH_H */

@@ -287,6 +287,7 @@ typedef struct {
   double* ax;        /* [n] a_sph, the SPH acceleration (body-frame components) */
   double* ay;
   double wrench[3];  /* force of the fluid on the tank (frame of the inputs) and torque */
+  double* fwall;     /* [n][3] or NULL: each particle's reaction on the tank (F_x, F_y, torque) */
 } sums_t;
 
 /* The particle sums.  Positions and velocities are in one frame (the body
@@ -391,6 +392,12 @@ static void particle_sums(const ora_params* p, int n, const double* sx, const do
     }
     free(l.j);
   }
+  if (out->fwall)
+    for (int i = 0; i < n; ++i) {
+      out->fwall[3 * i] = fwx[i];
+      out->fwall[3 * i + 1] = fwy[i];
+      out->fwall[3 * i + 2] = fwt[i];
+    }
   out->wrench[0] = out->wrench[1] = out->wrench[2] = 0.0;
   for (int i = 0; i < n; ++i) {
     out->wrench[0] += fwx[i];
@@ -456,13 +463,14 @@ static void rigid_accel(const ora_params* p, const ora_rigid* b, const double wr
 /* Evaluates xdot = f(x, u) at the given state (Algorithm "state transition
  * function") without advancing it.  Outputs: rho, P, a_sph and the body-frame
  * fluid acceleration dw/dt [n]; the body-frame slosh wrench [3]; the rigid
- * accelerations (r''_x, r''_y, theta'') [3].  `rigid` = r_x, r_y, theta,
+ * accelerations (r''_x, r''_y, theta'') [3]; optionally (fwall non-NULL) the
+ * per-particle terms of the wrench sum [n][3].  `rigid` = r_x, r_y, theta,
  * rdot_x, rdot_y, thetadot; tau_ctrl the held controller torque; step n. */
 int ora_rhs(const ora_params* p, int n, const double* sx, const double* sy, const double* wx,
             const double* wy, int ng, const double* gx, const double* gy, const double* rigid,
             double tau_ctrl, int64_t step, const double* u, double* rho, double* P, double* ax,
-            double* ay, double* dwx, double* dwy, double* wrench, double* acc) {
-  sums_t s = {rho, P, ax, ay, {0, 0, 0}};
+            double* ay, double* dwx, double* dwy, double* wrench, double* acc, double* fwall) {
+  sums_t s = {rho, P, ax, ay, {0, 0, 0}, fwall};
   double origin[2] = {0.0, 0.0};
   particle_sums(p, n, sx, sy, wx, wy, ng, gx, gy, NULL, NULL, origin, p->use_cells, &s);
   ora_rigid b = {{rigid[0], rigid[1]}, rigid[2], {rigid[3], rigid[4]}, rigid[5], tau_ctrl, step};
@@ -520,7 +528,7 @@ int ora_rollout(const ora_params* p, int n, double* sx, double* sy, double* wx, 
     double rg[6] = {b.r[0], b.r[1], b.theta, b.rdot[0], b.rdot[1], b.thetadot};
     double wrench[3], acc[3];
     ora_rhs(p, n, sx, sy, wx, wy, ng, gx, gy, rg, b.tau_ctrl, b.step, u, rho, P, ax, ay, dwx, dwy,
-            wrench, acc);
+            wrench, acc, NULL);
     if (log_stride > 0 && it % log_stride == 0) {
       int k = it / log_stride;
       if (y_log) {
@@ -627,7 +635,7 @@ int ora_rollout_world(const ora_params* p, int n, double* xx, double* xy, double
       gvx[k] = b.rdot[0] - thd * (gy[k] - b.r[1]);
       gvy[k] = b.rdot[1] + thd * (gx[k] - b.r[0]);
     }
-    sums_t sm = {rho, P, ax, ay, {0, 0, 0}};
+    sums_t sm = {rho, P, ax, ay, {0, 0, 0}, NULL};
     ora_params q = *p;
     q.use_cells = 0;
     particle_sums(&q, n, xx, xy, vx, vy, ng, gx, gy, gvx, gvy, b.r, 0, &sm);

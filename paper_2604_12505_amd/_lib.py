@@ -1,0 +1,80 @@
+"""Loads libslosh.so and declares the C ABI (include/slosh.h) for ctypes."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libslosh.so")
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class SphParams(C.Structure):
+    _fields_ = [
+        ("eos", C.c_int32), ("motion", C.c_int32), ("ctrl", C.c_int32), ("kernel_norm", C.c_int32),
+        ("h", C.c_double), ("h_spiky", C.c_double), ("rho0", C.c_double), ("mass", C.c_double),
+        ("c0", C.c_double), ("tait_gamma", C.c_double), ("k_lin", C.c_double),
+        ("visc_alpha", C.c_double), ("visc_beta", C.c_double), ("eps", C.c_double),
+        ("gamma1", C.c_double), ("dt", C.c_double), ("body_mass", C.c_double),
+        ("body_inertia", C.c_double), ("kp", C.c_double), ("kd", C.c_double),
+        ("ctrl_period", C.c_int32), ("reserved", C.c_int32),
+        ("sine_amp", C.c_double), ("sine_freq", C.c_double),
+        ("domain_min", C.c_double * 2), ("domain_max", C.c_double * 2),
+    ]
+
+
+SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sph_rollout",
+               "sph_slosh_wrench", "sph_rhs", "sph_get_state", "sph_set_state", "sph_status",
+               "sph_neighbours", "sph_strerror")
+MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
+               "mlp_get_params")
+
+
+def load():
+    """Returns the loaded library; raises LibraryMissing if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                             "or python paper_2604_12505_amd/build.py")
+    L = C.CDLL(LIB_PATH)
+    p, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    P = C.POINTER
+    L.sph_workspace_bytes.argtypes = [P(SphParams), i32, i32, P(sz)]
+    L.sph_init.argtypes = [P(SphParams), i32, p, p, i32, p, p, p, sz, p, P(p)]
+    L.sph_destroy.argtypes = [p]
+    L.sph_step.argtypes = [p, p]
+    L.sph_rollout.argtypes = [p, i32, p, p, i32, i32, p, p, p, p]
+    L.sph_slosh_wrench.argtypes = [p, i32, p]
+    L.sph_rhs.argtypes = [p, p, p, p, p, p, p, p]
+    L.sph_get_state.argtypes = [p, p, p, p, p, p]
+    L.sph_set_state.argtypes = [p, p, p, p, C.c_double, i64]
+    L.sph_status.argtypes = [p, P(C.c_uint32)]
+    L.sph_neighbours.argtypes = [p, i32, p, p]
+    L.sph_strerror.argtypes = [C.c_int]
+    L.sph_strerror.restype = C.c_char_p
+    for name in SPH_SYMBOLS[:-1]:
+        getattr(L, name).restype = C.c_int
+    if hasattr(L, "mlp_init"):
+        L.mlp_workspace_bytes.argtypes = [i32, P(sz)]
+        L.mlp_init.argtypes = [p, i32, p, sz, p, P(p)]
+        L.mlp_destroy.argtypes = [p]
+        L.mlp_forward.argtypes = [p, p, i32, p]
+        L.mlp_train_step.argtypes = [p, p, p, i32, C.c_float, C.c_float, C.c_float, C.c_float, p, p]
+        L.mlp_get_params.argtypes = [p, p]
+        for name in MLP_SYMBOLS:
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str = "") -> None:
+    if rc != 0:
+        msg = load().sph_strerror(rc).decode()
+        raise RuntimeError(f"{what} failed with code {rc}: {msg}")

@@ -1,0 +1,465 @@
+// Slosh-wrench surrogate: a 128 -> 4 x (256, GELU) -> 3 MLP on gfx950 MFMA.
+//
+// Every dense product is one kernel, gemm_tn: C[m][n] = sum_k A[m][k] B[n][k]
+// with both operands BF16 and contiguous along k, accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16.  Each product of the network is cast in that form
+// by choosing what the epilogues store:
+//   forward   z_l = a_{l-1} W_l^T + b_l          A = a_{l-1} [B][in],  B = W_l [out][in]
+//   dgrad     g_{l-1} = (g_l W_l) * gelu'(z)     A = g_l [B][out],     B = W_l^T [in][out]
+//   wgrad     dW_l = g_l^T a_{l-1}                A = g_l^T [out][B],   B = a_{l-1}^T [in][B]
+// so the forward epilogue also writes the transposed activation and the
+// pre-activation, and the dgrad epilogue writes the gradient both ways.  The
+// 3-wide head, the loss, the bias gradients and Adam are small VALU kernels.
+// GELU is the tanh form; Adam keeps FP32 master weights and refreshes the
+// BF16 copies (row-major and transposed) after every step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "slosh.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIn = 128, kHid = 256, kOut = 3, kLayers = 5;
+constexpr int kDims[kLayers + 1] = {kIn, kHid, kHid, kHid, kHid, kOut};
+// packed parameter offsets: W_l then b_l for l = 0..4
+constexpr int kOffW[kLayers] = {0, 33024, 98816, 164608, 230400};
+constexpr int kOffB[kLayers] = {32768, 98560, 164352, 230144, 231168};
+static_assert(kOffB[4] + kOut == MLP_N_PARAMS, "packing");
+
+constexpr float kGeluK = 0.7978845608028654f;  // sqrt(2/pi)
+constexpr float kGeluC = 0.044715f;
+
+__device__ __forceinline__ float gelu(float x) {
+  float t = tanhf(kGeluK * (x + kGeluC * x * x * x));
+  return 0.5f * x * (1.0f + t);
+}
+
+__device__ __forceinline__ float gelu_grad(float x) {
+  float t = tanhf(kGeluK * (x + kGeluC * x * x * x));
+  float du = kGeluK * (1.0f + 3.0f * kGeluC * x * x);
+  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * du;
+}
+
+// ---------------------------------------------------------------------------
+// gemm_tn: 256 threads = 4 waves in a 2x2 arrangement, 64x64 output tile, each
+// wave 32x32 = 2x2 MFMA tiles of 16x16.  Lane l holds row (l % 16) of A and
+// column (l % 16) of B for k in [8 (l / 16), 8 (l / 16) + 8) of each 32-wide
+// k step; the result element e of lane l is row 4 (l / 16) + e, column l % 16.
+// Rows m >= M and columns n >= N read zeros and are not stored.  K % 32 == 0.
+// ---------------------------------------------------------------------------
+
+struct EpiFwd {            // hidden forward layer
+  const float* bias;       // [N]
+  bf16* act;               // [M][ld_act] row-major, next layer's A
+  int ld_act;
+  bf16* actT;              // [N][ldT] or null (training)
+  float* zT;               // [N][ldT] or null (training)
+  int ldT;
+  __device__ void operator()(int m, int n, float v) const {
+    float z = v + bias[n];
+    float a = gelu(z);
+    act[(size_t)m * ld_act + n] = (bf16)a;
+    if (actT) {
+      actT[(size_t)n * ldT + m] = (bf16)a;
+      zT[(size_t)n * ldT + m] = z;
+    }
+  }
+};
+
+struct EpiDgrad {          // g_{l-1} = (g_l W_l) * gelu'(z_{l-1})
+  const float* zT;         // [N][ldT] pre-activation of the layer below
+  bf16* g;                 // [M][ld_g] row-major or null
+  int ld_g;
+  bf16* gT;                // [N][ldT]
+  int ldT;
+  __device__ void operator()(int m, int n, float v) const {
+    float gv = v * gelu_grad(zT[(size_t)n * ldT + m]);
+    if (g) g[(size_t)m * ld_g + n] = (bf16)gv;
+    gT[(size_t)n * ldT + m] = (bf16)gv;
+  }
+};
+
+struct EpiStore {          // plain FP32 store (weight gradients)
+  float* c;
+  int ldc;
+  __device__ void operator()(int m, int n, float v) const { c[(size_t)m * ldc + n] = v; }
+};
+
+template <class Epi>
+__global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int lda,
+                                               const bf16* __restrict__ B, int ldb, int M, int N,
+                                               int K, Epi epi) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int m0 = blockIdx.y * 64 + wy * 32;
+  const int n0 = blockIdx.x * 64 + wx * 32;
+  const int li = lane & 15, kq = (lane >> 4) * 8;
+  floatx4 acc[2][2];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = {};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a[2], b[2];
+    for (int r = 0; r < 2; ++r) {
+      int m = m0 + r * 16 + li;
+      a[r] = m < M ? *reinterpret_cast<const bf16x8*>(A + (size_t)m * lda + k0 + kq) : zero;
+    }
+    for (int c = 0; c < 2; ++c) {
+      int n = n0 + c * 16 + li;
+      b[c] = n < N ? *reinterpret_cast<const bf16x8*>(B + (size_t)n * ldb + k0 + kq) : zero;
+    }
+    for (int r = 0; r < 2; ++r)
+      for (int c = 0; c < 2; ++c)
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+  }
+  const int rq = (lane >> 4) * 4;
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      int n = n0 + c * 16 + li;
+      if (n >= N) continue;
+      for (int e = 0; e < 4; ++e) {
+        int m = m0 + r * 16 + rq + e;
+        if (m < M) epi(m, n, acc[r][c][e]);
+      }
+    }
+}
+
+// FP32 input [B][128] -> BF16 row-major and (training) transposed copies.
+__global__ void mlp_cast_input(const float* __restrict__ x, int B, bf16* __restrict__ xb,
+                               bf16* __restrict__ xT, int ldT) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * kIn) return;
+  int m = t / kIn, k = t - m * kIn;
+  bf16 v = (bf16)x[t];
+  xb[t] = v;
+  if (xT) xT[(size_t)k * ldT + m] = v;
+}
+
+// Head y = a4 W4^T + b4 (one wave per row).  Training: loss terms, dL/dy,
+// and g4 = (dL/dy W4) * gelu'(z4) written both ways.
+__global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, const bf16* __restrict__ W4,
+                                                const float* __restrict__ b4, int B, float* __restrict__ y,
+                                                const float* __restrict__ target, float* __restrict__ gy,
+                                                float* __restrict__ loss_rows, const float* __restrict__ z4T,
+                                                bf16* __restrict__ g4, bf16* __restrict__ g4T, int ldT) {
+  int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= B) return;
+  float a[4];
+  for (int q = 0; q < 4; ++q) a[q] = (float)a4[(size_t)row * kHid + lane * 4 + q];
+  float out[kOut];
+  for (int o = 0; o < kOut; ++o) {
+    float s = 0.f;
+    for (int q = 0; q < 4; ++q) s += a[q] * (float)W4[o * kHid + lane * 4 + q];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    out[o] = s + b4[o];
+  }
+  if (lane == 0)
+    for (int o = 0; o < kOut; ++o) y[(size_t)row * kOut + o] = out[o];
+  if (!target) return;
+  float g[kOut], l = 0.f;
+  float scale = 2.0f / (float(B) * kOut);
+  for (int o = 0; o < kOut; ++o) {
+    float d = out[o] - target[(size_t)row * kOut + o];
+    g[o] = scale * d;
+    l += d * d;
+  }
+  if (lane == 0) {
+    loss_rows[row] = l;
+    for (int o = 0; o < kOut; ++o) gy[(size_t)row * kOut + o] = g[o];
+  }
+  for (int q = 0; q < 4; ++q) {
+    int k = lane * 4 + q;
+    float s = 0.f;
+    for (int o = 0; o < kOut; ++o) s += g[o] * (float)W4[o * kHid + k];
+    float gv = s * gelu_grad(z4T[(size_t)k * ldT + row]);
+    g4[(size_t)row * kHid + k] = (bf16)gv;
+    g4T[(size_t)k * ldT + row] = (bf16)gv;
+  }
+}
+
+// dW4[o][k] = sum_b gy[b][o] a4[b][k]; db4[o] = sum_b gy[b][o].
+__global__ void mlp_head_wgrad(const float* __restrict__ gy, const bf16* __restrict__ a4T, int ldT,
+                               int B, float* __restrict__ grad) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kOut * (kHid + 1)) return;
+  int o = t / (kHid + 1), k = t - o * (kHid + 1);
+  float s = 0.f;
+  if (k < kHid) {
+    for (int b = 0; b < B; ++b) s += gy[(size_t)b * kOut + o] * (float)a4T[(size_t)k * ldT + b];
+    grad[kOffW[4] + o * kHid + k] = s;
+  } else {
+    for (int b = 0; b < B; ++b) s += gy[(size_t)b * kOut + o];
+    grad[kOffB[4] + o] = s;
+  }
+}
+
+// db_l[n] = sum_b g_l^T[n][b] (one wave per n, fixed-order reduction).
+__global__ void mlp_bias_grad(const bf16* __restrict__ gT, int ldT, int B, float* __restrict__ db) {
+  int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (n >= kHid) return;
+  float s = 0.f;
+  for (int b = lane; b < B; b += 64) s += (float)gT[(size_t)n * ldT + b];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) db[n] = s;
+}
+
+__global__ void mlp_loss(const float* __restrict__ rows, int B, float* __restrict__ out) {
+  __shared__ float part[256];
+  float s = 0.f;
+  for (int b = threadIdx.x; b < B; b += 256) s += rows[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0] / (float(B) * kOut);
+}
+
+// Adam with bias correction on FP32 masters, then the BF16 copies.
+__global__ void mlp_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                         const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
+                         float c1, float c2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.0f - b1) * gi;
+  float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 row-major copy of all parameters, and transposed copies of W1..W3.
+__global__ void mlp_refresh(const float* __restrict__ w, bf16* __restrict__ wb, bf16* __restrict__ wT) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MLP_N_PARAMS) return;
+  bf16 v = (bf16)w[i];
+  wb[i] = v;
+  for (int l = 1; l <= 3; ++l) {
+    int off = kOffW[l];
+    if (i >= off && i < off + kHid * kHid) {
+      int r = (i - off) / kHid, c = (i - off) % kHid;     // W_l[r][c], r = out, c = in
+      wT[(size_t)(l - 1) * kHid * kHid + (size_t)c * kHid + r] = v;
+    }
+  }
+}
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct MlpLayout {
+  size_t master, m, v, grad, wb, wT, xb, xT, act[4], actT[4], zT[4], g[4], gT[4], y, gy, rows,
+      loss, total;
+  int ldT;   // leading dimension of the feature-major (transposed) buffers, a multiple of 32
+};
+
+MlpLayout mlp_layout(int maxB) {
+  MlpLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += al(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  size_t B = (size_t)maxB, P = MLP_N_PARAMS;
+  L.ldT = (maxB + 31) & ~31;
+  size_t BT = (size_t)L.ldT;
+  L.master = take(P * 4);
+  L.m = take(P * 4);
+  L.v = take(P * 4);
+  L.grad = take(P * 4);
+  L.wb = take(P * 2);
+  L.wT = take((size_t)3 * kHid * kHid * 2);
+  L.xb = take(B * kIn * 2);
+  L.xT = take(BT * kIn * 2);
+  for (int l = 0; l < 4; ++l) {
+    L.act[l] = take(B * kHid * 2);
+    L.actT[l] = take(BT * kHid * 2);
+    L.zT[l] = take(BT * kHid * 4);
+    L.g[l] = take(B * kHid * 2);
+    L.gT[l] = take(BT * kHid * 2);
+  }
+  L.y = take(B * kOut * 4);
+  L.gy = take(B * kOut * 4);
+  L.rows = take(B * 4);
+  L.loss = take(4);
+  L.total = o;
+  return L;
+}
+
+thread_local char m_err[256];
+
+int mlp_hip_fail(hipError_t e, const char* what) {
+  snprintf(m_err, sizeof m_err, "%s: %s", what, hipGetErrorString(e));
+  return SPH_E_HIP;
+}
+
+#define MHIP(x)                                        \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return mlp_hip_fail(e_, #x); \
+  } while (0)
+
+}  // namespace
+
+struct mlp_handle {
+  int maxB;
+  hipStream_t stream;
+  char* ws;
+  MlpLayout L;
+  long long t;   // Adam step counter
+  template <class T>
+  T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+// Forward through the four hidden layers; training keeps transposes and z.
+void forward(mlp_handle* h, const float* x, int B, bool train) {
+  const int ldT = h->L.ldT;
+  hipLaunchKernelGGL(mlp_cast_input, dim3((B * kIn + 255) / 256), dim3(256), 0, h->stream, x, B,
+                     h->at<bf16>(h->L.xb), train ? h->at<bf16>(h->L.xT) : nullptr, ldT);
+  const bf16* a = h->at<bf16>(h->L.xb);
+  int lda = kIn;
+  for (int l = 0; l < 4; ++l) {
+    EpiFwd e;
+    e.bias = h->at<float>(h->L.master) + kOffB[l];
+    e.act = h->at<bf16>(h->L.act[l]);
+    e.ld_act = kHid;
+    e.actT = train ? h->at<bf16>(h->L.actT[l]) : nullptr;
+    e.zT = train ? h->at<float>(h->L.zT[l]) : nullptr;
+    e.ldT = ldT;
+    dim3 grid((kHid + 63) / 64, (B + 63) / 64);
+    hipLaunchKernelGGL(gemm_tn<EpiFwd>, grid, dim3(256), 0, h->stream, a, lda,
+                       h->at<bf16>(h->L.wb) + kOffW[l], kDims[l], B, kHid, kDims[l], e);
+    a = e.act;
+    lda = kHid;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlp_workspace_bytes(int32_t max_batch, size_t* bytes) {
+  if (max_batch < 1 || max_batch > (1 << 24) || !bytes) return SPH_E_INVAL;
+  *bytes = mlp_layout(max_batch).total;
+  return SPH_OK;
+}
+
+int mlp_init(const float* params_dev, int32_t max_batch, void* ws_dev, size_t ws_bytes, void* stream,
+             mlp_handle** out) {
+  if (!out || !params_dev || !ws_dev || max_batch < 1 || max_batch > (1 << 24)) return SPH_E_INVAL;
+  if (reinterpret_cast<uintptr_t>(ws_dev) & 255) return SPH_E_INVAL;
+  MlpLayout L = mlp_layout(max_batch);
+  if (ws_bytes < L.total) return SPH_E_CAPACITY;
+  mlp_handle* h = new (std::nothrow) mlp_handle();
+  if (!h) return SPH_E_INVAL;
+  h->maxB = max_batch;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->ws = reinterpret_cast<char*>(ws_dev);
+  h->L = L;
+  h->t = 0;
+  hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->at<float>(L.master), params_dev, (size_t)MLP_N_PARAMS * 4,
+                       hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return mlp_hip_fail(e, "mlp_init copy");
+  }
+  hipLaunchKernelGGL(mlp_refresh, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
+                     h->at<float>(L.master), h->at<bf16>(L.wb), h->at<bf16>(L.wT));
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return mlp_hip_fail(e, "mlp_init");
+  }
+  *out = h;
+  return SPH_OK;
+}
+
+int mlp_destroy(mlp_handle* h) {
+  if (!h) return SPH_E_INVAL;
+  delete h;
+  return SPH_OK;
+}
+
+int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev) {
+  if (!h || !x_dev || !y_dev || batch < 1 || batch > h->maxB) return SPH_E_INVAL;
+  forward(h, x_dev, batch, false);
+  hipLaunchKernelGGL(mlp_head, dim3((batch + 3) / 4), dim3(256), 0, h->stream, h->at<bf16>(h->L.act[3]),
+                     h->at<bf16>(h->L.wb) + kOffW[4], h->at<float>(h->L.master) + kOffB[4], batch, y_dev,
+                     (const float*)nullptr, (float*)nullptr, (float*)nullptr, (const float*)nullptr,
+                     (bf16*)nullptr, (bf16*)nullptr, h->L.ldT);
+  MHIP(hipGetLastError());
+  return SPH_OK;
+}
+
+int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, int32_t batch, float lr,
+                   float beta1, float beta2, float eps, float* grad_dev, float* loss_dev) {
+  if (!h || !x_dev || !target_dev || batch < 32 || batch > h->maxB || batch % 32) return SPH_E_INVAL;
+  const int B = batch, ldT = h->L.ldT;
+  forward(h, x_dev, B, true);
+  float* grad = h->at<float>(h->L.grad);
+  hipLaunchKernelGGL(mlp_head, dim3((B + 3) / 4), dim3(256), 0, h->stream, h->at<bf16>(h->L.act[3]),
+                     h->at<bf16>(h->L.wb) + kOffW[4], h->at<float>(h->L.master) + kOffB[4], B,
+                     h->at<float>(h->L.y), target_dev, h->at<float>(h->L.gy), h->at<float>(h->L.rows),
+                     h->at<float>(h->L.zT[3]), h->at<bf16>(h->L.g[3]), h->at<bf16>(h->L.gT[3]), ldT);
+  hipLaunchKernelGGL(mlp_head_wgrad, dim3((kOut * (kHid + 1) + 255) / 256), dim3(256), 0, h->stream,
+                     h->at<float>(h->L.gy), h->at<bf16>(h->L.actT[3]), ldT, B, grad);
+  // hidden layers, top down: g[l] holds dL/dz of hidden layer l (output of W_l)
+  for (int l = 3; l >= 0; --l) {
+    const bf16* aT = l > 0 ? h->at<bf16>(h->L.actT[l - 1]) : h->at<bf16>(h->L.xT);
+    EpiStore es{grad + kOffW[l], kDims[l]};
+    dim3 gw((kDims[l] + 63) / 64, (kHid + 63) / 64);
+    hipLaunchKernelGGL(gemm_tn<EpiStore>, gw, dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]), ldT, aT,
+                       ldT, kHid, kDims[l], B, es);
+    hipLaunchKernelGGL(mlp_bias_grad, dim3(kHid / 4), dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]),
+                       ldT, B, grad + kOffB[l]);
+    if (l > 0) {
+      EpiDgrad ed;
+      ed.zT = h->at<float>(h->L.zT[l - 1]);
+      ed.g = h->at<bf16>(h->L.g[l - 1]);
+      ed.ld_g = kHid;
+      ed.gT = h->at<bf16>(h->L.gT[l - 1]);
+      ed.ldT = ldT;
+      dim3 gd((kHid + 63) / 64, (B + 63) / 64);
+      hipLaunchKernelGGL(gemm_tn<EpiDgrad>, gd, dim3(256), 0, h->stream, h->at<bf16>(h->L.g[l]), kHid,
+                         h->at<bf16>(h->L.wT) + (size_t)(l - 1) * kHid * kHid, kHid, B, kHid, kHid, ed);
+    }
+  }
+  hipLaunchKernelGGL(mlp_loss, dim3(1), dim3(256), 0, h->stream, h->at<float>(h->L.rows), B,
+                     loss_dev ? loss_dev : h->at<float>(h->L.loss));
+  if (grad_dev)
+    MHIP(hipMemcpyAsync(grad_dev, grad, (size_t)MLP_N_PARAMS * 4, hipMemcpyDeviceToDevice, h->stream));
+  h->t += 1;
+  float c1 = 1.0f - powf(beta1, (float)h->t), c2 = 1.0f - powf(beta2, (float)h->t);
+  hipLaunchKernelGGL(mlp_adam, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
+                     h->at<float>(h->L.master), h->at<float>(h->L.m), h->at<float>(h->L.v), grad,
+                     MLP_N_PARAMS, lr, beta1, beta2, eps, c1, c2);
+  hipLaunchKernelGGL(mlp_refresh, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
+                     h->at<float>(h->L.master), h->at<bf16>(h->L.wb), h->at<bf16>(h->L.wT));
+  MHIP(hipGetLastError());
+  return SPH_OK;
+}
+
+int mlp_get_params(mlp_handle* h, float* params_dev) {
+  if (!h || !params_dev) return SPH_E_INVAL;
+  MHIP(hipMemcpyAsync(params_dev, h->at<float>(h->L.master), (size_t)MLP_N_PARAMS * 4,
+                      hipMemcpyDeviceToDevice, h->stream));
+  return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""Python binding of the surrogate-network part of libslosh.so (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import check, load
+
+N_PARAMS = 231171
+DIMS = (128, 256, 256, 256, 256, 3)
+
+
+def pack(params) -> np.ndarray:
+    """[(W [out, in], b [out]), ...] -> the packed FP32 vector of the C ABI."""
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
+
+
+def unpack(vec) -> list:
+    v = np.asarray(vec, np.float64)
+    out, o = [], 0
+    for i in range(len(DIMS) - 1):
+        n_in, n_out = DIMS[i], DIMS[i + 1]
+        W = v[o:o + n_in * n_out].reshape(n_out, n_in); o += n_in * n_out
+        b = v[o:o + n_out]; o += n_out
+        out.append((W, b))
+    return out
+
+
+class Mlp:
+    """``mlp_init`` on construction; forward / train_step / params."""
+
+    def __init__(self, params_vec, max_batch: int, device="cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.L = load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        p = torch.as_tensor(np.asarray(params_vec, np.float32), device=self.device).contiguous()
+        assert p.numel() == N_PARAMS
+        nbytes = C.c_size_t()
+        check(self.L.mlp_workspace_bytes(int(max_batch), C.byref(nbytes)), "mlp_workspace_bytes")
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + nbytes.value]
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        check(self.L.mlp_init(C.c_void_p(p.data_ptr()), int(max_batch), C.c_void_p(self.ws.data_ptr()),
+                              C.c_size_t(nbytes.value), C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+              "mlp_init")
+        self.h = h
+        self._keep = []
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def forward(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        x = x.to(self.device, torch.float32).contiguous()
+        B = x.shape[0]
+        y = out if out is not None else torch.empty(B, 3, device=self.device)
+        self._enter()
+        check(self.L.mlp_forward(self.h, C.c_void_p(x.data_ptr()), int(B), C.c_void_p(y.data_ptr())),
+              "mlp_forward")
+        self._keep = [x]
+        self._leave()
+        return y
+
+    def train_step(self, x, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_grad=False):
+        x = x.to(self.device, torch.float32).contiguous()
+        t = target.to(self.device, torch.float32).contiguous()
+        loss = torch.empty(1, device=self.device)
+        grad = torch.empty(N_PARAMS, device=self.device) if want_grad else None
+        self._enter()
+        check(self.L.mlp_train_step(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                    int(x.shape[0]), float(lr), float(beta1), float(beta2), float(eps),
+                                    None if grad is None else C.c_void_p(grad.data_ptr()),
+                                    C.c_void_p(loss.data_ptr())), "mlp_train_step")
+        self._keep = [x, t]
+        self._leave()
+        return loss, grad
+
+    def params(self) -> torch.Tensor:
+        p = torch.empty(N_PARAMS, device=self.device)
+        self._enter()
+        check(self.L.mlp_get_params(self.h, C.c_void_p(p.data_ptr())), "mlp_get_params")
+        self._leave()
+        return p
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            check(self.L.mlp_destroy(self.h), "mlp_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,188 @@
+"""Python binding of the SPH part of libslosh.so (argument marshalling only).
+
+Every step of the simulation runs in the library's HIP kernels; PyTorch
+provides device memory and the stream the library enqueues on.  The names
+follow the C ABI: ``Simulator.step`` is ``sph_step``, ``rollout`` is
+``sph_rollout`` and so on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import SphParams, check, load
+
+FRAME_BODY, FRAME_WORLD = 0, 1
+ST_ESCAPED, ST_NONFINITE, ST_SORT = 1, 2, 4
+
+
+def make_params(prm) -> SphParams:
+    """Marshals any object with the fields of ``sph_params`` (e.g. workloads.Params)."""
+    o = SphParams()
+    for name, _ in SphParams._fields_:
+        if name == "reserved":
+            continue
+        v = getattr(prm, name)
+        if name in ("domain_min", "domain_max"):
+            setattr(o, name, (C.c_double * 2)(*[float(x) for x in v]))
+        else:
+            setattr(o, name, v)
+    return o
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f32(a, device) -> torch.Tensor:
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32) if isinstance(a, np.ndarray) else a,
+                           dtype=torch.float32, device=device).contiguous()
+
+
+class Simulator:
+    """One tank: ``sph_init`` on construction, ``sph_destroy`` on close()."""
+
+    def __init__(self, params, pos, vel, ghosts, rigid0, device="cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.L = load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.params = params
+        self._prm = make_params(params)
+        s0 = _dev_f32(pos, self.device).reshape(-1, 2)
+        w0 = _dev_f32(vel, self.device).reshape(-1, 2)
+        g0 = _dev_f32(ghosts, self.device).reshape(-1, 2)
+        self.n, self.g = int(s0.shape[0]), int(g0.shape[0])
+        nbytes = C.c_size_t()
+        check(self.L.sph_workspace_bytes(C.byref(self._prm), self.n, self.g, C.byref(nbytes)),
+              "sph_workspace_bytes")
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes.value]
+        rig = (C.c_double * 6)(*[float(x) for x in np.asarray(rigid0, np.float64)])
+        h = C.c_void_p()
+        self._enter()
+        check(self.L.sph_init(C.byref(self._prm), self.n, _ptr(s0), _ptr(w0), self.g, _ptr(g0), rig,
+                              _ptr(self.ws), C.c_size_t(nbytes.value), C.c_void_p(self.stream.cuda_stream),
+                              C.byref(h)), "sph_init")
+        self.h = h
+        self._keep = []
+
+    @classmethod
+    def from_scenario(cls, sc, device="cuda:0", stream=None):
+        return cls(sc.params, sc.pos, sc.vel, sc.ghosts, sc.rigid0, device, stream)
+
+    # stream ordering with the caller's current stream
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            check(self.L.sph_destroy(self.h), "sph_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, u: Optional[torch.Tensor] = None):
+        self._enter()
+        if u is not None:
+            u = _dev_f32(u, self.device)
+            self._keep.append(u)
+        check(self.L.sph_step(self.h, _ptr(u)), "sph_step")
+        self._leave()
+
+    def rollout(self, n_steps: int, u_seq=None, theta_ref=None, log_stride: int = 0,
+                logs: bool = True):
+        """Runs n_steps; returns a dict of device log tensors (y, wrench, u, wrench_mean)."""
+        self._enter()
+        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(-1, 3)
+        if u is not None and u.shape[0] < n_steps:
+            raise ValueError("u_seq shorter than n_steps")
+        ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
+                                                              device=self.device).contiguous()
+        n_log = (n_steps + log_stride - 1) // log_stride if log_stride > 0 else 0
+        out = {}
+        if n_log and logs:
+            out = {"y": torch.zeros(n_log, 6, device=self.device),
+                   "wrench": torch.zeros(n_log, 3, device=self.device),
+                   "u": torch.zeros(n_log, 3, device=self.device),
+                   "wrench_mean": torch.zeros(n_log, 3, device=self.device)}
+            self._enter()
+        check(self.L.sph_rollout(self.h, int(n_steps), _ptr(u), _ptr(ref),
+                                 0 if ref is None else int(ref.numel()), int(log_stride),
+                                 _ptr(out.get("y")), _ptr(out.get("wrench")), _ptr(out.get("u")),
+                                 _ptr(out.get("wrench_mean"))), "sph_rollout")
+        self._keep = [u, ref]
+        self._leave()
+        return out
+
+    def rhs(self, u=None):
+        """x_dot at the current state (no advance): rho, P, a_sph, wdot, wrench, acc."""
+        self._enter()
+        uu = None if u is None else _dev_f32(u, self.device)
+        o = {"rho": torch.empty(self.n, device=self.device), "P": torch.empty(self.n, device=self.device),
+             "a_sph": torch.empty(self.n, 2, device=self.device),
+             "wdot": torch.empty(self.n, 2, device=self.device),
+             "wrench": torch.empty(3, device=self.device), "acc": torch.empty(3, device=self.device)}
+        self._enter()
+        check(self.L.sph_rhs(self.h, _ptr(uu), _ptr(o["rho"]), _ptr(o["P"]), _ptr(o["a_sph"]),
+                             _ptr(o["wdot"]), _ptr(o["wrench"]), _ptr(o["acc"])), "sph_rhs")
+        self._keep = [uu]
+        self._leave()
+        return o
+
+    def wrench(self, frame: int = FRAME_BODY) -> torch.Tensor:
+        out = torch.empty(3, device=self.device)
+        self._enter()
+        check(self.L.sph_slosh_wrench(self.h, int(frame), _ptr(out)), "sph_slosh_wrench")
+        self._leave()
+        return out
+
+    def get_state(self):
+        s = torch.empty(self.n, 2, device=self.device)
+        w = torch.empty(self.n, 2, device=self.device)
+        rig = (C.c_double * 6)()
+        tau = C.c_double()
+        step = C.c_int64()
+        self._enter()
+        check(self.L.sph_get_state(self.h, _ptr(s), _ptr(w), rig, C.byref(tau), C.byref(step)),
+              "sph_get_state")
+        self._leave()
+        return s, w, np.array(list(rig)), float(tau.value), int(step.value)
+
+    def set_state(self, s, w, rigid, tau_ctrl=0.0, step=0):
+        s = _dev_f32(s, self.device).reshape(-1, 2)
+        w = _dev_f32(w, self.device).reshape(-1, 2)
+        rig = (C.c_double * 6)(*[float(x) for x in np.asarray(rigid, np.float64)])
+        self._enter()
+        check(self.L.sph_set_state(self.h, _ptr(s), _ptr(w), rig, float(tau_ctrl), int(step)),
+              "sph_set_state")
+        self._leave()
+
+    def status(self) -> int:
+        f = C.c_uint32()
+        self._enter()
+        rc = self.L.sph_status(self.h, C.byref(f))
+        if rc not in (0, -4):
+            check(rc, "sph_status")
+        return int(f.value)
+
+    def neighbours(self, max_nbr: int = 64):
+        nbr = torch.full((self.n, max_nbr), -1, dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self._enter()
+        check(self.L.sph_neighbours(self.h, int(max_nbr), _ptr(nbr), _ptr(cnt)), "sph_neighbours")
+        self._leave()
+        return nbr, cnt
