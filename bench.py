@@ -1,0 +1,151 @@
+#!/usr/bin/env python
+"""Benchmark of the coupled SPH sloshing step on one MI355X.
+
+Workload: the closed-loop circular-tank run -- tank radius 0.5 m, 30 % fill,
+particle spacing 4 mm (14,542 fluid + 2,385 boundary particles), h = 1.3 dx,
+Tait EOS (gamma 7, c0 = 20 m/s), dt = 0.2 h / c0, spacecraft 1000 kg and
+500 kg m^2 under a PD attitude law (zero-order hold 0.05 s) tracking a
+30-degree trapezoidal-rate slew.  A step is one pass of the whole step
+(cell list, density/EOS, forces, slosh wrench, controller, rigid body,
+fictitious accelerations, integrator); the timed region is one rollout of
+--steps steps replayed from HIP graphs, inputs resident in HBM.
+
+Prints one JSON line: particle-steps/s, the roofline position of the
+dominant kernel (HIP-event kernel times measured in this run), and the FP64
+oracle timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic bytes per launch of each step kernel, per fluid particle (p),
+# boundary particle (g) and grid cell (c): what the method must move.
+#   bin:     read s, w, a_sph (24 B), write s, w (16 B) and the cell key (4 B)
+#   scan:    read the count, write the start, clear the count (12 B per cell)
+#   place:   read key, s, w, id (24 B), write s, w, id (20 B)
+#   density: read s (8 B), write rho, P/rho^2 (8 B); boundary positions 8 B
+#   force:   read s, w, rho, P/rho^2 (24 B), write a_sph (8 B); boundary 8 B
+BYTES = {"bin": (44, 0, 0), "scan": (0, 0, 12), "place": (44, 0, 8), "density": (16, 8, 8),
+         "force": (32, 8, 8)}
+
+# HBM traffic of the force kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (per dispatch, scaled by the copy-kernel calibration), valid for the source
+# whose hash is recorded; null once the kernel source changes.
+TRAFFIC = {"kernel": "sph_force", "src_sha1": None, "bytes_per_launch": None}
+
+
+def src_hash() -> str:
+    h = hashlib.sha1()
+    with open(os.path.join(ROOT, "paper_2604_12505_amd", "csrc", "sph.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(sc, n_steps: int):
+    """The FP64 oracle, as it stands, on the first n_steps of the workload."""
+    from oracle import sph as O
+    st = O.state_from_scenario(sc)
+    t0 = time.perf_counter()
+    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n_steps, sc.u_seq[:n_steps], sc.theta_ref)
+    dt = time.perf_counter() - t0
+    return {"value": sc.n_fluid * n_steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {n_steps} steps of the same workload ({sc.n_fluid} fluid particles), "
+                      f"{dt:.1f} s, FP64 C with OpenMP over particles"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--cpu-steps", type=int, default=1500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=200)
+    ap.add_argument("--dx", type=float, default=0.004)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd.sph import Simulator
+
+    total = args.warmup + args.steps + args.kernel_steps
+    sc = W.closed_loop_circle(seed=0, n_steps=total, dx=args.dx)
+    dev = torch.device("cuda:0")
+    sim = Simulator.from_scenario(sc, device=dev)
+    u = torch.as_tensor(sc.u_seq, device=dev)
+    ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
+
+    sim.rollout(args.warmup, u[:args.warmup], ref)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.rollout(args.steps, u[args.warmup:args.warmup + args.steps], ref)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    status = sim.status()
+    value = sc.n_fluid * args.steps / (ms / 1e3)
+
+    # per-kernel durations, HIP events around each kernel of directly launched steps
+    kus = sim.time_kernels(args.kernel_steps, u[args.warmup + args.steps:], ref)
+    status |= sim.status()
+    dominant = max(kus, key=kus.get)
+    bp, bg, bc = BYTES[dominant]
+    nc = int(np.ceil((sc.params.domain_max[0] - sc.params.domain_min[0]) / (2.6 * sc.dx * (1 + 1e-6)))) * \
+        int(np.ceil((sc.params.domain_max[1] - sc.params.domain_min[1]) / (2.6 * sc.dx * (1 + 1e-6))))
+    alg_bytes = bp * sc.n_fluid + bg * sc.n_ghost + bc * nc
+    achieved = alg_bytes / (kus[dominant] * 1e-6) / 1e9
+    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["src_sha1"] == src_hash() else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sph_" + dominant,
+                "algorithmic_bytes_per_launch": alg_bytes}
+    sim.close()
+
+    out = {
+        "metric": "SPH particle-steps/s at 1 GPU (% HBM roofline); NN vs SPH speedup at <=2% err",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"closed_loop_circle: R 0.5 m, fill 0.3, dx {sc.dx * 1e3:g} mm, "
+                               f"{sc.n_fluid} fluid + {sc.n_ghost} boundary particles, PD slew",
+                   "n_fluid": sc.n_fluid, "n_ghost": sc.n_ghost, "dt": sc.params.dt,
+                   "parallelism": "single GPU"},
+        "status": status,
+        "kernel_us": {k: round(v, 3) for k, v in kus.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+    print(json.dumps(out))
+    return 0 if status == 0 else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -30,7 +30,7 @@ class SphParams(C.Structure):
 
 SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sph_rollout",
                "sph_slosh_wrench", "sph_rhs", "sph_get_state", "sph_set_state", "sph_status",
-               "sph_neighbours", "sph_strerror")
+               "sph_neighbours", "sph_time_kernels", "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
                "mlp_get_params")
 
@@ -57,6 +57,7 @@ def load():
     L.sph_set_state.argtypes = [p, p, p, p, C.c_double, i64]
     L.sph_status.argtypes = [p, P(C.c_uint32)]
     L.sph_neighbours.argtypes = [p, i32, p, p]
+    L.sph_time_kernels.argtypes = [p, i32, p, p, i32, p]
     L.sph_strerror.argtypes = [C.c_int]
     L.sph_strerror.restype = C.c_char_p
     for name in SPH_SYMBOLS[:-1]:

@@ -825,28 +825,37 @@ struct sph_handle {
 
 namespace {
 
-// Enqueues one step (first: the state is already integrated, skip the deferred update).
-void enqueue_step(sph_handle* h, bool first, int mode) {
+// Enqueues one step (first: the state is already integrated, skip the deferred
+// update).  ev, if given, holds 6 events recorded around the 5 kernels.
+void enqueue_step(sph_handle* h, bool first, int mode, hipEvent_t* ev = nullptr) {
   int src = h->cur, dst = 1 - h->cur;
   const sph_params& p = h->p;
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], h->stream);
+  };
+  mark(0);
   hipLaunchKernelGGL(sph_bin, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
                      h->at<float2>(h->L.pos[src]), h->at<float2>(h->L.vel[src]),
                      h->at<float2>(h->L.acc), h->N, first ? 0 : 1, h->at<DevRigid>(h->L.rigid),
                      h->grid, h->k.dt, p.domain_min[0], p.domain_min[1], p.domain_max[0],
                      p.domain_max[1], h->at<int>(h->L.key), h->at<int>(h->L.count), (int*)nullptr,
                      h->at<unsigned>(h->L.status));
+  mark(1);
   hipLaunchKernelGGL(sph_scan, dim3(1), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
                      h->nc, h->at<int>(h->L.cstart[dst]), h->N, h->at<unsigned>(h->L.status));
+  mark(2);
   hipLaunchKernelGGL(sph_place, dim3(nblocks(h->nc)), dim3(kBlock), 0, h->stream,
                      h->at<int>(h->L.key), h->at<int>(h->L.cstart[src]),
                      h->at<int>(h->L.cstart[dst]), h->grid, h->at<float2>(h->L.pos[src]),
                      h->at<float2>(h->L.vel[src]), h->at<int>(h->L.id[src]),
                      h->at<float2>(h->L.pos[dst]), h->at<float2>(h->L.vel[dst]),
                      h->at<int>(h->L.id[dst]), h->at<unsigned>(h->L.status));
+  mark(3);
   hipLaunchKernelGGL(sph_density, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
                      h->at<float2>(h->L.pos[dst]), h->at<int>(h->L.cstart[dst]),
                      h->at<float2>(h->L.gpos), h->at<int>(h->L.gstart), h->N, h->grid, h->k,
                      h->at<float2>(h->L.rp));
+  mark(4);
   RigidArgs ra = h->ra;
   ra.mode = mode;
   hipLaunchKernelGGL(sph_force, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
@@ -855,6 +864,7 @@ void enqueue_step(sph_handle* h, bool first, int mode) {
                      h->at<int>(h->L.gstart), h->N, h->grid, h->k, h->at<float2>(h->L.acc),
                      h->at<double>(h->L.partials), h->at<unsigned>(h->L.ticket),
                      h->at<DevRigid>(h->L.rigid), h->at<DevRollout>(h->L.rollout), ra);
+  mark(5);
   h->cur = dst;
 }
 
@@ -1066,6 +1076,31 @@ int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const do
     enqueue_integrate(h);
     HIPCHK(hipGetLastError());
   }
+  return SPH_OK;
+}
+
+int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
+                     const double* theta_ref_dev, int32_t n_ref, float* avg_us) {
+  if (!h || n_steps < 1 || !avg_us || n_ref < 0) return SPH_E_INVAL;
+  int rc = set_rollout(h, u_seq_dev, theta_ref_dev, n_ref, 0, n_steps, nullptr, nullptr, nullptr,
+                       nullptr);
+  if (rc) return rc;
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  double sum[5] = {0, 0, 0, 0, 0};
+  for (int st = 0; st < n_steps; ++st) {
+    enqueue_step(h, st == 0, kStep, ev);
+    HIPCHK(hipEventSynchronize(ev[5]));
+    for (int k = 0; k < 5; ++k) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      sum[k] += ms;
+    }
+  }
+  enqueue_integrate(h);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+  for (int k = 0; k < 5; ++k) avg_us[k] = (float)(sum[k] * 1000.0 / n_steps);
   return SPH_OK;
 }
 

@@ -186,3 +186,16 @@ class Simulator:
         check(self.L.sph_neighbours(self.h, int(max_nbr), _ptr(nbr), _ptr(cnt)), "sph_neighbours")
         self._leave()
         return nbr, cnt
+
+    def time_kernels(self, n_steps: int, u_seq=None, theta_ref=None):
+        """Mean per-kernel microseconds over n_steps directly launched steps:
+        bin, scan, place, density, force."""
+        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(-1, 3)
+        ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
+                                                              device=self.device).contiguous()
+        out = (C.c_float * 5)()
+        self._enter()
+        check(self.L.sph_time_kernels(self.h, int(n_steps), _ptr(u), _ptr(ref),
+                                      0 if ref is None else int(ref.numel()), out), "sph_time_kernels")
+        self._leave()
+        return dict(zip(("bin", "scan", "place", "density", "force"), [float(x) for x in out]))
