@@ -31,15 +31,19 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
-# Algorithmic bytes per launch of each step kernel, per fluid particle (p),
+# Algorithmic bytes per launch of each kernel, per fluid particle (p),
 # boundary particle (g) and grid cell (c): what the method must move.
-#   bin:     read s, w, a_sph (24 B), write s, w (16 B) and the cell key (4 B)
-#   scan:    read the count, write the start, clear the count (12 B per cell)
-#   place:   read key, s, w, id (24 B), write s, w, id (20 B)
-#   density: read s (8 B), write rho, P/rho^2 (8 B); boundary positions 8 B
+#   density: read s, w, a_sph (24 B), write the updated s, w (16 B) and
+#            rho, P/rho^2 (8 B); boundary positions 8 B
 #   force:   read s, w, rho, P/rho^2 (24 B), write a_sph (8 B); boundary 8 B
-BYTES = {"bin": (44, 0, 0), "scan": (0, 0, 12), "place": (44, 0, 8), "density": (16, 8, 8),
-         "force": (32, 8, 8)}
+# and, every SORT_EVERY steps, the cell-list rebuild:
+#   bin:     read s (8 B), write the cell key (4 B)
+#   scan:    read the count, write the start, clear the count (12 B per cell)
+#   place:   read key, s, w, a_sph, id (32 B), write s, w, a_sph, id and s at
+#            the rebuild (36 B)
+BYTES = {"density": (48, 8, 0), "force": (32, 8, 0), "bin": (12, 0, 0), "scan": (0, 0, 12),
+         "place": (68, 0, 0)}
+SORT_EVERY = 8
 
 # HBM traffic of the force kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (per dispatch, scaled by the copy-kernel calibration), valid for the source
@@ -67,6 +71,85 @@ def cpu_baseline(sc, n_steps: int):
                       f"{dt:.1f} s, FP64 C with OpenMP over particles"}
 
 
+def kernel_roofline(kus, n_fluid, n_ghost, n_cells):
+    """Roofline position of the kernel that takes the most time per step."""
+    per_step = {k: v / (SORT_EVERY if k in ("bin", "scan", "place") else 1) for k, v in kus.items()}
+    dominant = max(per_step, key=per_step.get)
+    bp, bg, bc = BYTES[dominant]
+    alg_bytes = bp * n_fluid + bg * n_ghost + bc * n_cells
+    achieved = alg_bytes / (kus[dominant] * 1e-6) / 1e9
+    traffic = TRAFFIC["bytes_per_launch"] if (TRAFFIC["src_sha1"] == src_hash()
+                                              and TRAFFIC["kernel"] == "sph_" + dominant) else None
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sph_" + dominant,
+            "algorithmic_bytes_per_launch": alg_bytes}
+
+
+def n_cells_of(sc):
+    cell = (2.0 + 1.0) * sc.params.h * (1 + 1e-6)
+    return int(np.ceil((sc.params.domain_max[0] - sc.params.domain_min[0]) / cell)) * \
+        int(np.ceil((sc.params.domain_max[1] - sc.params.domain_min[1]) / cell))
+
+
+def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int):
+    """Many random tanks (rectangular or circular, fill U[0.2, 0.8], 2k-60k
+    particles, multisine torque) advanced together in the same launches."""
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd.sph import Simulator
+    total = warmup + steps + kernel_steps
+    scs = [W.random_tank(seed, n_steps=total) for seed in range(n_tanks)]
+    dev = torch.device("cuda:0")
+    sim = Simulator.batch(scs, device=dev)
+    lanes = sim.autotune(reps=5)
+    u = torch.stack([torch.as_tensor(sc.u_seq) for sc in scs]).to(dev)
+    sim.rollout(warmup, u[:, :warmup])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.rollout(steps, u[:, warmup:warmup + steps])
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kus = sim.time_kernels(kernel_steps, u[:, warmup + steps:])
+    status = sim.status()
+    sim.close()
+    n = sum(sc.n_fluid for sc in scs)
+    g = sum(sc.n_ghost for sc in scs)
+    nc = sum(n_cells_of(sc) for sc in scs)
+    return {"tanks": n_tanks, "n_fluid": n, "n_ghost": g, "steps": steps, "lanes": lanes,
+            "value": n * steps / (ms / 1e3), "unit": "particle-steps/s", "ms_per_step": ms / steps,
+            "status": status, "kernel_us": {k: round(v, 3) for k, v in kus.items()},
+            "roofline": kernel_roofline(kus, n, g, nc)}
+
+
+def paper_leg(steps: int = 30000):
+    """The paper's benchmark parameters (Tables 1-2: 666-particle circular tank,
+    linear EOS, dt = 1 ms, PD attitude law at 0.05 s) for a 30 s simulated run;
+    the paper's manoeuvre inputs are published only as a figure, so the input
+    is zero and the controller holds theta = 0."""
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd.sph import Simulator
+    sc = W.paper_p0(seed=0, n_steps=steps)
+    dev = torch.device("cuda:0")
+    sim = Simulator.from_scenario(sc, device=dev)
+    ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
+    sim.rollout(256, theta_ref=ref)
+    sim.set_state(torch.as_tensor(sc.pos), torch.as_tensor(sc.vel), sc.rigid0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.rollout(steps, theta_ref=ref, log_stride=50)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = sim.status()
+    sim.close()
+    return {"workload": f"paper Tables 1-2: {sc.n_fluid} fluid + {sc.n_ghost} boundary particles, "
+                        f"{steps} steps of 1 ms", "wall_s": wall, "status": status,
+            "paper_wall_s": 9.9093, "paper_hardware": "i7-13850HX + RTX 2000 Ada laptop, JAX"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +159,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--dx", type=float, default=0.004)
+    ap.add_argument("--batch-tanks", type=int, default=256,
+                    help="tanks of the batched leg (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-paper-leg", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -85,6 +174,15 @@ def main() -> int:
     import torch
     import workloads as W
     from paper_2604_12505_amd.sph import Simulator
+
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     total = args.warmup + args.steps + args.kernel_steps
     sc = W.closed_loop_circle(seed=0, n_steps=total, dx=args.dx)
@@ -108,16 +206,7 @@ def main() -> int:
     # per-kernel durations, HIP events around each kernel of directly launched steps
     kus = sim.time_kernels(args.kernel_steps, u[args.warmup + args.steps:], ref)
     status |= sim.status()
-    dominant = max(kus, key=kus.get)
-    bp, bg, bc = BYTES[dominant]
-    nc = int(np.ceil((sc.params.domain_max[0] - sc.params.domain_min[0]) / (2.6 * sc.dx * (1 + 1e-6)))) * \
-        int(np.ceil((sc.params.domain_max[1] - sc.params.domain_min[1]) / (2.6 * sc.dx * (1 + 1e-6))))
-    alg_bytes = bp * sc.n_fluid + bg * sc.n_ghost + bc * nc
-    achieved = alg_bytes / (kus[dominant] * 1e-6) / 1e9
-    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["src_sha1"] == src_hash() else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sph_" + dominant,
-                "algorithmic_bytes_per_launch": alg_bytes}
+    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc))
     sim.close()
 
     out = {
@@ -141,6 +230,12 @@ def main() -> int:
         "kernel_us": {k: round(v, 3) for k, v in kus.items()},
         "roofline": roofline,
     }
+    if not args.no_paper_leg:
+        out["paper_scenario"] = paper_leg()
+        status |= out["paper_scenario"]["status"]
+    if args.batch_tanks > 0:
+        out["batch"] = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
+        status |= out["batch"]["status"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out))

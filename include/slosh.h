@@ -104,6 +104,42 @@ int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const fl
              int32_t n_ghost, const float* g_dev, const double* rigid0, void* ws_dev,
              size_t ws_bytes, void* stream, sph_handle** out);
 
+/* ---- many tanks in one handle ------------------------------------------- */
+/*
+ * A batch handle advances n_tanks independent tanks (each its own sph_params,
+ * particle counts, cell grid, time step, rigid body and inputs) in the same
+ * kernel launches.  Tank t's fluid particles are rows [P_t, P_t + n_fluid[t])
+ * of the concatenated arrays, P_t = sum of the earlier n_fluid; ghosts
+ * likewise.  For a batch, every per-tank argument of the calls below is
+ * tank-major: rigid0 / rigid [T][6], u_dev [T][3], u_seq_dev [T][n_steps][3],
+ * theta_ref_dev [T][n_ref], logs [T][n_log][...], wrench / acc [T][3],
+ * tau_ctrl and step [T] in sph_get_state; particle arrays are concatenated.
+ * A tank gives bitwise the same results alone or in a batch.
+ */
+int sph_batch_workspace_bytes(int32_t n_tanks, const sph_params* params, const int32_t* n_fluid,
+                              const int32_t* n_ghost, size_t* bytes);
+
+/* Like sph_init for n_tanks tanks: params [T] (host), n_fluid [T], n_ghost
+ * [T] (host), s0_dev / w0_dev [sum n_fluid][2], g_dev [sum n_ghost][2],
+ * rigid0 host [T][6]. */
+int sph_batch_init(int32_t n_tanks, const sph_params* params, const int32_t* n_fluid, const float* s0_dev,
+                   const float* w0_dev, const int32_t* n_ghost, const float* g_dev, const double* rigid0,
+                   void* ws_dev, size_t ws_bytes, void* stream, sph_handle** out);
+
+/* Number of tanks of a handle (1 for sph_init). */
+int sph_num_tanks(sph_handle* h, int32_t* n_tanks);
+
+/* Autotuner of the neighbour kernels: times, at the current state and
+ * without advancing it, `reps` evaluations of the density and force kernels
+ * for each supported number of lanes per particle (4, 8, 16; the tile is
+ * 256 / lanes particles) and keeps the fastest; *lanes receives it (may be
+ * NULL).  Rebuilds the cell list.  The choice changes the summation order,
+ * so results are reproducible for a fixed choice (sph_set_lanes). */
+int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes);
+
+/* Selects the lanes per particle (4, 8 or 16; default 8). */
+int sph_set_lanes(sph_handle* h, int32_t lanes);
+
 /* Frees the host handle and its graphs (the workspace stays the caller's). */
 int sph_destroy(sph_handle* h);
 
@@ -201,7 +237,8 @@ int mlp_init(const float* params_dev, int32_t max_batch, void* ws_dev, size_t ws
 
 int mlp_destroy(mlp_handle* h);
 
-/* y_dev [B][3] FP32 = net(x_dev [B][128] FP32), inputs rounded to BF16. */
+/* y_dev [B][3] FP32 = net(x_dev [B][128] FP32), inputs rounded to BF16; one
+ * fused kernel (activations stay on chip).  Asynchronous. */
 int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev);
 
 /* One training step on the mean squared error: forward, backward (gradients
@@ -211,6 +248,20 @@ int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev);
 int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, int32_t batch,
                    float lr, float beta1, float beta2, float eps, float* grad_dev,
                    float* loss_dev);
+
+/* Builds standardised surrogate inputs and targets from rollout logs.
+ * feat_dev [n_roll][n_t][3] = theta, thetadot, input torque per log sample;
+ * fill_dev [n_roll] fill ratios; wrench_dev [n_roll][n_t][3] body-frame slosh
+ * force and torque (may be NULL when y_dev is NULL); norm: host [14] =
+ * input means [4], input stds [4] (channels theta, thetadot, torque, fill),
+ * output means [3], output stds [3] (stds > 0).  With n_win = n_t - window + 1
+ * windows per rollout, x_dev [n_roll * n_win][window * 4] receives window w
+ * of rollout r as samples t = w .. w + window - 1, 4 channels per sample, and
+ * y_dev [n_roll * n_win][3] the wrench at sample w + window - 1 (the
+ * surrogate's target, Section 2 eq. surrogate as a one-step map).  Enqueued on
+ * `stream`; asynchronous. */
+int mlp_make_windows(const float* feat_dev, const float* fill_dev, const float* wrench_dev, int32_t n_roll,
+                     int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev, void* stream);
 
 /* Copies the FP32 master weights to params_dev [231171]. */
 int mlp_get_params(mlp_handle* h, float* params_dev);

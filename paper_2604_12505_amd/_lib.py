@@ -30,9 +30,10 @@ class SphParams(C.Structure):
 
 SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sph_rollout",
                "sph_slosh_wrench", "sph_rhs", "sph_get_state", "sph_set_state", "sph_status",
-               "sph_neighbours", "sph_time_kernels", "sph_strerror")
+               "sph_neighbours", "sph_time_kernels", "sph_batch_workspace_bytes", "sph_batch_init",
+               "sph_num_tanks", "sph_autotune", "sph_set_lanes", "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
-               "mlp_get_params")
+               "mlp_make_windows", "mlp_get_params")
 
 
 def load():
@@ -58,6 +59,11 @@ def load():
     L.sph_status.argtypes = [p, P(C.c_uint32)]
     L.sph_neighbours.argtypes = [p, i32, p, p]
     L.sph_time_kernels.argtypes = [p, i32, p, p, i32, p]
+    L.sph_batch_workspace_bytes.argtypes = [i32, P(SphParams), p, p, P(sz)]
+    L.sph_batch_init.argtypes = [i32, P(SphParams), p, p, p, p, p, p, p, sz, p, P(p)]
+    L.sph_num_tanks.argtypes = [p, P(i32)]
+    L.sph_autotune.argtypes = [p, i32, P(i32)]
+    L.sph_set_lanes.argtypes = [p, i32]
     L.sph_strerror.argtypes = [C.c_int]
     L.sph_strerror.restype = C.c_char_p
     for name in SPH_SYMBOLS[:-1]:
@@ -69,6 +75,7 @@ def load():
         L.mlp_forward.argtypes = [p, p, i32, p]
         L.mlp_train_step.argtypes = [p, p, p, i32, C.c_float, C.c_float, C.c_float, C.c_float, p, p]
         L.mlp_get_params.argtypes = [p, p]
+        L.mlp_make_windows.argtypes = [p, p, p, i32, i32, i32, p, p, p, p]
         for name in MLP_SYMBOLS:
             getattr(L, name).restype = C.c_int
     _lib = L

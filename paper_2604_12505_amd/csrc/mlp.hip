@@ -133,6 +133,68 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
     }
 }
 
+// Inference: the whole network for a tile of kRows rows in one workgroup.
+// Activations stay in LDS (two BF16 buffers, rows padded by 16 bytes); each of
+// the 4 waves computes kRows x 64 outputs of a layer as 4 x 4 MFMA tiles with
+// the weights read from L2; bias + GELU are applied in the epilogue; the
+// 3-wide head is a dot product per (row, output).
+constexpr int kRows = 64;
+constexpr int kLdsStride = kHid + 8;
+
+__global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict__ x, int B,
+                                                         const bf16* __restrict__ wb,
+                                                         const float* __restrict__ master,
+                                                         float* __restrict__ y) {
+  __shared__ __align__(16) bf16 buf[2][kRows * kLdsStride];
+  const int row0 = blockIdx.x * kRows;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < kRows * kIn; e += 256) {
+    int r = e / kIn, k = e - r * kIn;
+    int m = row0 + r;
+    float v = m < B ? x[(size_t)m * kIn + k] : 0.0f;
+    buf[0][r * kLdsStride + k] = (bf16)v;
+  }
+  __syncthreads();
+  int cur = 0;
+  const int li = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  const int n0 = wave * 64;
+  for (int l = 0; l < 4; ++l) {
+    const int K = kDims[l];
+    const bf16* W = wb + kOffW[l];
+    const float* bias = master + kOffB[l];
+    floatx4 acc[4][4];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf16x8 a[4], b[4];
+      for (int r = 0; r < 4; ++r)
+        a[r] = *reinterpret_cast<const bf16x8*>(&buf[cur][(r * 16 + li) * kLdsStride + k0 + kq]);
+      for (int c = 0; c < 4; ++c)
+        b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + kq);
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+    }
+    for (int c = 0; c < 4; ++c) {
+      const int n = n0 + c * 16 + li;
+      const float bn = bias[n];
+      for (int r = 0; r < 4; ++r)
+        for (int e = 0; e < 4; ++e)
+          buf[1 - cur][(r * 16 + rq + e) * kLdsStride + n] = (bf16)gelu(acc[r][c][e] + bn);
+    }
+    __syncthreads();
+    cur = 1 - cur;
+  }
+  if (threadIdx.x < kRows * kOut) {
+    const int r = threadIdx.x / kOut, o = threadIdx.x - r * kOut;
+    const bf16* w4 = wb + kOffW[4] + o * kHid;
+    float s = 0.0f;
+    for (int k = 0; k < kHid; ++k) s += (float)buf[cur][r * kLdsStride + k] * (float)w4[k];
+    const int m = row0 + r;
+    if (m < B) y[(size_t)m * kOut + o] = s + master[kOffB[4] + o];
+  }
+}
+
 // FP32 input [B][128] -> BF16 row-major and (training) transposed copies.
 __global__ void mlp_cast_input(const float* __restrict__ x, int B, bf16* __restrict__ xb,
                                bf16* __restrict__ xT, int ldT) {
@@ -253,6 +315,35 @@ __global__ void mlp_refresh(const float* __restrict__ w, bf16* __restrict__ wb, 
       int r = (i - off) / kHid, c = (i - off) % kHid;     // W_l[r][c], r = out, c = in
       wT[(size_t)(l - 1) * kHid * kHid + (size_t)c * kHid + r] = v;
     }
+  }
+}
+
+// Surrogate inputs from rollout logs: window w of rollout r holds samples
+// t = w .. w + window - 1 of (theta, omega, input torque) and the fill ratio,
+// each standardised; its target is the wrench at the window's last sample.
+//   x [(r * n_win + w)][t * 4 + c],  y [(r * n_win + w)][3],  n_win = T - window + 1.
+struct WinNorm {
+  float in_mean[4], in_inv[4], out_mean[3], out_inv[3];
+};
+
+__global__ void mlp_windows(const float* __restrict__ feat, const float* __restrict__ fill,
+                            const float* __restrict__ wrench, int R, int T, int window, WinNorm nm,
+                            float* __restrict__ x, float* __restrict__ y) {
+  const int n_win = T - window + 1;
+  const long long width = (long long)window * 4;
+  const long long total = (long long)R * n_win * width;
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  long long row = e / width;
+  int k = (int)(e - row * width);
+  int ti = k >> 2, c = k & 3;
+  int r = (int)(row / n_win), w = (int)(row - (long long)r * n_win);
+  int t = w + ti;
+  float v = c < 3 ? feat[((size_t)r * T + t) * 3 + c] : fill[r];
+  x[e] = (v - nm.in_mean[c]) * nm.in_inv[c];
+  if (y && k < 3) {
+    float o = wrench[((size_t)r * T + w + window - 1) * 3 + k];
+    y[row * 3 + k] = (o - nm.out_mean[k]) * nm.out_inv[k];
   }
 }
 
@@ -398,11 +489,8 @@ int mlp_destroy(mlp_handle* h) {
 
 int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev) {
   if (!h || !x_dev || !y_dev || batch < 1 || batch > h->maxB) return SPH_E_INVAL;
-  forward(h, x_dev, batch, false);
-  hipLaunchKernelGGL(mlp_head, dim3((batch + 3) / 4), dim3(256), 0, h->stream, h->at<bf16>(h->L.act[3]),
-                     h->at<bf16>(h->L.wb) + kOffW[4], h->at<float>(h->L.master) + kOffB[4], batch, y_dev,
-                     (const float*)nullptr, (float*)nullptr, (float*)nullptr, (const float*)nullptr,
-                     (bf16*)nullptr, (bf16*)nullptr, h->L.ldT);
+  hipLaunchKernelGGL(mlp_forward_fused, dim3((batch + kRows - 1) / kRows), dim3(256), 0, h->stream, x_dev,
+                     batch, h->at<bf16>(h->L.wb), h->at<float>(h->L.master), y_dev);
   MHIP(hipGetLastError());
   return SPH_OK;
 }
@@ -451,6 +539,30 @@ int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, i
                      MLP_N_PARAMS, lr, beta1, beta2, eps, c1, c2);
   hipLaunchKernelGGL(mlp_refresh, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
                      h->at<float>(h->L.master), h->at<bf16>(h->L.wb), h->at<bf16>(h->L.wT));
+  MHIP(hipGetLastError());
+  return SPH_OK;
+}
+
+int mlp_make_windows(const float* feat_dev, const float* fill_dev, const float* wrench_dev, int32_t n_roll,
+                     int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev, void* stream) {
+  if (!feat_dev || !fill_dev || !norm || !x_dev || n_roll < 1 || window < 1 || n_t < window) return SPH_E_INVAL;
+  if (y_dev && !wrench_dev) return SPH_E_INVAL;
+  WinNorm nm;
+  for (int c = 0; c < 4; ++c) {
+    if (!(norm[4 + c] > 0.0f)) return SPH_E_INVAL;
+    nm.in_mean[c] = norm[c];
+    nm.in_inv[c] = 1.0f / norm[4 + c];
+  }
+  for (int c = 0; c < 3; ++c) {
+    if (!(norm[11 + c] > 0.0f)) return SPH_E_INVAL;
+    nm.out_mean[c] = norm[8 + c];
+    nm.out_inv[c] = 1.0f / norm[11 + c];
+  }
+  long long total = (long long)n_roll * (n_t - window + 1) * window * 4;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffffLL) return SPH_E_INVAL;
+  hipLaunchKernelGGL(mlp_windows, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                     feat_dev, fill_dev, wrench_dev, n_roll, n_t, window, nm, x_dev, y_dev);
   MHIP(hipGetLastError());
   return SPH_OK;
 }

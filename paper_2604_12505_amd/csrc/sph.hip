@@ -1,37 +1,48 @@
 // Body-frame weakly compressible SPH step for gfx950 (MI355X), coupled to
-// planar rigid-body dynamics, behind the C ABI of include/slosh.h.
+// planar rigid-body dynamics, behind the C ABI of include/slosh.h.  One
+// handle advances one tank or a batch of independent tanks of any sizes in
+// the same launches.
 //
-// One step (the paper's state-transition algorithm, Section 3.4, followed by
-// first-order symplectic Euler) is five kernels, captured into HIP graphs
-// for rollouts:
+// A step (the paper's state-transition algorithm, Section 3.4, followed by
+// first-order symplectic Euler) is two kernels; rollouts replay them from
+// captured HIP graphs:
 //
-//   sph_bin      apply the previous step's fluid update (deferred so that it
-//                can use the rigid accelerations of that step), compute each
-//                particle's cell key, count particles per cell (atomics on
-//                integer counters only), latch escape / non-finite flags;
-//   sph_scan     exclusive scan of the cell counts (one workgroup), which
-//                also clears the counters for the next step;
-//   sph_place    stable counting-sort placement: one thread per destination
-//                cell walks the 3x3 block of source cells in ascending key
-//                order and copies the particles that now belong to it, so the
-//                new order is deterministic and particle state is rewritten
-//                cell-contiguously (coalesced reads in the neighbour loops);
-//   sph_density  density with the gamma1 ghost term (eq. density_update) and
-//                the equation of state (eq. EOS, or its Tait form), stored as
-//                (rho, P/rho^2);
+//   sph_density  applies the previous step's fluid update (fictitious
+//                accelerations + symplectic Euler; it needs the rigid-body
+//                accelerations of that step, known only once its wrench was
+//                reduced), stores the updated state, and computes the density
+//                with the gamma1 ghost term (eq. density_update) and the
+//                equation of state (eq. EOS, or its Tait form).  Neighbour
+//                positions are updated on the fly with the same arithmetic,
+//                so no separate integration pass is needed;
 //   sph_force    fluid-fluid pressure (eq. momentum) and viscosity (eq.
 //                viscous), ghost-to-fluid pressure and viscosity with the
-//                spiky kernel (eqs. pressure_b2f, viscous_b2f), per-particle
-//                reaction wrench reduced per workgroup, then the last
-//                workgroup to finish reduces the partials in a fixed order,
-//                applies the zero-order-hold attitude law, the rigid-body
-//                equations (eq. tankdynamics) and writes the logs.
+//                spiky kernel (eqs. pressure_b2f, viscous_b2f); the tank's
+//                reactions are reduced per workgroup, and the last workgroup
+//                of each tank to finish sums that tank's partials in a fixed
+//                order and runs the zero-order-hold attitude law, the
+//                rigid-body equations (eq. tankdynamics) and the logs.
 //
-// Neighbours are found on a body-frame cell grid of side 2h (1 + 1e-6): the
-// support of every pair sum, so candidates of a particle lie in the three
-// contiguous key ranges of its 3x3 cell block.  Ghost particles are fixed in
-// the body frame, so their cell list is built once.  No floating-point
-// atomics are used: repeated runs are bitwise identical.
+// Both neighbour kernels work on tiles of 256/G consecutive particles of one
+// tank (in cell order), G lanes per particle.  A tile is cut into row
+// segments (its particles that share a grid row); for each segment the
+// workgroup stages in LDS, with one coalesced pass, every fluid and ghost
+// candidate of the three neighbouring rows over the segment's cell span, then
+// each particle's G lanes walk its own 3x3 block from LDS and combine their
+// sums with cross-lane shuffles.  A segment too large for the LDS stage
+// reads its candidates from global memory instead.  G is 4, 8 or 16, chosen
+// by sph_autotune (8 by default).
+//
+// Neighbours come from a body-frame cell grid of side (S + skin)(1 + 1e-6),
+// S = max(2h, h_spiky) the widest support, rebuilt every kSortEvery steps by
+// a stable counting sort (sph_bin, sph_scan, sph_place) that also rewrites
+// the particle state in cell order.  A particle is searched from the cell it
+// was sorted into; while every particle stays within skin/2 of its position at
+// the rebuild, every pair closer than S is in adjacent cells.  The density
+// kernel checks that bound each step and latches SPH_ST_SORT if it fails.
+// Ghost particles are fixed in the body frame: their cell list is built once.
+// No floating-point atomics are used: repeated runs are bitwise identical, and
+// a tank gives the same bits alone or in a batch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -45,8 +56,18 @@
 namespace {
 
 constexpr int kBlock = 256;       // threads per workgroup of the particle kernels
+constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
 constexpr int kScanThreads = 1024;
-constexpr int kChunk = 64;        // steps per captured graph (even: parity returns)
+constexpr int kSortEvery = 4;     // steps between cell-list rebuilds
+constexpr int kChunk = 64;        // steps per captured graph (multiple of kSortEvery, even)
+constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
+constexpr int kStageF = 1024;     // fluid candidates staged in LDS per row segment
+constexpr int kStageG = 512;      // ghost candidates staged in LDS per row segment
+constexpr int kNumVariants = 3;   // lanes per particle: 4, 8, 16
+constexpr int kLanes[kNumVariants] = {4, 8, 16};
+constexpr int kDefaultVariant = 1;
+
+static_assert(kChunk % kSortEvery == 0 && kChunk % 2 == 0, "graph chunk");
 
 // --------------------------------------------------------------------------
 // device-side structures
@@ -68,8 +89,30 @@ struct Consts {
   float beta2;              // 2 beta
   float eps_h2;             // eps h^2
   float dt;
+  float half_skin2;         // (skin / 2)^2: allowed squared displacement between rebuilds
   int eos, tgamma;          // tgamma > 0: integer Tait exponent
   float tgamma_f;
+};
+
+struct Box {
+  double lo_x, lo_y, hi_x, hi_y;
+};
+
+struct RigidArgs {
+  double dt, body_mass, body_inertia, kp, kd, sine_amp, sine_freq;
+  int motion, ctrl, ctrl_period, pad;
+};
+
+// Everything a kernel needs to know about one tank.
+struct Tank {
+  Grid g;
+  Consts k;
+  Box box;
+  RigidArgs ra;
+  int p0, n;      // particles [p0, p0 + n) of the global arrays
+  int c0, nc;     // cells [c0, c0 + nc) of the global cell arrays
+  int q0, ng;     // ghosts [q0, q0 + ng)
+  int pad[2];
 };
 
 struct DevRigid {
@@ -80,21 +123,22 @@ struct DevRigid {
   double th_eval, thd_eval;               // theta, thetadot used by the last evaluation
   double wsum[3];                         // running sum for the mean-wrench log
   long long step;
+  long long step0;                        // global step of the current rollout's local step 0
   int wcount, pad0;
   // binary32 coefficients of the fluid update of the last evaluated step
   float c, s, abx, aby, thd, thdd, pad1[2];
 };
 
+// Rollout inputs and logs, tank-major: tank t uses u + t * n_steps * 3, ...
 struct DevRollout {
-  const float* u;           // [n_steps][3] or null
-  const double* theta_ref;  // [n_ref] or null
-  float* y_log;
-  float* w_log;
-  float* u_log;
-  float* wm_log;
-  long long step0;          // global step of local step 0
+  const float* u;           // [T][n_steps][3] or null
+  const double* theta_ref;  // [T][n_ref] or null
+  float* y_log;             // [T][n_log][6]
+  float* w_log;             // [T][n_log][3]
+  float* u_log;             // [T][n_log][3]
+  float* wm_log;            // [T][n_log][3]
   long long n_steps;
-  int n_ref, log_stride;
+  int n_ref, log_stride, n_log, pad;
 };
 
 enum Mode { kStep = 0, kEval = 1 };
@@ -165,154 +209,213 @@ __device__ __forceinline__ float eos_over_rho2(float rho, const Consts& k, float
   return P / (rho * rho);
 }
 
-// Visits every fluid particle j in the 3x3 cell block of position s, in
-// ascending sorted order per grid row: f(j, s_j).
-template <class F>
-__device__ __forceinline__ void for_each_in_block(float2 s, const Grid& g, const int* __restrict__ start,
-                                                  const float2* __restrict__ pos, F&& f) {
-  int cx, cy;
-  cell_of(s, g, cx, cy);
-  int xa = cx > 0 ? cx - 1 : 0;
-  int xb = cx < g.ncx - 1 ? cx + 1 : g.ncx - 1;
-  for (int oy = -1; oy <= 1; ++oy) {
-    int yy = cy + oy;
-    if (yy < 0 || yy >= g.ncy) continue;
-    int j0 = start[yy * g.ncx + xa];
-    int j1 = start[yy * g.ncx + xb + 1];
-    for (int j = j0; j < j1; ++j) f(j, pos[j]);
-  }
+// Coefficients of the body-frame fluid update of the last evaluated step.
+struct Frame {
+  float abx, aby, thd, thdd;
+};
+
+__device__ __forceinline__ Frame load_frame(const DevRigid* __restrict__ rb) {
+  return Frame{rb->abx, rb->aby, rb->thd, rb->thdd};
 }
 
 // Body-frame fluid acceleration with the fictitious terms of the rotating,
 // accelerating tank frame (x = r + R(theta) s differentiated twice):
 //   dw/dt = a_sph - R^T r'' - 2 thetadot J w - theta'' J s + thetadot^2 s,  J v = (-v_y, v_x).
-__device__ __forceinline__ float2 body_frame_accel(float2 s, float2 w, float2 a,
-                                                   const DevRigid* __restrict__ rb) {
-  float thd = rb->thd, thdd = rb->thdd, om2 = thd * thd;
-  return make_float2(a.x - rb->abx + 2.0f * thd * w.y + thdd * s.y + om2 * s.x,
-                     a.y - rb->aby - 2.0f * thd * w.x - thdd * s.x + om2 * s.y);
+__device__ __forceinline__ float2 body_frame_accel(float2 s, float2 w, float2 a, const Frame& f) {
+  float om2 = f.thd * f.thd;
+  return make_float2(a.x - f.abx + 2.0f * f.thd * w.y + f.thdd * s.y + om2 * s.x,
+                     a.y - f.aby - 2.0f * f.thd * w.x - f.thdd * s.x + om2 * s.y);
 }
 
 // First-order symplectic Euler: velocity first, then position with the new velocity.
-__device__ __forceinline__ void fluid_update(float2& s, float2& w, float2 a,
-                                             const DevRigid* __restrict__ rb, float dt) {
-  float2 dw = body_frame_accel(s, w, a, rb);
+__device__ __forceinline__ void fluid_update(float2& s, float2& w, float2 a, const Frame& f, float dt) {
+  float2 dw = body_frame_accel(s, w, a, f);
   w.x += dt * dw.x;
   w.y += dt * dw.y;
   s.x += dt * w.x;
   s.y += dt * w.y;
 }
 
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ void flag(unsigned* status, unsigned bits) {
   if (bits) atomicOr(status, bits);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
 }
 
 // --------------------------------------------------------------------------
 // cell-list kernels
 // --------------------------------------------------------------------------
 
-// Deferred fluid update of the previous step (fictitious accelerations and
-// symplectic Euler, velocity first), then cell key and count.
-//   dw/dt = a_sph - R^T r'' - 2 thetadot J w - theta'' J s + thetadot^2 s
-__global__ void __launch_bounds__(kBlock) sph_bin(float2* __restrict__ pos, float2* __restrict__ vel,
-                                                  const float2* __restrict__ acc, int n, int integrate,
-                                                  const DevRigid* __restrict__ rb, Grid g,
-                                                  float dt, double lo_x, double lo_y, double hi_x,
-                                                  double hi_y, int* __restrict__ key,
-                                                  int* __restrict__ count, int* __restrict__ slot,
-                                                  unsigned* __restrict__ status) {
+// Global cell key and per-cell count (integer atomics); slot, if given,
+// receives the order of arrival (used by the first, general sort only).
+// owner[i] is the tank of element i.
+__global__ void __launch_bounds__(kBlock) sph_bin(const float2* __restrict__ pos, int n,
+                                                  const int* __restrict__ owner,
+                                                  const Tank* __restrict__ tanks, int* __restrict__ key,
+                                                  int* __restrict__ count, int* __restrict__ slot) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  float2 s = pos[i];
-  if (integrate) {
-    float2 w = vel[i];
-    fluid_update(s, w, acc[i], rb, dt);
-    pos[i] = s;
-    vel[i] = w;
-    unsigned bad = 0;
-    if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) bad |= SPH_ST_NONFINITE;
-    flag(status, bad);
-  }
-  unsigned bad = 0;
-  if (!((double)s.x >= lo_x && (double)s.x < hi_x && (double)s.y >= lo_y && (double)s.y < hi_y))
-    bad |= (isfinite(s.x) && isfinite(s.y)) ? SPH_ST_ESCAPED : SPH_ST_NONFINITE;
-  flag(status, bad);
+  const Tank& tk = tanks[owner[i]];
   int cx, cy;
-  cell_of(s, g, cx, cy);
-  int k = cy * g.ncx + cx;
+  cell_of(pos[i], tk.g, cx, cy);
+  int k = tk.c0 + cy * tk.g.ncx + cx;
   key[i] = k;
   int sl = atomicAdd(&count[k], 1);
   if (slot) slot[i] = sl;
 }
 
-// Exclusive scan of count[0..nc) into start[0..nc]; clears count.  One
-// workgroup: each thread scans a contiguous slice, slice totals are scanned
-// in LDS.
-__global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count, int nc,
-                                                         int* __restrict__ start, int expect,
+// Exclusive scan of each tank's cell counts into start (global indices,
+// first element of the tank at p0 / q0); clears the counts.  One workgroup
+// per tank walks its cells in coalesced chunks of 1024: wave scans by
+// shuffles, wave totals scanned in LDS, a running carry between chunks.
+// ghosts = 1 scans the ghost layout (base q0, count ng).
+__global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count,
+                                                         const Tank* __restrict__ tanks, int n_tanks,
+                                                         int ghosts, int* __restrict__ start,
                                                          unsigned* __restrict__ status) {
-  __shared__ int part[kScanThreads];
-  int t = threadIdx.x;
-  int per = (nc + kScanThreads - 1) / kScanThreads;
-  int b = t * per;
-  int e = b + per < nc ? b + per : nc;
-  int sum = 0;
-  for (int c = b; c < e; ++c) sum += count[c];
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
+  __shared__ int wsum[kScanThreads / 64];
+  const Tank& tk = tanks[blockIdx.x];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int base0 = ghosts ? tk.q0 : tk.p0, expect = ghosts ? tk.ng : tk.n;
+  int carry = 0;
+  for (int base = 0; base < tk.nc; base += kScanThreads) {
+    int i = base + t;
+    int v = i < tk.nc ? count[tk.c0 + i] : 0;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    part[t] += v;
+    if (wave == 0) {
+      int w = lane < kScanThreads / 64 ? wsum[lane] : 0;
+      for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+        int y = __shfl_up(w, off, 64);
+        if (lane >= off) w += y;
+      }
+      if (lane < kScanThreads / 64) wsum[lane] = w;
+    }
+    __syncthreads();
+    int before = (wave > 0 ? wsum[wave - 1] : 0);
+    if (i < tk.nc) {
+      start[tk.c0 + i] = base0 + carry + before + x - v;
+      count[tk.c0 + i] = 0;
+    }
+    carry += wsum[kScanThreads / 64 - 1];
     __syncthreads();
   }
-  int run = part[t] - sum;
-  for (int c = b; c < e; ++c) {
-    start[c] = run;
-    run += count[c];
-    count[c] = 0;
-  }
-  if (t == kScanThreads - 1) {
-    start[nc] = part[t];
-    if (part[t] != expect) atomicOr(status, SPH_ST_SORT);
+  if (t == 0) {
+    // the entry past a tank's last cell is the next tank's first; the last
+    // tank writes the final one
+    if ((int)blockIdx.x == n_tanks - 1) start[tk.c0 + tk.nc] = base0 + carry;
+    if (carry != expect && status) atomicOr(status, SPH_ST_SORT);
   }
 }
 
-// Stable placement after a step: thread c gathers, in ascending source
-// position, the particles of the 3x3 source block whose new key is c.
+// Stable placement after a rebuild: a group of kPlaceGroup lanes per
+// destination cell c walks the 3x3 block of source cells in ascending key
+// (= ascending source position) and compacts the particles whose new key is
+// c with a ballot, so their order is preserved.  Also records each particle's
+// position at the rebuild.
+// The candidate ranges of a particle in cell (cx, cy): for the rows cy-1,
+// cy, cy+1, the fluid index range [lo, hi) and the ghost range covering
+// cells cx-1 .. cx+1 (empty for rows outside the grid), packed as three int4:
+// {f_lo0, f_hi0, f_lo1, f_hi1}, {f_lo2, f_hi2, g_lo0, g_hi0}, {g_lo1, g_hi1, g_lo2, g_hi2}.
+__device__ __forceinline__ void cell_ranges(const Tank& tk, int cx, int cy, const int* __restrict__ start,
+                                            const int* __restrict__ gstart, int v[12]) {
+  const int ncx = tk.g.ncx;
+  const int xa = cx > 0 ? cx - 1 : 0;
+  const int xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
+  for (int r = 0; r < 3; ++r) {
+    const int yy = cy - 1 + r;
+    if (yy < 0 || yy >= tk.g.ncy) {
+      v[2 * r] = v[2 * r + 1] = 0;
+      v[6 + 2 * r] = v[6 + 2 * r + 1] = 0;
+      continue;
+    }
+    const int c = tk.c0 + yy * ncx;
+    v[2 * r] = start[c + xa];
+    v[2 * r + 1] = start[c + xb + 1];
+    v[6 + 2 * r] = gstart[c + xa];
+    v[6 + 2 * r + 1] = gstart[c + xb + 1];
+  }
+}
+
+__device__ __forceinline__ void store_ranges(int4* __restrict__ rng, int d, const int v[12]) {
+  rng[3 * d] = make_int4(v[0], v[1], v[2], v[3]);
+  rng[3 * d + 1] = make_int4(v[4], v[5], v[6], v[7]);
+  rng[3 * d + 2] = make_int4(v[8], v[9], v[10], v[11]);
+}
+
 __global__ void __launch_bounds__(kBlock) sph_place(const int* __restrict__ key,
+                                                    const int* __restrict__ cell_owner,
+                                                    const Tank* __restrict__ tanks, int n_cells,
                                                     const int* __restrict__ start_old,
-                                                    const int* __restrict__ start_new, Grid g,
+                                                    const int* __restrict__ start_new,
+                                                    const int* __restrict__ gstart,
+                                                    int4* __restrict__ rng, int* __restrict__ pkey,
                                                     const float2* __restrict__ pos_in,
                                                     const float2* __restrict__ vel_in,
+                                                    const float2* __restrict__ acc_in,
                                                     const int* __restrict__ id_in,
                                                     float2* __restrict__ pos_out,
                                                     float2* __restrict__ vel_out,
+                                                    float2* __restrict__ acc_out,
                                                     int* __restrict__ id_out,
+                                                    float2* __restrict__ pos_sort,
                                                     unsigned* __restrict__ status) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  int nc = g.ncx * g.ncy;
-  if (c >= nc) return;
-  int cy = c / g.ncx, cx = c - cy * g.ncx;
-  int dst = start_new[c], end = start_new[c + 1];
-  int xa = cx > 0 ? cx - 1 : 0;
-  int xb = cx < g.ncx - 1 ? cx + 1 : g.ncx - 1;
+  constexpr int G = kPlaceGroup;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = t / G, l = t % G;
+  if (c >= n_cells) return;
+  const Tank& tk = tanks[cell_owner[c]];
+  const int ncx = tk.g.ncx, ncy = tk.g.ncy;
+  const int shift = (threadIdx.x & 63) & ~(G - 1);   // first lane of this group in the wave
+  const int lc = c - tk.c0;
+  const int cy = lc / ncx, cx = lc - cy * ncx;
+  int dst = start_new[c];
+  const int end = start_new[c + 1];
+  const int xa = cx > 0 ? cx - 1 : 0;
+  const int xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
+  int rv[12];
+  cell_ranges(tk, cx, cy, start_new, gstart, rv);
   for (int oy = -1; oy <= 1; ++oy) {
     int yy = cy + oy;
-    if (yy < 0 || yy >= g.ncy) continue;
-    int i0 = start_old[yy * g.ncx + xa];
-    int i1 = start_old[yy * g.ncx + xb + 1];
-    for (int i = i0; i < i1; ++i) {
-      if (key[i] != c) continue;
-      if (dst < end) {
-        pos_out[dst] = pos_in[i];
-        vel_out[dst] = vel_in[i];
-        id_out[dst] = id_in[i];
+    if (yy < 0 || yy >= ncy) continue;
+    int i0 = start_old[tk.c0 + yy * ncx + xa];
+    int i1 = start_old[tk.c0 + yy * ncx + xb + 1];
+    for (int b = i0; b < i1; b += G) {
+      int i = b + l;
+      bool match = i < i1 && key[i] == c;
+      unsigned long long m = __ballot(match);
+      unsigned gm = (unsigned)(m >> shift) & ((1u << G) - 1u);
+      if (match) {
+        int d = dst + __popc(gm & ((1u << l) - 1u));
+        if (d < end) {
+          float2 s = pos_in[i];
+          pos_out[d] = s;
+          vel_out[d] = vel_in[i];
+          acc_out[d] = acc_in[i];
+          id_out[d] = id_in[i];
+          pos_sort[d] = s;
+          pkey[d] = c;
+          store_ranges(rng, d, rv);
+        }
       }
-      ++dst;
+      dst += __popc(gm);
     }
   }
-  if (dst != end) atomicOr(status, SPH_ST_SORT);
+  if (l == 0 && dst != end) atomicOr(status, SPH_ST_SORT);
 }
 
 // General (first) sort: scatter by (key, atomic slot), then order each cell by
@@ -340,89 +443,289 @@ __global__ void sph_cell_order(const int* __restrict__ start, int nc, int* __res
 }
 
 __global__ void sph_gather(const int* __restrict__ order, int n, const float2* __restrict__ pos_in,
-                           const float2* __restrict__ vel_in, const int* __restrict__ id_in,
-                           float2* __restrict__ pos_out, float2* __restrict__ vel_out,
-                           int* __restrict__ id_out) {
+                           const float2* __restrict__ vel_in, float2* __restrict__ pos_out,
+                           float2* __restrict__ vel_out, int* __restrict__ id_out,
+                           float2* __restrict__ pos_sort) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   int i = order[p];
-  pos_out[p] = pos_in[i];
+  float2 s = pos_in[i];
+  pos_out[p] = s;
   if (vel_in) vel_out[p] = vel_in[i];
-  if (id_out) id_out[p] = id_in ? id_in[i] : i;
+  if (id_out) id_out[p] = i;
+  if (pos_sort) pos_sort[p] = s;
+}
+
+// Cell key and candidate ranges of every particle after the general sort.
+__global__ void sph_ranges(const float2* __restrict__ pos_sort, int n, const int* __restrict__ owner,
+                           const Tank* __restrict__ tanks, const int* __restrict__ start,
+                           const int* __restrict__ gstart, int4* __restrict__ rng, int* __restrict__ pkey) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const Tank& tk = tanks[owner[p]];
+  int cx, cy;
+  cell_of(pos_sort[p], tk.g, cx, cy);
+  int v[12];
+  cell_ranges(tk, cx, cy, start, gstart, v);
+  pkey[p] = tk.c0 + cy * tk.g.ncx + cx;
+  store_ranges(rng, p, v);
+}
+
+// Marks escaped or non-finite particles of a state handed in by the caller.
+__global__ void sph_check(const float2* __restrict__ pos, const float2* __restrict__ vel, int n,
+                          const int* __restrict__ owner, const Tank* __restrict__ tanks,
+                          unsigned* __restrict__ status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Box& box = tanks[owner[i]].box;
+  float2 s = pos[i], w = vel[i];
+  unsigned bad = 0;
+  if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) bad |= SPH_ST_NONFINITE;
+  else if (!((double)s.x >= box.lo_x && (double)s.x < box.hi_x && (double)s.y >= box.lo_y &&
+             (double)s.y < box.hi_y))
+    bad |= SPH_ST_ESCAPED;
+  flag(status, bad);
+}
+
+// --------------------------------------------------------------------------
+// tiles and row segments
+// --------------------------------------------------------------------------
+
+// A tile is (tank, first particle, count); tiles never cross a tank.
+struct TileRef {
+  int tank, p0, np, pad;
+};
+
+// Per-tile data in LDS: each particle's grid row and its candidate ranges.
+template <int TP>
+struct TileLds {
+  int cy[TP];
+  int rng[TP][12];
+};
+
+// One row segment of a tile: slots [first, last] share grid row cy[first];
+// their candidates (rows cy-1 .. cy+1) are staged contiguously row after row:
+// fluid index j of row r sits at LDS index off[r] + j - lo[r].  The cells of
+// a segment are non-decreasing along the row, so its staged span of row r is
+// [lo of its first particle, hi of its last].
+struct Seg {
+  int lo[3], off[3], glo[3], goff[3];
+  int nf, ng, first, last;
+};
+
+template <int TP>
+__device__ void make_segment(Seg& sg, const TileLds<TP>& tl, int first) {
+  const int row = tl.cy[first];
+  int last = first;
+  while (last + 1 < TP && tl.cy[last + 1] == row) ++last;
+  int nf = 0, ng = 0;
+  for (int r = 0; r < 3; ++r) {
+    sg.off[r] = nf;
+    sg.goff[r] = ng;
+    sg.lo[r] = tl.rng[first][2 * r];
+    sg.glo[r] = tl.rng[first][6 + 2 * r];
+    nf += tl.rng[last][2 * r + 1] - sg.lo[r];
+    ng += tl.rng[last][6 + 2 * r + 1] - sg.glo[r];
+  }
+  sg.nf = nf;
+  sg.ng = ng;
+  sg.first = first;
+  sg.last = last;
+}
+
+// Global index of staged element e (row ranges stored back to back).
+__device__ __forceinline__ int seg_src(const int* lo, const int* off, int e) {
+  if (e < off[1]) return lo[0] + e - off[0];
+  if (e < off[2]) return lo[1] + e - off[1];
+  return lo[2] + e - off[2];
+}
+
+// Rows and candidate ranges of the tile's particles into LDS; -1 marks slots
+// past the end.
+template <int TP>
+__device__ __forceinline__ void tile_load(int p0, int np, const Tank& tk, const int* __restrict__ pkey,
+                                          const int4* __restrict__ rng, TileLds<TP>& tl) {
+  const int t = threadIdx.x;
+  if (t < TP) {
+    if (t < np) {
+      tl.cy[t] = (pkey[p0 + t] - tk.c0) / tk.g.ncx;
+      const int4 a = rng[3 * (p0 + t)], b = rng[3 * (p0 + t) + 1], c = rng[3 * (p0 + t) + 2];
+      int* v = tl.rng[t];
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+      v[8] = c.x; v[9] = c.y; v[10] = c.z; v[11] = c.w;
+    } else {
+      tl.cy[t] = -1;
+    }
+  }
+}
+
+// Visits the candidates of tile slot `pl` for lane l of its group (ghosts if
+// `ghost`): f(j, e) with global index j and LDS index e (valid when staged).
+template <int G, int TP, class F>
+__device__ __forceinline__ void visit(const TileLds<TP>& tl, int pl, bool ghost, const int* lo,
+                                      const int* off, int l, F&& f) {
+  const int* v = tl.rng[pl] + (ghost ? 6 : 0);
+  for (int r = 0; r < 3; ++r) {
+    const int a = v[2 * r], b = v[2 * r + 1];
+    const int shift = off[r] - lo[r];
+    for (int j = a + l; j < b; j += G) f(j, j + shift);
+  }
 }
 
 // --------------------------------------------------------------------------
 // particle sums
 // --------------------------------------------------------------------------
 
-// rho_i = m sigma (sum_f shape + gamma1 sum_g shape), then P and P/rho^2.
-__global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__ pos,
-                                                      const int* __restrict__ start,
+// Fluid update of the previous step (if `integrate`), then
+// rho_i = m sigma (sum_f shape + gamma1 sum_g shape), P and P/rho^2.
+template <int G>
+__global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__ pos_in,
+                                                      const float2* __restrict__ vel_in,
+                                                      const float2* __restrict__ acc_in, int integrate,
+                                                      const float2* __restrict__ pos_sort,
+                                                      const int* __restrict__ pkey,
+                                                      const int4* __restrict__ rng,
                                                       const float2* __restrict__ gpos,
-                                                      const int* __restrict__ gstart, int n, Grid g,
-                                                      Consts k, float2* __restrict__ rp) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  float2 s = pos[p];
-  float sf = 0.0f, sg = 0.0f;
-  for_each_in_block(s, g, start, pos, [&](int, float2 sj) {
-    float dx = s.x - sj.x, dy = s.y - sj.y;
-    float d2 = dist2(dx, dy);
-    if (d2 < k.R2) sf += cubic_shape(sqrtf(d2) * k.inv_h);
-  });
-  for_each_in_block(s, g, gstart, gpos, [&](int, float2 gj) {
-    float dx = s.x - gj.x, dy = s.y - gj.y;
-    float d2 = dist2(dx, dy);
-    if (d2 < k.R2) sg += cubic_shape(sqrtf(d2) * k.inv_h);
-  });
-  float rho = k.mass * k.wc * (sf + k.gamma1 * sg);
+                                                      const TileRef* __restrict__ tiles,
+                                                      const Tank* __restrict__ tanks,
+                                                      const DevRigid* __restrict__ rigid,
+                                                      float2* __restrict__ pos_out,
+                                                      float2* __restrict__ vel_out,
+                                                      float2* __restrict__ rp,
+                                                      unsigned* __restrict__ status) {
+  constexpr int TP = kBlock / G;
+  __shared__ float2 f_pos[kStageF];
+  __shared__ float2 g_pos[kStageG];
+  __shared__ TileLds<TP> tl;
+  __shared__ Seg sg;
+  const TileRef tr = tiles[blockIdx.x];
+  const Tank& tk = tanks[tr.tank];
+  const Consts& k = tk.k;
+  const int pl = threadIdx.x / G, l = threadIdx.x % G;
+  const int p = tr.p0 + pl;
+  const bool mine = pl < tr.np;
+  const Frame fr = load_frame(&rigid[tr.tank]);
+  const float dt = k.dt;
+  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl);
+  float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f);
+  if (mine) {
+    s = pos_in[p];
+    w = vel_in[p];
+    if (integrate) fluid_update(s, w, acc_in[p], fr, dt);
+  }
+  __syncthreads();
+  float sf = 0.0f, sgs = 0.0f;
+  int first = 0;
+  while (first < TP && tl.cy[first] >= 0) {
+    if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
+    __syncthreads();
+    const bool fst = sg.nf <= kStageF, gst = sg.ng <= kStageG;
+    if (fst)
+      for (int e = threadIdx.x; e < sg.nf; e += kBlock) {
+        const int j = seg_src(sg.lo, sg.off, e);
+        float2 sj = pos_in[j];
+        if (integrate) {
+          float2 wj = vel_in[j];
+          fluid_update(sj, wj, acc_in[j], fr, dt);
+        }
+        f_pos[e] = sj;
+      }
+    if (gst)
+      for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src(sg.glo, sg.goff, e)];
+    __syncthreads();
+    if (mine && pl >= sg.first && pl <= sg.last) {
+      auto fluid = [&](float2 sj) {
+        float d2 = dist2(s.x - sj.x, s.y - sj.y);
+        if (d2 < k.R2) sf += cubic_shape(sqrtf(d2) * k.inv_h);
+      };
+      if (fst) {
+        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e]); });
+      } else {
+        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) {
+          float2 sj = pos_in[j];
+          if (integrate) {
+            float2 wj = vel_in[j];
+            fluid_update(sj, wj, acc_in[j], fr, dt);
+          }
+          fluid(sj);
+        });
+      }
+      auto ghost = [&](float2 gj) {
+        float d2 = dist2(s.x - gj.x, s.y - gj.y);
+        if (d2 < k.R2) sgs += cubic_shape(sqrtf(d2) * k.inv_h);
+      };
+      if (gst)
+        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
+      else
+        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
+    }
+    const int next = sg.last + 1;
+    __syncthreads();
+    first = next;
+  }
+  sf = group_sum<G>(sf);
+  sgs = group_sum<G>(sgs);
+  if (!mine || l != 0) return;
+  const float2 s0 = pos_sort[p];
+  float rho = k.mass * k.wc * (sf + k.gamma1 * sgs);
   float pr = eos_over_rho2(rho, k, nullptr);
   rp[p] = make_float2(rho, pr);
+  pos_out[p] = s;
+  vel_out[p] = w;
+  unsigned bad = 0;
+  if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) {
+    bad |= SPH_ST_NONFINITE;
+  } else {
+    const Box& box = tk.box;
+    if (!((double)s.x >= box.lo_x && (double)s.x < box.hi_x && (double)s.y >= box.lo_y &&
+          (double)s.y < box.hi_y))
+      bad |= SPH_ST_ESCAPED;
+    if (dist2(s.x - s0.x, s.y - s0.y) > k.half_skin2) bad |= SPH_ST_SORT;
+  }
+  flag(status, bad);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-// Rigid-body part of a step, run by one thread after the wrench is reduced:
-// zero-order-hold attitude law, eq. tankdynamics, logs, symplectic Euler.
-__device__ void rigid_step(DevRigid* rb, const DevRollout* ro, const double F[3], int mode,
-                           double dt, double body_mass, double body_inertia, int motion, int ctrl,
-                           int ctrl_period, double kp, double kd, double sine_amp,
-                           double sine_freq) {
-  long long n = rb->step;
-  long long loc = n - ro->step0;
+// Rigid-body part of a step, run by one thread after the tank's wrench is
+// reduced: zero-order-hold attitude law, eq. tankdynamics, logs, symplectic
+// Euler.
+__device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const double F[3], int mode,
+                           const RigidArgs& ra) {
+  const long long n = rb->step;
+  const long long loc = n - rb->step0;
   double u[3] = {0.0, 0.0, 0.0};
   if (mode == kStep && ro->u && loc >= 0 && loc < ro->n_steps) {
-    u[0] = ro->u[3 * loc];
-    u[1] = ro->u[3 * loc + 1];
-    u[2] = ro->u[3 * loc + 2];
+    const float* ut = ro->u + ((size_t)tank * ro->n_steps + loc) * 3;
+    u[0] = ut[0];
+    u[1] = ut[1];
+    u[2] = ut[2];
   } else if (mode == kEval && ro->u) {
-    u[0] = ro->u[0];
-    u[1] = ro->u[1];
-    u[2] = ro->u[2];
+    const float* ut = ro->u + (size_t)tank * 3;
+    u[0] = ut[0];
+    u[1] = ut[1];
+    u[2] = ut[2];
   }
-  if (mode == kStep && ctrl == SPH_CTRL_PD_ZOH && ctrl_period > 0 && n % ctrl_period == 0) {
-    long long kk = n / ctrl_period;
+  if (mode == kStep && ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && n % ra.ctrl_period == 0) {
+    long long kk = n / ra.ctrl_period;
     double ref = 0.0;
-    if (ro->theta_ref && ro->n_ref > 0) ref = ro->theta_ref[kk < ro->n_ref ? kk : ro->n_ref - 1];
-    rb->tau_ctrl = kp * (ref - rb->theta) - kd * rb->thetadot;
+    if (ro->theta_ref && ro->n_ref > 0)
+      ref = ro->theta_ref[(size_t)tank * ro->n_ref + (kk < ro->n_ref ? kk : ro->n_ref - 1)];
+    rb->tau_ctrl = ra.kp * (ref - rb->theta) - ra.kd * rb->thetadot;
   }
   double th, thd, acc[3];
-  if (motion == SPH_MOTION_SINE) {
-    double w = 2.0 * M_PI * sine_freq, t = (double)n * dt;
-    th = sine_amp * sin(w * t);
-    thd = sine_amp * w * cos(w * t);
+  if (ra.motion == SPH_MOTION_SINE) {
+    double w = 2.0 * M_PI * ra.sine_freq, t = (double)n * ra.dt;
+    th = ra.sine_amp * sin(w * t);
+    thd = ra.sine_amp * w * cos(w * t);
     acc[0] = acc[1] = 0.0;
-    acc[2] = -sine_amp * w * w * sin(w * t);
+    acc[2] = -ra.sine_amp * w * w * sin(w * t);
   } else {
     th = rb->theta;
     thd = rb->thetadot;
     double c = cos(th), s = sin(th);
-    acc[0] = (c * F[0] - s * F[1] + u[0]) / body_mass;
-    acc[1] = (s * F[0] + c * F[1] + u[1]) / body_mass;
-    acc[2] = (F[2] + u[2] + rb->tau_ctrl) / body_inertia;
+    acc[0] = (c * F[0] - s * F[1] + u[0]) / ra.body_mass;
+    acc[1] = (s * F[0] + c * F[1] + u[1]) / ra.body_mass;
+    acc[2] = (F[2] + u[2] + rb->tau_ctrl) / ra.body_inertia;
   }
   for (int d = 0; d < 3; ++d) {
     rb->wrench[d] = F[d];
@@ -440,10 +743,11 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, const double F[3]
   if (mode != kStep) return;
 
   if (ro->log_stride > 0 && loc >= 0 && loc < ro->n_steps) {
-    long long kk = loc / ro->log_stride;
+    const long long kk = loc / ro->log_stride;
+    const size_t row = (size_t)tank * ro->n_log + kk;
     if (loc % ro->log_stride == 0) {
       if (ro->y_log) {
-        float* y = ro->y_log + 6 * kk;
+        float* y = ro->y_log + 6 * row;
         y[0] = (float)rb->r[0];
         y[1] = (float)rb->r[1];
         y[2] = (float)rb->theta;
@@ -452,110 +756,154 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, const double F[3]
         y[5] = (float)rb->thetadot;
       }
       if (ro->w_log)
-        for (int d = 0; d < 3; ++d) ro->w_log[3 * kk + d] = (float)F[d];
+        for (int d = 0; d < 3; ++d) ro->w_log[3 * row + d] = (float)F[d];
       if (ro->u_log) {
-        ro->u_log[3 * kk] = (float)u[0];
-        ro->u_log[3 * kk + 1] = (float)u[1];
-        ro->u_log[3 * kk + 2] = (float)(u[2] + rb->tau_ctrl);
+        ro->u_log[3 * row] = (float)u[0];
+        ro->u_log[3 * row + 1] = (float)u[1];
+        ro->u_log[3 * row + 2] = (float)(u[2] + rb->tau_ctrl);
       }
     }
     for (int d = 0; d < 3; ++d) rb->wsum[d] += F[d];
     rb->wcount += 1;
     if (loc % ro->log_stride == ro->log_stride - 1 || loc == ro->n_steps - 1) {
       if (ro->wm_log)
-        for (int d = 0; d < 3; ++d) ro->wm_log[3 * kk + d] = (float)(rb->wsum[d] / rb->wcount);
+        for (int d = 0; d < 3; ++d) ro->wm_log[3 * row + d] = (float)(rb->wsum[d] / rb->wcount);
       rb->wsum[0] = rb->wsum[1] = rb->wsum[2] = 0.0;
       rb->wcount = 0;
     }
   }
-  if (motion == SPH_MOTION_SINE) {
-    double w = 2.0 * M_PI * sine_freq, t = (double)(n + 1) * dt;
-    rb->theta = sine_amp * sin(w * t);
-    rb->thetadot = sine_amp * w * cos(w * t);
+  if (ra.motion == SPH_MOTION_SINE) {
+    double w = 2.0 * M_PI * ra.sine_freq, t = (double)(n + 1) * ra.dt;
+    rb->theta = ra.sine_amp * sin(w * t);
+    rb->thetadot = ra.sine_amp * w * cos(w * t);
     rb->r[0] = rb->r[1] = rb->rdot[0] = rb->rdot[1] = 0.0;
   } else {
-    rb->rdot[0] += dt * acc[0];
-    rb->rdot[1] += dt * acc[1];
-    rb->thetadot += dt * acc[2];
-    rb->r[0] += dt * rb->rdot[0];
-    rb->r[1] += dt * rb->rdot[1];
-    rb->theta += dt * rb->thetadot;
+    rb->rdot[0] += ra.dt * acc[0];
+    rb->rdot[1] += ra.dt * acc[1];
+    rb->thetadot += ra.dt * acc[2];
+    rb->r[0] += ra.dt * rb->rdot[0];
+    rb->r[1] += ra.dt * rb->rdot[1];
+    rb->theta += ra.dt * rb->thetadot;
   }
   rb->step = n + 1;
 }
-
-struct RigidArgs {
-  double dt, body_mass, body_inertia, kp, kd, sine_amp, sine_freq;
-  int motion, ctrl, ctrl_period, mode;
-};
 
 // Forces and the slosh wrench.  a_i = m sum_j [-(P_i/rho_i^2 + P_j/rho_j^2)
 //   + 2 alpha h (w_ij . s_ij) / ((rho_i + rho_j)(r^2 + eps h^2))] grad_i W_ij
 //   + sum_g m [-2 P_i/rho_i^2 + (2 beta / (2 rho_i)) min(w_i . s_ig, 0)/(r^2 + eps h^2)] grad_i W_s3
 // The tank receives -m * (wall term) per pair, with torque arm g.
+template <int G>
 __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ pos,
                                                     const float2* __restrict__ vel,
                                                     const float2* __restrict__ rp,
-                                                    const int* __restrict__ start,
+                                                    const int* __restrict__ pkey,
+                                                    const int4* __restrict__ rng,
                                                     const float2* __restrict__ gpos,
-                                                    const int* __restrict__ gstart, int n, Grid g,
-                                                    Consts k, float2* __restrict__ acc,
+                                                    const TileRef* __restrict__ tiles,
+                                                    const int* __restrict__ tank_tile0,
+                                                    const Tank* __restrict__ tanks,
+                                                    float2* __restrict__ acc,
                                                     double* __restrict__ partials,
-                                                    unsigned* __restrict__ ticket, DevRigid* rb,
-                                                    const DevRollout* __restrict__ ro, RigidArgs ra) {
+                                                    unsigned* __restrict__ tickets, DevRigid* rigid,
+                                                    const DevRollout* __restrict__ ro, int mode) {
+  constexpr int TP = kBlock / G;
+  __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
+  __shared__ float2 g_pos[kStageG];
+  __shared__ TileLds<TP> tl;
+  __shared__ Seg sg;
   __shared__ double red[3][kBlock / 64];
   __shared__ int last;
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  float fx = 0.0f, fy = 0.0f, tq = 0.0f;
-  if (p < n) {
-    float2 s = pos[p];
-    float2 w = vel[p];
-    float2 me = rp[p];
-    float rho_i = me.x, Pi = me.y;
-    float axf = 0.0f, ayf = 0.0f;
-    for_each_in_block(s, g, start, pos, [&](int j, float2 sj) {
-      float dx = s.x - sj.x, dy = s.y - sj.y;
-      float d2 = dist2(dx, dy);
-      if (d2 < k.R2 && d2 > 0.0f) {
-        float2 wj = vel[j];
-        float2 o = rp[j];
-        float q = sqrtf(d2) * k.inv_h;
-        float gW = k.dwc * cubic_grad_f(q);
-        float vr = (w.x - wj.x) * dx + (w.y - wj.y) * dy;
-        float coef = (-(Pi + o.y) + k.a2h * vr / ((rho_i + o.x) * (d2 + k.eps_h2))) * gW;
-        axf += coef * dx;
-        ayf += coef * dy;
-      }
-    });
-    float axg = 0.0f, ayg = 0.0f;
-    for_each_in_block(s, g, gstart, gpos, [&](int, float2 gj) {
-      float dx = s.x - gj.x, dy = s.y - gj.y;
-      float d2 = dist2(dx, dy);
-      if (d2 < k.Rs2 && d2 > 0.0f) {
-        float r = sqrtf(d2);
-        float t = k.hs - r;
-        float gW = k.dws * t * t / r;
-        float vr = w.x * dx + w.y * dy;
-        float coef = k.mass * (-2.0f * Pi + k.beta2 / (2.0f * rho_i) * fminf(vr, 0.0f) / (d2 + k.eps_h2)) * gW;
-        float ax = coef * dx, ay = coef * dy;   // wall force on the fluid / m
-        axg += ax;
-        ayg += ay;
-        float Fx = k.mass * ax, Fy = k.mass * ay;
-        fx -= Fx;
-        fy -= Fy;
-        tq -= gj.x * Fy - gj.y * Fx;
-      }
-    });
-    acc[p] = make_float2(k.mass * axf + axg, k.mass * ayf + ayg);
+  const TileRef tr = tiles[blockIdx.x];
+  const Tank& tk = tanks[tr.tank];
+  const Consts& k = tk.k;
+  const int pl = threadIdx.x / G, l = threadIdx.x % G;
+  const int p = tr.p0 + pl;
+  const bool mine = pl < tr.np;
+  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl);
+  float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f), me = make_float2(1.f, 0.f);
+  if (mine) {
+    s = pos[p];
+    w = vel[p];
+    me = rp[p];
   }
+  const float rho_i = me.x, Pi = me.y;
+  __syncthreads();
+  float axf = 0.0f, ayf = 0.0f, axg = 0.0f, ayg = 0.0f;
+  float fx = 0.0f, fy = 0.0f, tq = 0.0f;
+  int first = 0;
+  while (first < TP && tl.cy[first] >= 0) {
+    if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
+    __syncthreads();
+    const bool fst = sg.nf <= kStageF, gst = sg.ng <= kStageG;
+    if (fst)
+      for (int e = threadIdx.x; e < sg.nf; e += kBlock) {
+        const int j = seg_src(sg.lo, sg.off, e);
+        f_pos[e] = pos[j];
+        f_vel[e] = vel[j];
+        f_rp[e] = rp[j];
+      }
+    if (gst)
+      for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src(sg.glo, sg.goff, e)];
+    __syncthreads();
+    if (mine && pl >= sg.first && pl <= sg.last) {
+      auto fluid = [&](float2 sj, float2 wj, float2 o) {
+        float dx = s.x - sj.x, dy = s.y - sj.y;
+        float d2 = dist2(dx, dy);
+        if (d2 < k.R2 && d2 > 0.0f) {
+          float q = sqrtf(d2) * k.inv_h;
+          float gW = k.dwc * cubic_grad_f(q);
+          float vr = (w.x - wj.x) * dx + (w.y - wj.y) * dy;
+          float coef = (-(Pi + o.y) + k.a2h * vr / ((rho_i + o.x) * (d2 + k.eps_h2))) * gW;
+          axf += coef * dx;
+          ayf += coef * dy;
+        }
+      };
+      if (fst)
+        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e], f_vel[e], f_rp[e]); });
+      else
+        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) { fluid(pos[j], vel[j], rp[j]); });
+      auto ghost = [&](float2 gj) {
+        float dx = s.x - gj.x, dy = s.y - gj.y;
+        float d2 = dist2(dx, dy);
+        if (d2 < k.Rs2 && d2 > 0.0f) {
+          float r = sqrtf(d2);
+          float tt = k.hs - r;
+          float gW = k.dws * tt * tt / r;
+          float vr = w.x * dx + w.y * dy;
+          float coef = k.mass * (-2.0f * Pi + k.beta2 / (2.0f * rho_i) * fminf(vr, 0.0f) / (d2 + k.eps_h2)) * gW;
+          float ax = coef * dx, ay = coef * dy;   // wall force on the fluid / m
+          axg += ax;
+          ayg += ay;
+          float Fx = k.mass * ax, Fy = k.mass * ay;
+          fx -= Fx;
+          fy -= Fy;
+          tq -= gj.x * Fy - gj.y * Fx;
+        }
+      };
+      if (gst)
+        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
+      else
+        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
+    }
+    const int next = sg.last + 1;
+    __syncthreads();
+    first = next;
+  }
+  axf = group_sum<G>(axf);
+  ayf = group_sum<G>(ayf);
+  axg = group_sum<G>(axg);
+  ayg = group_sum<G>(ayg);
+  if (mine && l == 0) acc[p] = make_float2(k.mass * axf + axg, k.mass * ayf + ayg);
+
   // workgroup reduction of the wrench, in double, fixed order
   double v[3] = {(double)fx, (double)fy, (double)tq};
-  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int d = 0; d < 3; ++d) {
     double t = wave_sum(v[d]);
     if (lane == 0) red[d][wv] = t;
   }
   __syncthreads();
+  const int t0 = tank_tile0[tr.tank], nt = tank_tile0[tr.tank + 1] - t0;
   if (threadIdx.x == 0) {
     for (int d = 0; d < 3; ++d) {
       double t = 0.0;
@@ -563,16 +911,16 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       partials[3 * blockIdx.x + d] = t;
     }
     __threadfence();
-    unsigned tk = atomicAdd(ticket, 1u);
-    last = (tk == gridDim.x - 1);
+    unsigned tkt = atomicAdd(&tickets[tr.tank], 1u);
+    last = (tkt == (unsigned)nt - 1);
   }
   __syncthreads();
   if (!last) return;
-  // last workgroup: reduce all partials in a fixed order
+  // last workgroup of this tank: reduce its tiles' partials in a fixed order
   __threadfence();
   double acc3[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
-    for (int d = 0; d < 3; ++d) acc3[d] += partials[3 * b + d];
+  for (int b = threadIdx.x; b < nt; b += blockDim.x)
+    for (int d = 0; d < 3; ++d) acc3[d] += partials[3 * (t0 + b) + d];
   for (int d = 0; d < 3; ++d) {
     double t = wave_sum(acc3[d]);
     if (lane == 0) red[d][wv] = t;
@@ -585,21 +933,23 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       for (int q = 0; q < kBlock / 64; ++q) t += red[d][q];
       F[d] = t;
     }
-    rigid_step(rb, ro, F, ra.mode, ra.dt, ra.body_mass, ra.body_inertia, ra.motion, ra.ctrl,
-               ra.ctrl_period, ra.kp, ra.kd, ra.sine_amp, ra.sine_freq);
-    *ticket = 0u;
+    rigid_step(&rigid[tr.tank], ro, tr.tank, F, mode, tk.ra);
+    tickets[tr.tank] = 0u;
   }
 }
 
-// Final fluid update at the end of a rollout (the same update sph_bin defers).
+// Final fluid update at the end of a rollout (the update sph_density defers).
 __global__ void __launch_bounds__(kBlock) sph_integrate(float2* __restrict__ pos, float2* __restrict__ vel,
                                                         const float2* __restrict__ acc, int n,
-                                                        const DevRigid* __restrict__ rb, float dt,
+                                                        const int* __restrict__ owner,
+                                                        const Tank* __restrict__ tanks,
+                                                        const DevRigid* __restrict__ rigid,
                                                         unsigned* __restrict__ status) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int t = owner[i];
   float2 s = pos[i], w = vel[i];
-  fluid_update(s, w, acc[i], rb, dt);
+  fluid_update(s, w, acc[i], load_frame(&rigid[t]), tanks[t].k.dt);
   pos[i] = s;
   vel[i] = w;
   if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) flag(status, SPH_ST_NONFINITE);
@@ -608,23 +958,28 @@ __global__ void __launch_bounds__(kBlock) sph_integrate(float2* __restrict__ pos
 // Outputs of sph_rhs in caller order.
 __global__ void sph_rhs_out(const float2* __restrict__ pos, const float2* __restrict__ vel,
                             const float2* __restrict__ acc, const float2* __restrict__ rp,
-                            const int* __restrict__ id, int n, const DevRigid* __restrict__ rb,
-                            Consts k, float* rho_o, float* p_o, float2* a_o, float2* wd_o) {
+                            const int* __restrict__ id, int n, const int* __restrict__ owner,
+                            const Tank* __restrict__ tanks, const DevRigid* __restrict__ rigid,
+                            float* rho_o, float* p_o, float2* a_o, float2* wd_o) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
+  const int t = owner[q];
   int i = id[q];
   float rho = rp[q].x;
   float P;
-  eos_over_rho2(rho, k, &P);
+  eos_over_rho2(rho, tanks[t].k, &P);
   if (rho_o) rho_o[i] = rho;
   if (p_o) p_o[i] = P;
   float2 a = acc[q], s = pos[q], w = vel[q];
   if (a_o) a_o[i] = a;
-  if (wd_o) wd_o[i] = body_frame_accel(s, w, a, rb);
+  if (wd_o) wd_o[i] = body_frame_accel(s, w, a, load_frame(&rigid[t]));
 }
 
-__global__ void sph_small_out(const DevRigid* __restrict__ rb, float* wrench, float* acc3, int frame) {
-  if (threadIdx.x != 0) return;
+__global__ void sph_small_out(const DevRigid* __restrict__ rigid, int n_tanks, float* wrench, float* acc3,
+                              int frame) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tanks) return;
+  const DevRigid* rb = &rigid[t];
   double F0 = rb->wrench[0], F1 = rb->wrench[1];
   if (frame == SPH_FRAME_WORLD) {
     double c = cos(rb->th_eval), s = sin(rb->th_eval);
@@ -633,12 +988,12 @@ __global__ void sph_small_out(const DevRigid* __restrict__ rb, float* wrench, fl
     F1 = b;
   }
   if (wrench) {
-    wrench[0] = (float)F0;
-    wrench[1] = (float)F1;
-    wrench[2] = (float)rb->wrench[2];
+    wrench[3 * t] = (float)F0;
+    wrench[3 * t + 1] = (float)F1;
+    wrench[3 * t + 2] = (float)rb->wrench[2];
   }
   if (acc3)
-    for (int d = 0; d < 3; ++d) acc3[d] = (float)rb->acc[d];
+    for (int d = 0; d < 3; ++d) acc3[3 * t + d] = (float)rb->acc[d];
 }
 
 __global__ void sph_unpermute(const float2* __restrict__ src, const int* __restrict__ id, int n,
@@ -648,39 +1003,76 @@ __global__ void sph_unpermute(const float2* __restrict__ src, const int* __restr
   dst[id[q]] = src[q];
 }
 
-__global__ void sph_set_rollout(DevRollout* ro, DevRollout v, const DevRigid* rb) {
-  if (threadIdx.x != 0) return;
-  v.step0 = rb->step;
-  *ro = v;
+__global__ void sph_set_rollout(DevRollout* ro, DevRollout v, DevRigid* rigid, int n_tanks) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) *ro = v;
+  if (t < n_tanks) rigid[t].step0 = rigid[t].step;
 }
 
-// Test hook: neighbour ids (caller order) of every particle, ascending.
-__global__ void sph_nbr_list(const float2* __restrict__ pos, const int* __restrict__ start,
-                             const int* __restrict__ id, int n, Grid g, Consts k, int max_nbr,
-                             int* __restrict__ nbr, int* __restrict__ cnt) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  float2 s = pos[p];
-  int i = id[p];
-  int c = 0;
-  int* row = nbr + (size_t)i * max_nbr;
-  for_each_in_block(s, g, start, pos, [&](int j, float2 sj) {
-    if (j == p) return;
-    float dx = s.x - sj.x, dy = s.y - sj.y;
-    if (dist2(dx, dy) < k.R2) {
-      if (c < max_nbr) row[c] = id[j];
-      ++c;
+// Test hook: neighbour ids (caller order) of every particle, ascending, found
+// by the same tile / row-segment / LDS-staged traversal the particle sums use.
+template <int G>
+__global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict__ pos,
+                                                       const int* __restrict__ pkey,
+                                                       const int4* __restrict__ rng,
+                                                       const int* __restrict__ id,
+                                                       const TileRef* __restrict__ tiles,
+                                                       const Tank* __restrict__ tanks, int max_nbr,
+                                                       int* __restrict__ nbr, int* __restrict__ cnt) {
+  constexpr int TP = kBlock / G;
+  __shared__ float2 f_pos[kStageF];
+  __shared__ int f_id[kStageF];
+  __shared__ TileLds<TP> tl;
+  __shared__ Seg sg;
+  const TileRef tr = tiles[blockIdx.x];
+  const Tank& tk = tanks[tr.tank];
+  const int pl = threadIdx.x / G, l = threadIdx.x % G;
+  const int p = tr.p0 + pl;
+  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl);
+  __syncthreads();
+  int first = 0;
+  while (first < TP && tl.cy[first] >= 0) {
+    if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
+    __syncthreads();
+    const bool fst = sg.nf <= kStageF;
+    if (fst)
+      for (int e = threadIdx.x; e < sg.nf; e += kBlock) {
+        const int j = seg_src(sg.lo, sg.off, e);
+        f_pos[e] = pos[j];
+        f_id[e] = j;
+      }
+    __syncthreads();
+    // one lane per particle collects, so that the count is exact
+    if (pl < tr.np && l == 0 && pl >= sg.first && pl <= sg.last) {
+      const float2 s = pos[p];
+      const int i = id[p];
+      int* row_out = nbr + (size_t)i * max_nbr;
+      int c = 0;
+      auto take = [&](int j, float2 sj) {
+        if (j == p) return;
+        if (dist2(s.x - sj.x, s.y - sj.y) < tk.k.R2) {
+          if (c < max_nbr) row_out[c] = id[j];
+          ++c;
+        }
+      };
+      if (fst)
+        visit<1, TP>(tl, pl, false, sg.lo, sg.off, 0, [&](int, int e) { take(f_id[e], f_pos[e]); });
+      else
+        visit<1, TP>(tl, pl, false, sg.lo, sg.off, 0, [&](int j, int) { take(j, pos[j]); });
+      cnt[i] = c;
+      const int m = c < max_nbr ? c : max_nbr;
+      for (int a2 = 1; a2 < m; ++a2) {
+        int v = row_out[a2], b2 = a2 - 1;
+        while (b2 >= 0 && row_out[b2] > v) {
+          row_out[b2 + 1] = row_out[b2];
+          --b2;
+        }
+        row_out[b2 + 1] = v;
+      }
     }
-  });
-  cnt[i] = c;
-  int m = c < max_nbr ? c : max_nbr;
-  for (int a = 1; a < m; ++a) {
-    int v = row[a], b = a - 1;
-    while (b >= 0 && row[b] > v) {
-      row[b + 1] = row[b];
-      --b;
-    }
-    row[b + 1] = v;
+    const int next = sg.last + 1;
+    __syncthreads();
+    first = next;
   }
 }
 
@@ -703,14 +1095,10 @@ int hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-struct Layout {
-  size_t pos[2], vel[2], id[2], acc, rp, key, slot, order, count, cstart[2], gpos, graw, gstart,
-      partials, rigid, rollout, ticket, status, total;
-};
+double support_of(const sph_params* p) { return 2.0 * p->h > p->h_spiky ? 2.0 * p->h : p->h_spiky; }
 
 bool make_grid(const sph_params* p, Grid* g) {
-  double support = 2.0 * p->h > p->h_spiky ? 2.0 * p->h : p->h_spiky;
-  double cell = support * (1.0 + 1e-6);
+  double cell = (support_of(p) + kSkinOverH * p->h) * (1.0 + 1e-6);
   double w = p->domain_max[0] - p->domain_min[0], hh = p->domain_max[1] - p->domain_min[1];
   if (!(w > 0 && hh > 0 && cell > 0)) return false;
   double nx = std::ceil(w / cell), ny = std::ceil(hh / cell);
@@ -725,41 +1113,7 @@ bool make_grid(const sph_params* p, Grid* g) {
   return true;
 }
 
-int nblocks(int n) { return n > 0 ? (n + kBlock - 1) / kBlock : 1; }
-
-Layout make_layout(int N, int G, int nc) {
-  Layout L;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t at = o;
-    o += align256(bytes > 0 ? bytes : 1);
-    return at;
-  };
-  size_t n = (size_t)N, gg = (size_t)G;
-  for (int b = 0; b < 2; ++b) {
-    L.pos[b] = take(n * 8);
-    L.vel[b] = take(n * 8);
-    L.id[b] = take(n * 4);
-  }
-  L.acc = take(n * 8);
-  L.rp = take(n * 8);
-  L.key = take((n > gg ? n : gg) * 4);
-  L.slot = take((n > gg ? n : gg) * 4);
-  L.order = take((n > gg ? n : gg) * 4);
-  L.count = take((size_t)nc * 4);
-  L.cstart[0] = take(((size_t)nc + 1) * 4);
-  L.cstart[1] = take(((size_t)nc + 1) * 4);
-  L.gpos = take(gg * 8);
-  L.graw = take(gg * 8);
-  L.gstart = take(((size_t)nc + 1) * 4);
-  L.partials = take((size_t)nblocks(N) * 3 * 8);
-  L.rigid = take(sizeof(DevRigid));
-  L.rollout = take(sizeof(DevRollout));
-  L.ticket = take(4);
-  L.status = take(4);
-  L.total = o;
-  return L;
-}
+int nblocks(long long threads) { return threads > 0 ? (int)((threads + kBlock - 1) / kBlock) : 1; }
 
 bool params_ok(const sph_params* p) {
   if (!p) return false;
@@ -797,6 +1151,9 @@ Consts make_consts(const sph_params* p) {
   k.beta2 = (float)(2.0 * p->visc_beta);
   k.eps_h2 = (float)(p->eps * h * h);
   k.dt = (float)p->dt;
+  // a slightly smaller bound than skin/2 absorbs the rounding of the check
+  double hsk = 0.5 * kSkinOverH * h * (1.0 - 1e-5);
+  k.half_skin2 = (float)(hsk * hsk);
   k.eos = p->eos;
   double gi = std::round(p->tait_gamma);
   k.tgamma = (std::fabs(gi - p->tait_gamma) < 1e-12 && gi >= 1 && gi <= 64) ? (int)gi : 0;
@@ -804,150 +1161,288 @@ Consts make_consts(const sph_params* p) {
   return k;
 }
 
+// Sizes of a batch, known on the host.
+struct Plan {
+  int T = 0;
+  long long N = 0, Gh = 0, C = 0;          // particles, ghosts, cells (totals)
+  long long tiles[kNumVariants] = {0, 0, 0};
+  std::vector<Tank> tanks;
+};
+
+int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int32_t* n_ghost, Plan* pl) {
+  if (T < 1 || !params || !n_fluid || !n_ghost) return SPH_E_INVAL;
+  pl->T = T;
+  pl->tanks.resize(T);
+  long long p0 = 0, q0 = 0, c0 = 0;
+  for (int t = 0; t < T; ++t) {
+    const sph_params* p = &params[t];
+    if (!params_ok(p) || n_fluid[t] < 0 || n_ghost[t] < 0) return SPH_E_INVAL;
+    Tank& tk = pl->tanks[t];
+    memset(&tk, 0, sizeof tk);
+    if (!make_grid(p, &tk.g)) return SPH_E_INVAL;
+    tk.k = make_consts(p);
+    tk.box = Box{p->domain_min[0], p->domain_min[1], p->domain_max[0], p->domain_max[1]};
+    tk.ra = RigidArgs{p->dt, p->body_mass, p->body_inertia, p->kp, p->kd, p->sine_amp, p->sine_freq,
+                      p->motion, p->ctrl, p->ctrl_period, 0};
+    tk.p0 = (int)p0;
+    tk.n = n_fluid[t];
+    tk.q0 = (int)q0;
+    tk.ng = n_ghost[t];
+    tk.c0 = (int)c0;
+    tk.nc = tk.g.ncx * tk.g.ncy;
+    p0 += tk.n;
+    q0 += tk.ng;
+    c0 += tk.nc;
+    for (int v = 0; v < kNumVariants; ++v) {
+      const int tp = kBlock / kLanes[v];
+      pl->tiles[v] += tk.n > 0 ? (tk.n + tp - 1) / tp : 1;   // an empty tank still reduces its wrench
+    }
+    if (p0 > (1LL << 30) || q0 > (1LL << 30) || c0 > (1LL << 30)) return SPH_E_INVAL;
+  }
+  pl->N = p0;
+  pl->Gh = q0;
+  pl->C = c0;
+  return SPH_OK;
+}
+
+struct Layout {
+  size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, key, slot, order, count, gpos,
+      graw, gstart, owner, gowner, cowner, tanks, tiles[kNumVariants], tile0[kNumVariants], partials, tickets,
+      rigid, rollout, status, total;
+};
+
+Layout make_layout(const Plan& pl) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  const size_t n = (size_t)pl.N, gg = (size_t)pl.Gh, nc = (size_t)pl.C, T = (size_t)pl.T;
+  const size_t mx = n > gg ? n : gg;
+  size_t max_tiles = 0;
+  for (int v = 0; v < kNumVariants; ++v) max_tiles = max_tiles > (size_t)pl.tiles[v] ? max_tiles : (size_t)pl.tiles[v];
+  for (int b = 0; b < 2; ++b) {
+    L.pos[b] = take(n * 8);
+    L.vel[b] = take(n * 8);
+    L.acc[b] = take(n * 8);
+    L.id[b] = take(n * 4);
+    L.cstart[b] = take((nc + 1) * 4);
+  }
+  L.pos_sort = take(n * 8);
+  L.rng = take(n * 48);
+  L.pkey = take(n * 4);
+  L.rp = take(n * 8);
+  L.key = take(mx * 4);
+  L.slot = take(mx * 4);
+  L.order = take(mx * 4);
+  L.count = take(nc * 4);
+  L.gpos = take(gg * 8);
+  L.graw = take(gg * 8);
+  L.gstart = take((nc + 1) * 4);
+  L.owner = take(n * 4);
+  L.gowner = take(gg * 4);
+  L.cowner = take(nc * 4);
+  L.tanks = take(T * sizeof(Tank));
+  for (int v = 0; v < kNumVariants; ++v) {
+    L.tiles[v] = take((size_t)pl.tiles[v] * sizeof(TileRef));
+    L.tile0[v] = take((T + 1) * 4);
+  }
+  L.partials = take(max_tiles * 3 * 8);
+  L.tickets = take(T * 4);
+  L.rigid = take(T * sizeof(DevRigid));
+  L.rollout = take(sizeof(DevRollout));
+  L.status = take(4);
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
 struct sph_handle {
-  sph_params p;
-  int N, G, nc;
-  Grid grid;
-  Consts k;
-  RigidArgs ra;
+  Plan plan;
+  int T, N, Gh, C;
   hipStream_t stream;
   char* ws;
   Layout L;
-  int cur;
-  hipGraphExec_t graph[2];   // kChunk steps starting from buffer 0 / 1
-  bool graph_ok[2];
+  int cur;          // buffer of the current particle state (pos, vel, acc)
+  int ord;          // buffer of the current ordering (id, cell starts)
+  int since_sort;   // steps since the last cell-list rebuild
+  int variant;      // lanes per particle = kLanes[variant]
+  hipGraphExec_t graph[kNumVariants][2][2];   // kChunk steps from (cur, ord)
+  bool graph_ok[kNumVariants][2][2];
 
-  template <class T>
-  T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+  template <class T_>
+  T_* at(size_t off) { return reinterpret_cast<T_*>(ws + off); }
 };
 
 namespace {
 
-// Enqueues one step (first: the state is already integrated, skip the deferred
-// update).  ev, if given, holds 6 events recorded around the 5 kernels.
-void enqueue_step(sph_handle* h, bool first, int mode, hipEvent_t* ev = nullptr) {
-  int src = h->cur, dst = 1 - h->cur;
-  const sph_params& p = h->p;
+// Rebuilds the cell list from the current state: key + count, per-tank scan,
+// stable placement into the other buffers.  ev, if given, holds 4 events.
+void enqueue_sort(sph_handle* h, hipEvent_t* ev = nullptr) {
+  const int c = h->cur, o = h->ord;
   auto mark = [&](int i) {
     if (ev) (void)hipEventRecord(ev[i], h->stream);
   };
   mark(0);
-  hipLaunchKernelGGL(sph_bin, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
-                     h->at<float2>(h->L.pos[src]), h->at<float2>(h->L.vel[src]),
-                     h->at<float2>(h->L.acc), h->N, first ? 0 : 1, h->at<DevRigid>(h->L.rigid),
-                     h->grid, h->k.dt, p.domain_min[0], p.domain_min[1], p.domain_max[0],
-                     p.domain_max[1], h->at<int>(h->L.key), h->at<int>(h->L.count), (int*)nullptr,
-                     h->at<unsigned>(h->L.status));
+  hipLaunchKernelGGL(sph_bin, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
+                     h->N, h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.key),
+                     h->at<int>(h->L.count), (int*)nullptr);
   mark(1);
-  hipLaunchKernelGGL(sph_scan, dim3(1), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
-                     h->nc, h->at<int>(h->L.cstart[dst]), h->N, h->at<unsigned>(h->L.status));
+  hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
+                     h->at<Tank>(h->L.tanks), h->T, 0, h->at<int>(h->L.cstart[1 - o]),
+                     h->at<unsigned>(h->L.status));
   mark(2);
-  hipLaunchKernelGGL(sph_place, dim3(nblocks(h->nc)), dim3(kBlock), 0, h->stream,
-                     h->at<int>(h->L.key), h->at<int>(h->L.cstart[src]),
-                     h->at<int>(h->L.cstart[dst]), h->grid, h->at<float2>(h->L.pos[src]),
-                     h->at<float2>(h->L.vel[src]), h->at<int>(h->L.id[src]),
-                     h->at<float2>(h->L.pos[dst]), h->at<float2>(h->L.vel[dst]),
-                     h->at<int>(h->L.id[dst]), h->at<unsigned>(h->L.status));
+  hipLaunchKernelGGL(sph_place, dim3(nblocks((long long)h->C * kPlaceGroup)), dim3(kBlock), 0, h->stream,
+                     h->at<int>(h->L.key), h->at<int>(h->L.cowner), h->at<Tank>(h->L.tanks), h->C,
+                     h->at<int>(h->L.cstart[o]), h->at<int>(h->L.cstart[1 - o]), h->at<int>(h->L.gstart),
+                     h->at<int4>(h->L.rng), h->at<int>(h->L.pkey), h->at<float2>(h->L.pos[c]),
+                     h->at<float2>(h->L.vel[c]), h->at<float2>(h->L.acc[c]), h->at<int>(h->L.id[o]),
+                     h->at<float2>(h->L.pos[1 - c]), h->at<float2>(h->L.vel[1 - c]),
+                     h->at<float2>(h->L.acc[1 - c]), h->at<int>(h->L.id[1 - o]),
+                     h->at<float2>(h->L.pos_sort), h->at<unsigned>(h->L.status));
   mark(3);
-  hipLaunchKernelGGL(sph_density, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
-                     h->at<float2>(h->L.pos[dst]), h->at<int>(h->L.cstart[dst]),
-                     h->at<float2>(h->L.gpos), h->at<int>(h->L.gstart), h->N, h->grid, h->k,
-                     h->at<float2>(h->L.rp));
-  mark(4);
-  RigidArgs ra = h->ra;
-  ra.mode = mode;
-  hipLaunchKernelGGL(sph_force, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
-                     h->at<float2>(h->L.pos[dst]), h->at<float2>(h->L.vel[dst]),
-                     h->at<float2>(h->L.rp), h->at<int>(h->L.cstart[dst]), h->at<float2>(h->L.gpos),
-                     h->at<int>(h->L.gstart), h->N, h->grid, h->k, h->at<float2>(h->L.acc),
-                     h->at<double>(h->L.partials), h->at<unsigned>(h->L.ticket),
-                     h->at<DevRigid>(h->L.rigid), h->at<DevRollout>(h->L.rollout), ra);
-  mark(5);
-  h->cur = dst;
+  h->cur = 1 - c;
+  h->ord = 1 - o;
+  h->since_sort = 0;
+}
+
+template <int G>
+void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev) {
+  const int c = h->cur, o = h->ord;
+  const int nt = (int)h->plan.tiles[v];
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], h->stream);
+  };
+  mark(0);
+  hipLaunchKernelGGL(sph_density<G>, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
+                     h->at<float2>(h->L.vel[c]), h->at<float2>(h->L.acc[c]), integrate ? 1 : 0,
+                     h->at<float2>(h->L.pos_sort), h->at<int>(h->L.pkey), h->at<int4>(h->L.rng),
+                     h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), h->at<Tank>(h->L.tanks),
+                     h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
+                     h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status));
+  mark(1);
+  hipLaunchKernelGGL(sph_force<G>, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1 - c]),
+                     h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
+                     h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), h->at<int>(h->L.tile0[v]), h->at<Tank>(h->L.tanks),
+                     h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials),
+                     h->at<unsigned>(h->L.tickets), h->at<DevRigid>(h->L.rigid),
+                     h->at<DevRollout>(h->L.rollout), mode);
+  mark(2);
+}
+
+// Enqueues the two kernels of one step.  integrate = 0 when the state is
+// already integrated (first step of a rollout).  ev, if given, holds 3 events.
+void enqueue_step(sph_handle* h, bool integrate, int mode, hipEvent_t* ev = nullptr) {
+  switch (h->variant) {
+    case 0: launch_pair<4>(h, 0, integrate, mode, ev); break;
+    case 1: launch_pair<8>(h, 1, integrate, mode, ev); break;
+    default: launch_pair<16>(h, 2, integrate, mode, ev); break;
+  }
+  h->cur = 1 - h->cur;
+  h->since_sort += 1;
 }
 
 void enqueue_integrate(sph_handle* h) {
   hipLaunchKernelGGL(sph_integrate, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
                      h->at<float2>(h->L.pos[h->cur]), h->at<float2>(h->L.vel[h->cur]),
-                     h->at<float2>(h->L.acc), h->N, h->at<DevRigid>(h->L.rigid), h->k.dt,
-                     h->at<unsigned>(h->L.status));
+                     h->at<float2>(h->L.acc[h->cur]), h->N, h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks),
+                     h->at<DevRigid>(h->L.rigid), h->at<unsigned>(h->L.status));
 }
 
-// Full stable sort of the raw fluid arrays (caller order) into buffer 0.
+// Steps of a rollout with the rebuild schedule; the state is integrated on
+// entry and on exit.
+void enqueue_steps(sph_handle* h, int n_steps) {
+  for (int s = 0; s < n_steps; ++s) {
+    enqueue_step(h, s > 0, kStep);
+    if (h->since_sort >= kSortEvery) enqueue_sort(h);
+  }
+  enqueue_integrate(h);
+}
+
+// Full stable sort of raw fluid arrays (caller order) into buffers (cur, ord) = (0, 0).
 int sort_fluid(sph_handle* h, const float2* s, const float2* w) {
-  int nb = nblocks(h->N);
-  const sph_params& p = h->p;
-  // the raw arrays go through buffer 1 so that s/w may alias nothing of ours
+  const int nb = nblocks(h->N);
   if (h->N > 0) {
     HIPCHK(hipMemcpyAsync(h->at<float2>(h->L.pos[1]), s, (size_t)h->N * 8, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->at<float2>(h->L.vel[1]), w, (size_t)h->N * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemsetAsync(h->at<float2>(h->L.acc[0]), 0, (size_t)h->N * 8, h->stream));
   }
-  HIPCHK(hipMemsetAsync(h->at<int>(h->L.count), 0, (size_t)h->nc * 4, h->stream));
-  hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1]),
-                     h->at<float2>(h->L.vel[1]), h->at<float2>(h->L.acc), h->N, 0,
-                     h->at<DevRigid>(h->L.rigid), h->grid, h->k.dt, p.domain_min[0],
-                     p.domain_min[1], p.domain_max[0], p.domain_max[1], h->at<int>(h->L.key),
-                     h->at<int>(h->L.count), h->at<int>(h->L.slot), h->at<unsigned>(h->L.status));
-  hipLaunchKernelGGL(sph_scan, dim3(1), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
-                     h->nc, h->at<int>(h->L.cstart[0]), h->N, h->at<unsigned>(h->L.status));
+  HIPCHK(hipMemsetAsync(h->at<int>(h->L.count), 0, (size_t)h->C * 4, h->stream));
+  hipLaunchKernelGGL(sph_check, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1]),
+                     h->at<float2>(h->L.vel[1]), h->N, h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks),
+                     h->at<unsigned>(h->L.status));
+  hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1]), h->N,
+                     h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.key),
+                     h->at<int>(h->L.count), h->at<int>(h->L.slot));
+  hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
+                     h->at<Tank>(h->L.tanks), h->T, 0, h->at<int>(h->L.cstart[0]), h->at<unsigned>(h->L.status));
   if (h->N > 0) {
     hipLaunchKernelGGL(sph_scatter, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.key),
                        h->at<int>(h->L.slot), h->N, h->at<int>(h->L.cstart[0]), h->at<int>(h->L.order));
-    hipLaunchKernelGGL(sph_cell_order, dim3(nblocks(h->nc)), dim3(kBlock), 0, h->stream,
-                       h->at<int>(h->L.cstart[0]), h->nc, h->at<int>(h->L.order));
+    hipLaunchKernelGGL(sph_cell_order, dim3(nblocks(h->C)), dim3(kBlock), 0, h->stream,
+                       h->at<int>(h->L.cstart[0]), h->C, h->at<int>(h->L.order));
     hipLaunchKernelGGL(sph_gather, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.order), h->N,
-                       h->at<float2>(h->L.pos[1]), h->at<float2>(h->L.vel[1]), (const int*)nullptr,
-                       h->at<float2>(h->L.pos[0]), h->at<float2>(h->L.vel[0]), h->at<int>(h->L.id[0]));
+                       h->at<float2>(h->L.pos[1]), h->at<float2>(h->L.vel[1]), h->at<float2>(h->L.pos[0]),
+                       h->at<float2>(h->L.vel[0]), h->at<int>(h->L.id[0]), h->at<float2>(h->L.pos_sort));
+    hipLaunchKernelGGL(sph_ranges, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos_sort), h->N,
+                       h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.cstart[0]),
+                       h->at<int>(h->L.gstart), h->at<int4>(h->L.rng), h->at<int>(h->L.pkey));
   }
   HIPCHK(hipGetLastError());
   h->cur = 0;
+  h->ord = 0;
+  h->since_sort = 0;
   return SPH_OK;
 }
 
 int sort_ghosts(sph_handle* h, const float2* graw) {
-  int nb = nblocks(h->G);
-  HIPCHK(hipMemsetAsync(h->at<int>(h->L.count), 0, (size_t)h->nc * 4, h->stream));
-  unsigned* scratch_status = h->at<unsigned>(h->L.ticket);  // ghost escapes are not fluid errors
-  hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, const_cast<float2*>(graw),
-                     (float2*)nullptr, (const float2*)nullptr, h->G, 0, h->at<DevRigid>(h->L.rigid),
-                     h->grid, h->k.dt, -1e300, -1e300, 1e300, 1e300, h->at<int>(h->L.key),
-                     h->at<int>(h->L.count), h->at<int>(h->L.slot), scratch_status);
-  hipLaunchKernelGGL(sph_scan, dim3(1), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
-                     h->nc, h->at<int>(h->L.gstart), h->G, scratch_status);
-  if (h->G > 0) {
+  const int nb = nblocks(h->Gh);
+  HIPCHK(hipMemsetAsync(h->at<int>(h->L.count), 0, (size_t)h->C * 4, h->stream));
+  hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, graw, h->Gh, h->at<int>(h->L.gowner),
+                     h->at<Tank>(h->L.tanks), h->at<int>(h->L.key), h->at<int>(h->L.count),
+                     h->at<int>(h->L.slot));
+  hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
+                     h->at<Tank>(h->L.tanks), h->T, 1, h->at<int>(h->L.gstart), (unsigned*)nullptr);
+  if (h->Gh > 0) {
     hipLaunchKernelGGL(sph_scatter, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.key),
-                       h->at<int>(h->L.slot), h->G, h->at<int>(h->L.gstart), h->at<int>(h->L.order));
-    hipLaunchKernelGGL(sph_cell_order, dim3(nblocks(h->nc)), dim3(kBlock), 0, h->stream,
-                       h->at<int>(h->L.gstart), h->nc, h->at<int>(h->L.order));
-    hipLaunchKernelGGL(sph_gather, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.order), h->G,
-                       graw, (const float2*)nullptr, (const int*)nullptr, h->at<float2>(h->L.gpos),
-                       (float2*)nullptr, (int*)nullptr);
+                       h->at<int>(h->L.slot), h->Gh, h->at<int>(h->L.gstart), h->at<int>(h->L.order));
+    hipLaunchKernelGGL(sph_cell_order, dim3(nblocks(h->C)), dim3(kBlock), 0, h->stream,
+                       h->at<int>(h->L.gstart), h->C, h->at<int>(h->L.order));
+    hipLaunchKernelGGL(sph_gather, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.order), h->Gh,
+                       graw, (const float2*)nullptr, h->at<float2>(h->L.gpos), (float2*)nullptr, (int*)nullptr,
+                       (float2*)nullptr);
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemsetAsync(h->at<unsigned>(h->L.ticket), 0, 4, h->stream));
   return SPH_OK;
 }
 
 int set_rigid(sph_handle* h, const double* rigid, double tau_ctrl, long long step) {
-  DevRigid r;
-  memset(&r, 0, sizeof r);
-  r.r[0] = rigid[0];
-  r.r[1] = rigid[1];
-  r.theta = rigid[2];
-  r.rdot[0] = rigid[3];
-  r.rdot[1] = rigid[4];
-  r.thetadot = rigid[5];
-  r.tau_ctrl = tau_ctrl;
-  r.step = step;
-  HIPCHK(hipMemcpyAsync(h->at<DevRigid>(h->L.rigid), &r, sizeof r, hipMemcpyHostToDevice, h->stream));
+  std::vector<DevRigid> rs(h->T);
+  for (int t = 0; t < h->T; ++t) {
+    DevRigid& r = rs[t];
+    memset(&r, 0, sizeof r);
+    const double* g = rigid + 6 * t;
+    r.r[0] = g[0];
+    r.r[1] = g[1];
+    r.theta = g[2];
+    r.rdot[0] = g[3];
+    r.rdot[1] = g[4];
+    r.thetadot = g[5];
+    r.tau_ctrl = tau_ctrl;
+    r.step = step;
+    r.step0 = step;
+  }
+  HIPCHK(hipMemcpyAsync(h->at<DevRigid>(h->L.rigid), rs.data(), sizeof(DevRigid) * h->T,
+                        hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return SPH_OK;
 }
 
-int set_rollout(sph_handle* h, const float* u, const double* ref, int n_ref, int stride,
-                long long n_steps, float* y, float* wl, float* ul, float* wm) {
+int set_rollout(sph_handle* h, const float* u, const double* ref, int n_ref, int stride, long long n_steps,
+                float* y, float* wl, float* ul, float* wm) {
   DevRollout v;
   memset(&v, 0, sizeof v);
   v.u = u;
@@ -955,85 +1450,114 @@ int set_rollout(sph_handle* h, const float* u, const double* ref, int n_ref, int
   v.n_ref = n_ref;
   v.log_stride = stride;
   v.n_steps = n_steps;
+  v.n_log = stride > 0 ? (int)((n_steps + stride - 1) / stride) : 0;
   v.y_log = y;
   v.w_log = wl;
   v.u_log = ul;
   v.wm_log = wm;
-  hipLaunchKernelGGL(sph_set_rollout, dim3(1), dim3(64), 0, h->stream, h->at<DevRollout>(h->L.rollout),
-                     v, h->at<DevRigid>(h->L.rigid));
+  hipLaunchKernelGGL(sph_set_rollout, dim3(nblocks(h->T)), dim3(kBlock), 0, h->stream,
+                     h->at<DevRollout>(h->L.rollout), v, h->at<DevRigid>(h->L.rigid), h->T);
   HIPCHK(hipGetLastError());
   return SPH_OK;
 }
 
-int build_graph(sph_handle* h, int parity) {
-  if (h->graph_ok[parity]) return SPH_OK;
-  int saved = h->cur;
-  h->cur = parity;
+// Captures kChunk steps starting from (cur, ord) with since_sort == 0.
+int build_graph(sph_handle* h) {
+  const int c = h->cur, o = h->ord, v = h->variant;
+  if (h->graph_ok[v][c][o]) return SPH_OK;
   hipGraph_t gr;
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  for (int s = 0; s < kChunk; ++s) enqueue_step(h, s == 0, kStep);
-  enqueue_integrate(h);
+  enqueue_steps(h, kChunk);
   hipError_t e = hipStreamEndCapture(h->stream, &gr);
-  h->cur = saved;
+  h->cur = c;   // the capture only recorded the launches
+  h->ord = o;
+  h->since_sort = 0;
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&h->graph[parity], gr, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&h->graph[v][c][o], gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-  h->graph_ok[parity] = true;
+  h->graph_ok[v][c][o] = true;
   return SPH_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int sph_workspace_bytes(const sph_params* p, int32_t n_fluid, int32_t n_ghost, size_t* bytes) {
-  if (!params_ok(p) || n_fluid < 0 || n_ghost < 0 || !bytes) return SPH_E_INVAL;
-  Grid g;
-  if (!make_grid(p, &g)) return SPH_E_INVAL;
-  *bytes = make_layout(n_fluid, n_ghost, g.ncx * g.ncy).total;
+// Host tables: tank of every particle, ghost and cell; the tiles of each variant.
+int upload_tables(sph_handle* h) {
+  const Plan& pl = h->plan;
+  std::vector<int> owner((size_t)pl.N), gowner((size_t)pl.Gh), cowner((size_t)pl.C);
+  for (int t = 0; t < pl.T; ++t) {
+    const Tank& tk = pl.tanks[t];
+    for (int i = 0; i < tk.n; ++i) owner[(size_t)tk.p0 + i] = t;
+    for (int i = 0; i < tk.ng; ++i) gowner[(size_t)tk.q0 + i] = t;
+    for (int i = 0; i < tk.nc; ++i) cowner[(size_t)tk.c0 + i] = t;
+  }
+  HIPCHK(hipMemcpyAsync(h->at<Tank>(h->L.tanks), pl.tanks.data(), sizeof(Tank) * pl.T, hipMemcpyHostToDevice,
+                        h->stream));
+  if (pl.N) HIPCHK(hipMemcpyAsync(h->at<int>(h->L.owner), owner.data(), 4 * pl.N, hipMemcpyHostToDevice, h->stream));
+  if (pl.Gh)
+    HIPCHK(hipMemcpyAsync(h->at<int>(h->L.gowner), gowner.data(), 4 * pl.Gh, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->at<int>(h->L.cowner), cowner.data(), 4 * pl.C, hipMemcpyHostToDevice, h->stream));
+  for (int v = 0; v < kNumVariants; ++v) {
+    const int tp = kBlock / kLanes[v];
+    std::vector<TileRef> tiles;
+    std::vector<int> tile0(pl.T + 1);
+    tiles.reserve((size_t)pl.tiles[v]);
+    for (int t = 0; t < pl.T; ++t) {
+      const Tank& tk = pl.tanks[t];
+      tile0[t] = (int)tiles.size();
+      if (tk.n == 0) tiles.push_back(TileRef{t, tk.p0, 0, 0});
+      for (int a = 0; a < tk.n; a += tp) tiles.push_back(TileRef{t, tk.p0 + a, tk.n - a < tp ? tk.n - a : tp, 0});
+    }
+    tile0[pl.T] = (int)tiles.size();
+    HIPCHK(hipMemcpyAsync(h->at<TileRef>(h->L.tiles[v]), tiles.data(), sizeof(TileRef) * tiles.size(),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->at<int>(h->L.tile0[v]), tile0.data(), 4 * tile0.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));   // the host vectors die here
   return SPH_OK;
 }
 
-int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const float* w0_dev,
-             int32_t n_ghost, const float* g_dev, const double* rigid0, void* ws_dev,
-             size_t ws_bytes, void* stream, sph_handle** out) {
-  if (!out || !params_ok(p) || n_fluid < 0 || n_ghost < 0 || !rigid0 || !ws_dev) return SPH_E_INVAL;
-  if ((n_fluid > 0 && (!s0_dev || !w0_dev)) || (n_ghost > 0 && !g_dev)) return SPH_E_INVAL;
+int init_common(int T, const sph_params* params, const int32_t* n_fluid, const float* s0_dev,
+                const float* w0_dev, const int32_t* n_ghost, const float* g_dev, const double* rigid0,
+                void* ws_dev, size_t ws_bytes, void* stream, sph_handle** out) {
+  if (!out || !rigid0 || !ws_dev) return SPH_E_INVAL;
   if (reinterpret_cast<uintptr_t>(ws_dev) & 255) return SPH_E_INVAL;
-  Grid g;
-  if (!make_grid(p, &g)) return SPH_E_INVAL;
-  Layout L = make_layout(n_fluid, n_ghost, g.ncx * g.ncy);
+  Plan pl;
+  int rc = make_plan(T, params, n_fluid, n_ghost, &pl);
+  if (rc) return rc;
+  if ((pl.N > 0 && (!s0_dev || !w0_dev)) || (pl.Gh > 0 && !g_dev)) return SPH_E_INVAL;
+  Layout L = make_layout(pl);
   if (ws_bytes < L.total) return SPH_E_CAPACITY;
   sph_handle* h = new (std::nothrow) sph_handle();
   if (!h) return SPH_E_INVAL;
-  h->p = *p;
-  h->N = n_fluid;
-  h->G = n_ghost;
-  h->grid = g;
-  h->nc = g.ncx * g.ncy;
-  h->k = make_consts(p);
-  h->ra = RigidArgs{p->dt, p->body_mass, p->body_inertia, p->kp, p->kd, p->sine_amp, p->sine_freq,
-                    p->motion, p->ctrl, p->ctrl_period, kStep};
+  h->plan = pl;
+  h->T = T;
+  h->N = (int)pl.N;
+  h->Gh = (int)pl.Gh;
+  h->C = (int)pl.C;
   h->stream = reinterpret_cast<hipStream_t>(stream);
   h->ws = reinterpret_cast<char*>(ws_dev);
   h->L = L;
-  h->cur = 0;
-  h->graph_ok[0] = h->graph_ok[1] = false;
-  int rc = SPH_OK;
+  h->cur = h->ord = h->since_sort = 0;
+  h->variant = kDefaultVariant;
+  for (int v = 0; v < kNumVariants; ++v)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) h->graph_ok[v][a][b] = false;
   auto fail = [&](int code) {
     delete h;
     return code;
   };
   hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
   if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
+  if ((rc = upload_tables(h)) != SPH_OK) return fail(rc);
   if ((rc = set_rigid(h, rigid0, 0.0, 0)) != SPH_OK) return fail(rc);
-  if (n_ghost > 0) {
-    e = hipMemcpyAsync(h->at<float2>(L.graw), g_dev, (size_t)n_ghost * 8, hipMemcpyDeviceToDevice, h->stream);
+  if (pl.Gh > 0) {
+    e = hipMemcpyAsync(h->at<float2>(L.graw), g_dev, (size_t)pl.Gh * 8, hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return fail(hip_fail(e, "hipMemcpyAsync"));
   }
   if ((rc = sort_ghosts(h, h->at<float2>(L.graw))) != SPH_OK) return fail(rc);
-  if ((rc = sort_fluid(h, reinterpret_cast<const float2*>(s0_dev), reinterpret_cast<const float2*>(w0_dev))) != SPH_OK)
+  if ((rc = sort_fluid(h, reinterpret_cast<const float2*>(s0_dev), reinterpret_cast<const float2*>(w0_dev))) !=
+      SPH_OK)
     return fail(rc);
   e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(hip_fail(e, "hipStreamSynchronize"));
@@ -1048,10 +1572,43 @@ int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const fl
   return SPH_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int sph_batch_workspace_bytes(int32_t n_tanks, const sph_params* params, const int32_t* n_fluid,
+                              const int32_t* n_ghost, size_t* bytes) {
+  if (!bytes) return SPH_E_INVAL;
+  Plan pl;
+  int rc = make_plan(n_tanks, params, n_fluid, n_ghost, &pl);
+  if (rc) return rc;
+  *bytes = make_layout(pl).total;
+  return SPH_OK;
+}
+
+int sph_workspace_bytes(const sph_params* p, int32_t n_fluid, int32_t n_ghost, size_t* bytes) {
+  return sph_batch_workspace_bytes(1, p, &n_fluid, &n_ghost, bytes);
+}
+
+int sph_batch_init(int32_t n_tanks, const sph_params* params, const int32_t* n_fluid, const float* s0_dev,
+                   const float* w0_dev, const int32_t* n_ghost, const float* g_dev, const double* rigid0,
+                   void* ws_dev, size_t ws_bytes, void* stream, sph_handle** out) {
+  return init_common(n_tanks, params, n_fluid, s0_dev, w0_dev, n_ghost, g_dev, rigid0, ws_dev, ws_bytes,
+                     stream, out);
+}
+
+int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const float* w0_dev,
+             int32_t n_ghost, const float* g_dev, const double* rigid0, void* ws_dev,
+             size_t ws_bytes, void* stream, sph_handle** out) {
+  return init_common(1, p, &n_fluid, s0_dev, w0_dev, &n_ghost, g_dev, rigid0, ws_dev, ws_bytes, stream, out);
+}
+
 int sph_destroy(sph_handle* h) {
   if (!h) return SPH_E_INVAL;
-  for (int b = 0; b < 2; ++b)
-    if (h->graph_ok[b]) (void)hipGraphExecDestroy(h->graph[b]);
+  for (int v = 0; v < kNumVariants; ++v)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        if (h->graph_ok[v][a][b]) (void)hipGraphExecDestroy(h->graph[v][a][b]);
   delete h;
   return SPH_OK;
 }
@@ -1061,107 +1618,179 @@ int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const do
                 float* u_log_dev, float* wmean_log_dev) {
   if (!h || n_steps < 0 || log_stride < 0 || n_ref < 0) return SPH_E_INVAL;
   if (n_steps == 0) return SPH_OK;
-  int rc = set_rollout(h, u_seq_dev, theta_ref_dev, n_ref, log_stride, n_steps, y_log_dev,
-                       wrench_log_dev, u_log_dev, wmean_log_dev);
+  int rc = set_rollout(h, u_seq_dev, theta_ref_dev, n_ref, log_stride, n_steps, y_log_dev, wrench_log_dev,
+                       u_log_dev, wmean_log_dev);
   if (rc) return rc;
-  // graphs need a capturable stream; on the legacy default stream steps are launched directly
-  int full = h->stream ? n_steps / kChunk : 0;
-  int rem = n_steps - full * kChunk;
-  for (int c = 0; c < full; ++c) {
-    if ((rc = build_graph(h, h->cur)) != SPH_OK) return rc;
-    HIPCHK(hipGraphLaunch(h->graph[h->cur], h->stream));
-  }
-  if (rem) {
-    for (int s = 0; s < rem; ++s) enqueue_step(h, s == 0, kStep);
-    enqueue_integrate(h);
+  if (!h->stream || n_steps < kChunk) {
+    // no capturable stream, or too short for a graph: direct launches
+    enqueue_steps(h, n_steps);
     HIPCHK(hipGetLastError());
+    return SPH_OK;
   }
+  int left = n_steps;
+  // align to the rebuild schedule so that every graph starts right after a rebuild
+  int lead = (kSortEvery - h->since_sort) % kSortEvery;
+  if (lead > 0) {
+    enqueue_steps(h, lead);
+    left -= lead;
+  }
+  while (left >= kChunk) {
+    if ((rc = build_graph(h)) != SPH_OK) return rc;
+    HIPCHK(hipGraphLaunch(h->graph[h->variant][h->cur][h->ord], h->stream));
+    left -= kChunk;
+  }
+  if (left > 0) enqueue_steps(h, left);
+  HIPCHK(hipGetLastError());
   return SPH_OK;
 }
 
-int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
-                     const double* theta_ref_dev, int32_t n_ref, float* avg_us) {
+int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const double* theta_ref_dev,
+                     int32_t n_ref, float* avg_us) {
   if (!h || n_steps < 1 || !avg_us || n_ref < 0) return SPH_E_INVAL;
-  int rc = set_rollout(h, u_seq_dev, theta_ref_dev, n_ref, 0, n_steps, nullptr, nullptr, nullptr,
-                       nullptr);
+  int rc = set_rollout(h, u_seq_dev, theta_ref_dev, n_ref, 0, n_steps, nullptr, nullptr, nullptr, nullptr);
   if (rc) return rc;
-  hipEvent_t ev[6];
-  for (int i = 0; i < 6; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
   double sum[5] = {0, 0, 0, 0, 0};
+  int sorts = 0;
   for (int st = 0; st < n_steps; ++st) {
-    enqueue_step(h, st == 0, kStep, ev);
-    HIPCHK(hipEventSynchronize(ev[5]));
-    for (int k = 0; k < 5; ++k) {
+    enqueue_step(h, st > 0, kStep, ev);
+    HIPCHK(hipEventSynchronize(ev[2]));
+    for (int k = 0; k < 2; ++k) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-      sum[k] += ms;
+      sum[3 + k] += ms;
+    }
+    if (h->since_sort >= kSortEvery) {
+      enqueue_sort(h, ev);
+      HIPCHK(hipEventSynchronize(ev[3]));
+      for (int k = 0; k < 3; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+        sum[k] += ms;
+      }
+      ++sorts;
     }
   }
   enqueue_integrate(h);
   HIPCHK(hipStreamSynchronize(h->stream));
-  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
-  for (int k = 0; k < 5; ++k) avg_us[k] = (float)(sum[k] * 1000.0 / n_steps);
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  for (int k = 0; k < 3; ++k) avg_us[k] = sorts ? (float)(sum[k] * 1000.0 / sorts) : 0.0f;
+  for (int k = 3; k < 5; ++k) avg_us[k] = (float)(sum[k] * 1000.0 / n_steps);
   return SPH_OK;
+}
+
+int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes) {
+  if (!h || reps < 1) return SPH_E_INVAL;
+  int rc = set_rollout(h, nullptr, nullptr, 0, 0, 0, nullptr, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  hipEvent_t ev[3];
+  for (int i = 0; i < 3; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  enqueue_sort(h);
+  int best = kDefaultVariant;
+  double best_ms = 1e300;
+  const int cur = h->cur, ord = h->ord;
+  for (int v = 0; v < kNumVariants; ++v) {
+    h->variant = v;
+    double total = 0.0;
+    for (int r = 0; r <= reps; ++r) {   // the first pass warms up
+      h->cur = cur;
+      h->ord = ord;
+      enqueue_step(h, false, kEval, ev);
+      HIPCHK(hipEventSynchronize(ev[2]));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[2]));
+      if (r > 0) total += ms;
+    }
+    if (total < best_ms) {
+      best_ms = total;
+      best = v;
+    }
+  }
+  for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  // evaluation only: the state is what it was after the rebuild
+  h->cur = 1 - cur;
+  h->ord = ord;
+  h->since_sort = 0;
+  h->variant = best;
+  if (lanes) *lanes = kLanes[best];
+  return SPH_OK;
+}
+
+int sph_set_lanes(sph_handle* h, int32_t lanes) {
+  if (!h) return SPH_E_INVAL;
+  for (int v = 0; v < kNumVariants; ++v)
+    if (kLanes[v] == lanes) {
+      h->variant = v;
+      return SPH_OK;
+    }
+  return SPH_E_INVAL;
 }
 
 int sph_step(sph_handle* h, const float* u_dev) {
   return sph_rollout(h, 1, u_dev, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr);
 }
 
-int sph_rhs(sph_handle* h, const float* u_dev, float* rho_dev, float* p_dev, float* a_sph_dev,
-            float* wdot_dev, float* wrench_dev, float* acc_dev) {
+int sph_rhs(sph_handle* h, const float* u_dev, float* rho_dev, float* p_dev, float* a_sph_dev, float* wdot_dev,
+            float* wrench_dev, float* acc_dev) {
   if (!h) return SPH_E_INVAL;
   int rc = set_rollout(h, u_dev, nullptr, 0, 0, 0, nullptr, nullptr, nullptr, nullptr);
   if (rc) return rc;
-  enqueue_step(h, true, kEval);
+  enqueue_sort(h);
+  enqueue_step(h, false, kEval);
+  h->since_sort = 0;   // evaluation only: the positions did not move
   hipLaunchKernelGGL(sph_rhs_out, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
                      h->at<float2>(h->L.pos[h->cur]), h->at<float2>(h->L.vel[h->cur]),
-                     h->at<float2>(h->L.acc), h->at<float2>(h->L.rp), h->at<int>(h->L.id[h->cur]),
-                     h->N, h->at<DevRigid>(h->L.rigid), h->k, rho_dev, p_dev,
+                     h->at<float2>(h->L.acc[h->cur]), h->at<float2>(h->L.rp), h->at<int>(h->L.id[h->ord]), h->N,
+                     h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid), rho_dev, p_dev,
                      reinterpret_cast<float2*>(a_sph_dev), reinterpret_cast<float2*>(wdot_dev));
-  hipLaunchKernelGGL(sph_small_out, dim3(1), dim3(64), 0, h->stream, h->at<DevRigid>(h->L.rigid),
-                     wrench_dev, acc_dev, (int)SPH_FRAME_BODY);
+  hipLaunchKernelGGL(sph_small_out, dim3(nblocks(h->T)), dim3(kBlock), 0, h->stream, h->at<DevRigid>(h->L.rigid),
+                     h->T, wrench_dev, acc_dev, (int)SPH_FRAME_BODY);
   HIPCHK(hipGetLastError());
   return SPH_OK;
 }
 
 int sph_slosh_wrench(sph_handle* h, int32_t frame, float* out_dev) {
   if (!h || !out_dev || (frame != SPH_FRAME_BODY && frame != SPH_FRAME_WORLD)) return SPH_E_INVAL;
-  hipLaunchKernelGGL(sph_small_out, dim3(1), dim3(64), 0, h->stream, h->at<DevRigid>(h->L.rigid),
-                     out_dev, (float*)nullptr, (int)frame);
+  hipLaunchKernelGGL(sph_small_out, dim3(nblocks(h->T)), dim3(kBlock), 0, h->stream, h->at<DevRigid>(h->L.rigid),
+                     h->T, out_dev, (float*)nullptr, (int)frame);
   HIPCHK(hipGetLastError());
   return SPH_OK;
 }
 
-int sph_get_state(sph_handle* h, float* s_dev, float* w_dev, double* rigid, double* tau_ctrl,
-                  int64_t* step) {
+int sph_get_state(sph_handle* h, float* s_dev, float* w_dev, double* rigid, double* tau_ctrl, int64_t* step) {
   if (!h) return SPH_E_INVAL;
-  int nb = nblocks(h->N);
+  const int nb = nblocks(h->N);
   if (s_dev && h->N > 0)
     hipLaunchKernelGGL(sph_unpermute, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[h->cur]),
-                       h->at<int>(h->L.id[h->cur]), h->N, reinterpret_cast<float2*>(s_dev));
+                       h->at<int>(h->L.id[h->ord]), h->N, reinterpret_cast<float2*>(s_dev));
   if (w_dev && h->N > 0)
     hipLaunchKernelGGL(sph_unpermute, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.vel[h->cur]),
-                       h->at<int>(h->L.id[h->cur]), h->N, reinterpret_cast<float2*>(w_dev));
+                       h->at<int>(h->L.id[h->ord]), h->N, reinterpret_cast<float2*>(w_dev));
   HIPCHK(hipGetLastError());
-  DevRigid r;
-  HIPCHK(hipMemcpyAsync(&r, h->at<DevRigid>(h->L.rigid), sizeof r, hipMemcpyDeviceToHost, h->stream));
+  std::vector<DevRigid> rs(h->T);
+  HIPCHK(hipMemcpyAsync(rs.data(), h->at<DevRigid>(h->L.rigid), sizeof(DevRigid) * h->T, hipMemcpyDeviceToHost,
+                        h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  if (rigid) {
-    rigid[0] = r.r[0];
-    rigid[1] = r.r[1];
-    rigid[2] = r.theta;
-    rigid[3] = r.rdot[0];
-    rigid[4] = r.rdot[1];
-    rigid[5] = r.thetadot;
+  for (int t = 0; t < h->T; ++t) {
+    const DevRigid& r = rs[t];
+    if (rigid) {
+      double* g = rigid + 6 * t;
+      g[0] = r.r[0];
+      g[1] = r.r[1];
+      g[2] = r.theta;
+      g[3] = r.rdot[0];
+      g[4] = r.rdot[1];
+      g[5] = r.thetadot;
+    }
+    if (tau_ctrl) tau_ctrl[t] = r.tau_ctrl;
+    if (step) step[t] = r.step;
   }
-  if (tau_ctrl) *tau_ctrl = r.tau_ctrl;
-  if (step) *step = r.step;
   return SPH_OK;
 }
 
-int sph_set_state(sph_handle* h, const float* s_dev, const float* w_dev, const double* rigid,
-                  double tau_ctrl, int64_t step) {
+int sph_set_state(sph_handle* h, const float* s_dev, const float* w_dev, const double* rigid, double tau_ctrl,
+                  int64_t step) {
   if (!h || !rigid || (h->N > 0 && (!s_dev || !w_dev))) return SPH_E_INVAL;
   HIPCHK(hipMemsetAsync(h->at<unsigned>(h->L.status), 0, 4, h->stream));
   int rc = set_rigid(h, rigid, tau_ctrl, step);
@@ -1183,14 +1812,24 @@ int sph_status(sph_handle* h, uint32_t* flags) {
 
 int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* count_dev) {
   if (!h || max_nbr < 1 || !nbr_dev || !count_dev) return SPH_E_INVAL;
-  // re-sort so the cell structure matches the current positions
-  int rc = set_rollout(h, nullptr, nullptr, 0, 0, 0, nullptr, nullptr, nullptr, nullptr);
-  if (rc) return rc;
-  enqueue_step(h, true, kEval);
-  hipLaunchKernelGGL(sph_nbr_list, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
-                     h->at<float2>(h->L.pos[h->cur]), h->at<int>(h->L.cstart[h->cur]),
-                     h->at<int>(h->L.id[h->cur]), h->N, h->grid, h->k, max_nbr, nbr_dev, count_dev);
+  enqueue_sort(h);
+  const int v = h->variant;
+  const int nt = (int)h->plan.tiles[v];
+  auto args = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[h->cur]),
+                       h->at<int>(h->L.pkey), h->at<int4>(h->L.rng), h->at<int>(h->L.id[h->ord]),
+                       h->at<TileRef>(h->L.tiles[v]), h->at<Tank>(h->L.tanks), max_nbr, nbr_dev, count_dev);
+  };
+  if (v == 0) args(sph_nbr_list<4>);
+  else if (v == 1) args(sph_nbr_list<8>);
+  else args(sph_nbr_list<16>);
   HIPCHK(hipGetLastError());
+  return SPH_OK;
+}
+
+int sph_num_tanks(sph_handle* h, int32_t* n_tanks) {
+  if (!h || !n_tanks) return SPH_E_INVAL;
+  *n_tanks = h->T;
   return SPH_OK;
 }
 

@@ -3,12 +3,14 @@
 Every step of the simulation runs in the library's HIP kernels; PyTorch
 provides device memory and the stream the library enqueues on.  The names
 follow the C ABI: ``Simulator.step`` is ``sph_step``, ``rollout`` is
-``sph_rollout`` and so on.
+``sph_rollout`` and so on.  A ``Simulator`` holds one tank
+(``sph_init``) or a batch of tanks (``sph_batch_init``); for a batch the
+per-tank inputs and outputs carry a leading tank dimension.
 """
 from __future__ import annotations
 
 import ctypes as C
-from typing import Optional
+from typing import Optional, Sequence
 
 import numpy as np
 import torch
@@ -43,38 +45,60 @@ def _dev_f32(a, device) -> torch.Tensor:
 
 
 class Simulator:
-    """One tank: ``sph_init`` on construction, ``sph_destroy`` on close()."""
+    """One tank or a batch: ``sph_init`` / ``sph_batch_init`` on construction,
+    ``sph_destroy`` on close()."""
 
     def __init__(self, params, pos, vel, ghosts, rigid0, device="cuda:0",
                  stream: Optional[torch.cuda.Stream] = None):
-        self.L = load()
-        self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        self.params = params
-        self._prm = make_params(params)
-        s0 = _dev_f32(pos, self.device).reshape(-1, 2)
-        w0 = _dev_f32(vel, self.device).reshape(-1, 2)
-        g0 = _dev_f32(ghosts, self.device).reshape(-1, 2)
-        self.n, self.g = int(s0.shape[0]), int(g0.shape[0])
-        nbytes = C.c_size_t()
-        check(self.L.sph_workspace_bytes(C.byref(self._prm), self.n, self.g, C.byref(nbytes)),
-              "sph_workspace_bytes")
-        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
-        off = (-raw.data_ptr()) % 256
-        self._ws_raw = raw
-        self.ws = raw[off:off + nbytes.value]
-        rig = (C.c_double * 6)(*[float(x) for x in np.asarray(rigid0, np.float64)])
-        h = C.c_void_p()
-        self._enter()
-        check(self.L.sph_init(C.byref(self._prm), self.n, _ptr(s0), _ptr(w0), self.g, _ptr(g0), rig,
-                              _ptr(self.ws), C.c_size_t(nbytes.value), C.c_void_p(self.stream.cuda_stream),
-                              C.byref(h)), "sph_init")
-        self.h = h
-        self._keep = []
+        self._setup([params], [pos], [vel], [ghosts], [rigid0], device, stream, batch=False)
 
     @classmethod
     def from_scenario(cls, sc, device="cuda:0", stream=None):
         return cls(sc.params, sc.pos, sc.vel, sc.ghosts, sc.rigid0, device, stream)
+
+    @classmethod
+    def batch(cls, scenarios: Sequence, device="cuda:0", stream=None):
+        self = cls.__new__(cls)
+        self._setup([s.params for s in scenarios], [s.pos for s in scenarios], [s.vel for s in scenarios],
+                    [s.ghosts for s in scenarios], [s.rigid0 for s in scenarios], device, stream, batch=True)
+        return self
+
+    def _setup(self, params, pos, vel, ghosts, rigid0, device, stream, batch):
+        self.L = load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.is_batch = batch
+        self.T = len(params)
+        self.params = params if batch else params[0]
+        prm = (SphParams * self.T)(*[make_params(p) for p in params])
+        self._prm = prm
+        s0 = torch.cat([_dev_f32(p, self.device).reshape(-1, 2) for p in pos]).contiguous()
+        w0 = torch.cat([_dev_f32(v, self.device).reshape(-1, 2) for v in vel]).contiguous()
+        g0 = torch.cat([_dev_f32(g, self.device).reshape(-1, 2) for g in ghosts]).contiguous()
+        self.counts = [int(np.asarray(p).reshape(-1, 2).shape[0]) for p in pos]
+        gcounts = [int(np.asarray(g).reshape(-1, 2).shape[0]) for g in ghosts]
+        self.n, self.g = int(s0.shape[0]), int(g0.shape[0])
+        nf = (C.c_int32 * self.T)(*self.counts)
+        ng = (C.c_int32 * self.T)(*gcounts)
+        nbytes = C.c_size_t()
+        check(self.L.sph_batch_workspace_bytes(self.T, prm, nf, ng, C.byref(nbytes)), "sph_batch_workspace_bytes")
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + nbytes.value]
+        rig = (C.c_double * (6 * self.T))(*np.concatenate([np.asarray(r, np.float64).ravel() for r in rigid0]))
+        h = C.c_void_p()
+        self._enter()
+        if batch:
+            rc = self.L.sph_batch_init(self.T, prm, nf, _ptr(s0), _ptr(w0), ng, _ptr(g0), rig, _ptr(self.ws),
+                                       C.c_size_t(nbytes.value), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            rc = self.L.sph_init(C.byref(prm[0]), self.n, _ptr(s0), _ptr(w0), self.g, _ptr(g0), rig,
+                                 _ptr(self.ws), C.c_size_t(nbytes.value), C.c_void_p(self.stream.cuda_stream),
+                                 C.byref(h))
+        check(rc, "sph_init")
+        self.h = h
+        self._keep = []
 
     # stream ordering with the caller's current stream
     def _enter(self):
@@ -103,25 +127,32 @@ class Simulator:
         check(self.L.sph_step(self.h, _ptr(u)), "sph_step")
         self._leave()
 
-    def rollout(self, n_steps: int, u_seq=None, theta_ref=None, log_stride: int = 0,
-                logs: bool = True):
-        """Runs n_steps; returns a dict of device log tensors (y, wrench, u, wrench_mean)."""
+    def rollout(self, n_steps: int, u_seq=None, theta_ref=None, log_stride: int = 0, logs: bool = True):
+        """Runs n_steps; returns a dict of device log tensors (y, wrench, u,
+        wrench_mean), [n_log, k] for one tank, [T, n_log, k] for a batch.
+        Batch inputs: u_seq [T, n_steps, 3], theta_ref [T, n_ref]."""
         self._enter()
-        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(-1, 3)
-        if u is not None and u.shape[0] < n_steps:
-            raise ValueError("u_seq shorter than n_steps")
-        ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
-                                                              device=self.device).contiguous()
+        u = None
+        if u_seq is not None:
+            u = _dev_f32(u_seq, self.device)
+            u = u.reshape(self.T, -1, 3)
+            if u.shape[1] < n_steps:
+                raise ValueError("u_seq shorter than n_steps")
+            u = u[:, :n_steps].contiguous()
+        ref = None
+        if theta_ref is not None:
+            ref = torch.as_tensor(theta_ref, dtype=torch.float64, device=self.device).reshape(self.T, -1).contiguous()
         n_log = (n_steps + log_stride - 1) // log_stride if log_stride > 0 else 0
         out = {}
         if n_log and logs:
-            out = {"y": torch.zeros(n_log, 6, device=self.device),
-                   "wrench": torch.zeros(n_log, 3, device=self.device),
-                   "u": torch.zeros(n_log, 3, device=self.device),
-                   "wrench_mean": torch.zeros(n_log, 3, device=self.device)}
+            shape = (self.T, n_log) if self.is_batch else (n_log,)
+            out = {"y": torch.zeros(*shape, 6, device=self.device),
+                   "wrench": torch.zeros(*shape, 3, device=self.device),
+                   "u": torch.zeros(*shape, 3, device=self.device),
+                   "wrench_mean": torch.zeros(*shape, 3, device=self.device)}
             self._enter()
         check(self.L.sph_rollout(self.h, int(n_steps), _ptr(u), _ptr(ref),
-                                 0 if ref is None else int(ref.numel()), int(log_stride),
+                                 0 if ref is None else int(ref.shape[1]), int(log_stride),
                                  _ptr(out.get("y")), _ptr(out.get("wrench")), _ptr(out.get("u")),
                                  _ptr(out.get("wrench_mean"))), "sph_rollout")
         self._keep = [u, ref]
@@ -132,10 +163,11 @@ class Simulator:
         """x_dot at the current state (no advance): rho, P, a_sph, wdot, wrench, acc."""
         self._enter()
         uu = None if u is None else _dev_f32(u, self.device)
+        tshape = (self.T, 3) if self.is_batch else (3,)
         o = {"rho": torch.empty(self.n, device=self.device), "P": torch.empty(self.n, device=self.device),
              "a_sph": torch.empty(self.n, 2, device=self.device),
              "wdot": torch.empty(self.n, 2, device=self.device),
-             "wrench": torch.empty(3, device=self.device), "acc": torch.empty(3, device=self.device)}
+             "wrench": torch.empty(*tshape, device=self.device), "acc": torch.empty(*tshape, device=self.device)}
         self._enter()
         check(self.L.sph_rhs(self.h, _ptr(uu), _ptr(o["rho"]), _ptr(o["P"]), _ptr(o["a_sph"]),
                              _ptr(o["wdot"]), _ptr(o["wrench"]), _ptr(o["acc"])), "sph_rhs")
@@ -144,31 +176,34 @@ class Simulator:
         return o
 
     def wrench(self, frame: int = FRAME_BODY) -> torch.Tensor:
-        out = torch.empty(3, device=self.device)
+        out = torch.empty(*((self.T, 3) if self.is_batch else (3,)), device=self.device)
         self._enter()
         check(self.L.sph_slosh_wrench(self.h, int(frame), _ptr(out)), "sph_slosh_wrench")
         self._leave()
         return out
 
     def get_state(self):
+        """(s [N,2], w [N,2], rigid, tau_ctrl, step); rigid [6] / [T,6]."""
         s = torch.empty(self.n, 2, device=self.device)
         w = torch.empty(self.n, 2, device=self.device)
-        rig = (C.c_double * 6)()
-        tau = C.c_double()
-        step = C.c_int64()
+        rig = (C.c_double * (6 * self.T))()
+        tau = (C.c_double * self.T)()
+        step = (C.c_int64 * self.T)()
         self._enter()
-        check(self.L.sph_get_state(self.h, _ptr(s), _ptr(w), rig, C.byref(tau), C.byref(step)),
-              "sph_get_state")
+        check(self.L.sph_get_state(self.h, _ptr(s), _ptr(w), rig, tau, step), "sph_get_state")
         self._leave()
-        return s, w, np.array(list(rig)), float(tau.value), int(step.value)
+        r = np.array(list(rig)).reshape(self.T, 6)
+        if self.is_batch:
+            return s, w, r, np.array(list(tau)), np.array(list(step))
+        return s, w, r[0], float(tau[0]), int(step[0])
 
     def set_state(self, s, w, rigid, tau_ctrl=0.0, step=0):
         s = _dev_f32(s, self.device).reshape(-1, 2)
         w = _dev_f32(w, self.device).reshape(-1, 2)
-        rig = (C.c_double * 6)(*[float(x) for x in np.asarray(rigid, np.float64)])
+        r = np.asarray(rigid, np.float64).ravel()
+        rig = (C.c_double * r.size)(*r)
         self._enter()
-        check(self.L.sph_set_state(self.h, _ptr(s), _ptr(w), rig, float(tau_ctrl), int(step)),
-              "sph_set_state")
+        check(self.L.sph_set_state(self.h, _ptr(s), _ptr(w), rig, float(tau_ctrl), int(step)), "sph_set_state")
         self._leave()
 
     def status(self) -> int:
@@ -187,15 +222,25 @@ class Simulator:
         self._leave()
         return nbr, cnt
 
+    def autotune(self, reps: int = 10) -> int:
+        lanes = C.c_int32()
+        self._enter()
+        check(self.L.sph_autotune(self.h, int(reps), C.byref(lanes)), "sph_autotune")
+        self._leave()
+        return int(lanes.value)
+
+    def set_lanes(self, lanes: int) -> None:
+        check(self.L.sph_set_lanes(self.h, int(lanes)), "sph_set_lanes")
+
     def time_kernels(self, n_steps: int, u_seq=None, theta_ref=None):
-        """Mean per-kernel microseconds over n_steps directly launched steps:
-        bin, scan, place, density, force."""
-        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(-1, 3)
+        """Mean per-launch microseconds over n_steps directly launched steps:
+        bin, scan, place (per rebuild), density, force (per step)."""
+        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(self.T, -1, 3)[:, :n_steps].contiguous()
         ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
-                                                              device=self.device).contiguous()
+                                                              device=self.device).reshape(self.T, -1).contiguous()
         out = (C.c_float * 5)()
         self._enter()
         check(self.L.sph_time_kernels(self.h, int(n_steps), _ptr(u), _ptr(ref),
-                                      0 if ref is None else int(ref.numel()), out), "sph_time_kernels")
+                                      0 if ref is None else int(ref.shape[1]), out), "sph_time_kernels")
         self._leave()
         return dict(zip(("bin", "scan", "place", "density", "force"), [float(x) for x in out]))

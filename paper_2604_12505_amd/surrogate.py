@@ -1,0 +1,201 @@
+"""Slosh-wrench surrogate: data from SPH rollouts, training and evaluation.
+
+Orchestration only: every rollout runs in the SPH kernels (``sph_rollout``),
+windows are built by ``mlp_make_windows``, and the network is trained and
+evaluated by the MFMA kernels (``mlp_train_step``, ``mlp_forward``).
+
+Data recipe (the random-tank generator of ``workloads.random_tank``):
+rectangular or circular tank, fill U[0.2, 0.8], 2k-60k particles, torque a
+5-tone random-phase multisine on the 0.05 Hz grid with amplitude U[0, 50] N m,
+spacecraft m = 1000 kg, J = 500 kg m^2.  Each tank is first brought to rest
+(the paper initialises the fluid at rest after a preliminary simulation,
+Section 5.1): ``relax_cycles`` times, ``relax_steps`` unforced steps followed
+by zeroing every velocity (kinetic damping).  Then ``n_steps`` forced steps
+are logged every ``log_stride`` steps; the target is the mean body-frame slosh
+wrench over each log interval, the inputs the logged (theta, thetadot, input
+torque) and the fill ratio.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+import workloads as W
+
+from ._lib import check, load
+from .mlp import Mlp
+from .sph import Simulator
+
+WINDOW = 32
+
+
+@dataclasses.dataclass
+class RolloutSet:
+    feat: torch.Tensor      # [R, T, 3] theta, thetadot, input torque (device)
+    fill: torch.Tensor      # [R] (device)
+    wrench: torch.Tensor    # [R, T, 3] mean body-frame wrench per log interval (device)
+    n_fluid: np.ndarray     # [R]
+    sph_seconds: float      # GPU time of the logged (forced) rollouts
+    sph_steps: int          # SPH steps per rollout (logged part)
+
+
+def _relax(sim: Simulator, cycles: int, steps: int) -> None:
+    zero_rigid = np.zeros((sim.T, 6))
+    for _ in range(cycles):
+        sim.rollout(steps)
+        s, _, _, _, _ = sim.get_state()
+        sim.set_state(s, torch.zeros_like(s), zero_rigid, 0.0, 0)
+
+
+def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, relax_cycles: int = 40,
+             relax_steps: int = 100, n_min: int = 2000, n_max: int = 60000, device="cuda:0",
+             batch: int = 256, lanes: Optional[int] = None) -> RolloutSet:
+    """Runs one relaxed, forced rollout per seed, up to ``batch`` tanks per
+    handle (one set of launches).  sph_seconds sums the GPU time of the forced
+    rollouts (relaxation excluded)."""
+    dev = torch.device(device)
+    R = len(seeds)
+    T = (n_steps + log_stride - 1) // log_stride
+    feat = torch.empty(R, T, 3, device=dev)
+    wrench = torch.empty(R, T, 3, device=dev)
+    fill = torch.empty(R, device=dev)
+    n_fluid = np.zeros(R, np.int64)
+    sph_seconds = 0.0
+    for g0 in range(0, R, batch):
+        idx = list(range(g0, min(R, g0 + batch)))
+        scs = [W.random_tank(int(seeds[i]), n_steps=n_steps, n_min=n_min, n_max=n_max) for i in idx]
+        for i, sc in zip(idx, scs):
+            n_fluid[i] = sc.n_fluid
+            fill[i] = float(sc.fill)
+        sim = Simulator.batch(scs, device=dev)
+        if lanes:
+            sim.set_lanes(lanes)
+        _relax(sim, relax_cycles, relax_steps)
+        u = torch.stack([torch.as_tensor(sc.u_seq) for sc in scs]).to(dev)
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        lg = sim.rollout(n_steps, u, log_stride=log_stride)
+        e1.record(sim.stream)
+        e1.synchronize()
+        sph_seconds += e0.elapsed_time(e1) / 1e3
+        st = sim.status()
+        if st != 0:
+            raise RuntimeError(f"rollouts of seeds {seeds[idx[0]]}..{seeds[idx[-1]]} raised status {st}")
+        sl = slice(idx[0], idx[-1] + 1)
+        feat[sl, :, 0] = lg["y"][:, :, 2]
+        feat[sl, :, 1] = lg["y"][:, :, 5]
+        feat[sl, :, 2] = lg["u"][:, :, 2]
+        wrench[sl] = lg["wrench_mean"]
+        sim.close()
+    return RolloutSet(feat, fill, wrench, n_fluid, sph_seconds, n_steps)
+
+
+def norm_from(data: RolloutSet) -> np.ndarray:
+    """Per-channel mean and std of the inputs (theta, thetadot, torque, fill)
+    and of the targets, as the 14 numbers mlp_make_windows takes."""
+    f = data.feat.reshape(-1, 3).double()
+    in_mean = torch.cat([f.mean(0), data.fill.double().mean().reshape(1)])
+    in_std = torch.cat([f.std(0), data.fill.double().std().reshape(1)])
+    w = data.wrench.reshape(-1, 3).double()
+    out_mean, out_std = w.mean(0), w.std(0)
+    v = torch.cat([in_mean, in_std.clamp_min(1e-12), out_mean, out_std.clamp_min(1e-12)])
+    return v.cpu().numpy().astype(np.float32)
+
+
+def windows(data: RolloutSet, norm: np.ndarray, with_targets: bool = True, stream=None):
+    """(x [n, 128], y [n, 3]) standardised, built by the window kernel."""
+    L = load()
+    R, T, _ = data.feat.shape
+    n = R * (T - WINDOW + 1)
+    dev = data.feat.device
+    x = torch.empty(n, WINDOW * 4, device=dev)
+    y = torch.empty(n, 3, device=dev) if with_targets else None
+    nm = (C.c_float * 14)(*[float(v) for v in norm])
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    check(L.mlp_make_windows(C.c_void_p(data.feat.data_ptr()), C.c_void_p(data.fill.data_ptr()),
+                             C.c_void_p(data.wrench.data_ptr()) if with_targets else None, int(R), int(T),
+                             WINDOW, nm, C.c_void_p(x.data_ptr()),
+                             C.c_void_p(y.data_ptr()) if with_targets else None,
+                             C.c_void_p(st.cuda_stream)), "mlp_make_windows")
+    return x, y
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """Fan-in uniform initialisation, packed in the C-ABI order."""
+    from .mlp import DIMS, pack
+    rng = np.random.default_rng(seed)
+    params = []
+    for i in range(len(DIMS) - 1):
+        bound = 1.0 / math.sqrt(DIMS[i])
+        params.append((rng.uniform(-bound, bound, (DIMS[i + 1], DIMS[i])),
+                       rng.uniform(-bound, bound, DIMS[i + 1])))
+    return pack(params)
+
+
+def train(x: torch.Tensor, y: torch.Tensor, epochs: int = 10, batch: int = 4096, lr: float = 1e-3,
+          seed: int = 0, lr_final: float = 1e-4, device="cuda:0", log=None) -> Mlp:
+    """Adam on the mean squared error, shuffled minibatches, cosine-decayed lr."""
+    net = Mlp(init_params(seed), max_batch=batch, device=device)
+    n = x.shape[0]
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    gen = torch.Generator(device=x.device)
+    gen.manual_seed(seed)
+    k = 0
+    for ep in range(epochs):
+        perm = torch.randperm(n, device=x.device, generator=gen)
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            a = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * k / max(1, total - 1)))
+            loss, _ = net.train_step(x.index_select(0, idx), y.index_select(0, idx), lr=a)
+            k += 1
+        if log is not None:
+            log(f"epoch {ep + 1}/{epochs}: batch loss {float(loss.item()):.4e}")
+    return net
+
+
+def inference_net(net: Mlp, max_batch: int = 65536) -> Mlp:
+    """A handle for large inference batches with the trained weights."""
+    return Mlp(net.params().cpu().numpy(), max_batch=max_batch, device=net.device)
+
+
+def predict(net: Mlp, x: torch.Tensor, batch: int = 65536) -> torch.Tensor:
+    out = torch.empty(x.shape[0], 3, device=x.device)
+    step = min(batch, net.max_batch)
+    for b in range(0, x.shape[0], step):
+        net.forward(x[b:b + step], out=out[b:b + step])
+    return out
+
+
+def nrmse(pred_std: torch.Tensor, y_std: torch.Tensor, norm: np.ndarray) -> np.ndarray:
+    """Per-channel RMS(prediction - SPH) / RMS(SPH), in physical units."""
+    mean = torch.as_tensor(norm[8:11], device=y_std.device)
+    std = torch.as_tensor(norm[11:14], device=y_std.device)
+    p = pred_std * std + mean
+    t = y_std * std + mean
+    err = torch.sqrt(((p - t) ** 2).mean(0))
+    ref = torch.sqrt((t ** 2).mean(0))
+    return (err / ref).cpu().numpy()
+
+
+def time_inference(net: Mlp, x: torch.Tensor, reps: int = 20) -> float:
+    """Seconds per forward pass of the batch x (HIP events, after a warm-up);
+    x must fit the handle's max_batch."""
+    out = torch.empty(x.shape[0], 3, device=x.device)
+    net.forward(x, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    for _ in range(reps):
+        net.forward(x, out=out)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps

@@ -1,0 +1,100 @@
+"""Many tanks in one handle (one set of launches) against single-tank runs
+and the FP64 oracle; the lanes-per-particle variants and the autotuner."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+from oracle import sph as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _tanks():
+    return [W.random_tank(21, n_steps=60, n_min=2000, n_max=3000, shape="rect"),
+            W.random_tank(22, n_steps=60, n_min=3000, n_max=4000, shape="circle"),
+            W.plain_rect(4, n_steps=60),
+            W.random_tank(23, n_steps=60, n_min=2000, n_max=2500, shape="circle")]
+
+
+def test_batch_equals_single_tank_runs_bitwise():
+    from paper_2604_12505_amd.sph import Simulator
+    scs = _tanks()
+    n = 60
+    batch = Simulator.batch(scs)
+    u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
+    logs = batch.rollout(n, u, log_stride=10)
+    s, w, rig, tau, step = batch.get_state()
+    assert batch.status() == 0 and list(step) == [n] * len(scs)
+    off = 0
+    for t, sc in enumerate(scs):
+        one = Simulator.from_scenario(sc)
+        l1 = one.rollout(n, torch.as_tensor(sc.u_seq[:n]), log_stride=10)
+        s1, w1, r1, _, _ = one.get_state()
+        k = sc.n_fluid
+        assert torch.equal(s[off:off + k], s1) and torch.equal(w[off:off + k], w1)
+        assert np.array_equal(rig[t], r1)
+        assert torch.equal(logs["wrench"][t], l1["wrench"]) and torch.equal(logs["y"][t], l1["y"])
+        off += k
+        one.close()
+    batch.close()
+
+
+def test_batch_tracks_the_oracle_per_tank():
+    from paper_2604_12505_amd.sph import Simulator
+    scs = _tanks()
+    n = 50
+    batch = Simulator.batch(scs)
+    u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
+    batch.rollout(n, u)
+    s, _, rig, _, _ = batch.get_state()
+    s = s.cpu().numpy().astype(np.float64)
+    off = 0
+    for t, sc in enumerate(scs):
+        st = O.state_from_scenario(sc)
+        O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n, sc.u_seq[:n])
+        err = np.sqrt(((s[off:off + sc.n_fluid] - st.s) ** 2).sum(1)).max()
+        assert err <= 1e-3 * sc.tank_size, (t, err)
+        assert abs(rig[t][2] - st.rigid[2]) <= 1e-3
+        off += sc.n_fluid
+    batch.close()
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+def test_every_lane_variant_matches_the_oracle(lanes):
+    from paper_2604_12505_amd.sph import Simulator
+    sc = W.closed_loop_circle(0, n_steps=40)
+    sim = Simulator.from_scenario(sc)
+    sim.set_lanes(lanes)
+    sim.rollout(40, torch.as_tensor(sc.u_seq), theta_ref=sc.theta_ref)
+    s, _, rig, _, _ = sim.get_state()
+    assert sim.status() == 0
+    st = O.state_from_scenario(sc)
+    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), 40, sc.u_seq, sc.theta_ref)
+    err = np.sqrt(((s.cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
+    assert err <= 1e-3 * sc.tank_size
+    nbr, cnt = sim.neighbours(96)
+    s_now = sim.get_state()[0].cpu().numpy()
+    pi, pj = O.pairs_f32(s_now, np.float32(2.0 * sc.params.h))
+    assert np.array_equal(cnt.cpu().numpy(), np.bincount(pi, minlength=sc.n_fluid))
+    sim.close()
+
+
+def test_autotune_picks_a_variant_and_keeps_parity():
+    from paper_2604_12505_amd.sph import Simulator
+    scs = _tanks()
+    batch = Simulator.batch(scs)
+    lanes = batch.autotune(reps=3)
+    assert lanes in (4, 8, 16)
+    n = 40
+    u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
+    batch.rollout(n, u)
+    assert batch.status() == 0
+    s, _, _, _, _ = batch.get_state()
+    sc = scs[0]
+    st = O.state_from_scenario(sc)
+    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n, sc.u_seq[:n])
+    err = np.sqrt(((s[:sc.n_fluid].cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
+    assert err <= 1e-3 * sc.tank_size
+    batch.close()

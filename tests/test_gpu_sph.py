@@ -159,22 +159,41 @@ def test_trajectory_50_steps(name):
 
 
 def test_rollout_is_deterministic_and_graph_equals_direct():
-    sc = W.plain_rect(1, n_steps=130)
-    a = _sim(sc)
-    b = _sim(sc)
-    c = _sim(sc)
+    # a, b: one rollout (graph-replayed chunks); c: single steps; d: three
+    # single steps, then a rollout that first aligns to the rebuild schedule
+    sc = W.plain_rect(1, n_steps=150)
+    sims = [_sim(sc) for _ in range(4)]
+    a, b, c, d = sims
     u = torch.as_tensor(sc.u_seq)
-    a.rollout(130, u)
-    b.rollout(130, u)
-    for k in range(130):
+    a.rollout(150, u)
+    b.rollout(150, u)
+    for k in range(150):
         c.step(u[k].contiguous())
-    sa, wa, ra, _, _ = a.get_state()
-    sb, wb, rb, _, _ = b.get_state()
-    sc_, wc, rc, _, _ = c.get_state()
-    assert torch.equal(sa, sb) and torch.equal(wa, wb) and np.array_equal(ra, rb)
-    assert torch.equal(sa, sc_) and torch.equal(wa, wc) and np.array_equal(ra, rc)
-    for s in (a, b, c):
-        s.close()
+    for k in range(3):
+        d.step(u[k].contiguous())
+    d.rollout(147, u[3:].contiguous())
+    ref = a.get_state()
+    for other in (b, c, d):
+        s, w, r, _, step = other.get_state()
+        assert step == 150
+        assert torch.equal(ref[0], s) and torch.equal(ref[1], w) and np.array_equal(ref[2], r)
+    assert all(x.status() == 0 for x in sims)
+    for x in sims:
+        x.close()
+
+
+def test_long_rollout_stays_within_the_rebuild_skin_and_tracks_the_oracle():
+    sc = W.plain_rect(3, n_steps=400)
+    sim = _sim(sc)
+    logs = sim.rollout(400, torch.as_tensor(sc.u_seq), log_stride=50)
+    s, w, rig, _, _ = sim.get_state()
+    assert sim.status() == 0
+    st = O.state_from_scenario(sc)
+    _, ol = O.rollout(sc.params, st, sc.ghosts.astype(np.float64), 400, sc.u_seq, log_stride=50)
+    err = np.sqrt(((s.cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
+    print("400 steps: pos err / L", err / sc.tank_size)
+    assert err <= 1e-3 * sc.tank_size
+    sim.close()
 
 
 def test_state_roundtrip_and_resume():
