@@ -41,9 +41,9 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 #   scan:    read the count, write the start, clear the count (12 B per cell)
 #   place:   read key, s, w, a_sph, id (32 B), write s, w, a_sph, id and s at
 #            the rebuild (36 B)
-BYTES = {"density": (48, 8, 0), "force": (32, 8, 0), "bin": (12, 0, 0), "scan": (0, 0, 12),
+BYTES = {"density": (48, 8, 0), "force": (32, 8, 0), "wrench": (0, 0, 0), "bin": (12, 0, 0), "scan": (0, 0, 12),
          "place": (68, 0, 0)}
-SORT_EVERY = 8
+SORT_EVERY = 4
 
 # HBM traffic of the force kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (per dispatch, scaled by the copy-kernel calibration), valid for the source

@@ -206,10 +206,11 @@ int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* co
 
 /* Measurement hook: advances the state by n_steps steps like sph_rollout (no
  * logs), launching each step's kernels directly with HIP events between them,
- * and writes the mean event-to-event time in microseconds of the five step
- * kernels to avg_us [5]: cell binning (with the deferred fluid update), count
- * scan, stable placement, density/EOS, forces/wrench/rigid body.
- * Synchronises the stream. */
+ * and writes the mean event-to-event time in microseconds of the six step
+ * kernels to avg_us [6]: cell binning, count scan, stable placement (these
+ * three per rebuild), density/EOS (with the deferred fluid update),
+ * forces with the per-workgroup wrench partials, and the per-tank wrench sum
+ * with the rigid-body update (these three per step).  Synchronises the stream. */
 int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
                      const double* theta_ref_dev, int32_t n_ref, float* avg_us);
 

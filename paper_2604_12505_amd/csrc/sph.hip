@@ -4,7 +4,7 @@
 // the same launches.
 //
 // A step (the paper's state-transition algorithm, Section 3.4, followed by
-// first-order symplectic Euler) is two kernels; rollouts replay them from
+// first-order symplectic Euler) is three kernels; rollouts replay them from
 // captured HIP graphs:
 //
 //   sph_density  applies the previous step's fluid update (fictitious
@@ -18,10 +18,13 @@
 //   sph_force    fluid-fluid pressure (eq. momentum) and viscosity (eq.
 //                viscous), ghost-to-fluid pressure and viscosity with the
 //                spiky kernel (eqs. pressure_b2f, viscous_b2f); the tank's
-//                reactions are reduced per workgroup, and the last workgroup
-//                of each tank to finish sums that tank's partials in a fixed
+//                reactions are reduced per workgroup;
+//   sph_wrench   one workgroup per tank sums that tank's partials in a fixed
 //                order and runs the zero-order-hold attitude law, the
 //                rigid-body equations (eq. tankdynamics) and the logs.
+//                (A separate launch, not a last-workgroup handoff: on this
+//                chip a device-scope fence writes back and invalidates the
+//                L2 of the issuing XCD, once per workgroup.)
 //
 // Both neighbour kernels work on tiles of 256/G consecutive particles of one
 // tank (in cell order), G lanes per particle.  A tile is cut into row
@@ -63,6 +66,8 @@ constexpr int kChunk = 64;        // steps per captured graph (multiple of kSort
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
 constexpr int kStageF = 1024;     // fluid candidates staged in LDS per row segment
 constexpr int kStageG = 512;      // ghost candidates staged in LDS per row segment
+constexpr int kListF = 40;        // in-support fluid neighbours listed per particle and pass
+constexpr int kListG = 24;        // in-support ghost neighbours listed per particle and pass
 constexpr int kNumVariants = 3;   // lanes per particle: 4, 8, 16
 constexpr int kLanes[kNumVariants] = {4, 8, 16};
 constexpr int kDefaultVariant = 1;
@@ -165,6 +170,10 @@ __device__ __forceinline__ float dist2(float dx, float dy) {
   return __builtin_fmaf(dy, dy, dx * dx);
 }
 
+// Hardware square root and reciprocal (1 ulp), for the pair terms.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Cubic spline (eq. cubicspline) shape without its constant, q = r/h < 2.
 __device__ __forceinline__ float cubic_shape(float q) {
   float a = 2.0f - q;
@@ -181,7 +190,7 @@ __device__ __forceinline__ float cubic_shape(float q) {
 __device__ __forceinline__ float cubic_grad_f(float q) {
   if (q < 1.0f) return 9.0f * q - 12.0f;
   float a = 2.0f - q;
-  return -3.0f * a * a / q;
+  return -3.0f * a * a * frcp(q);
 }
 
 __device__ __forceinline__ float eos_over_rho2(float rho, const Consts& k, float* P_out) {
@@ -573,6 +582,53 @@ __device__ __forceinline__ void visit(const TileLds<TP>& tl, int pl, bool ghost,
   }
 }
 
+
+// Orders LDS accesses of one wavefront (a compiler fence; no hardware barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One listing pass over the staged candidates of tile slot `pl` (ghosts if
+// `ghost`), in the visit order of `visit`, from ordinal c on: the G lanes of
+// the particle test G candidates at a time and append the LDS indices of
+// those that pass `keep` to `lst` (ballot compaction, order kept).  Stops
+// before the list could overflow; returns its length and advances c (both
+// the same on the G lanes).
+template <int G, int TP, class F>
+__device__ __forceinline__ int list_pass(const TileLds<TP>& tl, int pl, bool ghost, const int* lo,
+                                         const int* off, int l, int& c, int cap, unsigned short* lst,
+                                         F&& keep) {
+  const int* v = tl.rng[pl] + (ghost ? 6 : 0);
+  const int n0 = v[1] - v[0], n01 = n0 + v[3] - v[2], total = n01 + v[5] - v[4];
+  const int e0 = v[0] + off[0] - lo[0], e1 = v[2] + off[1] - lo[1] - n0, e2 = v[4] + off[2] - lo[2] - n01;
+  const int base = (int)(threadIdx.x & 63) - l;
+  const unsigned below = (1u << l) - 1u;
+  int cnt = 0;
+  while (c < total && cnt <= cap - G) {
+    const int cc = c + l;
+    int e = 0;
+    bool in = false;
+    if (cc < total) {
+      e = cc + (cc < n0 ? e0 : (cc < n01 ? e1 : e2));
+      in = keep(e);
+    }
+    const unsigned m = (unsigned)(__ballot(in) >> base) & ((1u << G) - 1u);
+    if (in) lst[cnt + __popc(m & below)] = (unsigned short)e;
+    cnt += __popc(m);
+    c += G;
+  }
+  return cnt;
+}
+
+// Number of candidates of tile slot `pl` (ghosts if `ghost`).
+template <int TP>
+__device__ __forceinline__ int n_candidates(const TileLds<TP>& tl, int pl, bool ghost) {
+  const int* v = tl.rng[pl] + (ghost ? 6 : 0);
+  return v[1] - v[0] + v[3] - v[2] + v[5] - v[4];
+}
+
 // --------------------------------------------------------------------------
 // particle sums
 // --------------------------------------------------------------------------
@@ -637,7 +693,7 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
     if (mine && pl >= sg.first && pl <= sg.last) {
       auto fluid = [&](float2 sj) {
         float d2 = dist2(s.x - sj.x, s.y - sj.y);
-        if (d2 < k.R2) sf += cubic_shape(sqrtf(d2) * k.inv_h);
+        if (d2 < k.R2) sf += cubic_shape(fsqrt(d2) * k.inv_h);
       };
       if (fst) {
         visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e]); });
@@ -653,7 +709,7 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
       }
       auto ghost = [&](float2 gj) {
         float d2 = dist2(s.x - gj.x, s.y - gj.y);
-        if (d2 < k.R2) sgs += cubic_shape(sqrtf(d2) * k.inv_h);
+        if (d2 < k.R2) sgs += cubic_shape(fsqrt(d2) * k.inv_h);
       };
       if (gst)
         visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
@@ -800,19 +856,16 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
                                                     const int4* __restrict__ rng,
                                                     const float2* __restrict__ gpos,
                                                     const TileRef* __restrict__ tiles,
-                                                    const int* __restrict__ tank_tile0,
                                                     const Tank* __restrict__ tanks,
                                                     float2* __restrict__ acc,
-                                                    double* __restrict__ partials,
-                                                    unsigned* __restrict__ tickets, DevRigid* rigid,
-                                                    const DevRollout* __restrict__ ro, int mode) {
+                                                    double* __restrict__ partials) {
   constexpr int TP = kBlock / G;
   __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
   __shared__ float2 g_pos[kStageG];
+  __shared__ unsigned short f_list[TP][kListF], g_list[TP][kListG];
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
   __shared__ double red[3][kBlock / 64];
-  __shared__ int last;
   const TileRef tr = tiles[blockIdx.x];
   const Tank& tk = tanks[tr.tank];
   const Consts& k = tk.k;
@@ -827,6 +880,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
     me = rp[p];
   }
   const float rho_i = me.x, Pi = me.y;
+  const float visc_g = k.beta2 / (2.0f * rho_i);   // wall viscosity with rho_g = rho_i
   __syncthreads();
   float axf = 0.0f, ayf = 0.0f, axg = 0.0f, ayg = 0.0f;
   float fx = 0.0f, fy = 0.0f, tq = 0.0f;
@@ -846,44 +900,80 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src(sg.glo, sg.goff, e)];
     __syncthreads();
     if (mine && pl >= sg.first && pl <= sg.last) {
+      // pair terms of a neighbour inside the support (0 < r < 2h)
       auto fluid = [&](float2 sj, float2 wj, float2 o) {
         float dx = s.x - sj.x, dy = s.y - sj.y;
         float d2 = dist2(dx, dy);
-        if (d2 < k.R2 && d2 > 0.0f) {
-          float q = sqrtf(d2) * k.inv_h;
-          float gW = k.dwc * cubic_grad_f(q);
-          float vr = (w.x - wj.x) * dx + (w.y - wj.y) * dy;
-          float coef = (-(Pi + o.y) + k.a2h * vr / ((rho_i + o.x) * (d2 + k.eps_h2))) * gW;
-          axf += coef * dx;
-          ayf += coef * dy;
-        }
+        float q = fsqrt(d2) * k.inv_h;
+        float gW = k.dwc * cubic_grad_f(q);
+        float vr = (w.x - wj.x) * dx + (w.y - wj.y) * dy;
+        float coef = (-(Pi + o.y) + k.a2h * vr * frcp((rho_i + o.x) * (d2 + k.eps_h2))) * gW;
+        axf += coef * dx;
+        ayf += coef * dy;
       };
-      if (fst)
-        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e], f_vel[e], f_rp[e]); });
-      else
-        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) { fluid(pos[j], vel[j], rp[j]); });
+      auto fluid_test = [&](float2 sj, float2 wj, float2 o) {
+        float d2 = dist2(s.x - sj.x, s.y - sj.y);
+        if (d2 < k.R2 && d2 > 0.0f) fluid(sj, wj, o);
+      };
+      if (fst) {
+        // list the neighbours inside the support, then all G lanes work on the list
+        unsigned short* lst = f_list[pl];
+        const int total = n_candidates<TP>(tl, pl, false);
+        int c = 0;
+        while (c < total) {
+          const int cnt = list_pass<G, TP>(tl, pl, false, sg.lo, sg.off, l, c, kListF, lst, [&](int e) {
+            const float2 sj = f_pos[e];
+            const float d2 = dist2(s.x - sj.x, s.y - sj.y);
+            return d2 < k.R2 && d2 > 0.0f;
+          });
+          wave_sync();
+          for (int q = l; q < cnt; q += G) {
+            const int e = lst[q];
+            fluid(f_pos[e], f_vel[e], f_rp[e]);
+          }
+          wave_sync();
+        }
+      } else {
+        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) { fluid_test(pos[j], vel[j], rp[j]); });
+      }
+      // wall terms of a ghost inside the spiky support (0 < r < h_s)
       auto ghost = [&](float2 gj) {
         float dx = s.x - gj.x, dy = s.y - gj.y;
         float d2 = dist2(dx, dy);
-        if (d2 < k.Rs2 && d2 > 0.0f) {
-          float r = sqrtf(d2);
-          float tt = k.hs - r;
-          float gW = k.dws * tt * tt / r;
-          float vr = w.x * dx + w.y * dy;
-          float coef = k.mass * (-2.0f * Pi + k.beta2 / (2.0f * rho_i) * fminf(vr, 0.0f) / (d2 + k.eps_h2)) * gW;
-          float ax = coef * dx, ay = coef * dy;   // wall force on the fluid / m
-          axg += ax;
-          ayg += ay;
-          float Fx = k.mass * ax, Fy = k.mass * ay;
-          fx -= Fx;
-          fy -= Fy;
-          tq -= gj.x * Fy - gj.y * Fx;
-        }
+        float r = fsqrt(d2);
+        float tt = k.hs - r;
+        float gW = k.dws * tt * tt * frcp(r);
+        float vr = w.x * dx + w.y * dy;
+        float coef = k.mass * (-2.0f * Pi + visc_g * fminf(vr, 0.0f) * frcp(d2 + k.eps_h2)) * gW;
+        float ax = coef * dx, ay = coef * dy;   // wall force on the fluid / m
+        axg += ax;
+        ayg += ay;
+        float Fx = k.mass * ax, Fy = k.mass * ay;
+        fx -= Fx;
+        fy -= Fy;
+        tq -= gj.x * Fy - gj.y * Fx;
       };
-      if (gst)
-        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
-      else
-        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
+      if (gst) {
+        unsigned short* lst = g_list[pl];
+        const int total = n_candidates<TP>(tl, pl, true);
+        int c = 0;
+        while (c < total) {
+          const int cnt = list_pass<G, TP>(tl, pl, true, sg.glo, sg.goff, l, c, kListG, lst, [&](int e) {
+            const float2 gj = g_pos[e];
+            const float d2 = dist2(s.x - gj.x, s.y - gj.y);
+            return d2 < k.Rs2 && d2 > 0.0f;
+          });
+          wave_sync();
+          for (int q = l; q < cnt; q += G) ghost(g_pos[lst[q]]);
+          wave_sync();
+        }
+      } else {
+        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) {
+          const float2 gj = gpos[j];
+          const float d2 = dist2(s.x - gj.x, s.y - gj.y);
+          if (d2 < k.Rs2 && d2 > 0.0f) ghost(gj);
+        });
+      }
     }
     const int next = sg.last + 1;
     __syncthreads();
@@ -903,21 +993,25 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
     if (lane == 0) red[d][wv] = t;
   }
   __syncthreads();
-  const int t0 = tank_tile0[tr.tank], nt = tank_tile0[tr.tank + 1] - t0;
   if (threadIdx.x == 0) {
     for (int d = 0; d < 3; ++d) {
       double t = 0.0;
       for (int q = 0; q < kBlock / 64; ++q) t += red[d][q];
       partials[3 * blockIdx.x + d] = t;
     }
-    __threadfence();
-    unsigned tkt = atomicAdd(&tickets[tr.tank], 1u);
-    last = (tkt == (unsigned)nt - 1);
   }
-  __syncthreads();
-  if (!last) return;
-  // last workgroup of this tank: reduce its tiles' partials in a fixed order
-  __threadfence();
+}
+
+// One workgroup per tank: the tank's tile partials summed in a fixed order,
+// then the rigid-body part of the step.
+__global__ void __launch_bounds__(kBlock) sph_wrench(const double* __restrict__ partials,
+                                                     const int* __restrict__ tank_tile0,
+                                                     const Tank* __restrict__ tanks, DevRigid* rigid,
+                                                     const DevRollout* __restrict__ ro, int mode) {
+  __shared__ double red[3][kBlock / 64];
+  const int tank = blockIdx.x;
+  const int t0 = tank_tile0[tank], nt = tank_tile0[tank + 1] - t0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double acc3[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nt; b += blockDim.x)
     for (int d = 0; d < 3; ++d) acc3[d] += partials[3 * (t0 + b) + d];
@@ -933,8 +1027,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       for (int q = 0; q < kBlock / 64; ++q) t += red[d][q];
       F[d] = t;
     }
-    rigid_step(&rigid[tr.tank], ro, tr.tank, F, mode, tk.ra);
-    tickets[tr.tank] = 0u;
+    rigid_step(&rigid[tank], ro, tank, F, mode, tanks[tank].ra);
   }
 }
 
@@ -1207,7 +1300,7 @@ int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int
 
 struct Layout {
   size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, key, slot, order, count, gpos,
-      graw, gstart, owner, gowner, cowner, tanks, tiles[kNumVariants], tile0[kNumVariants], partials, tickets,
+      graw, gstart, owner, gowner, cowner, tanks, tiles[kNumVariants], tile0[kNumVariants], partials,
       rigid, rollout, status, total;
 };
 
@@ -1250,7 +1343,6 @@ Layout make_layout(const Plan& pl) {
     L.tile0[v] = take((T + 1) * 4);
   }
   L.partials = take(max_tiles * 3 * 8);
-  L.tickets = take(T * 4);
   L.rigid = take(T * sizeof(DevRigid));
   L.rollout = take(sizeof(DevRollout));
   L.status = take(4);
@@ -1326,15 +1418,17 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
   mark(1);
   hipLaunchKernelGGL(sph_force<G>, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
-                     h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), h->at<int>(h->L.tile0[v]), h->at<Tank>(h->L.tanks),
-                     h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials),
-                     h->at<unsigned>(h->L.tickets), h->at<DevRigid>(h->L.rigid),
-                     h->at<DevRollout>(h->L.rollout), mode);
+                     h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]),
+                     h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials));
   mark(2);
+  hipLaunchKernelGGL(sph_wrench, dim3(h->T), dim3(kBlock), 0, h->stream, h->at<double>(h->L.partials),
+                     h->at<int>(h->L.tile0[v]), h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid),
+                     h->at<DevRollout>(h->L.rollout), mode);
+  mark(3);
 }
 
-// Enqueues the two kernels of one step.  integrate = 0 when the state is
-// already integrated (first step of a rollout).  ev, if given, holds 3 events.
+// Enqueues the three kernels of one step.  integrate = 0 when the state is
+// already integrated (first step of a rollout).  ev, if given, holds 4 events.
 void enqueue_step(sph_handle* h, bool integrate, int mode, hipEvent_t* ev = nullptr) {
   switch (h->variant) {
     case 0: launch_pair<4>(h, 0, integrate, mode, ev); break;
@@ -1651,12 +1745,12 @@ int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev, con
   if (rc) return rc;
   hipEvent_t ev[4];
   for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
-  double sum[5] = {0, 0, 0, 0, 0};
+  double sum[6] = {0, 0, 0, 0, 0, 0};
   int sorts = 0;
   for (int st = 0; st < n_steps; ++st) {
     enqueue_step(h, st > 0, kStep, ev);
-    HIPCHK(hipEventSynchronize(ev[2]));
-    for (int k = 0; k < 2; ++k) {
+    HIPCHK(hipEventSynchronize(ev[3]));
+    for (int k = 0; k < 3; ++k) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
       sum[3 + k] += ms;
@@ -1676,7 +1770,7 @@ int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev, con
   HIPCHK(hipStreamSynchronize(h->stream));
   for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
   for (int k = 0; k < 3; ++k) avg_us[k] = sorts ? (float)(sum[k] * 1000.0 / sorts) : 0.0f;
-  for (int k = 3; k < 5; ++k) avg_us[k] = (float)(sum[k] * 1000.0 / n_steps);
+  for (int k = 3; k < 6; ++k) avg_us[k] = (float)(sum[k] * 1000.0 / n_steps);
   return SPH_OK;
 }
 
@@ -1684,8 +1778,8 @@ int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes) {
   if (!h || reps < 1) return SPH_E_INVAL;
   int rc = set_rollout(h, nullptr, nullptr, 0, 0, 0, nullptr, nullptr, nullptr, nullptr);
   if (rc) return rc;
-  hipEvent_t ev[3];
-  for (int i = 0; i < 3; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
   enqueue_sort(h);
   int best = kDefaultVariant;
   double best_ms = 1e300;
@@ -1697,9 +1791,9 @@ int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes) {
       h->cur = cur;
       h->ord = ord;
       enqueue_step(h, false, kEval, ev);
-      HIPCHK(hipEventSynchronize(ev[2]));
+      HIPCHK(hipEventSynchronize(ev[3]));
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[2]));
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[3]));
       if (r > 0) total += ms;
     }
     if (total < best_ms) {
@@ -1707,7 +1801,7 @@ int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes) {
       best = v;
     }
   }
-  for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
   // evaluation only: the state is what it was after the rebuild
   h->cur = 1 - cur;
   h->ord = ord;

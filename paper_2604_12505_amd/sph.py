@@ -234,13 +234,13 @@ class Simulator:
 
     def time_kernels(self, n_steps: int, u_seq=None, theta_ref=None):
         """Mean per-launch microseconds over n_steps directly launched steps:
-        bin, scan, place (per rebuild), density, force (per step)."""
+        bin, scan, place (per rebuild), density, force, wrench (per step)."""
         u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(self.T, -1, 3)[:, :n_steps].contiguous()
         ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
                                                               device=self.device).reshape(self.T, -1).contiguous()
-        out = (C.c_float * 5)()
+        out = (C.c_float * 6)()
         self._enter()
         check(self.L.sph_time_kernels(self.h, int(n_steps), _ptr(u), _ptr(ref),
                                       0 if ref is None else int(ref.shape[1]), out), "sph_time_kernels")
         self._leave()
-        return dict(zip(("bin", "scan", "place", "density", "force"), [float(x) for x in out]))
+        return dict(zip(("bin", "scan", "place", "density", "force", "wrench"), [float(x) for x in out]))
