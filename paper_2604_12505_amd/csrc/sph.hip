@@ -266,20 +266,38 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Global cell key and per-cell count (integer atomics); slot, if given,
 // receives the order of arrival (used by the first, general sort only).
-// owner[i] is the tank of element i.
+// owner[i] is the tank of element i.  Without slots, lanes of a wavefront
+// that hold a run of equal keys (the common case: the input is in cell order
+// since the last rebuild) add their run length with one atomic.
 __global__ void __launch_bounds__(kBlock) sph_bin(const float2* __restrict__ pos, int n,
                                                   const int* __restrict__ owner,
                                                   const Tank* __restrict__ tanks, int* __restrict__ key,
                                                   int* __restrict__ count, int* __restrict__ slot) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Tank& tk = tanks[owner[i]];
-  int cx, cy;
-  cell_of(pos[i], tk.g, cx, cy);
-  int k = tk.c0 + cy * tk.g.ncx + cx;
-  key[i] = k;
-  int sl = atomicAdd(&count[k], 1);
-  if (slot) slot[i] = sl;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  int k = -1;
+  if (valid) {
+    const Tank& tk = tanks[owner[i]];
+    int cx, cy;
+    cell_of(pos[i], tk.g, cx, cy);
+    k = tk.c0 + cy * tk.g.ncx + cx;
+    key[i] = k;
+  }
+  if (slot) {
+    if (valid) slot[i] = atomicAdd(&count[k], 1);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int kprev = __shfl_up(k, 1, 64);
+  const bool head = valid && (lane == 0 || kprev != k);
+  const unsigned long long heads = __ballot(head);
+  const int nvalid = __popcll(__ballot(valid));   // valid lanes are a prefix of the wavefront
+  if (head) {
+    const unsigned long long after = heads & ~((2ull << lane) - 1ull);
+    int end = after ? __ffsll((long long)after) - 1 : 64;
+    end = end < nvalid ? end : nvalid;
+    atomicAdd(&count[k], end - lane);
+  }
 }
 
 // Exclusive scan of each tank's cell counts into start (global indices,
