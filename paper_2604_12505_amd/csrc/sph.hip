@@ -61,6 +61,7 @@ namespace {
 constexpr int kBlock = 256;       // threads per workgroup of the particle kernels
 constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;       // cells per thread per scan chunk
 constexpr int kSortEvery = 4;     // steps between cell-list rebuilds
 constexpr int kChunk = 64;        // steps per captured graph (multiple of kSortEvery, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
@@ -264,6 +265,24 @@ __device__ __forceinline__ double wave_sum(double v) {
 // cell-list kernels
 // --------------------------------------------------------------------------
 
+// Adds one to count[k] for every valid lane, with one atomic per run of
+// equal keys: the keys sit on lanes 0, S, 2S, ... of the wavefront and the
+// valid ones form a prefix of them.
+template <int S>
+__device__ __forceinline__ void add_runs(int* __restrict__ count, int k, bool valid) {
+  const int lane = threadIdx.x & 63;
+  const int kprev = __shfl_up(k, S, 64);
+  const bool head = valid && (lane < S || kprev != k);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long vm = __ballot(valid);
+  if (head) {
+    const unsigned long long after = heads & ~((2ull << lane) - 1ull);
+    const int last = 63 - __clzll((long long)vm);
+    const int end = after ? __ffsll((unsigned long long)after) - 1 : last + S;
+    atomicAdd(&count[k], (end - lane) / S);
+  }
+}
+
 // Global cell key and per-cell count (integer atomics); slot, if given,
 // receives the order of arrival (used by the first, general sort only).
 // owner[i] is the tank of element i.  Without slots, lanes of a wavefront
@@ -287,37 +306,43 @@ __global__ void __launch_bounds__(kBlock) sph_bin(const float2* __restrict__ pos
     if (valid) slot[i] = atomicAdd(&count[k], 1);
     return;
   }
-  const int lane = threadIdx.x & 63;
-  const int kprev = __shfl_up(k, 1, 64);
-  const bool head = valid && (lane == 0 || kprev != k);
-  const unsigned long long heads = __ballot(head);
-  const int nvalid = __popcll(__ballot(valid));   // valid lanes are a prefix of the wavefront
-  if (head) {
-    const unsigned long long after = heads & ~((2ull << lane) - 1ull);
-    int end = after ? __ffsll((long long)after) - 1 : 64;
-    end = end < nvalid ? end : nvalid;
-    atomicAdd(&count[k], end - lane);
-  }
+  add_runs<1>(count, k, valid);
 }
 
 // Exclusive scan of each tank's cell counts into start (global indices,
 // first element of the tank at p0 / q0); clears the counts.  One workgroup
-// per tank walks its cells in coalesced chunks of 1024: wave scans by
-// shuffles, wave totals scanned in LDS, a running carry between chunks.
+// per tank takes its cells in chunks of kScanThreads * kScanPer: a coalesced
+// load into LDS, a sequential scan of kScanPer cells per thread, a
+// workgroup scan of the per-thread sums (wave shuffles, wave totals in LDS),
+// a coalesced write back, and a running carry between chunks.
 // ghosts = 1 scans the ghost layout (base q0, count ng).
+__device__ __forceinline__ int scan_slot(int i) { return i + i / kScanPer; }   // padded: no bank conflicts
+
 __global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count,
                                                          const Tank* __restrict__ tanks, int n_tanks,
                                                          int ghosts, int* __restrict__ start,
                                                          unsigned* __restrict__ status) {
+  constexpr int kChunkCells = kScanThreads * kScanPer;
+  __shared__ int buf[kChunkCells + kScanThreads];
   __shared__ int wsum[kScanThreads / 64];
   const Tank& tk = tanks[blockIdx.x];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int base0 = ghosts ? tk.q0 : tk.p0, expect = ghosts ? tk.ng : tk.n;
   int carry = 0;
-  for (int base = 0; base < tk.nc; base += kScanThreads) {
-    int i = base + t;
-    int v = i < tk.nc ? count[tk.c0 + i] : 0;
-    int x = v;
+  for (int base = 0; base < tk.nc; base += kChunkCells) {
+    for (int q = 0; q < kScanPer; ++q) {
+      const int i = q * kScanThreads + t;
+      buf[scan_slot(i)] = base + i < tk.nc ? count[tk.c0 + base + i] : 0;
+    }
+    __syncthreads();
+    int sum = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+      const int k = scan_slot(t * kScanPer + q);
+      const int v = buf[k];
+      buf[k] = sum;
+      sum += v;
+    }
+    int x = sum;   // inclusive scan of the per-thread sums
     for (int off = 1; off < 64; off <<= 1) {
       int y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
@@ -333,12 +358,17 @@ __global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count
       if (lane < kScanThreads / 64) wsum[lane] = w;
     }
     __syncthreads();
-    int before = (wave > 0 ? wsum[wave - 1] : 0);
-    if (i < tk.nc) {
-      start[tk.c0 + i] = base0 + carry + before + x - v;
-      count[tk.c0 + i] = 0;
-    }
+    const int excl = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - sum;
+    for (int q = 0; q < kScanPer; ++q) buf[scan_slot(t * kScanPer + q)] += excl;
     carry += wsum[kScanThreads / 64 - 1];
+    __syncthreads();
+    for (int q = 0; q < kScanPer; ++q) {
+      const int i = q * kScanThreads + t;
+      if (base + i < tk.nc) {
+        start[tk.c0 + base + i] = base0 + buf[scan_slot(i)];
+        count[tk.c0 + base + i] = 0;
+      }
+    }
     __syncthreads();
   }
   if (t == 0) {
@@ -760,32 +790,50 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
   flag(status, bad);
 }
 
+// Inputs of a tank's rigid-body step that live in memory other than the
+// wrench: the applied force/torque of the step and, at a controller sample,
+// the attitude reference.  Separate so that they can be fetched early.
+struct RigidIn {
+  double u[3], ref;
+  long long n, loc;
+};
+
+__device__ RigidIn rigid_inputs(const DevRigid* rb, const DevRollout* ro, int tank, int mode,
+                                const RigidArgs& ra) {
+  RigidIn in;
+  in.n = rb->step;
+  in.loc = in.n - rb->step0;
+  in.u[0] = in.u[1] = in.u[2] = 0.0;
+  in.ref = 0.0;
+  if (mode == kStep && ro->u && in.loc >= 0 && in.loc < ro->n_steps) {
+    const float* ut = ro->u + ((size_t)tank * ro->n_steps + in.loc) * 3;
+    in.u[0] = ut[0];
+    in.u[1] = ut[1];
+    in.u[2] = ut[2];
+  } else if (mode == kEval && ro->u) {
+    const float* ut = ro->u + (size_t)tank * 3;
+    in.u[0] = ut[0];
+    in.u[1] = ut[1];
+    in.u[2] = ut[2];
+  }
+  if (mode == kStep && ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && in.n % ra.ctrl_period == 0 &&
+      ro->theta_ref && ro->n_ref > 0) {
+    const long long kk = in.n / ra.ctrl_period;
+    in.ref = ro->theta_ref[(size_t)tank * ro->n_ref + (kk < ro->n_ref ? kk : ro->n_ref - 1)];
+  }
+  return in;
+}
+
 // Rigid-body part of a step, run by one thread after the tank's wrench is
 // reduced: zero-order-hold attitude law, eq. tankdynamics, logs, symplectic
 // Euler.
 __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const double F[3], int mode,
-                           const RigidArgs& ra) {
-  const long long n = rb->step;
-  const long long loc = n - rb->step0;
-  double u[3] = {0.0, 0.0, 0.0};
-  if (mode == kStep && ro->u && loc >= 0 && loc < ro->n_steps) {
-    const float* ut = ro->u + ((size_t)tank * ro->n_steps + loc) * 3;
-    u[0] = ut[0];
-    u[1] = ut[1];
-    u[2] = ut[2];
-  } else if (mode == kEval && ro->u) {
-    const float* ut = ro->u + (size_t)tank * 3;
-    u[0] = ut[0];
-    u[1] = ut[1];
-    u[2] = ut[2];
-  }
-  if (mode == kStep && ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && n % ra.ctrl_period == 0) {
-    long long kk = n / ra.ctrl_period;
-    double ref = 0.0;
-    if (ro->theta_ref && ro->n_ref > 0)
-      ref = ro->theta_ref[(size_t)tank * ro->n_ref + (kk < ro->n_ref ? kk : ro->n_ref - 1)];
-    rb->tau_ctrl = ra.kp * (ref - rb->theta) - ra.kd * rb->thetadot;
-  }
+                           const RigidArgs& ra, const RigidIn& in) {
+  const long long n = in.n;
+  const long long loc = in.loc;
+  const double* u = in.u;
+  if (mode == kStep && ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && n % ra.ctrl_period == 0)
+    rb->tau_ctrl = ra.kp * (in.ref - rb->theta) - ra.kd * rb->thetadot;
   double th, thd, acc[3];
   if (ra.motion == SPH_MOTION_SINE) {
     double w = 2.0 * M_PI * ra.sine_freq, t = (double)n * ra.dt;
@@ -796,7 +844,10 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const d
   } else {
     th = rb->theta;
     thd = rb->thetadot;
-    double c = cos(th), s = sin(th);
+  }
+  double s, c;
+  sincos(th, &s, &c);
+  if (ra.motion != SPH_MOTION_SINE) {
     acc[0] = (c * F[0] - s * F[1] + u[0]) / ra.body_mass;
     acc[1] = (s * F[0] + c * F[1] + u[1]) / ra.body_mass;
     acc[2] = (F[2] + u[2] + rb->tau_ctrl) / ra.body_inertia;
@@ -807,7 +858,6 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const d
   }
   rb->th_eval = th;
   rb->thd_eval = thd;
-  double c = cos(th), s = sin(th);
   rb->c = (float)c;
   rb->s = (float)s;
   rb->abx = (float)(c * acc[0] + s * acc[1]);    // R^T r''
@@ -866,7 +916,7 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const d
 //   + 2 alpha h (w_ij . s_ij) / ((rho_i + rho_j)(r^2 + eps h^2))] grad_i W_ij
 //   + sum_g m [-2 P_i/rho_i^2 + (2 beta / (2 rho_i)) min(w_i . s_ig, 0)/(r^2 + eps h^2)] grad_i W_s3
 // The tank receives -m * (wall term) per pair, with torque arm g.
-template <int G>
+template <int G, bool Bin>
 __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ pos,
                                                     const float2* __restrict__ vel,
                                                     const float2* __restrict__ rp,
@@ -876,7 +926,8 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
                                                     const TileRef* __restrict__ tiles,
                                                     const Tank* __restrict__ tanks,
                                                     float2* __restrict__ acc,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials,
+                                                    int* __restrict__ key, int* __restrict__ count) {
   constexpr int TP = kBlock / G;
   __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
   __shared__ float2 g_pos[kStageG];
@@ -1002,6 +1053,18 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   axg = group_sum<G>(axg);
   ayg = group_sum<G>(ayg);
   if (mine && l == 0) acc[p] = make_float2(k.mass * axf + axg, k.mass * ayf + ayg);
+  if (Bin) {
+    // the binning pass of the rebuild that follows this step, on the
+    // positions this step ends with
+    int kc = -1;
+    if (mine && l == 0) {
+      int cx, cy;
+      cell_of(s, tk.g, cx, cy);
+      kc = tk.c0 + cy * tk.g.ncx + cx;
+      key[p] = kc;
+    }
+    add_runs<G>(count, kc, mine && l == 0);
+  }
 
   // workgroup reduction of the wrench, in double, fixed order
   double v[3] = {(double)fx, (double)fy, (double)tq};
@@ -1028,6 +1091,9 @@ __global__ void __launch_bounds__(kBlock) sph_wrench(const double* __restrict__ 
                                                      const DevRollout* __restrict__ ro, int mode) {
   __shared__ double red[3][kBlock / 64];
   const int tank = blockIdx.x;
+  const RigidArgs& ra = tanks[tank].ra;
+  RigidIn in;
+  if (threadIdx.x == 0) in = rigid_inputs(&rigid[tank], ro, tank, mode, ra);   // in flight during the sum
   const int t0 = tank_tile0[tank], nt = tank_tile0[tank + 1] - t0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double acc3[3] = {0.0, 0.0, 0.0};
@@ -1045,7 +1111,7 @@ __global__ void __launch_bounds__(kBlock) sph_wrench(const double* __restrict__ 
       for (int q = 0; q < kBlock / 64; ++q) t += red[d][q];
       F[d] = t;
     }
-    rigid_step(&rigid[tank], ro, tank, F, mode, tanks[tank].ra);
+    rigid_step(&rigid[tank], ro, tank, F, mode, ra, in);
   }
 }
 
@@ -1379,6 +1445,7 @@ struct sph_handle {
   int cur;          // buffer of the current particle state (pos, vel, acc)
   int ord;          // buffer of the current ordering (id, cell starts)
   int since_sort;   // steps since the last cell-list rebuild
+  bool binned;      // the last force launch computed the keys and counts of the next rebuild
   int variant;      // lanes per particle = kLanes[variant]
   hipGraphExec_t graph[kNumVariants][2][2];   // kChunk steps from (cur, ord)
   bool graph_ok[kNumVariants][2][2];
@@ -1397,9 +1464,11 @@ void enqueue_sort(sph_handle* h, hipEvent_t* ev = nullptr) {
     if (ev) (void)hipEventRecord(ev[i], h->stream);
   };
   mark(0);
-  hipLaunchKernelGGL(sph_bin, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
-                     h->N, h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.key),
-                     h->at<int>(h->L.count), (int*)nullptr);
+  if (!h->binned)   // else the force kernel of the last step binned the particles
+    hipLaunchKernelGGL(sph_bin, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
+                       h->N, h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.key),
+                       h->at<int>(h->L.count), (int*)nullptr);
+  h->binned = false;
   mark(1);
   hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
                      h->at<Tank>(h->L.tanks), h->T, 0, h->at<int>(h->L.cstart[1 - o]),
@@ -1434,10 +1503,15 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
                      h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status));
   mark(1);
-  hipLaunchKernelGGL(sph_force<G>, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1 - c]),
+  // the step before a scheduled rebuild also bins the particles for it
+  const bool bin = mode == kStep && h->since_sort + 1 >= kSortEvery;
+  auto force = bin ? sph_force<G, true> : sph_force<G, false>;
+  hipLaunchKernelGGL(force, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
                      h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]),
-                     h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials));
+                     h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials),
+                     h->at<int>(h->L.key), h->at<int>(h->L.count));
+  h->binned = bin;
   mark(2);
   hipLaunchKernelGGL(sph_wrench, dim3(h->T), dim3(kBlock), 0, h->stream, h->at<double>(h->L.partials),
                      h->at<int>(h->L.tile0[v]), h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid),
@@ -1584,6 +1658,7 @@ int build_graph(sph_handle* h) {
   h->cur = c;   // the capture only recorded the launches
   h->ord = o;
   h->since_sort = 0;
+  h->binned = false;
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(&h->graph[v][c][o], gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
@@ -1651,6 +1726,7 @@ int init_common(int T, const sph_params* params, const int32_t* n_fluid, const f
   h->ws = reinterpret_cast<char*>(ws_dev);
   h->L = L;
   h->cur = h->ord = h->since_sort = 0;
+  h->binned = false;
   h->variant = kDefaultVariant;
   for (int v = 0; v < kNumVariants; ++v)
     for (int a = 0; a < 2; ++a)
