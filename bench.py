@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+# FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 # Algorithmic bytes per launch of each kernel, per fluid particle (p),
@@ -36,14 +37,23 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 #   density: read s, w, a_sph (24 B), write the updated s, w (16 B) and
 #            rho, P/rho^2 (8 B); boundary positions 8 B
 #   force:   read s, w, rho, P/rho^2 (24 B), write a_sph (8 B); boundary 8 B
+#   wrench:  negligible (a few partials per tank)
 # and, every SORT_EVERY steps, the cell-list rebuild:
-#   bin:     read s (8 B), write the cell key (4 B)
+#   bin:     read s (8 B), write the cell key (4 B) (inside the force launch)
 #   scan:    read the count, write the start, clear the count (12 B per cell)
 #   place:   read key, s, w, a_sph, id (32 B), write s, w, a_sph, id and s at
 #            the rebuild (36 B)
-BYTES = {"density": (48, 8, 0), "force": (32, 8, 0), "wrench": (0, 0, 0), "bin": (12, 0, 0), "scan": (0, 0, 12),
-         "place": (68, 0, 0)}
+BYTES = {"density": (48, 8, 0), "force": (32, 8, 0), "wrench": (0, 0, 0), "bin": (12, 0, 0),
+         "scan": (0, 0, 12), "place": (68, 0, 0)}
 SORT_EVERY = 4
+
+# Algorithmic FP32 operations per fluid particle and launch: about 20
+# in-support fluid neighbours at h = 1.3 dx, times 28 operations per pair
+# term of the force (differences, squared distance, square root, kernel
+# gradient, viscous quotient, pressure sum, two accumulations) and 14 per
+# density term (squared distance, square root, the spline shape, one sum).
+NEIGHBOURS = 20
+FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 
 # HBM traffic of the force kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (per dispatch, scaled by the copy-kernel calibration), valid for the source
@@ -72,17 +82,30 @@ def cpu_baseline(sc, n_steps: int):
 
 
 def kernel_roofline(kus, n_fluid, n_ghost, n_cells):
-    """Roofline position of the kernel that takes the most time per step."""
+    """Roofline position of the kernel that takes the most time per step.
+
+    The neighbour kernels are arithmetic-bound, not HBM-bound, by the
+    operation count (bound "alu", against the FP32 vector peak); the HBM
+    view of the same launch is reported beside it."""
     per_step = {k: v / (SORT_EVERY if k in ("bin", "scan", "place") else 1) for k, v in kus.items()}
     dominant = max(per_step, key=per_step.get)
     bp, bg, bc = BYTES[dominant]
     alg_bytes = bp * n_fluid + bg * n_ghost + bc * n_cells
-    achieved = alg_bytes / (kus[dominant] * 1e-6) / 1e9
+    secs = kus[dominant] * 1e-6
+    gbs = alg_bytes / secs / 1e9
     traffic = TRAFFIC["bytes_per_launch"] if (TRAFFIC["src_sha1"] == src_hash()
                                               and TRAFFIC["kernel"] == "sph_" + dominant) else None
-    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sph_" + dominant,
-            "algorithmic_bytes_per_launch": alg_bytes}
+    hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_launch": alg_bytes}
+    if dominant in FLOP:
+        flops = FLOP[dominant] * n_fluid
+        tf = flops / secs / 1e12
+        return {"bound": "alu", "achieved": round(tf, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic, "kernel": "sph_" + dominant,
+                "algorithmic_flop_per_launch": flops, "launch_us": kus[dominant], "hbm": hbm}
+    return {"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hbm["frac"], "traffic": traffic, "kernel": "sph_" + dominant,
+            "algorithmic_bytes_per_launch": alg_bytes, "launch_us": kus[dominant]}
 
 
 def n_cells_of(sc):

@@ -176,7 +176,8 @@ int sph_slosh_wrench(sph_handle* h, int32_t frame, float* out_dev);
  * (device, caller order, any may be NULL): rho_dev [N], p_dev [N] pressure,
  * a_sph_dev [N][2] SPH acceleration, wdot_dev [N][2] body-frame fluid
  * acceleration including fictitious terms, wrench_dev [3] body frame,
- * acc_dev [3] = r''_x, r''_y, theta''.  Reorders particles internally. */
+ * acc_dev [3] = r''_x, r''_y, theta''.  Uses the neighbour lists of the last
+ * rebuild (rebuilds first if one is due). */
 int sph_rhs(sph_handle* h, const float* u_dev, float* rho_dev, float* p_dev, float* a_sph_dev,
             float* wdot_dev, float* wrench_dev, float* acc_dev);
 

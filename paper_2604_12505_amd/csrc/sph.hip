@@ -65,10 +65,16 @@ constexpr int kScanPer = 8;       // cells per thread per scan chunk
 constexpr int kSortEvery = 4;     // steps between cell-list rebuilds
 constexpr int kChunk = 64;        // steps per captured graph (multiple of kSortEvery, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
-constexpr int kStageF = 1024;     // fluid candidates staged in LDS per row segment
+constexpr int kStageF = 640;      // fluid candidates staged in LDS per row segment
 constexpr int kStageG = 512;      // ghost candidates staged in LDS per row segment
-constexpr int kListF = 40;        // in-support fluid neighbours listed per particle and pass
-constexpr int kListG = 24;        // in-support ghost neighbours listed per particle and pass
+constexpr int kListF = 64;        // in-support fluid neighbours listed per particle and pass
+constexpr int kListG = 32;        // in-support ghost neighbours listed per particle and pass
+// Near lists, built at the first step after each rebuild: for every particle
+// the ordinals (positions in its candidate enumeration, one byte each) of
+// the candidates that can come within the support before the next rebuild.
+constexpr int kNearF = 64;        // capacity of a fluid near list
+constexpr int kNearG = 32;        // capacity of a ghost near list
+constexpr int kNearNone = 255;    // list length meaning "not listed: walk all candidates"
 constexpr int kNumVariants = 3;   // lanes per particle: 4, 8, 16
 constexpr int kLanes[kNumVariants] = {4, 8, 16};
 constexpr int kDefaultVariant = 1;
@@ -96,6 +102,8 @@ struct Consts {
   float eps_h2;             // eps h^2
   float dt;
   float half_skin2;         // (skin / 2)^2: allowed squared displacement between rebuilds
+  float RL2;                // near-list radius^2 for fluid pairs: (2h + skin)^2, both move
+  float RG2;                // near-list radius^2 for ghosts: (S + skin/2)^2, ghosts are fixed
   int eos, tgamma;          // tgamma > 0: integer Tait exponent
   float tgamma_f;
 };
@@ -393,18 +401,15 @@ __device__ __forceinline__ void cell_ranges(const Tank& tk, int cx, int cy, cons
   const int ncx = tk.g.ncx;
   const int xa = cx > 0 ? cx - 1 : 0;
   const int xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
+#pragma unroll
   for (int r = 0; r < 3; ++r) {
     const int yy = cy - 1 + r;
-    if (yy < 0 || yy >= tk.g.ncy) {
-      v[2 * r] = v[2 * r + 1] = 0;
-      v[6 + 2 * r] = v[6 + 2 * r + 1] = 0;
-      continue;
-    }
-    const int c = tk.c0 + yy * ncx;
-    v[2 * r] = start[c + xa];
-    v[2 * r + 1] = start[c + xb + 1];
-    v[6 + 2 * r] = gstart[c + xa];
-    v[6 + 2 * r + 1] = gstart[c + xb + 1];
+    const bool in = yy >= 0 && yy < tk.g.ncy;
+    const int c = tk.c0 + (in ? yy : 0) * ncx;
+    v[2 * r] = in ? start[c + xa] : 0;
+    v[2 * r + 1] = in ? start[c + xb + 1] : 0;
+    v[6 + 2 * r] = in ? gstart[c + xa] : 0;
+    v[6 + 2 * r + 1] = in ? gstart[c + xb + 1] : 0;
   }
 }
 
@@ -558,6 +563,7 @@ template <int TP>
 struct TileLds {
   int cy[TP];
   int rng[TP][12];
+  int near[TP];   // fluid near-list length | ghost near-list length << 8
 };
 
 // One row segment of a tile: slots [first, last] share grid row cy[first];
@@ -601,10 +607,12 @@ __device__ __forceinline__ int seg_src(const int* lo, const int* off, int e) {
 // past the end.
 template <int TP>
 __device__ __forceinline__ void tile_load(int p0, int np, const Tank& tk, const int* __restrict__ pkey,
-                                          const int4* __restrict__ rng, TileLds<TP>& tl) {
+                                          const int4* __restrict__ rng, TileLds<TP>& tl,
+                                          const int* __restrict__ near_n = nullptr) {
   const int t = threadIdx.x;
   if (t < TP) {
     if (t < np) {
+      tl.near[t] = near_n ? near_n[p0 + t] : (kNearNone | kNearNone << 8);
       tl.cy[t] = (pkey[p0 + t] - tk.c0) / tk.g.ncx;
       const int4 a = rng[3 * (p0 + t)], b = rng[3 * (p0 + t) + 1], c = rng[3 * (p0 + t) + 2];
       int* v = tl.rng[t];
@@ -638,19 +646,46 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One listing pass over the staged candidates of tile slot `pl` (ghosts if
-// `ghost`), in the visit order of `visit`, from ordinal c on: the G lanes of
-// the particle test G candidates at a time and append the LDS indices of
-// those that pass `keep` to `lst` (ballot compaction, order kept).  Stops
-// before the list could overflow; returns its length and advances c (both
-// the same on the G lanes).
-template <int G, int TP, class F>
-__device__ __forceinline__ int list_pass(const TileLds<TP>& tl, int pl, bool ghost, const int* lo,
-                                         const int* off, int l, int& c, int cap, unsigned short* lst,
-                                         F&& keep) {
+// Lanes of a G-lane group: the mask of the group's bits in a wavefront ballot.
+template <int G>
+__device__ __forceinline__ unsigned group_bits() {
+  return G == 32 ? 0xffffffffu : ((1u << G) - 1u);
+}
+
+// Candidate ordinal (position in the enumeration row 0, row 1, row 2 of a
+// tile slot's candidate ranges) -> LDS index of the staged candidate.
+struct OrdMap {
+  int n0, n01, e0, d1, d2;   // d1 = e1 - e0, d2 = e2 - e1: offsets added past each row boundary
+  __device__ __forceinline__ int operator()(int c) const {
+    return c + e0 + (d1 & -(int)(c >= n0)) + (d2 & -(int)(c >= n01));
+  }
+};
+
+template <int TP>
+__device__ __forceinline__ OrdMap ord_map(const TileLds<TP>& tl, int pl, bool ghost, const int* lo, const int* off,
+                                          int* total) {
   const int* v = tl.rng[pl] + (ghost ? 6 : 0);
-  const int n0 = v[1] - v[0], n01 = n0 + v[3] - v[2], total = n01 + v[5] - v[4];
-  const int e0 = v[0] + off[0] - lo[0], e1 = v[2] + off[1] - lo[1] - n0, e2 = v[4] + off[2] - lo[2] - n01;
+  OrdMap m;
+  m.n0 = v[1] - v[0];
+  m.n01 = m.n0 + v[3] - v[2];
+  *total = m.n01 + v[5] - v[4];
+  const int e0 = v[0] + off[0] - lo[0];
+  const int e1 = v[2] + off[1] - lo[1] - m.n0;
+  const int e2 = v[4] + off[2] - lo[2] - m.n01;
+  m.e0 = e0;
+  m.d1 = e1 - e0;
+  m.d2 = e2 - e1;
+  return m;
+}
+
+// One listing pass over the staged candidates of a tile slot, in ordinal
+// order from c on: the G lanes of the particle test G candidates at a time
+// and append the LDS indices of those that pass `keep` to `lst` (ballot
+// compaction, order kept).  Stops before the list could overflow; returns
+// its length and advances c (both the same on the G lanes).
+template <int G, class F>
+__device__ __forceinline__ int list_pass(const OrdMap& m, int total, int l, int& c, int cap, unsigned short* lst,
+                                         F&& keep) {
   const int base = (int)(threadIdx.x & 63) - l;
   const unsigned below = (1u << l) - 1u;
   int cnt = 0;
@@ -659,22 +694,113 @@ __device__ __forceinline__ int list_pass(const TileLds<TP>& tl, int pl, bool gho
     int e = 0;
     bool in = false;
     if (cc < total) {
-      e = cc + (cc < n0 ? e0 : (cc < n01 ? e1 : e2));
+      e = m(cc);
       in = keep(e);
     }
-    const unsigned m = (unsigned)(__ballot(in) >> base) & ((1u << G) - 1u);
-    if (in) lst[cnt + __popc(m & below)] = (unsigned short)e;
-    cnt += __popc(m);
+    const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
+    if (in) lst[cnt + __popc(msk & below)] = (unsigned short)e;
+    cnt += __popc(msk);
     c += G;
   }
   return cnt;
 }
 
-// Number of candidates of tile slot `pl` (ghosts if `ghost`).
-template <int TP>
-__device__ __forceinline__ int n_candidates(const TileLds<TP>& tl, int pl, bool ghost) {
-  const int* v = tl.rng[pl] + (ghost ? 6 : 0);
-  return v[1] - v[0] + v[3] - v[2] + v[5] - v[4];
+// Near-list build: the ordinals of the candidates that pass `keep`, in
+// order, as bytes into lst (capacity cap).  Returns the number that passed,
+// which may exceed cap (the list is then not used).  total <= 255.
+template <int G, class F>
+__device__ __forceinline__ int near_build(const OrdMap& m, int total, int l, unsigned char* lst, int cap,
+                                          F&& keep) {
+  const int base = (int)(threadIdx.x & 63) - l;
+  const unsigned below = (1u << l) - 1u;
+  int cnt = 0;
+  for (int c = 0; c < total; c += G) {
+    const int cc = c + l;
+    const bool in = cc < total && keep(m(cc));
+    const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
+    if (in) {
+      const int at = cnt + __popc(msk & below);
+      if (at < cap) lst[at] = (unsigned char)cc;
+    }
+    cnt += __popc(msk);
+  }
+  return cnt;
+}
+
+// A near list of n ordinals (bytes of 32-bit words in memory) is cut into G
+// runs of whole words; lane l takes run l, at most kMaxW words (<= 4).  The
+// words are fetched together and consumed by rotation (no indexed array,
+// which the compiler would place in scratch memory).
+template <int G, int CAP>
+struct NearRun {
+  static constexpr int kMaxW = (CAP / 4 + G - 1) / G;
+  static_assert(kMaxW <= 4, "near-list run longer than four words");
+  unsigned w0, w1, w2, w3;
+  int first, wpl;   // first entry of the run, words per lane
+  __device__ __forceinline__ NearRun(const unsigned* __restrict__ row, int n, int l) {
+    wpl = ((n + 3) / 4 + G - 1) / G;
+    const int wb = l * wpl;
+    first = 4 * wb;
+    w0 = (wpl > 0 && 4 * wb < n) ? row[wb] : 0u;
+    w1 = (kMaxW > 1 && wpl > 1 && 4 * (wb + 1) < n) ? row[wb + 1] : 0u;
+    w2 = (kMaxW > 2 && wpl > 2 && 4 * (wb + 2) < n) ? row[wb + 2] : 0u;
+    w3 = (kMaxW > 3 && wpl > 3 && 4 * (wb + 3) < n) ? row[wb + 3] : 0u;
+  }
+  __device__ __forceinline__ unsigned pop() {
+    const unsigned w = w0;
+    w0 = w1;
+    w1 = w2;
+    w2 = w3;
+    return w;
+  }
+};
+
+// Calls f(e) for the staged candidates of lane l's run of a near list.
+template <int G, int CAP, class F>
+__device__ __forceinline__ void near_visit(const unsigned* __restrict__ row, int n, int l, const OrdMap& m, F&& f) {
+  NearRun<G, CAP> run(row, n, l);
+#pragma unroll
+  for (int q = 0; q < NearRun<G, CAP>::kMaxW; ++q) {
+    unsigned word = run.pop();
+    if (q < run.wpl)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (run.first + 4 * q + b < n) f(m((int)(word & 255u)));
+        word >>= 8;
+      }
+  }
+}
+
+// Compacts the entries of a near list that pass `keep` into lst (LDS
+// indices, in ballot-round order); returns the count (<= n), the same on
+// the G lanes.
+template <int G, int CAP, class F>
+__device__ __forceinline__ int near_pass(const unsigned* __restrict__ row, int n, int l, const OrdMap& m,
+                                         unsigned short* lst, F&& keep) {
+  NearRun<G, CAP> run(row, n, l);
+  const int base = (int)(threadIdx.x & 63) - l;
+  const unsigned below = (1u << l) - 1u;
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < NearRun<G, CAP>::kMaxW; ++q) {
+    unsigned word = run.pop();
+    if (q < run.wpl) {   // the same on the G lanes
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        int e = 0;
+        bool in = false;
+        if (run.first + 4 * q + b < n) {
+          e = m((int)(word & 255u));
+          in = keep(e);
+        }
+        word >>= 8;
+        const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
+        if (in) lst[cnt + __popc(msk & below)] = (unsigned short)e;
+        cnt += __popc(msk);
+      }
+    }
+  }
+  return cnt;
 }
 
 // --------------------------------------------------------------------------
@@ -683,7 +809,13 @@ __device__ __forceinline__ int n_candidates(const TileLds<TP>& tl, int pl, bool 
 
 // Fluid update of the previous step (if `integrate`), then
 // rho_i = m sigma (sum_f shape + gamma1 sum_g shape), P and P/rho^2.
-template <int G>
+// Build (the first step after a rebuild): every candidate is walked, and
+// each particle's near lists are written: the fluid candidates within RL of
+// it and the ghosts within RG, at the positions of the rebuild (pos_sort).
+// While every particle stays within skin/2 of those positions, every pair
+// closer than the support is listed.  Otherwise a listed particle walks only
+// its near lists.
+template <int G, bool Build>
 __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__ pos_in,
                                                       const float2* __restrict__ vel_in,
                                                       const float2* __restrict__ acc_in, int integrate,
@@ -697,10 +829,15 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
                                                       float2* __restrict__ pos_out,
                                                       float2* __restrict__ vel_out,
                                                       float2* __restrict__ rp,
-                                                      unsigned* __restrict__ status) {
+                                                      unsigned* __restrict__ status,
+                                                      int* __restrict__ near_n,
+                                                      unsigned* __restrict__ near_f,
+                                                      unsigned* __restrict__ near_g) {
   constexpr int TP = kBlock / G;
   __shared__ float2 f_pos[kStageF];
+  __shared__ float2 f_raw[Build ? kStageF : 1];
   __shared__ float2 g_pos[kStageG];
+  __shared__ unsigned nb_f[Build ? TP : 1][kNearF / 4], nb_g[Build ? TP : 1][kNearG / 4];
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
   const TileRef tr = tiles[blockIdx.x];
@@ -711,15 +848,17 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
   const bool mine = pl < tr.np;
   const Frame fr = load_frame(&rigid[tr.tank]);
   const float dt = k.dt;
-  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl);
-  float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f);
+  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl, Build ? nullptr : near_n);
+  float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f), s_raw = s;
   if (mine) {
     s = pos_in[p];
+    if (Build) s_raw = pos_sort[p];   // near lists use the positions of the rebuild
     w = vel_in[p];
     if (integrate) fluid_update(s, w, acc_in[p], fr, dt);
   }
   __syncthreads();
   float sf = 0.0f, sgs = 0.0f;
+  int nf_out = kNearNone, ng_out = kNearNone;
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
     if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
@@ -729,6 +868,7 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
       for (int e = threadIdx.x; e < sg.nf; e += kBlock) {
         const int j = seg_src(sg.lo, sg.off, e);
         float2 sj = pos_in[j];
+        if (Build) f_raw[e] = pos_sort[j];
         if (integrate) {
           float2 wj = vel_in[j];
           fluid_update(sj, wj, acc_in[j], fr, dt);
@@ -743,7 +883,12 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
         float d2 = dist2(s.x - sj.x, s.y - sj.y);
         if (d2 < k.R2) sf += cubic_shape(fsqrt(d2) * k.inv_h);
       };
-      if (fst) {
+      int total;
+      const OrdMap fm = ord_map<TP>(tl, pl, false, sg.lo, sg.off, &total);
+      const int nlf = tl.near[pl] & 255;
+      if (!Build && fst && nlf <= kNearF) {
+        near_visit<G, kNearF>(near_f + (size_t)p * (kNearF / 4), nlf, l, fm, [&](int e) { fluid(f_pos[e]); });
+      } else if (fst) {
         visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e]); });
       } else {
         visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) {
@@ -755,14 +900,35 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
           fluid(sj);
         });
       }
+      if (Build && fst && total <= 255) {
+        const int cnt = near_build<G>(fm, total, l, reinterpret_cast<unsigned char*>(nb_f[pl]), kNearF,
+                                      [&](int e) {
+                                        const float2 r = f_raw[e];
+                                        return dist2(s_raw.x - r.x, s_raw.y - r.y) < k.RL2;
+                                      });
+        nf_out = cnt <= kNearF ? cnt : kNearNone;
+      }
       auto ghost = [&](float2 gj) {
         float d2 = dist2(s.x - gj.x, s.y - gj.y);
         if (d2 < k.R2) sgs += cubic_shape(fsqrt(d2) * k.inv_h);
       };
-      if (gst)
+      int gtotal;
+      const OrdMap gm = ord_map<TP>(tl, pl, true, sg.glo, sg.goff, &gtotal);
+      const int nlg = (tl.near[pl] >> 8) & 255;
+      if (!Build && gst && nlg <= kNearG)
+        near_visit<G, kNearG>(near_g + (size_t)p * (kNearG / 4), nlg, l, gm, [&](int e) { ghost(g_pos[e]); });
+      else if (gst)
         visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
       else
         visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
+      if (Build && gst && gtotal <= 255) {
+        const int cnt = near_build<G>(gm, gtotal, l, reinterpret_cast<unsigned char*>(nb_g[pl]), kNearG,
+                                      [&](int e) {
+                                        const float2 r = g_pos[e];
+                                        return dist2(s_raw.x - r.x, s_raw.y - r.y) < k.RG2;
+                                      });
+        ng_out = cnt <= kNearG ? cnt : kNearNone;
+      }
     }
     const int next = sg.last + 1;
     __syncthreads();
@@ -770,6 +936,15 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
   }
   sf = group_sum<G>(sf);
   sgs = group_sum<G>(sgs);
+  if (Build && mine) {
+    // near lists out, as whole words (the group's lanes wrote the bytes)
+    wave_sync();
+    const int nwf = nf_out == kNearNone ? 0 : (nf_out + 3) / 4;
+    const int nwg = ng_out == kNearNone ? 0 : (ng_out + 3) / 4;
+    for (int q = l; q < nwf; q += G) near_f[(size_t)p * (kNearF / 4) + q] = nb_f[pl][q];
+    for (int q = l; q < nwg; q += G) near_g[(size_t)p * (kNearG / 4) + q] = nb_g[pl][q];
+    if (l == 0) near_n[p] = nf_out | ng_out << 8;
+  }
   if (!mine || l != 0) return;
   const float2 s0 = pos_sort[p];
   float rho = k.mass * k.wc * (sf + k.gamma1 * sgs);
@@ -927,7 +1102,10 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
                                                     const Tank* __restrict__ tanks,
                                                     float2* __restrict__ acc,
                                                     double* __restrict__ partials,
-                                                    int* __restrict__ key, int* __restrict__ count) {
+                                                    int* __restrict__ key, int* __restrict__ count,
+                                                    const int* __restrict__ near_n,
+                                                    const unsigned* __restrict__ near_f,
+                                                    const unsigned* __restrict__ near_g) {
   constexpr int TP = kBlock / G;
   __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
   __shared__ float2 g_pos[kStageG];
@@ -941,7 +1119,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
   const int p = tr.p0 + pl;
   const bool mine = pl < tr.np;
-  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl);
+  tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl, near_n);
   float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f), me = make_float2(1.f, 0.f);
   if (mine) {
     s = pos[p];
@@ -987,20 +1165,27 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       if (fst) {
         // list the neighbours inside the support, then all G lanes work on the list
         unsigned short* lst = f_list[pl];
-        const int total = n_candidates<TP>(tl, pl, false);
-        int c = 0;
-        while (c < total) {
-          const int cnt = list_pass<G, TP>(tl, pl, false, sg.lo, sg.off, l, c, kListF, lst, [&](int e) {
-            const float2 sj = f_pos[e];
-            const float d2 = dist2(s.x - sj.x, s.y - sj.y);
-            return d2 < k.R2 && d2 > 0.0f;
-          });
+        int total;
+        const OrdMap fm = ord_map<TP>(tl, pl, false, sg.lo, sg.off, &total);
+        auto inside = [&](int e) {
+          const float2 sj = f_pos[e];
+          const float d2 = dist2(s.x - sj.x, s.y - sj.y);
+          return d2 < k.R2 && d2 > 0.0f;
+        };
+        auto pairs = [&](int cnt) {
           wave_sync();
           for (int q = l; q < cnt; q += G) {
             const int e = lst[q];
             fluid(f_pos[e], f_vel[e], f_rp[e]);
           }
           wave_sync();
+        };
+        const int nlf = tl.near[pl] & 255;
+        if (nlf <= kNearF) {
+          pairs(near_pass<G, kNearF>(near_f + (size_t)p * (kNearF / 4), nlf, l, fm, lst, inside));
+        } else {
+          int c = 0;
+          while (c < total) pairs(list_pass<G>(fm, total, l, c, kListF, lst, inside));
         }
       } else {
         visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) { fluid_test(pos[j], vel[j], rp[j]); });
@@ -1024,17 +1209,24 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       };
       if (gst) {
         unsigned short* lst = g_list[pl];
-        const int total = n_candidates<TP>(tl, pl, true);
-        int c = 0;
-        while (c < total) {
-          const int cnt = list_pass<G, TP>(tl, pl, true, sg.glo, sg.goff, l, c, kListG, lst, [&](int e) {
-            const float2 gj = g_pos[e];
-            const float d2 = dist2(s.x - gj.x, s.y - gj.y);
-            return d2 < k.Rs2 && d2 > 0.0f;
-          });
+        int total;
+        const OrdMap gm = ord_map<TP>(tl, pl, true, sg.glo, sg.goff, &total);
+        auto inside = [&](int e) {
+          const float2 gj = g_pos[e];
+          const float d2 = dist2(s.x - gj.x, s.y - gj.y);
+          return d2 < k.Rs2 && d2 > 0.0f;
+        };
+        auto walls = [&](int cnt) {
           wave_sync();
           for (int q = l; q < cnt; q += G) ghost(g_pos[lst[q]]);
           wave_sync();
+        };
+        const int nlg = (tl.near[pl] >> 8) & 255;
+        if (nlg <= kNearG) {
+          walls(near_pass<G, kNearG>(near_g + (size_t)p * (kNearG / 4), nlg, l, gm, lst, inside));
+        } else {
+          int c = 0;
+          while (c < total) walls(list_pass<G>(gm, total, l, c, kListG, lst, inside));
         }
       } else {
         visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) {
@@ -1331,6 +1523,11 @@ Consts make_consts(const sph_params* p) {
   // a slightly smaller bound than skin/2 absorbs the rounding of the check
   double hsk = 0.5 * kSkinOverH * h * (1.0 - 1e-5);
   k.half_skin2 = (float)(hsk * hsk);
+  // near-list radii, slightly enlarged against rounding of the test
+  const double skin = kSkinOverH * h;
+  const double rl = (2.0 * h + skin) * (1.0 + 1e-5), rg = (support_of(p) + 0.5 * skin) * (1.0 + 1e-5);
+  k.RL2 = (float)(rl * rl);
+  k.RG2 = (float)(rg * rg);
   k.eos = p->eos;
   double gi = std::round(p->tait_gamma);
   k.tgamma = (std::fabs(gi - p->tait_gamma) < 1e-12 && gi >= 1 && gi <= 64) ? (int)gi : 0;
@@ -1383,7 +1580,8 @@ int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int
 }
 
 struct Layout {
-  size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, key, slot, order, count, gpos,
+  size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, near_n, near_f, near_g, key, slot,
+      order, count, gpos,
       graw, gstart, owner, gowner, cowner, tanks, tiles[kNumVariants], tile0[kNumVariants], partials,
       rigid, rollout, status, total;
 };
@@ -1411,6 +1609,9 @@ Layout make_layout(const Plan& pl) {
   L.rng = take(n * 48);
   L.pkey = take(n * 4);
   L.rp = take(n * 8);
+  L.near_n = take(n * 4);
+  L.near_f = take(n * kNearF);
+  L.near_g = take(n * kNearG);
   L.key = take(mx * 4);
   L.slot = take(mx * 4);
   L.order = take(mx * 4);
@@ -1496,12 +1697,16 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
     if (ev) (void)hipEventRecord(ev[i], h->stream);
   };
   mark(0);
-  hipLaunchKernelGGL(sph_density<G>, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
+  // the first step after a rebuild walks every candidate and writes the near lists
+  const bool build = h->since_sort == 0;
+  auto density = build ? sph_density<G, true> : sph_density<G, false>;
+  hipLaunchKernelGGL(density, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
                      h->at<float2>(h->L.vel[c]), h->at<float2>(h->L.acc[c]), integrate ? 1 : 0,
                      h->at<float2>(h->L.pos_sort), h->at<int>(h->L.pkey), h->at<int4>(h->L.rng),
                      h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), h->at<Tank>(h->L.tanks),
                      h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
-                     h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status));
+                     h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status),
+                     h->at<int>(h->L.near_n), h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
   mark(1);
   // the step before a scheduled rebuild also bins the particles for it
   const bool bin = mode == kStep && h->since_sort + 1 >= kSortEvery;
@@ -1510,7 +1715,8 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
                      h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]),
                      h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials),
-                     h->at<int>(h->L.key), h->at<int>(h->L.count));
+                     h->at<int>(h->L.key), h->at<int>(h->L.count), h->at<int>(h->L.near_n),
+                     h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
   h->binned = bin;
   mark(2);
   hipLaunchKernelGGL(sph_wrench, dim3(h->T), dim3(kBlock), 0, h->stream, h->at<double>(h->L.partials),
@@ -1737,6 +1943,9 @@ int init_common(int T, const sph_params* params, const int32_t* n_fluid, const f
   };
   hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
   if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
+  // no particle has a near list until the first step after a rebuild writes one
+  e = hipMemsetAsync(h->ws + L.near_n, 0xff, (size_t)pl.N * 4, h->stream);
+  if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync"));
   if ((rc = upload_tables(h)) != SPH_OK) return fail(rc);
   if ((rc = set_rigid(h, rigid0, 0.0, 0)) != SPH_OK) return fail(rc);
   if (pl.Gh > 0) {
@@ -1924,9 +2133,12 @@ int sph_rhs(sph_handle* h, const float* u_dev, float* rho_dev, float* p_dev, flo
   if (!h) return SPH_E_INVAL;
   int rc = set_rollout(h, u_dev, nullptr, 0, 0, 0, nullptr, nullptr, nullptr, nullptr);
   if (rc) return rc;
-  enqueue_sort(h);
+  // the cell list and near lists of the last rebuild stay valid until the
+  // next scheduled one (the displacement check still runs)
+  if (h->since_sort >= kSortEvery) enqueue_sort(h);
+  const int since = h->since_sort;
   enqueue_step(h, false, kEval);
-  h->since_sort = 0;   // evaluation only: the positions did not move
+  h->since_sort = since;   // evaluation only: the positions did not move
   hipLaunchKernelGGL(sph_rhs_out, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
                      h->at<float2>(h->L.pos[h->cur]), h->at<float2>(h->L.vel[h->cur]),
                      h->at<float2>(h->L.acc[h->cur]), h->at<float2>(h->L.rp), h->at<int>(h->L.id[h->ord]), h->N,
