@@ -125,6 +125,7 @@ def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int):
     dev = torch.device("cuda:0")
     sim = Simulator.batch(scs, device=dev)
     lanes = sim.autotune(reps=5)
+    near = sim.tuning()[1]
     u = torch.stack([torch.as_tensor(sc.u_seq) for sc in scs]).to(dev)
     sim.rollout(warmup, u[:, :warmup])
     torch.cuda.synchronize()
@@ -141,7 +142,7 @@ def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int):
     n = sum(sc.n_fluid for sc in scs)
     g = sum(sc.n_ghost for sc in scs)
     nc = sum(n_cells_of(sc) for sc in scs)
-    return {"tanks": n_tanks, "n_fluid": n, "n_ghost": g, "steps": steps, "lanes": lanes,
+    return {"tanks": n_tanks, "n_fluid": n, "n_ghost": g, "steps": steps, "lanes": lanes, "near_lists": near,
             "value": n * steps / (ms / 1e3), "unit": "particle-steps/s", "ms_per_step": ms / steps,
             "status": status, "kernel_us": {k: round(v, 3) for k, v in kus.items()},
             "roofline": kernel_roofline(kus, n, g, nc)}
@@ -221,6 +222,7 @@ def main() -> int:
     u = torch.as_tensor(sc.u_seq, device=dev)
     ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
     lanes = sim.autotune(reps=20)
+    near = sim.tuning()[1]
 
     sim.rollout(args.warmup, u[:args.warmup], ref)
     torch.cuda.synchronize()
@@ -256,7 +258,7 @@ def main() -> int:
         "config": {"workload": f"closed_loop_circle: R 0.5 m, fill 0.3, dx {sc.dx * 1e3:g} mm, "
                                f"{sc.n_fluid} fluid + {sc.n_ghost} boundary particles, PD slew",
                    "n_fluid": sc.n_fluid, "n_ghost": sc.n_ghost, "dt": sc.params.dt,
-                   "lanes_per_particle": lanes, "parallelism": "single GPU"},
+                   "lanes_per_particle": lanes, "near_lists": near, "parallelism": "single GPU"},
         "status": status,
         "kernel_us": {k: round(v, 3) for k, v in kus.items()},
         "roofline": roofline,

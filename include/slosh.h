@@ -130,15 +130,29 @@ int sph_batch_init(int32_t n_tanks, const sph_params* params, const int32_t* n_f
 int sph_num_tanks(sph_handle* h, int32_t* n_tanks);
 
 /* Autotuner of the neighbour kernels: times, at the current state and
- * without advancing it, `reps` evaluations of the density and force kernels
- * for each supported number of lanes per particle (4, 8, 16; the tile is
- * 256 / lanes particles) and keeps the fastest; *lanes receives it (may be
- * NULL).  Rebuilds the cell list.  The choice changes the summation order,
- * so results are reproducible for a fixed choice (sph_set_lanes). */
+ * without advancing it, `reps` evaluations of one rebuild interval of the
+ * step kernels (density, forces, wrench) for each supported number of lanes
+ * per particle (4, 8, 16; the tile is 256 / lanes particles), with and
+ * without near lists, and keeps the fastest; *lanes receives the lanes (may
+ * be NULL; sph_get_tuning reports both choices).  Rebuilds the cell list.
+ * The choice changes the summation order, so results are reproducible for a
+ * fixed choice (sph_set_lanes, sph_set_near_lists). */
 int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes);
 
 /* Selects the lanes per particle (4, 8 or 16; default 8). */
 int sph_set_lanes(sph_handle* h, int32_t lanes);
+
+/* Near lists on (1) or off (0, default).  On: at the first step after each
+ * cell-list rebuild every particle lists the candidates of its 3x3 cell
+ * block that lie within 2h + skin of it (fluid) or S + skin/2 (boundary)
+ * at the rebuild positions, and the other kernels of the interval walk only
+ * those; off: every kernel walks the whole block.  Both give the same
+ * neighbour sets (the sums differ in order only). */
+int sph_set_near_lists(sph_handle* h, int32_t on);
+
+/* The current tuning choices: lanes per particle and near lists (0/1);
+ * either pointer may be NULL. */
+int sph_get_tuning(sph_handle* h, int32_t* lanes, int32_t* near_lists);
 
 /* Frees the host handle and its graphs (the workspace stays the caller's). */
 int sph_destroy(sph_handle* h);

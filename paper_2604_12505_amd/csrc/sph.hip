@@ -727,24 +727,22 @@ __device__ __forceinline__ int near_build(const OrdMap& m, int total, int l, uns
   return cnt;
 }
 
-// A near list of n ordinals (bytes of 32-bit words in memory) is cut into G
-// runs of whole words; lane l takes run l, at most kMaxW words (<= 4).  The
-// words are fetched together and consumed by rotation (no indexed array,
-// which the compiler would place in scratch memory).
+// A near list is CAP one-byte ordinals in CAP/4 words; lane l of a
+// particle's group takes words l, l + G, l + 2G, ... (at most kMaxW <= 4).
+// The words do not depend on the list length, so they are fetched at the
+// start of a kernel, in the same round trip as the tile's other loads, and
+// consumed by rotation (an indexed array would be placed in scratch memory).
 template <int G, int CAP>
-struct NearRun {
-  static constexpr int kMaxW = (CAP / 4 + G - 1) / G;
-  static_assert(kMaxW <= 4, "near-list run longer than four words");
-  unsigned w0, w1, w2, w3;
-  int first, wpl;   // first entry of the run, words per lane
-  __device__ __forceinline__ NearRun(const unsigned* __restrict__ row, int n, int l) {
-    wpl = ((n + 3) / 4 + G - 1) / G;
-    const int wb = l * wpl;
-    first = 4 * wb;
-    w0 = (wpl > 0 && 4 * wb < n) ? row[wb] : 0u;
-    w1 = (kMaxW > 1 && wpl > 1 && 4 * (wb + 1) < n) ? row[wb + 1] : 0u;
-    w2 = (kMaxW > 2 && wpl > 2 && 4 * (wb + 2) < n) ? row[wb + 2] : 0u;
-    w3 = (kMaxW > 3 && wpl > 3 && 4 * (wb + 3) < n) ? row[wb + 3] : 0u;
+struct NearWords {
+  static constexpr int kWords = CAP / 4;
+  static constexpr int kMaxW = (kWords + G - 1) / G;
+  static_assert(kMaxW <= 4, "more than four near-list words per lane");
+  unsigned w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+  __device__ __forceinline__ void load(const unsigned* __restrict__ row, int l) {
+    if (l < kWords) w0 = row[l];
+    if (kMaxW > 1 && l + G < kWords) w1 = row[l + G];
+    if (kMaxW > 2 && l + 2 * G < kWords) w2 = row[l + 2 * G];
+    if (kMaxW > 3 && l + 3 * G < kWords) w3 = row[l + 3 * G];
   }
   __device__ __forceinline__ unsigned pop() {
     const unsigned w = w0;
@@ -755,41 +753,43 @@ struct NearRun {
   }
 };
 
-// Calls f(e) for the staged candidates of lane l's run of a near list.
+// Calls f(e) for the staged candidates of lane l's entries of a near list of
+// n entries (consumes the words).
 template <int G, int CAP, class F>
-__device__ __forceinline__ void near_visit(const unsigned* __restrict__ row, int n, int l, const OrdMap& m, F&& f) {
-  NearRun<G, CAP> run(row, n, l);
+__device__ __forceinline__ void near_visit(NearWords<G, CAP>& nw, int n, int l, const OrdMap& m, F&& f) {
 #pragma unroll
-  for (int q = 0; q < NearRun<G, CAP>::kMaxW; ++q) {
-    unsigned word = run.pop();
-    if (q < run.wpl)
+  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
+    unsigned word = nw.pop();
+    const int i0 = 4 * (l + q * G);
+    if (i0 < n)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if (run.first + 4 * q + b < n) f(m((int)(word & 255u)));
+        if (i0 + b < n) f(m((int)(word & 255u)));
         word >>= 8;
       }
   }
 }
 
-// Compacts the entries of a near list that pass `keep` into lst (LDS
-// indices, in ballot-round order); returns the count (<= n), the same on
-// the G lanes.
+// Compacts the entries of a near list of n entries that pass `keep` into
+// lst (LDS indices, in ballot-round order); returns the count (<= n), the
+// same on the G lanes.
 template <int G, int CAP, class F>
-__device__ __forceinline__ int near_pass(const unsigned* __restrict__ row, int n, int l, const OrdMap& m,
+__device__ __forceinline__ int near_pass(NearWords<G, CAP>& nw, int n, int l, const OrdMap& m,
                                          unsigned short* lst, F&& keep) {
-  NearRun<G, CAP> run(row, n, l);
   const int base = (int)(threadIdx.x & 63) - l;
   const unsigned below = (1u << l) - 1u;
+  const int rounds = ((n + 3) / 4 + G - 1) / G;   // the same on the G lanes
   int cnt = 0;
 #pragma unroll
-  for (int q = 0; q < NearRun<G, CAP>::kMaxW; ++q) {
-    unsigned word = run.pop();
-    if (q < run.wpl) {   // the same on the G lanes
+  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
+    unsigned word = nw.pop();
+    if (q < rounds) {
+      const int i0 = 4 * (l + q * G);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         int e = 0;
         bool in = false;
-        if (run.first + 4 * q + b < n) {
+        if (i0 + b < n) {
           e = m((int)(word & 255u));
           in = keep(e);
         }
@@ -850,6 +850,12 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
   const float dt = k.dt;
   tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl, Build ? nullptr : near_n);
   float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f), s_raw = s;
+  NearWords<G, kNearF> nwf;
+  NearWords<G, kNearG> nwg;
+  if (!Build && mine && near_n) {
+    nwf.load(near_f + (size_t)p * (kNearF / 4), l);
+    nwg.load(near_g + (size_t)p * (kNearG / 4), l);
+  }
   if (mine) {
     s = pos_in[p];
     if (Build) s_raw = pos_sort[p];   // near lists use the positions of the rebuild
@@ -886,27 +892,37 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
       int total;
       const OrdMap fm = ord_map<TP>(tl, pl, false, sg.lo, sg.off, &total);
       const int nlf = tl.near[pl] & 255;
-      if (!Build && fst && nlf <= kNearF) {
-        near_visit<G, kNearF>(near_f + (size_t)p * (kNearF / 4), nlf, l, fm, [&](int e) { fluid(f_pos[e]); });
-      } else if (fst) {
-        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e]); });
-      } else {
-        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) {
-          float2 sj = pos_in[j];
-          if (integrate) {
-            float2 wj = vel_in[j];
-            fluid_update(sj, wj, acc_in[j], fr, dt);
-          }
-          fluid(sj);
-        });
-      }
+      bool walked = false;
       if (Build && fst && total <= 255) {
-        const int cnt = near_build<G>(fm, total, l, reinterpret_cast<unsigned char*>(nb_f[pl]), kNearF,
-                                      [&](int e) {
-                                        const float2 r = f_raw[e];
-                                        return dist2(s_raw.x - r.x, s_raw.y - r.y) < k.RL2;
-                                      });
+        // list first, then the density over the list just written
+        unsigned char* lb = reinterpret_cast<unsigned char*>(nb_f[pl]);
+        const int cnt = near_build<G>(fm, total, l, lb, kNearF, [&](int e) {
+          const float2 r = f_raw[e];
+          return dist2(s_raw.x - r.x, s_raw.y - r.y) < k.RL2;
+        });
         nf_out = cnt <= kNearF ? cnt : kNearNone;
+        if (cnt <= kNearF) {
+          wave_sync();
+          for (int i = l; i < cnt; i += G) fluid(f_pos[fm(lb[i])]);
+          walked = true;
+        }
+      } else if (!Build && fst && nlf <= kNearF) {
+        near_visit<G, kNearF>(nwf, nlf, l, fm, [&](int e) { fluid(f_pos[e]); });
+        walked = true;
+      }
+      if (!walked) {
+        if (fst) {
+          visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e]); });
+        } else {
+          visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) {
+            float2 sj = pos_in[j];
+            if (integrate) {
+              float2 wj = vel_in[j];
+              fluid_update(sj, wj, acc_in[j], fr, dt);
+            }
+            fluid(sj);
+          });
+        }
       }
       auto ghost = [&](float2 gj) {
         float d2 = dist2(s.x - gj.x, s.y - gj.y);
@@ -915,19 +931,28 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
       int gtotal;
       const OrdMap gm = ord_map<TP>(tl, pl, true, sg.glo, sg.goff, &gtotal);
       const int nlg = (tl.near[pl] >> 8) & 255;
-      if (!Build && gst && nlg <= kNearG)
-        near_visit<G, kNearG>(near_g + (size_t)p * (kNearG / 4), nlg, l, gm, [&](int e) { ghost(g_pos[e]); });
-      else if (gst)
-        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
-      else
-        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
+      bool gwalked = false;
       if (Build && gst && gtotal <= 255) {
-        const int cnt = near_build<G>(gm, gtotal, l, reinterpret_cast<unsigned char*>(nb_g[pl]), kNearG,
-                                      [&](int e) {
-                                        const float2 r = g_pos[e];
-                                        return dist2(s_raw.x - r.x, s_raw.y - r.y) < k.RG2;
-                                      });
+        unsigned char* lb = reinterpret_cast<unsigned char*>(nb_g[pl]);
+        const int cnt = near_build<G>(gm, gtotal, l, lb, kNearG, [&](int e) {
+          const float2 r = g_pos[e];
+          return dist2(s_raw.x - r.x, s_raw.y - r.y) < k.RG2;
+        });
         ng_out = cnt <= kNearG ? cnt : kNearNone;
+        if (cnt <= kNearG) {
+          wave_sync();
+          for (int i = l; i < cnt; i += G) ghost(g_pos[gm(lb[i])]);
+          gwalked = true;
+        }
+      } else if (!Build && gst && nlg <= kNearG) {
+        near_visit<G, kNearG>(nwg, nlg, l, gm, [&](int e) { ghost(g_pos[e]); });
+        gwalked = true;
+      }
+      if (!gwalked) {
+        if (gst)
+          visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
+        else
+          visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
       }
     }
     const int next = sg.last + 1;
@@ -1121,7 +1146,13 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   const bool mine = pl < tr.np;
   tile_load<TP>(tr.p0, tr.np, tk, pkey, rng, tl, near_n);
   float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f), me = make_float2(1.f, 0.f);
+  NearWords<G, kNearF> nwf;
+  NearWords<G, kNearG> nwg;
   if (mine) {
+    if (near_n) {
+      nwf.load(near_f + (size_t)p * (kNearF / 4), l);
+      nwg.load(near_g + (size_t)p * (kNearG / 4), l);
+    }
     s = pos[p];
     w = vel[p];
     me = rp[p];
@@ -1182,7 +1213,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
         };
         const int nlf = tl.near[pl] & 255;
         if (nlf <= kNearF) {
-          pairs(near_pass<G, kNearF>(near_f + (size_t)p * (kNearF / 4), nlf, l, fm, lst, inside));
+          pairs(near_pass<G, kNearF>(nwf, nlf, l, fm, lst, inside));
         } else {
           int c = 0;
           while (c < total) pairs(list_pass<G>(fm, total, l, c, kListF, lst, inside));
@@ -1223,7 +1254,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
         };
         const int nlg = (tl.near[pl] >> 8) & 255;
         if (nlg <= kNearG) {
-          walls(near_pass<G, kNearG>(near_g + (size_t)p * (kNearG / 4), nlg, l, gm, lst, inside));
+          walls(near_pass<G, kNearG>(nwg, nlg, l, gm, lst, inside));
         } else {
           int c = 0;
           while (c < total) walls(list_pass<G>(gm, total, l, c, kListG, lst, inside));
@@ -1648,8 +1679,10 @@ struct sph_handle {
   int since_sort;   // steps since the last cell-list rebuild
   bool binned;      // the last force launch computed the keys and counts of the next rebuild
   int variant;      // lanes per particle = kLanes[variant]
-  hipGraphExec_t graph[kNumVariants][2][2];   // kChunk steps from (cur, ord)
-  bool graph_ok[kNumVariants][2][2];
+  bool near;        // walk near lists (else every candidate of the 3x3 block)
+  bool near_valid;  // the near lists belong to the current cell order
+  hipGraphExec_t graph[kNumVariants][2][2][2];   // [variant][near] kChunk steps from (cur, ord)
+  bool graph_ok[kNumVariants][2][2][2];
 
   template <class T_>
   T_* at(size_t off) { return reinterpret_cast<T_*>(ws + off); }
@@ -1670,6 +1703,7 @@ void enqueue_sort(sph_handle* h, hipEvent_t* ev = nullptr) {
                        h->N, h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.key),
                        h->at<int>(h->L.count), (int*)nullptr);
   h->binned = false;
+  h->near_valid = false;
   mark(1);
   hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
                      h->at<Tank>(h->L.tanks), h->T, 0, h->at<int>(h->L.cstart[1 - o]),
@@ -1697,16 +1731,19 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
     if (ev) (void)hipEventRecord(ev[i], h->stream);
   };
   mark(0);
-  // the first step after a rebuild walks every candidate and writes the near lists
-  const bool build = h->since_sort == 0;
+  // with near lists on, the first step after a rebuild walks every candidate
+  // and writes them; without, every step walks every candidate
+  const bool build = h->near && !h->near_valid;
   auto density = build ? sph_density<G, true> : sph_density<G, false>;
+  int* near_n = h->near ? h->at<int>(h->L.near_n) : nullptr;
   hipLaunchKernelGGL(density, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
                      h->at<float2>(h->L.vel[c]), h->at<float2>(h->L.acc[c]), integrate ? 1 : 0,
                      h->at<float2>(h->L.pos_sort), h->at<int>(h->L.pkey), h->at<int4>(h->L.rng),
                      h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), h->at<Tank>(h->L.tanks),
                      h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status),
-                     h->at<int>(h->L.near_n), h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
+                     near_n, h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
+  if (build) h->near_valid = true;
   mark(1);
   // the step before a scheduled rebuild also bins the particles for it
   const bool bin = mode == kStep && h->since_sort + 1 >= kSortEvery;
@@ -1715,7 +1752,7 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
                      h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]),
                      h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials),
-                     h->at<int>(h->L.key), h->at<int>(h->L.count), h->at<int>(h->L.near_n),
+                     h->at<int>(h->L.key), h->at<int>(h->L.count), near_n,
                      h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
   h->binned = bin;
   mark(2);
@@ -1787,6 +1824,7 @@ int sort_fluid(sph_handle* h, const float2* s, const float2* w) {
   h->cur = 0;
   h->ord = 0;
   h->since_sort = 0;
+  h->near_valid = false;
   return SPH_OK;
 }
 
@@ -1853,10 +1891,13 @@ int set_rollout(sph_handle* h, const float* u, const double* ref, int n_ref, int
   return SPH_OK;
 }
 
-// Captures kChunk steps starting from (cur, ord) with since_sort == 0.
+// Captures kChunk steps starting from (cur, ord) with since_sort == 0 (the
+// first captured step rebuilds the near lists, whatever their host state).
 int build_graph(sph_handle* h) {
-  const int c = h->cur, o = h->ord, v = h->variant;
-  if (h->graph_ok[v][c][o]) return SPH_OK;
+  const int c = h->cur, o = h->ord, v = h->variant, n = h->near ? 1 : 0;
+  if (h->graph_ok[v][n][c][o]) return SPH_OK;
+  const bool valid = h->near_valid;
+  h->near_valid = false;
   hipGraph_t gr;
   HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   enqueue_steps(h, kChunk);
@@ -1865,11 +1906,12 @@ int build_graph(sph_handle* h) {
   h->ord = o;
   h->since_sort = 0;
   h->binned = false;
+  h->near_valid = valid;
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&h->graph[v][c][o], gr, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&h->graph[v][n][c][o], gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-  h->graph_ok[v][c][o] = true;
+  h->graph_ok[v][n][c][o] = true;
   return SPH_OK;
 }
 
@@ -1934,9 +1976,12 @@ int init_common(int T, const sph_params* params, const int32_t* n_fluid, const f
   h->cur = h->ord = h->since_sort = 0;
   h->binned = false;
   h->variant = kDefaultVariant;
+  h->near = false;
+  h->near_valid = false;
   for (int v = 0; v < kNumVariants; ++v)
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) h->graph_ok[v][a][b] = false;
+    for (int n = 0; n < 2; ++n)
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) h->graph_ok[v][n][a][b] = false;
   auto fail = [&](int code) {
     delete h;
     return code;
@@ -2003,9 +2048,10 @@ int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const fl
 int sph_destroy(sph_handle* h) {
   if (!h) return SPH_E_INVAL;
   for (int v = 0; v < kNumVariants; ++v)
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b)
-        if (h->graph_ok[v][a][b]) (void)hipGraphExecDestroy(h->graph[v][a][b]);
+    for (int n = 0; n < 2; ++n)
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          if (h->graph_ok[v][n][a][b]) (void)hipGraphExecDestroy(h->graph[v][n][a][b]);
   delete h;
   return SPH_OK;
 }
@@ -2033,7 +2079,8 @@ int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const do
   }
   while (left >= kChunk) {
     if ((rc = build_graph(h)) != SPH_OK) return rc;
-    HIPCHK(hipGraphLaunch(h->graph[h->variant][h->cur][h->ord], h->stream));
+    HIPCHK(hipGraphLaunch(h->graph[h->variant][h->near ? 1 : 0][h->cur][h->ord], h->stream));
+    h->near_valid = false;   // the chunk ends with a rebuild
     left -= kChunk;
   }
   if (left > 0) enqueue_steps(h, left);
@@ -2085,31 +2132,43 @@ int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes) {
   for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
   enqueue_sort(h);
   int best = kDefaultVariant;
+  bool best_near = false;
   double best_ms = 1e300;
   const int cur = h->cur, ord = h->ord;
-  for (int v = 0; v < kNumVariants; ++v) {
-    h->variant = v;
-    double total = 0.0;
-    for (int r = 0; r <= reps; ++r) {   // the first pass warms up
-      h->cur = cur;
-      h->ord = ord;
-      enqueue_step(h, false, kEval, ev);
-      HIPCHK(hipEventSynchronize(ev[3]));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[3]));
-      if (r > 0) total += ms;
+  for (int v = 0; v < kNumVariants; ++v)
+    for (int nr = 0; nr < 2; ++nr) {
+      h->variant = v;
+      h->near = nr != 0;
+      double total = 0.0;
+      for (int r = 0; r <= reps; ++r) {   // the first round warms up
+        // one rebuild interval: with near lists, its first step builds them
+        h->near_valid = false;
+        float ms = 0.f;
+        for (int k = 0; k < kSortEvery; ++k) {
+          h->cur = cur;
+          h->ord = ord;
+          enqueue_step(h, false, kEval, ev);
+          HIPCHK(hipEventSynchronize(ev[3]));
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, ev[0], ev[3]));
+          ms += t;
+        }
+        if (r > 0) total += ms;
+      }
+      if (total < best_ms) {
+        best_ms = total;
+        best = v;
+        best_near = nr != 0;
+      }
     }
-    if (total < best_ms) {
-      best_ms = total;
-      best = v;
-    }
-  }
   for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
   // evaluation only: the state is what it was after the rebuild
   h->cur = 1 - cur;
   h->ord = ord;
   h->since_sort = 0;
   h->variant = best;
+  h->near = best_near;
+  h->near_valid = false;
   if (lanes) *lanes = kLanes[best];
   return SPH_OK;
 }
@@ -2122,6 +2181,20 @@ int sph_set_lanes(sph_handle* h, int32_t lanes) {
       return SPH_OK;
     }
   return SPH_E_INVAL;
+}
+
+int sph_set_near_lists(sph_handle* h, int32_t on) {
+  if (!h || (on != 0 && on != 1)) return SPH_E_INVAL;
+  if (h->near != (on != 0)) h->near_valid = false;
+  h->near = on != 0;
+  return SPH_OK;
+}
+
+int sph_get_tuning(sph_handle* h, int32_t* lanes, int32_t* near_lists) {
+  if (!h) return SPH_E_INVAL;
+  if (lanes) *lanes = kLanes[h->variant];
+  if (near_lists) *near_lists = h->near ? 1 : 0;
+  return SPH_OK;
 }
 
 int sph_step(sph_handle* h, const float* u_dev) {

@@ -232,6 +232,15 @@ class Simulator:
     def set_lanes(self, lanes: int) -> None:
         check(self.L.sph_set_lanes(self.h, int(lanes)), "sph_set_lanes")
 
+    def set_near_lists(self, on: bool) -> None:
+        check(self.L.sph_set_near_lists(self.h, 1 if on else 0), "sph_set_near_lists")
+
+    def tuning(self):
+        """(lanes per particle, near lists on)."""
+        lanes, near = C.c_int32(), C.c_int32()
+        check(self.L.sph_get_tuning(self.h, C.byref(lanes), C.byref(near)), "sph_get_tuning")
+        return int(lanes.value), bool(near.value)
+
     def time_kernels(self, n_steps: int, u_seq=None, theta_ref=None):
         """Mean per-launch microseconds over n_steps directly launched steps:
         bin, scan, place (per rebuild), density, force, wrench (per step)."""

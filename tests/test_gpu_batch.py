@@ -1,5 +1,6 @@
 """Many tanks in one handle (one set of launches) against single-tank runs
-and the FP64 oracle; the lanes-per-particle variants and the autotuner."""
+and the FP64 oracle; the lanes-per-particle variants, near lists on and
+off, and the autotuner."""
 import numpy as np
 import pytest
 
@@ -18,11 +19,13 @@ def _tanks():
             W.random_tank(23, n_steps=60, n_min=2000, n_max=2500, shape="circle")]
 
 
-def test_batch_equals_single_tank_runs_bitwise():
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
+def test_batch_equals_single_tank_runs_bitwise(near):
     from paper_2604_12505_amd.sph import Simulator
     scs = _tanks()
     n = 60
     batch = Simulator.batch(scs)
+    batch.set_near_lists(near)
     u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
     logs = batch.rollout(n, u, log_stride=10)
     s, w, rig, tau, step = batch.get_state()
@@ -30,6 +33,7 @@ def test_batch_equals_single_tank_runs_bitwise():
     off = 0
     for t, sc in enumerate(scs):
         one = Simulator.from_scenario(sc)
+        one.set_near_lists(near)
         l1 = one.rollout(n, torch.as_tensor(sc.u_seq[:n]), log_stride=10)
         s1, w1, r1, _, _ = one.get_state()
         k = sc.n_fluid
@@ -61,12 +65,15 @@ def test_batch_tracks_the_oracle_per_tank():
     batch.close()
 
 
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
 @pytest.mark.parametrize("lanes", [4, 8, 16])
-def test_every_lane_variant_matches_the_oracle(lanes):
+def test_every_lane_variant_matches_the_oracle(lanes, near):
     from paper_2604_12505_amd.sph import Simulator
     sc = W.closed_loop_circle(0, n_steps=40)
     sim = Simulator.from_scenario(sc)
     sim.set_lanes(lanes)
+    sim.set_near_lists(near)
+    assert sim.tuning() == (lanes, near)
     sim.rollout(40, torch.as_tensor(sc.u_seq), theta_ref=sc.theta_ref)
     s, _, rig, _, _ = sim.get_state()
     assert sim.status() == 0
@@ -86,7 +93,7 @@ def test_autotune_picks_a_variant_and_keeps_parity():
     scs = _tanks()
     batch = Simulator.batch(scs)
     lanes = batch.autotune(reps=3)
-    assert lanes in (4, 8, 16)
+    assert lanes in (4, 8, 16) and batch.tuning()[0] == lanes
     n = 40
     u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
     batch.rollout(n, u)

@@ -23,9 +23,11 @@ from oracle import sph as O
 pytestmark = pytest.mark.gpu
 
 
-def _sim(sc):
+def _sim(sc, near=False):
     from paper_2604_12505_amd.sph import Simulator
-    return Simulator.from_scenario(sc)
+    sim = Simulator.from_scenario(sc)
+    sim.set_near_lists(near)
+    return sim
 
 
 def _rel(a, b):
@@ -123,10 +125,11 @@ def test_rhs_parity_initial_state(name):
     sim.close()
 
 
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
 @pytest.mark.parametrize("name", ["plain_rect", "closed_loop_circle", "random_rect"])
-def test_rhs_parity_after_evolution(name):
+def test_rhs_parity_after_evolution(name, near):
     sc = SCENARIOS[name]()
-    sim = _sim(sc)
+    sim = _sim(sc, near)
     # 203 steps: the evaluation falls three steps after a rebuild, so it walks
     # near lists built at positions that have moved since
     sim.rollout(203, torch.as_tensor(np.tile(sc.u_seq[:1], (203, 1))) if sc.u_seq is not None else None,
@@ -136,10 +139,11 @@ def test_rhs_parity_after_evolution(name):
     sim.close()
 
 
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
 @pytest.mark.parametrize("name", list(SCENARIOS))
-def test_trajectory_50_steps(name):
+def test_trajectory_50_steps(name, near):
     sc = SCENARIOS[name]()
-    sim = _sim(sc)
+    sim = _sim(sc, near)
     n = 50
     u = sc.u_seq[:n]
     logs = sim.rollout(n, torch.as_tensor(u), theta_ref=sc.theta_ref, log_stride=10)
@@ -160,11 +164,12 @@ def test_trajectory_50_steps(name):
     sim.close()
 
 
-def test_rollout_is_deterministic_and_graph_equals_direct():
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
+def test_rollout_is_deterministic_and_graph_equals_direct(near):
     # a, b: one rollout (graph-replayed chunks); c: single steps; d: three
     # single steps, then a rollout that first aligns to the rebuild schedule
     sc = W.plain_rect(1, n_steps=150)
-    sims = [_sim(sc) for _ in range(4)]
+    sims = [_sim(sc, near) for _ in range(4)]
     a, b, c, d = sims
     u = torch.as_tensor(sc.u_seq)
     a.rollout(150, u)
@@ -184,9 +189,10 @@ def test_rollout_is_deterministic_and_graph_equals_direct():
         x.close()
 
 
-def test_long_rollout_stays_within_the_rebuild_skin_and_tracks_the_oracle():
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
+def test_long_rollout_stays_within_the_rebuild_skin_and_tracks_the_oracle(near):
     sc = W.plain_rect(3, n_steps=400)
-    sim = _sim(sc)
+    sim = _sim(sc, near)
     logs = sim.rollout(400, torch.as_tensor(sc.u_seq), log_stride=50)
     s, w, rig, _, _ = sim.get_state()
     assert sim.status() == 0
