@@ -132,14 +132,14 @@ int sph_num_tanks(sph_handle* h, int32_t* n_tanks);
 /* Autotuner of the neighbour kernels: times, at the current state and
  * without advancing it, `reps` evaluations of one rebuild interval of the
  * step kernels (density, forces, wrench) for each supported number of lanes
- * per particle (4, 8, 16; the tile is 256 / lanes particles), with and
+ * per particle (4, 8, 16, 32; the tile is 256 / lanes particles), with and
  * without near lists, and keeps the fastest; *lanes receives the lanes (may
  * be NULL; sph_get_tuning reports both choices).  Rebuilds the cell list.
  * The choice changes the summation order, so results are reproducible for a
  * fixed choice (sph_set_lanes, sph_set_near_lists). */
 int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes);
 
-/* Selects the lanes per particle (4, 8 or 16; default 8). */
+/* Selects the lanes per particle (4, 8, 16 or 32; default 8). */
 int sph_set_lanes(sph_handle* h, int32_t lanes);
 
 /* Near lists on (1) or off (0, default).  On: at the first step after each

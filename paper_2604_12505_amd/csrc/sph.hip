@@ -33,7 +33,7 @@
 // candidate of the three neighbouring rows over the segment's cell span, then
 // each particle's G lanes walk its own 3x3 block from LDS and combine their
 // sums with cross-lane shuffles.  A segment too large for the LDS stage
-// reads its candidates from global memory instead.  G is 4, 8 or 16, chosen
+// reads its candidates from global memory instead.  G is 4, 8, 16 or 32, chosen
 // by sph_autotune (8 by default).
 //
 // Neighbours come from a body-frame cell grid of side (S + skin)(1 + 1e-6),
@@ -75,8 +75,8 @@ constexpr int kListG = 32;        // in-support ghost neighbours listed per part
 constexpr int kNearF = 64;        // capacity of a fluid near list
 constexpr int kNearG = 32;        // capacity of a ghost near list
 constexpr int kNearNone = 255;    // list length meaning "not listed: walk all candidates"
-constexpr int kNumVariants = 3;   // lanes per particle: 4, 8, 16
-constexpr int kLanes[kNumVariants] = {4, 8, 16};
+constexpr int kNumVariants = 4;   // lanes per particle: 4, 8, 16, 32
+constexpr int kLanes[kNumVariants] = {4, 8, 16, 32};
 constexpr int kDefaultVariant = 1;
 
 static_assert(kChunk % kSortEvery == 0 && kChunk % 2 == 0, "graph chunk");
@@ -1570,7 +1570,7 @@ Consts make_consts(const sph_params* p) {
 struct Plan {
   int T = 0;
   long long N = 0, Gh = 0, C = 0;          // particles, ghosts, cells (totals)
-  long long tiles[kNumVariants] = {0, 0, 0};
+  long long tiles[kNumVariants] = {0, 0, 0, 0};
   std::vector<Tank> tanks;
 };
 
@@ -1768,7 +1768,8 @@ void enqueue_step(sph_handle* h, bool integrate, int mode, hipEvent_t* ev = null
   switch (h->variant) {
     case 0: launch_pair<4>(h, 0, integrate, mode, ev); break;
     case 1: launch_pair<8>(h, 1, integrate, mode, ev); break;
-    default: launch_pair<16>(h, 2, integrate, mode, ev); break;
+    case 2: launch_pair<16>(h, 2, integrate, mode, ev); break;
+    default: launch_pair<32>(h, 3, integrate, mode, ev); break;
   }
   h->cur = 1 - h->cur;
   h->since_sort += 1;
@@ -2295,7 +2296,8 @@ int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* co
   };
   if (v == 0) args(sph_nbr_list<4>);
   else if (v == 1) args(sph_nbr_list<8>);
-  else args(sph_nbr_list<16>);
+  else if (v == 2) args(sph_nbr_list<16>);
+  else args(sph_nbr_list<32>);
   HIPCHK(hipGetLastError());
   return SPH_OK;
 }

@@ -66,7 +66,7 @@ def test_batch_tracks_the_oracle_per_tank():
 
 
 @pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
-@pytest.mark.parametrize("lanes", [4, 8, 16])
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32])
 def test_every_lane_variant_matches_the_oracle(lanes, near):
     from paper_2604_12505_amd.sph import Simulator
     sc = W.closed_loop_circle(0, n_steps=40)
@@ -93,7 +93,7 @@ def test_autotune_picks_a_variant_and_keeps_parity():
     scs = _tanks()
     batch = Simulator.batch(scs)
     lanes = batch.autotune(reps=3)
-    assert lanes in (4, 8, 16) and batch.tuning()[0] == lanes
+    assert lanes in (4, 8, 16, 32) and batch.tuning()[0] == lanes
     n = 40
     u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
     batch.rollout(n, u)
