@@ -58,7 +58,11 @@ FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 # HBM traffic of the force kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (per dispatch, scaled by the copy-kernel calibration), valid for the source
 # whose hash is recorded; null once the kernel source changes.
-TRAFFIC = {"kernel": "sph_force", "src_sha1": None, "bytes_per_launch": None}
+# Measured on the closed-loop tank with 16 lanes per particle and the full
+# walk (profiles/hbm_traffic_closed_loop_circle.md): 1,705,965 B per plain
+# force launch and 1,901,565 B per binning one (every fourth), averaged.
+TRAFFIC = {"kernel": "sph_force", "lanes": 16, "near_lists": False,
+           "src_sha1": "03120e04d5b06c9bc08891bfdaa386e361609926", "bytes_per_launch": 1754865}
 
 
 def src_hash() -> str:
@@ -81,7 +85,7 @@ def cpu_baseline(sc, n_steps: int):
                       f"{dt:.1f} s, FP64 C with OpenMP over particles"}
 
 
-def kernel_roofline(kus, n_fluid, n_ghost, n_cells):
+def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None):
     """Roofline position of the kernel that takes the most time per step.
 
     The neighbour kernels are arithmetic-bound, not HBM-bound, by the
@@ -94,7 +98,9 @@ def kernel_roofline(kus, n_fluid, n_ghost, n_cells):
     secs = kus[dominant] * 1e-6
     gbs = alg_bytes / secs / 1e9
     traffic = TRAFFIC["bytes_per_launch"] if (TRAFFIC["src_sha1"] == src_hash()
-                                              and TRAFFIC["kernel"] == "sph_" + dominant) else None
+                                              and TRAFFIC["kernel"] == "sph_" + dominant
+                                              and TRAFFIC["lanes"] == lanes
+                                              and TRAFFIC["near_lists"] == near) else None
     hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
            "algorithmic_bytes_per_launch": alg_bytes}
     if dominant in FLOP:
@@ -114,7 +120,7 @@ def n_cells_of(sc):
         int(np.ceil((sc.params.domain_max[1] - sc.params.domain_min[1]) / cell))
 
 
-def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int):
+def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int, lanes: int = 0, near: int = -1):
     """Many random tanks (rectangular or circular, fill U[0.2, 0.8], 2k-60k
     particles, multisine torque) advanced together in the same launches."""
     import torch
@@ -124,8 +130,12 @@ def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int):
     scs = [W.random_tank(seed, n_steps=total) for seed in range(n_tanks)]
     dev = torch.device("cuda:0")
     sim = Simulator.batch(scs, device=dev)
-    lanes = sim.autotune(reps=5)
-    near = sim.tuning()[1]
+    if lanes > 0:
+        sim.set_lanes(lanes)
+        sim.set_near_lists(near == 1)
+    else:
+        sim.autotune(reps=5)
+    lanes, near = sim.tuning()
     u = torch.stack([torch.as_tensor(sc.u_seq) for sc in scs]).to(dev)
     sim.rollout(warmup, u[:, :warmup])
     torch.cuda.synchronize()
@@ -179,7 +189,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--cpu-steps", type=int, default=1500)
+    ap.add_argument("--cpu-steps", type=int, default=6000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--dx", type=float, default=0.004)
@@ -187,6 +197,10 @@ def main() -> int:
                     help="tanks of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-paper-leg", action="store_true")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes per particle of the closed-loop leg (0: sph_autotune chooses)")
+    ap.add_argument("--near-lists", type=int, default=-1,
+                    help="near lists on (1) or off (0) with --lanes (-1: off); with --batch-only they apply to the batch")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched leg and print its JSON object (profiling)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -211,7 +225,7 @@ def main() -> int:
         del src, dst
 
     if args.batch_only:
-        res = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
+        res = batch_leg(args.batch_tanks, args.batch_steps, 16, 16, args.lanes, args.near_lists)
         print(json.dumps(res))
         return 0 if res["status"] == 0 else 1
 
@@ -221,8 +235,15 @@ def main() -> int:
     sim = Simulator.from_scenario(sc, device=dev)
     u = torch.as_tensor(sc.u_seq, device=dev)
     ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
-    lanes = sim.autotune(reps=20)
-    near = sim.tuning()[1]
+    if args.lanes > 0:
+        # a fixed choice (profiler runs, where serialised launches would
+        # mislead the autotuner)
+        sim.set_lanes(args.lanes)
+        sim.set_near_lists(args.near_lists == 1)
+        lanes, near = sim.tuning()
+    else:
+        lanes = sim.autotune(reps=20)
+        near = sim.tuning()[1]
 
     sim.rollout(args.warmup, u[:args.warmup], ref)
     torch.cuda.synchronize()
@@ -239,7 +260,7 @@ def main() -> int:
     # per-kernel durations, HIP events around each kernel of directly launched steps
     kus = sim.time_kernels(args.kernel_steps, u[args.warmup + args.steps:], ref)
     status |= sim.status()
-    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc))
+    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc), lanes, near)
     sim.close()
 
     out = {

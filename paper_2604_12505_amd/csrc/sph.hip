@@ -269,6 +269,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Workgroup -> tile, XCD-aware.  The dispatcher deals consecutive
+// workgroups out to the 8 XCDs in turn, and each XCD has its own L2; this
+// gives every XCD one contiguous run of tiles (cell-ordered particles), so
+// the candidate rows that neighbouring tiles share are fetched into one L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, i = b / kXcd, q = n / kXcd, r = n % kXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // --------------------------------------------------------------------------
 // cell-list kernels
 // --------------------------------------------------------------------------
@@ -437,7 +447,7 @@ __global__ void __launch_bounds__(kBlock) sph_place(const int* __restrict__ key,
                                                     float2* __restrict__ pos_sort,
                                                     unsigned* __restrict__ status) {
   constexpr int G = kPlaceGroup;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int c = t / G, l = t % G;
   if (c >= n_cells) return;
   const Tank& tk = tanks[cell_owner[c]];
@@ -840,7 +850,8 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
   __shared__ unsigned nb_f[Build ? TP : 1][kNearF / 4], nb_g[Build ? TP : 1][kNearG / 4];
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
-  const TileRef tr = tiles[blockIdx.x];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileRef tr = tiles[tile];
   const Tank& tk = tanks[tr.tank];
   const Consts& k = tk.k;
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
@@ -1138,7 +1149,8 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
   __shared__ double red[3][kBlock / 64];
-  const TileRef tr = tiles[blockIdx.x];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileRef tr = tiles[tile];
   const Tank& tk = tanks[tr.tank];
   const Consts& k = tk.k;
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
@@ -1301,7 +1313,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
     for (int d = 0; d < 3; ++d) {
       double t = 0.0;
       for (int q = 0; q < kBlock / 64; ++q) t += red[d][q];
-      partials[3 * blockIdx.x + d] = t;
+      partials[3 * tile + d] = t;
     }
   }
 }
@@ -1424,7 +1436,8 @@ __global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict_
   __shared__ int f_id[kStageF];
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
-  const TileRef tr = tiles[blockIdx.x];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileRef tr = tiles[tile];
   const Tank& tk = tanks[tr.tank];
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
   const int p = tr.p0 + pl;
