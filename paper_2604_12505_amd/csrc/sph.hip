@@ -62,6 +62,7 @@ constexpr int kBlock = 256;       // threads per workgroup of the particle kerne
 constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;       // cells per thread per scan chunk
+constexpr int kWrenchThreads = 1024;  // one workgroup per tank sums its tile partials
 constexpr int kSortEvery = 4;     // steps between cell-list rebuilds
 constexpr int kChunk = 64;        // steps per captured graph (multiple of kSortEvery, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
@@ -613,6 +614,18 @@ __device__ __forceinline__ int seg_src(const int* lo, const int* off, int e) {
   return lo[2] + e - off[2];
 }
 
+// The tile a workgroup works on.  A single-tank handle (single_n = its
+// particle count, else -1) has tiles of TP consecutive particles from 0, so
+// the record is computed instead of loaded: one dependent round trip less.
+template <int TP>
+__device__ __forceinline__ TileRef tile_ref(const TileRef* __restrict__ tiles, int tile, int single_n) {
+  if (single_n >= 0) {
+    const int p0 = tile * TP, left = single_n - p0;
+    return TileRef{0, p0, left < TP ? left : TP, 0};
+  }
+  return tiles[tile];
+}
+
 // Rows and candidate ranges of the tile's particles into LDS; -1 marks slots
 // past the end.
 template <int TP>
@@ -833,7 +846,7 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
                                                       const int* __restrict__ pkey,
                                                       const int4* __restrict__ rng,
                                                       const float2* __restrict__ gpos,
-                                                      const TileRef* __restrict__ tiles,
+                                                      const TileRef* __restrict__ tiles, int single_n,
                                                       const Tank* __restrict__ tanks,
                                                       const DevRigid* __restrict__ rigid,
                                                       float2* __restrict__ pos_out,
@@ -851,7 +864,7 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const TileRef tr = tiles[tile];
+  const TileRef tr = tile_ref<TP>(tiles, tile, single_n);
   const Tank& tk = tanks[tr.tank];
   const Consts& k = tk.k;
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
@@ -1134,7 +1147,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
                                                     const int* __restrict__ pkey,
                                                     const int4* __restrict__ rng,
                                                     const float2* __restrict__ gpos,
-                                                    const TileRef* __restrict__ tiles,
+                                                    const TileRef* __restrict__ tiles, int single_n,
                                                     const Tank* __restrict__ tanks,
                                                     float2* __restrict__ acc,
                                                     double* __restrict__ partials,
@@ -1150,7 +1163,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   __shared__ Seg sg;
   __shared__ double red[3][kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const TileRef tr = tiles[tile];
+  const TileRef tr = tile_ref<TP>(tiles, tile, single_n);
   const Tank& tk = tanks[tr.tank];
   const Consts& k = tk.k;
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
@@ -1320,19 +1333,22 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
 
 // One workgroup per tank: the tank's tile partials summed in a fixed order,
 // then the rigid-body part of the step.
-__global__ void __launch_bounds__(kBlock) sph_wrench(const double* __restrict__ partials,
-                                                     const int* __restrict__ tank_tile0,
+__global__ void __launch_bounds__(kWrenchThreads) sph_wrench(const double* __restrict__ partials,
+                                                     const int* __restrict__ tank_tile0, int single_nt,
                                                      const Tank* __restrict__ tanks, DevRigid* rigid,
                                                      const DevRollout* __restrict__ ro, int mode) {
-  __shared__ double red[3][kBlock / 64];
+  __shared__ double red[3][kWrenchThreads / 64];
   const int tank = blockIdx.x;
   const RigidArgs& ra = tanks[tank].ra;
   RigidIn in;
   if (threadIdx.x == 0) in = rigid_inputs(&rigid[tank], ro, tank, mode, ra);   // in flight during the sum
-  const int t0 = tank_tile0[tank], nt = tank_tile0[tank + 1] - t0;
+  // a single tank's tiles are 0 .. single_nt - 1 (no table load)
+  const int t0 = single_nt >= 0 ? 0 : tank_tile0[tank];
+  const int nt = single_nt >= 0 ? single_nt : tank_tile0[tank + 1] - t0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double acc3[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nt; b += blockDim.x)
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nt; b += kWrenchThreads)
     for (int d = 0; d < 3; ++d) acc3[d] += partials[3 * (t0 + b) + d];
   for (int d = 0; d < 3; ++d) {
     double t = wave_sum(acc3[d]);
@@ -1343,7 +1359,7 @@ __global__ void __launch_bounds__(kBlock) sph_wrench(const double* __restrict__ 
     double F[3];
     for (int d = 0; d < 3; ++d) {
       double t = 0.0;
-      for (int q = 0; q < kBlock / 64; ++q) t += red[d][q];
+      for (int q = 0; q < kWrenchThreads / 64; ++q) t += red[d][q];
       F[d] = t;
     }
     rigid_step(&rigid[tank], ro, tank, F, mode, ra, in);
@@ -1428,7 +1444,7 @@ __global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict_
                                                        const int* __restrict__ pkey,
                                                        const int4* __restrict__ rng,
                                                        const int* __restrict__ id,
-                                                       const TileRef* __restrict__ tiles,
+                                                       const TileRef* __restrict__ tiles, int single_n,
                                                        const Tank* __restrict__ tanks, int max_nbr,
                                                        int* __restrict__ nbr, int* __restrict__ cnt) {
   constexpr int TP = kBlock / G;
@@ -1437,7 +1453,7 @@ __global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict_
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const TileRef tr = tiles[tile];
+  const TileRef tr = tile_ref<TP>(tiles, tile, single_n);
   const Tank& tk = tanks[tr.tank];
   const int pl = threadIdx.x / G, l = threadIdx.x % G;
   const int p = tr.p0 + pl;
@@ -1736,6 +1752,10 @@ void enqueue_sort(sph_handle* h, hipEvent_t* ev = nullptr) {
   h->since_sort = 0;
 }
 
+// Particle count of a single-tank handle (its tiles are computed in the
+// kernels), -1 for a batch.
+int single_n(const sph_handle* h) { return h->T == 1 ? h->N : -1; }
+
 template <int G>
 void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev) {
   const int c = h->cur, o = h->ord;
@@ -1752,8 +1772,8 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
   hipLaunchKernelGGL(density, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[c]),
                      h->at<float2>(h->L.vel[c]), h->at<float2>(h->L.acc[c]), integrate ? 1 : 0,
                      h->at<float2>(h->L.pos_sort), h->at<int>(h->L.pkey), h->at<int4>(h->L.rng),
-                     h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), h->at<Tank>(h->L.tanks),
-                     h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
+                     h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), single_n(h),
+                     h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status),
                      near_n, h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
   if (build) h->near_valid = true;
@@ -1764,13 +1784,14 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
   hipLaunchKernelGGL(force, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
                      h->at<int4>(h->L.rng), h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]),
-                     h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]), h->at<double>(h->L.partials),
+                     single_n(h), h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]),
+                     h->at<double>(h->L.partials),
                      h->at<int>(h->L.key), h->at<int>(h->L.count), near_n,
                      h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
   h->binned = bin;
   mark(2);
-  hipLaunchKernelGGL(sph_wrench, dim3(h->T), dim3(kBlock), 0, h->stream, h->at<double>(h->L.partials),
-                     h->at<int>(h->L.tile0[v]), h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid),
+  hipLaunchKernelGGL(sph_wrench, dim3(h->T), dim3(kWrenchThreads), 0, h->stream, h->at<double>(h->L.partials),
+                     h->at<int>(h->L.tile0[v]), h->T == 1 ? nt : -1, h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid),
                      h->at<DevRollout>(h->L.rollout), mode);
   mark(3);
 }
@@ -2305,7 +2326,8 @@ int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* co
   auto args = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[h->cur]),
                        h->at<int>(h->L.pkey), h->at<int4>(h->L.rng), h->at<int>(h->L.id[h->ord]),
-                       h->at<TileRef>(h->L.tiles[v]), h->at<Tank>(h->L.tanks), max_nbr, nbr_dev, count_dev);
+                       h->at<TileRef>(h->L.tiles[v]), single_n(h), h->at<Tank>(h->L.tanks), max_nbr, nbr_dev,
+                       count_dev);
   };
   if (v == 0) args(sph_nbr_list<4>);
   else if (v == 1) args(sph_nbr_list<8>);
