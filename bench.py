@@ -184,6 +184,35 @@ def paper_leg(steps: int = 30000):
             "paper_wall_s": 9.9093, "paper_hardware": "i7-13850HX + RTX 2000 Ada laptop, JAX"}
 
 
+def linearization_leg(n_dir: int = 64, steps: int = 400):
+    """Tangent-linear rollout on a rectangular tank of ~8,000 particles: n_dir
+    directions (input torque sequence and initial rigid state) over `steps`
+    steps.  The gradient of the final slosh torque with respect to all 400
+    torques and the 6 initial rigid-state entries takes 406 directions."""
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd.sph import Simulator
+    sc = W.linearization_tank(seed=0, n_steps=steps + 40)
+    dev = torch.device("cuda:0")
+    sim = Simulator.from_scenario(sc, device=dev)
+    u = torch.as_tensor(sc.u_seq)
+    sim.rollout(40, u[:40].contiguous())
+    rng = np.random.default_rng(0)
+    du = (rng.normal(size=(n_dir, steps, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(n_dir, 6)) * 0.01
+    sim.jvp_rollout(8, u[40:48].contiguous(), du[:, :8].copy(), None, dr)   # warm-up
+    t0 = time.perf_counter()
+    sim.jvp_rollout(steps, u[40:40 + steps].contiguous(), du, None, dr)
+    secs = time.perf_counter() - t0
+    n = sc.n_fluid
+    sim.close()
+    return {"workload": f"linearization_tank: rectangle 1.0 x 0.5 m, 50 % fill, {n} fluid + {sc.n_ghost} "
+                        f"boundary particles, free body, {steps} steps",
+            "directions": n_dir, "seconds": secs,
+            "direction_particle_steps_per_s": n_dir * steps * n / secs,
+            "gradient_torques_and_state_s": secs * (steps + 6) / n_dir}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +226,7 @@ def main() -> int:
                     help="tanks of the batched leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-paper-leg", action="store_true")
+    ap.add_argument("--no-linearization-leg", action="store_true")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes per particle of the closed-loop leg (0: sph_autotune chooses)")
     ap.add_argument("--near-lists", type=int, default=-1,
@@ -293,6 +323,8 @@ def main() -> int:
     if args.batch_tanks > 0:
         out["batch"] = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
         status |= out["batch"]["status"]
+    if not args.no_linearization_leg:
+        out["linearization"] = linearization_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out))

@@ -229,6 +229,34 @@ int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* co
 int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
                      const double* theta_ref_dev, int32_t n_ref, float* avg_us);
 
+/* ---- linearization: tangent-linear rollout ---------------------------- */
+/*
+ * Forward-mode derivative of the coupled step (the linearization of
+ * x_{k+1} = f(x_k, u_k) that the paper obtains by automatic differentiation,
+ * Section 3.5; each step follows Algorithm 1 and the symplectic Euler
+ * update), propagated over n_steps steps along n_dir directions (1..64).
+ * A direction perturbs the initial fluid state (ds0_dev, dw0_dev: device
+ * [n_dir][N][2] caller order, or both NULL = zero), the initial rigid state
+ * (drigid0: host [n_dir][6] r_x, r_y, theta, r'_x, r'_y, theta', or NULL =
+ * zero) and the applied force/torque sequence (du_seq_dev: device
+ * [n_dir][n_steps][3], or NULL = zero).  The primal starts from the handle's
+ * state with u_seq_dev [n_steps][3] (or NULL) and theta_ref_dev [n_ref] as
+ * in sph_rollout; the handle's state is not changed.  Neighbour sets are
+ * those of the primal (rebuilt every step).  Single-tank handles only.
+ * Outputs (any may be NULL): wrench host [3] = the slosh wrench of the last
+ * step (body frame), dwrench host [n_dir][3] its derivative along each
+ * direction; rigid host [6] the final rigid state, drigid host [n_dir][6]
+ * its derivatives; ds_dev, dw_dev device [n_dir][N][2] the final fluid
+ * tangents.  ws_dev: caller-owned, 256-byte aligned, of at least
+ * sph_jvp_workspace_bytes.  Synchronises the stream.
+ */
+int sph_jvp_workspace_bytes(sph_handle* h, int32_t n_dir, size_t* bytes);
+int sph_jvp_rollout(sph_handle* h, int32_t n_dir, int32_t n_steps, const float* u_seq_dev,
+                    const float* du_seq_dev, const double* theta_ref_dev, int32_t n_ref,
+                    const double* drigid0, const float* ds0_dev, const float* dw0_dev, void* ws_dev,
+                    size_t ws_bytes, double* wrench, double* dwrench, double* rigid, double* drigid,
+                    float* ds_dev, float* dw_dev);
+
 /* Message for an error code (static storage). */
 const char* sph_strerror(int code);
 

@@ -1695,6 +1695,435 @@ Layout make_layout(const Plan& pl) {
   return L;
 }
 
+// --------------------------------------------------------------------------
+// tangent-linear rollout: the step's derivative along given directions
+// --------------------------------------------------------------------------
+//
+// Forward-mode derivative of the whole coupled step (the linearization the
+// paper obtains by automatic differentiation, Section 3.5), along n_dir
+// directions, each a perturbation of the initial fluid state, the initial
+// rigid state and the sequence of applied forces and torque.  Every
+// quantity of the step carries one tangent per direction, differentiated by
+// hand in the order of the step (product, quotient and chain rules), with
+// the neighbour sets of the primal.  One thread per particle, particles in
+// caller order; the cell list is rebuilt every step as an index (keys, scan,
+// stable scatter), so tangents never move.  Density and force handle
+// kJvpChunk directions per launch and recompute the primal for each chunk.
+
+constexpr int kJvpChunk = 8;
+constexpr int kJvpMaxDir = 64;
+
+struct JvpRigid {     // rigid-body primal, FP64
+  double r[2], th, rd[2], thd, tau;
+  long long step, step0;
+};
+// tangents of the rigid state, per direction: r0, r1, th, rd0, rd1, thd, tau
+constexpr int kJvpRigidT = 7;
+
+// d shape / dq of the cubic spline (shape as in cubic_shape).
+__device__ __forceinline__ float cubic_shape_d(float q) {
+  float a = 2.0f - q;
+  float d = -3.0f * a * a;
+  if (q < 1.0f) {
+    float b = 1.0f - q;
+    d += 12.0f * b * b;
+  }
+  return d;
+}
+
+// d cubic_grad_f / dq.
+__device__ __forceinline__ float cubic_grad_f_d(float q) {
+  if (q < 1.0f) return 9.0f;
+  float a = 2.0f - q;
+  return 6.0f * a / q + 3.0f * a * a / (q * q);
+}
+
+// P/rho^2 and its derivative with respect to rho.
+__device__ __forceinline__ float eos_over_rho2_d(float rho, const Consts& k, float* dpi) {
+  float P, dP;
+  if (k.eos == SPH_EOS_LINEAR) {
+    P = k.k_lin * (rho - k.rho0);
+    dP = k.k_lin;
+  } else {
+    const float x = rho * k.rho0_inv;
+    float xp1;   // x^(gamma - 1)
+    if (k.tgamma > 0) {
+      xp1 = 1.0f;
+      for (int e = 1; e < k.tgamma; ++e) xp1 *= x;
+    } else {
+      xp1 = powf(x, k.tgamma_f - 1.0f);
+    }
+    P = k.B * (xp1 * x - 1.0f);
+    dP = k.B * k.tgamma_f * xp1 * k.rho0_inv;
+  }
+  const float r2 = rho * rho;
+  *dpi = dP / r2 - 2.0f * P / (r2 * rho);
+  return P / r2;
+}
+
+// Index range [lo, hi) of row yy's cells cx-1 .. cx+1 in a start array.
+__device__ __forceinline__ bool jvp_row(const Tank& tk, int cx, int yy, const int* __restrict__ start, int* lo,
+                                        int* hi) {
+  if (yy < 0 || yy >= tk.g.ncy) return false;
+  const int ncx = tk.g.ncx;
+  const int xa = cx > 0 ? cx - 1 : 0, xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
+  const int c = tk.c0 + yy * ncx;
+  *lo = start[c + xa];
+  *hi = start[c + xb + 1];
+  return true;
+}
+
+template <int KC>
+__global__ void __launch_bounds__(kBlock) jvp_density(const float2* __restrict__ s, const float2* __restrict__ ds,
+                                                      int n, int n_dir, int k0, const int* __restrict__ order,
+                                                      const int* __restrict__ cstart,
+                                                      const float2* __restrict__ gpos,
+                                                      const int* __restrict__ gstart,
+                                                      const Tank* __restrict__ tanks, float2* __restrict__ rp,
+                                                      float2* __restrict__ drp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Tank& tk = tanks[0];
+  const Consts& k = tk.k;
+  const float2 si = s[i];
+  float2 dsi[KC];
+  float tf[KC], tg[KC];
+#pragma unroll
+  for (int q = 0; q < KC; ++q) {
+    dsi[q] = k0 + q < n_dir ? ds[(size_t)(k0 + q) * n + i] : make_float2(0.f, 0.f);
+    tf[q] = tg[q] = 0.0f;
+  }
+  float sf = 0.0f, sg = 0.0f;
+  int cx, cy;
+  cell_of(si, tk.g, cx, cy);
+  for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+    int lo, hi;
+    if (jvp_row(tk, cx, yy, cstart, &lo, &hi))
+      for (int e = lo; e < hi; ++e) {
+        const int j = order[e];
+        const float2 sj = s[j];
+        const float dx = si.x - sj.x, dy = si.y - sj.y, d2 = dist2(dx, dy);
+        if (!(d2 < k.R2)) continue;
+        const float r = sqrtf(d2), q = r * k.inv_h;
+        sf += cubic_shape(q);
+        if (j == i || r == 0.0f) continue;
+        const float fac = cubic_shape_d(q) * k.inv_h / r;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          if (k0 + c >= n_dir) break;
+          const float2 dsj = ds[(size_t)(k0 + c) * n + j];
+          tf[c] += fac * (dx * (dsi[c].x - dsj.x) + dy * (dsi[c].y - dsj.y));
+        }
+      }
+    if (jvp_row(tk, cx, yy, gstart, &lo, &hi))
+      for (int e = lo; e < hi; ++e) {
+        const float2 gp = gpos[e];
+        const float dx = si.x - gp.x, dy = si.y - gp.y, d2 = dist2(dx, dy);
+        if (!(d2 < k.R2)) continue;
+        const float r = sqrtf(d2), q = r * k.inv_h;
+        sg += cubic_shape(q);
+        if (r == 0.0f) continue;
+        const float fac = cubic_shape_d(q) * k.inv_h / r;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) tg[c] += fac * (dx * dsi[c].x + dy * dsi[c].y);
+      }
+  }
+  const float rho = k.mass * k.wc * (sf + k.gamma1 * sg);
+  float dpi;
+  const float pi = eos_over_rho2_d(rho, k, &dpi);
+  if (k0 == 0) rp[i] = make_float2(rho, pi);
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    if (k0 + c >= n_dir) break;
+    const float drho = k.mass * k.wc * (tf[c] + k.gamma1 * tg[c]);
+    drp[(size_t)(k0 + c) * n + i] = make_float2(drho, dpi * drho);
+  }
+}
+
+template <int KC>
+__global__ void __launch_bounds__(kBlock) jvp_force(const float2* __restrict__ s, const float2* __restrict__ w,
+                                                    const float2* __restrict__ rp, const float2* __restrict__ ds,
+                                                    const float2* __restrict__ dw, const float2* __restrict__ drp,
+                                                    int n, int n_dir, int k0, const int* __restrict__ order,
+                                                    const int* __restrict__ cstart,
+                                                    const float2* __restrict__ gpos,
+                                                    const int* __restrict__ gstart,
+                                                    const Tank* __restrict__ tanks, float2* __restrict__ a,
+                                                    float2* __restrict__ da, double* __restrict__ part,
+                                                    double* __restrict__ dpart) {
+  __shared__ double red[3 * (1 + KC)][kBlock / 64];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const Tank& tk = tanks[0];
+  const Consts& k = tk.k;
+  float ax = 0.f, ay = 0.f, agx = 0.f, agy = 0.f, fx = 0.f, fy = 0.f, tq = 0.f;
+  float tax[KC], tay[KC], tagx[KC], tagy[KC], tfx[KC], tfy[KC], ttq[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) tax[c] = tay[c] = tagx[c] = tagy[c] = tfx[c] = tfy[c] = ttq[c] = 0.0f;
+  if (valid) {
+    const float2 si = s[i], wi = w[i], mi = rp[i];
+    const float rho_i = mi.x, pi_i = mi.y;
+    float2 dsi[KC], dwi[KC], dmi[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const bool on = k0 + c < n_dir;
+      dsi[c] = on ? ds[(size_t)(k0 + c) * n + i] : make_float2(0.f, 0.f);
+      dwi[c] = on ? dw[(size_t)(k0 + c) * n + i] : make_float2(0.f, 0.f);
+      dmi[c] = on ? drp[(size_t)(k0 + c) * n + i] : make_float2(0.f, 0.f);
+    }
+    int cx, cy;
+    cell_of(si, tk.g, cx, cy);
+    for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+      int lo, hi;
+      if (jvp_row(tk, cx, yy, cstart, &lo, &hi))
+        for (int e = lo; e < hi; ++e) {
+          const int j = order[e];
+          const float2 sj = s[j];
+          const float dx = si.x - sj.x, dy = si.y - sj.y, d2 = dist2(dx, dy);
+          if (!(d2 < k.R2 && d2 > 0.0f)) continue;
+          const float2 wj = w[j], mj = rp[j];
+          const float rn = sqrtf(d2), q = rn * k.inv_h;
+          const float gW = k.dwc * cubic_grad_f(q), gWd = k.dwc * cubic_grad_f_d(q);
+          const float vx = wi.x - wj.x, vy = wi.y - wj.y, vr = vx * dx + vy * dy;
+          const float S = rho_i + mj.x, E = d2 + k.eps_h2, D = S * E;
+          const float visc = k.a2h * vr / D;
+          const float C0 = -(pi_i + mj.y) + visc, coef = C0 * gW;
+          ax += coef * dx;
+          ay += coef * dy;
+#pragma unroll
+          for (int c = 0; c < KC; ++c) {
+            if (k0 + c >= n_dir) break;
+            const size_t o = (size_t)(k0 + c) * n + j;
+            const float2 dsj = ds[o], dwj = dw[o], dmj = drp[o];
+            const float ddx = dsi[c].x - dsj.x, ddy = dsi[c].y - dsj.y;
+            const float rdr = dx * ddx + dy * ddy;
+            const float dgW = gWd * rdr * k.inv_h / rn;
+            const float dvr = (dwi[c].x - dwj.x) * dx + (dwi[c].y - dwj.y) * dy + vx * ddx + vy * ddy;
+            const float dD = (dmi[c].x + dmj.x) * E + S * 2.0f * rdr;
+            const float dvisc = k.a2h * (dvr * D - vr * dD) / (D * D);
+            const float dC0 = -(dmi[c].y + dmj.y) + dvisc;
+            const float dcoef = dC0 * gW + C0 * dgW;
+            tax[c] += dcoef * dx + coef * ddx;
+            tay[c] += dcoef * dy + coef * ddy;
+          }
+        }
+      if (jvp_row(tk, cx, yy, gstart, &lo, &hi))
+        for (int e = lo; e < hi; ++e) {
+          const float2 gp = gpos[e];
+          const float dx = si.x - gp.x, dy = si.y - gp.y, d2 = dist2(dx, dy);
+          if (!(d2 < k.Rs2 && d2 > 0.0f)) continue;
+          const float rn = sqrtf(d2), tt = k.hs - rn;
+          const float gWs = k.dws * tt * tt / rn;
+          const float vr = wi.x * dx + wi.y * dy, mv = fminf(vr, 0.0f);
+          const float vg = k.beta2 / (2.0f * rho_i), E = d2 + k.eps_h2, term = vg * mv / E;
+          const float C0 = -2.0f * pi_i + term, coef = k.mass * C0 * gWs;
+          const float awx = coef * dx, awy = coef * dy;
+          agx += awx;
+          agy += awy;
+          const float Fx = k.mass * awx, Fy = k.mass * awy;
+          fx -= Fx;
+          fy -= Fy;
+          tq -= gp.x * Fy - gp.y * Fx;
+#pragma unroll
+          for (int c = 0; c < KC; ++c) {
+            const float ddx = dsi[c].x, ddy = dsi[c].y;
+            const float rdr = dx * ddx + dy * ddy, drn = rdr / rn, dtt = -drn;
+            const float dgWs = k.dws * (2.0f * tt * dtt / rn - tt * tt * drn / (rn * rn));
+            const float dvr = dwi[c].x * dx + dwi[c].y * dy + wi.x * ddx + wi.y * ddy;
+            const float dmv = vr < 0.0f ? dvr : 0.0f;
+            const float dvg = -k.beta2 / (2.0f * rho_i * rho_i) * dmi[c].x;
+            const float dterm = (dvg * mv + vg * dmv) / E - vg * mv * (2.0f * rdr) / (E * E);
+            const float dcoef = k.mass * ((-2.0f * dmi[c].y + dterm) * gWs + C0 * dgWs);
+            const float dawx = dcoef * dx + coef * ddx, dawy = dcoef * dy + coef * ddy;
+            tagx[c] += dawx;
+            tagy[c] += dawy;
+            const float dFx = k.mass * dawx, dFy = k.mass * dawy;
+            tfx[c] -= dFx;
+            tfy[c] -= dFy;
+            ttq[c] -= gp.x * dFy - gp.y * dFx;
+          }
+        }
+    }
+    if (k0 == 0) a[i] = make_float2(k.mass * ax + agx, k.mass * ay + agy);
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (k0 + c < n_dir)
+        da[(size_t)(k0 + c) * n + i] = make_float2(k.mass * tax[c] + tagx[c], k.mass * tay[c] + tagy[c]);
+  }
+  // workgroup sums of the wall reactions and their tangents, in double
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  auto put = [&](int slot, float v) {
+    const double t = wave_sum((double)v);
+    if (lane == 0) red[slot][wv] = t;
+  };
+  put(0, fx);
+  put(1, fy);
+  put(2, tq);
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    put(3 + 3 * c, tfx[c]);
+    put(4 + 3 * c, tfy[c]);
+    put(5 + 3 * c, ttq[c]);
+  }
+  __syncthreads();
+  for (int slot = threadIdx.x; slot < 3 * (1 + KC); slot += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) t += red[slot][q];
+    if (slot < 3) {
+      if (k0 == 0) part[3 * blockIdx.x + slot] = t;
+    } else {
+      const int c = (slot - 3) / 3, d = (slot - 3) % 3;
+      if (k0 + c < n_dir) dpart[((size_t)blockIdx.x * n_dir + k0 + c) * 3 + d] = t;
+    }
+  }
+}
+
+// One workgroup: wrench sums in a fixed order, then the rigid-body step with
+// its tangents (zero-order-hold law, eq. tankdynamics, symplectic Euler), and
+// the coefficients of the fluid update.  frame: abx, aby, thetadot,
+// thetaddot (binary32, as the step uses them); tframe the same per direction.
+__global__ void __launch_bounds__(kBlock) jvp_rigid(const double* __restrict__ part,
+                                                    const double* __restrict__ dpart, int nb, int n_dir,
+                                                    const Tank* __restrict__ tanks, JvpRigid* st,
+                                                    double* __restrict__ tst, const float* __restrict__ u,
+                                                    const float* __restrict__ du, long long n_steps,
+                                                    const double* __restrict__ theta_ref, int n_ref,
+                                                    float4* __restrict__ frame, float4* __restrict__ tframe,
+                                                    double* __restrict__ wout, double* __restrict__ twout) {
+  __shared__ double F[3], dF[kJvpMaxDir][3];
+  __shared__ double P[8];   // primal: th, thd, tau, c, s, acc x, acc y, theta''
+  const RigidArgs& ra = tanks[0].ra;
+  for (int slot = threadIdx.x; slot < 3 * (1 + n_dir); slot += blockDim.x) {
+    double t = 0.0;
+    if (slot < 3) {
+      for (int b = 0; b < nb; ++b) t += part[3 * b + slot];
+      F[slot] = t;
+    } else {
+      const int c = (slot - 3) / 3, d = (slot - 3) % 3;
+      for (int b = 0; b < nb; ++b) t += dpart[((size_t)b * n_dir + c) * 3 + d];
+      dF[c][d] = t;
+    }
+  }
+  __syncthreads();
+  const long long n = st->step, loc = n - st->step0;
+  const bool have_u = u && loc >= 0 && loc < n_steps;
+  const bool sample = ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && n % ra.ctrl_period == 0;
+  const bool sine = ra.motion == SPH_MOTION_SINE;
+  if (threadIdx.x == 0) {
+    double uu[3] = {0.0, 0.0, 0.0};
+    if (have_u)
+      for (int d = 0; d < 3; ++d) uu[d] = u[loc * 3 + d];
+    double tau = st->tau;
+    if (sample) {
+      double ref = 0.0;
+      if (theta_ref && n_ref > 0) {
+        const long long kk = n / ra.ctrl_period;
+        ref = theta_ref[kk < n_ref ? kk : n_ref - 1];
+      }
+      tau = ra.kp * (ref - st->th) - ra.kd * st->thd;
+    }
+    double th, thd, acc[3];
+    if (sine) {
+      const double om = 2.0 * M_PI * ra.sine_freq, t = (double)n * ra.dt;
+      th = ra.sine_amp * sin(om * t);
+      thd = ra.sine_amp * om * cos(om * t);
+      acc[0] = acc[1] = 0.0;
+      acc[2] = -ra.sine_amp * om * om * sin(om * t);
+    } else {
+      th = st->th;
+      thd = st->thd;
+    }
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    if (!sine) {
+      acc[0] = (cs * F[0] - sn * F[1] + uu[0]) / ra.body_mass;
+      acc[1] = (sn * F[0] + cs * F[1] + uu[1]) / ra.body_mass;
+      acc[2] = (F[2] + uu[2] + tau) / ra.body_inertia;
+    }
+    P[0] = th; P[1] = thd; P[2] = tau; P[3] = cs; P[4] = sn; P[5] = acc[0]; P[6] = acc[1]; P[7] = acc[2];
+    frame[0] = make_float4((float)(cs * acc[0] + sn * acc[1]), (float)(-sn * acc[0] + cs * acc[1]), (float)thd,
+                           (float)acc[2]);
+    for (int d = 0; d < 3; ++d) wout[d] = F[d];
+  }
+  __syncthreads();
+  const double cs = P[3], sn = P[4], ax = P[5], ay = P[6];
+  for (int c = threadIdx.x; c < n_dir; c += blockDim.x) {
+    double* t = tst + (size_t)c * kJvpRigidT;
+    for (int d = 0; d < 3; ++d) twout[3 * c + d] = dF[c][d];
+    if (sine) {
+      tframe[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int q = 0; q < kJvpRigidT; ++q) t[q] = 0.0;
+      continue;
+    }
+    double tu[3] = {0.0, 0.0, 0.0};
+    if (have_u && du)
+      for (int d = 0; d < 3; ++d) tu[d] = du[((size_t)c * n_steps + loc) * 3 + d];
+    double tth = t[2], tthd = t[5], ttau = t[6];
+    if (sample) ttau = -ra.kp * tth - ra.kd * tthd;
+    const double Fx = F[0], Fy = F[1];
+    const double tax = (-sn * tth * Fx + cs * dF[c][0] - cs * tth * Fy - sn * dF[c][1] + tu[0]) / ra.body_mass;
+    const double tay = (cs * tth * Fx + sn * dF[c][0] - sn * tth * Fy + cs * dF[c][1] + tu[1]) / ra.body_mass;
+    const double tal = (dF[c][2] + tu[2] + ttau) / ra.body_inertia;
+    tframe[c] = make_float4((float)(-sn * tth * ax + cs * tax + cs * tth * ay + sn * tay),
+                            (float)(-cs * tth * ax - sn * tax - sn * tth * ay + cs * tay), (float)tthd, (float)tal);
+    // symplectic Euler, velocity first
+    t[3] += ra.dt * tax;
+    t[4] += ra.dt * tay;
+    t[5] += ra.dt * tal;
+    t[0] += ra.dt * t[3];
+    t[1] += ra.dt * t[4];
+    t[2] += ra.dt * t[5];
+    t[6] = ttau;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (sine) {
+      const double om = 2.0 * M_PI * ra.sine_freq, t = (double)(n + 1) * ra.dt;
+      st->th = ra.sine_amp * sin(om * t);
+      st->thd = ra.sine_amp * om * cos(om * t);
+      st->r[0] = st->r[1] = st->rd[0] = st->rd[1] = 0.0;
+    } else {
+      st->rd[0] += ra.dt * P[5];
+      st->rd[1] += ra.dt * P[6];
+      st->thd += ra.dt * P[7];
+      st->r[0] += ra.dt * st->rd[0];
+      st->r[1] += ra.dt * st->rd[1];
+      st->th += ra.dt * st->thd;
+    }
+    st->tau = P[2];
+    st->step = n + 1;
+  }
+}
+
+// Fluid update with the fictitious terms (as fluid_update) and its tangents.
+__global__ void __launch_bounds__(kBlock) jvp_update(float2* __restrict__ s, float2* __restrict__ w,
+                                                     const float2* __restrict__ a, float2* __restrict__ ds,
+                                                     float2* __restrict__ dw, const float2* __restrict__ da,
+                                                     int n, int n_dir, const float4* __restrict__ frame,
+                                                     const float4* __restrict__ tframe, float dt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 f = frame[0];
+  const float2 si = s[i], wi = w[i], ai = a[i];
+  const float om2 = f.z * f.z;
+  for (int c = 0; c < n_dir; ++c) {
+    const float4 tf = tframe[c];
+    const size_t o = (size_t)c * n + i;
+    const float2 tsi = ds[o], twi = dw[o], tai = da[o];
+    const float tdx = tai.x - tf.x + 2.0f * (tf.z * wi.y + f.z * twi.y) + (tf.w * si.y + f.w * tsi.y) +
+                      2.0f * f.z * tf.z * si.x + om2 * tsi.x;
+    const float tdy = tai.y - tf.y - 2.0f * (tf.z * wi.x + f.z * twi.x) - (tf.w * si.x + f.w * tsi.x) +
+                      2.0f * f.z * tf.z * si.y + om2 * tsi.y;
+    const float2 tw = make_float2(twi.x + dt * tdx, twi.y + dt * tdy);
+    dw[o] = tw;
+    ds[o] = make_float2(tsi.x + dt * tw.x, tsi.y + dt * tw.y);
+  }
+  float2 sn = si, wn = wi;
+  fluid_update(sn, wn, ai, Frame{f.x, f.y, f.z, f.w}, dt);
+  s[i] = sn;
+  w[i] = wn;
+}
+
 }  // namespace
 
 struct sph_handle {
@@ -2352,6 +2781,180 @@ const char* sph_strerror(int code) {
     case SPH_E_STATE: return "device status flags set (escaped / non-finite / sort)";
     default: return "unknown error";
   }
+}
+
+}  // extern "C"
+
+// ---- tangent-linear rollout: workspace layout and the C entry points ----
+
+namespace {
+
+struct JvpLayout {
+  size_t s, w, ds, dw, rp, drp, a, da, key, slot, order, count, cstart, part, dpart, st, tst, frame, tframe, wout,
+      twout, total;
+  int nb;
+};
+
+JvpLayout jvp_layout(const sph_handle* h, int n_dir) {
+  JvpLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  const size_t n = (size_t)h->N, K = (size_t)n_dir, C = (size_t)h->C;
+  L.nb = nblocks(h->N);
+  L.s = take(n * 8);
+  L.w = take(n * 8);
+  L.ds = take(K * n * 8);
+  L.dw = take(K * n * 8);
+  L.rp = take(n * 8);
+  L.drp = take(K * n * 8);
+  L.a = take(n * 8);
+  L.da = take(K * n * 8);
+  L.key = take(n * 4);
+  L.slot = take(n * 4);
+  L.order = take(n * 4);
+  L.count = take(C * 4);
+  L.cstart = take((C + 1) * 4);
+  L.part = take((size_t)L.nb * 3 * 8);
+  L.dpart = take((size_t)L.nb * K * 3 * 8);
+  L.st = take(sizeof(JvpRigid));
+  L.tst = take(K * kJvpRigidT * 8);
+  L.frame = take(16);
+  L.tframe = take(K * 16);
+  L.wout = take(3 * 8);
+  L.twout = take(K * 3 * 8);
+  L.total = o;
+  return L;
+}
+
+template <int KC>
+void jvp_chunks(sph_handle* h, const JvpLayout& L, char* ws, int n_dir) {
+  auto at = [&](size_t off) { return reinterpret_cast<void*>(ws + off); };
+  const int nb = L.nb;
+  for (int k0 = 0; k0 < n_dir; k0 += KC)
+    hipLaunchKernelGGL(jvp_density<KC>, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s),
+                       (const float2*)at(L.ds), h->N, n_dir, k0, (const int*)at(L.order), (const int*)at(L.cstart),
+                       h->at<float2>(h->L.gpos), h->at<int>(h->L.gstart), h->at<Tank>(h->L.tanks),
+                       (float2*)at(L.rp), (float2*)at(L.drp));
+  for (int k0 = 0; k0 < n_dir; k0 += KC)
+    hipLaunchKernelGGL(jvp_force<KC>, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s),
+                       (const float2*)at(L.w), (const float2*)at(L.rp), (const float2*)at(L.ds),
+                       (const float2*)at(L.dw), (const float2*)at(L.drp), h->N, n_dir, k0, (const int*)at(L.order),
+                       (const int*)at(L.cstart), h->at<float2>(h->L.gpos), h->at<int>(h->L.gstart),
+                       h->at<Tank>(h->L.tanks), (float2*)at(L.a), (float2*)at(L.da), (double*)at(L.part),
+                       (double*)at(L.dpart));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_jvp_workspace_bytes(sph_handle* h, int32_t n_dir, size_t* bytes) {
+  if (!h || !bytes || n_dir < 1 || n_dir > kJvpMaxDir) return SPH_E_INVAL;
+  *bytes = jvp_layout(h, n_dir).total;
+  return SPH_OK;
+}
+
+int sph_jvp_rollout(sph_handle* h, int32_t n_dir, int32_t n_steps, const float* u_seq_dev, const float* du_seq_dev,
+                    const double* theta_ref_dev, int32_t n_ref, const double* drigid0, const float* ds0_dev,
+                    const float* dw0_dev, void* ws_dev, size_t ws_bytes, double* wrench, double* dwrench,
+                    double* rigid, double* drigid, float* ds_dev, float* dw_dev) {
+  if (!h || h->T != 1 || n_dir < 1 || n_dir > kJvpMaxDir || n_steps < 1 || n_ref < 0 || !ws_dev) return SPH_E_INVAL;
+  if ((ds0_dev == nullptr) != (dw0_dev == nullptr)) return SPH_E_INVAL;
+  const JvpLayout L = jvp_layout(h, n_dir);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws_dev) & 255)) return SPH_E_INVAL;
+  char* ws = reinterpret_cast<char*>(ws_dev);
+  auto at = [&](size_t off) { return reinterpret_cast<void*>(ws + off); };
+  const int n = h->N, nb = L.nb;
+  const size_t tb = (size_t)n_dir * n * 8;
+  // the handle's state in caller order; rigid primal from the handle
+  if (n > 0) {
+    hipLaunchKernelGGL(sph_unpermute, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[h->cur]),
+                       h->at<int>(h->L.id[h->ord]), n, (float2*)at(L.s));
+    hipLaunchKernelGGL(sph_unpermute, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.vel[h->cur]),
+                       h->at<int>(h->L.id[h->ord]), n, (float2*)at(L.w));
+    if (ds0_dev) {
+      HIPCHK(hipMemcpyAsync(at(L.ds), ds0_dev, tb, hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(at(L.dw), dw0_dev, tb, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      HIPCHK(hipMemsetAsync(at(L.ds), 0, tb, h->stream));
+      HIPCHK(hipMemsetAsync(at(L.dw), 0, tb, h->stream));
+    }
+  }
+  DevRigid dr;
+  HIPCHK(hipMemcpyAsync(&dr, h->at<DevRigid>(h->L.rigid), sizeof dr, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  JvpRigid js;
+  js.r[0] = dr.r[0];
+  js.r[1] = dr.r[1];
+  js.th = dr.theta;
+  js.rd[0] = dr.rdot[0];
+  js.rd[1] = dr.rdot[1];
+  js.thd = dr.thetadot;
+  js.tau = dr.tau_ctrl;
+  js.step = dr.step;
+  js.step0 = dr.step;
+  std::vector<double> tst((size_t)n_dir * kJvpRigidT, 0.0);
+  if (drigid0)
+    for (int c = 0; c < n_dir; ++c)
+      for (int q = 0; q < 6; ++q) tst[(size_t)c * kJvpRigidT + q] = drigid0[6 * c + q];
+  HIPCHK(hipMemcpyAsync(at(L.st), &js, sizeof js, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(at(L.tst), tst.data(), tst.size() * 8, hipMemcpyHostToDevice, h->stream));
+  const float dt = (float)h->plan.tanks[0].ra.dt;
+  for (int stp = 0; stp < n_steps; ++stp) {
+    // cell index of the current positions: keys, counts, starts, stable order
+    HIPCHK(hipMemsetAsync(at(L.count), 0, (size_t)h->C * 4, h->stream));
+    if (n > 0) {
+      hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s), n,
+                         h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), (int*)at(L.key), (int*)at(L.count),
+                         (int*)at(L.slot));
+    }
+    hipLaunchKernelGGL(sph_scan, dim3(1), dim3(kScanThreads), 0, h->stream, (int*)at(L.count), h->at<Tank>(h->L.tanks),
+                       1, 0, (int*)at(L.cstart), h->at<unsigned>(h->L.status));
+    if (n > 0) {
+      hipLaunchKernelGGL(sph_scatter, dim3(nb), dim3(kBlock), 0, h->stream, (const int*)at(L.key),
+                         (const int*)at(L.slot), n, (const int*)at(L.cstart), (int*)at(L.order));
+      hipLaunchKernelGGL(sph_cell_order, dim3(nblocks(h->C)), dim3(kBlock), 0, h->stream, (const int*)at(L.cstart),
+                         h->C, (int*)at(L.order));
+    }
+    jvp_chunks<kJvpChunk>(h, L, ws, n_dir);
+    hipLaunchKernelGGL(jvp_rigid, dim3(1), dim3(kBlock), 0, h->stream, (const double*)at(L.part),
+                       (const double*)at(L.dpart), nb, n_dir, h->at<Tank>(h->L.tanks), (JvpRigid*)at(L.st),
+                       (double*)at(L.tst), u_seq_dev, du_seq_dev, (long long)n_steps, theta_ref_dev, n_ref,
+                       (float4*)at(L.frame), (float4*)at(L.tframe), (double*)at(L.wout), (double*)at(L.twout));
+    if (n > 0)
+      hipLaunchKernelGGL(jvp_update, dim3(nb), dim3(kBlock), 0, h->stream, (float2*)at(L.s), (float2*)at(L.w),
+                         (const float2*)at(L.a), (float2*)at(L.ds), (float2*)at(L.dw), (const float2*)at(L.da), n,
+                         n_dir, (const float4*)at(L.frame), (const float4*)at(L.tframe), dt);
+    HIPCHK(hipGetLastError());
+  }
+  if (ds_dev && n > 0) HIPCHK(hipMemcpyAsync(ds_dev, at(L.ds), tb, hipMemcpyDeviceToDevice, h->stream));
+  if (dw_dev && n > 0) HIPCHK(hipMemcpyAsync(dw_dev, at(L.dw), tb, hipMemcpyDeviceToDevice, h->stream));
+  std::vector<double> wo(3), two((size_t)n_dir * 3);
+  HIPCHK(hipMemcpyAsync(wo.data(), at(L.wout), 24, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(two.data(), at(L.twout), two.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(&js, at(L.st), sizeof js, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(tst.data(), at(L.tst), tst.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (wrench)
+    for (int d = 0; d < 3; ++d) wrench[d] = wo[d];
+  if (dwrench)
+    for (size_t q = 0; q < two.size(); ++q) dwrench[q] = two[q];
+  if (rigid) {
+    rigid[0] = js.r[0];
+    rigid[1] = js.r[1];
+    rigid[2] = js.th;
+    rigid[3] = js.rd[0];
+    rigid[4] = js.rd[1];
+    rigid[5] = js.thd;
+  }
+  if (drigid)
+    for (int c = 0; c < n_dir; ++c)
+      for (int q = 0; q < 6; ++q) drigid[6 * c + q] = tst[(size_t)c * kJvpRigidT + q];
+  return SPH_OK;
 }
 
 }  // extern "C"

@@ -241,6 +241,50 @@ class Simulator:
         check(self.L.sph_get_tuning(self.h, C.byref(lanes), C.byref(near)), "sph_get_tuning")
         return int(lanes.value), bool(near.value)
 
+    def jvp_rollout(self, n_steps: int, u_seq=None, du_seq=None, theta_ref=None, drigid0=None, ds0=None, dw0=None,
+                    fluid_tangents: bool = False):
+        """sph_jvp_rollout: derivatives of n_steps steps from the current state
+        along n_dir directions.  du_seq [n_dir, n_steps, 3], drigid0 [n_dir, 6],
+        ds0 / dw0 [n_dir, N, 2] (caller order); at least one of them fixes
+        n_dir.  Returns dict(wrench [3], dwrench [n_dir, 3], rigid [6],
+        drigid [n_dir, 6], ds, dw [n_dir, N, 2] or None).  The state is not
+        advanced."""
+        if self.is_batch:
+            raise ValueError("the tangent-linear rollout takes single-tank handles")
+        sizes = [x.shape[0] for x in (du_seq, drigid0, ds0) if x is not None]
+        if not sizes:
+            raise ValueError("give at least one of du_seq, drigid0, ds0")
+        K = int(sizes[0])
+        if any(k != K for k in sizes):
+            raise ValueError("direction counts differ")
+        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(-1, 3)[:n_steps].contiguous()
+        du = None if du_seq is None else _dev_f32(du_seq, self.device).reshape(K, -1, 3)[:, :n_steps].contiguous()
+        ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
+                                                             device=self.device).reshape(-1).contiguous()
+        dr = None
+        if drigid0 is not None:
+            r = np.ascontiguousarray(np.asarray(drigid0, np.float64).reshape(K, 6))
+            dr = (C.c_double * r.size)(*r.ravel())
+        s0 = None if ds0 is None else _dev_f32(ds0, self.device).reshape(K, self.n, 2).contiguous()
+        w0 = None if dw0 is None else _dev_f32(dw0, self.device).reshape(K, self.n, 2).contiguous()
+        nbytes = C.c_size_t()
+        check(self.L.sph_jvp_workspace_bytes(self.h, K, C.byref(nbytes)), "sph_jvp_workspace_bytes")
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ws = raw[(-raw.data_ptr()) % 256:]
+        wrench, dwrench = (C.c_double * 3)(), (C.c_double * (3 * K))()
+        rigid, drigid = (C.c_double * 6)(), (C.c_double * (6 * K))()
+        ds = torch.empty(K, self.n, 2, device=self.device) if fluid_tangents else None
+        dw = torch.empty(K, self.n, 2, device=self.device) if fluid_tangents else None
+        self._enter()
+        check(self.L.sph_jvp_rollout(self.h, K, int(n_steps), _ptr(u), _ptr(du), _ptr(ref),
+                                     0 if ref is None else int(ref.shape[0]), dr, _ptr(s0), _ptr(w0),
+                                     C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes.value), wrench, dwrench, rigid,
+                                     drigid, _ptr(ds), _ptr(dw)), "sph_jvp_rollout")
+        self._leave()
+        return {"wrench": np.array(list(wrench)), "dwrench": np.array(list(dwrench)).reshape(K, 3),
+                "rigid": np.array(list(rigid)), "drigid": np.array(list(drigid)).reshape(K, 6),
+                "ds": ds, "dw": dw}
+
     def time_kernels(self, n_steps: int, u_seq=None, theta_ref=None):
         """Mean per-launch microseconds over n_steps directly launched steps:
         bin, scan, place (per rebuild), density, force, wrench (per step)."""

@@ -1,0 +1,181 @@
+"""Linearizations of the step: the tangent-linear rollout (sph_jvp_rollout)
+against central differences of the FP64 oracle and of the GPU rollout, and
+the autograd function built on it.
+
+Tolerances: the oracle's central differences (FP64, eps = 1e-3 times a unit
+direction) agree with themselves at eps = 1e-5 to ~1e-4 of the derivative;
+the tangent-linear rollout runs in binary32 like the step, over 100 steps:
+its wrench derivatives must match the oracle's within 5e-3 of the largest
+component of each derivative, its rigid-state derivatives within 1e-3.
+The slosh wrench is a sum of wall forces that cancel (hundreds of N against
+derivatives of order 0.1 N per unit direction), so the GPU rollout's own
+central differences cannot resolve its derivative (binary32 rounding
+dominates); they check the rigid-state derivatives only."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+from oracle import sph as O
+
+pytestmark = pytest.mark.gpu
+
+N_STEPS = 100
+
+
+def _setup(sc, lead=40):
+    from paper_2604_12505_amd.sph import Simulator
+    sim = Simulator.from_scenario(sc)
+    u = torch.as_tensor(sc.u_seq)
+    sim.rollout(lead, u[:lead].contiguous(), theta_ref=sc.theta_ref)
+    ck = sim.get_state()
+    return sim, ck, u[lead:lead + N_STEPS].contiguous()
+
+
+def _oracle_run(sc, ck, u, rigid, ds=None, dw=None):
+    s, w, _, tau, step = ck
+    s = s.cpu().numpy().astype(np.float64)
+    w = w.cpu().numpy().astype(np.float64)
+    if ds is not None:
+        s = s + ds
+        w = w + dw
+    st = O.State(s, w, np.asarray(rigid, np.float64), tau, step)
+    _, lg = O.rollout(sc.params, st, sc.ghosts.astype(np.float64), u.shape[0], u, sc.theta_ref, log_stride=1)
+    return lg["wrench"][-1], st.rigid
+
+
+def _oracle_fd(sc, ck, u, du, dr, eps=1e-3, ds=None, dw=None):
+    r0 = ck[2]
+    wp, rp = _oracle_run(sc, ck, u + eps * du, r0 + eps * dr, None if ds is None else eps * ds,
+                         None if dw is None else eps * dw)
+    wm, rm = _oracle_run(sc, ck, u - eps * du, r0 - eps * dr, None if ds is None else -eps * ds,
+                         None if dw is None else -eps * dw)
+    return (wp - wm) / (2 * eps), (rp - rm) / (2 * eps)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-12)
+
+
+def test_jvp_matches_oracle_differences_on_32_directions():
+    sc = W.random_tank(7, n_steps=200, n_min=1500, n_max=2000, shape="rect")
+    sim, ck, u = _setup(sc)
+    rng = np.random.default_rng(0)
+    K = 32
+    du = (rng.normal(size=(K, N_STEPS, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(K, 6)) * 0.01
+    r = sim.jvp_rollout(N_STEPS, u, du, None, dr)
+    un = u.numpy().astype(np.float64)
+    worst_w = worst_r = 0.0
+    for k in range(K):
+        fw, fr = _oracle_fd(sc, ck, un, du[k].astype(np.float64), dr[k])
+        worst_w = max(worst_w, _rel(r["dwrench"][k], fw))
+        worst_r = max(worst_r, _rel(r["drigid"][k], fr))
+    print("32 directions: wrench rel err", worst_w, "rigid rel err", worst_r)
+    assert worst_w <= 5e-3 and worst_r <= 1e-3
+    sim.close()
+
+
+def test_jvp_rigid_state_matches_gpu_central_differences():
+    sc = W.random_tank(7, n_steps=200, n_min=1500, n_max=2000, shape="rect")
+    sim, ck, u = _setup(sc)
+    s0, w0, r0, tau0, step0 = ck
+    rng = np.random.default_rng(1)
+    K = 8
+    du = (rng.normal(size=(K, N_STEPS, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(K, 6)) * 0.01
+    r = sim.jvp_rollout(N_STEPS, u, du, None, dr)
+    eps = 1e-3
+    for k in range(K):
+        out = []
+        for sgn in (1.0, -1.0):
+            sim.set_state(s0, w0, r0 + sgn * eps * dr[k], tau0, step0)
+            sim.rollout(N_STEPS, u + sgn * eps * torch.as_tensor(du[k]))
+            out.append(sim.get_state()[2])
+        fd = (out[0] - out[1]) / (2 * eps)
+        assert _rel(r["drigid"][k], fd) <= 5e-3, (k, r["drigid"][k], fd)
+    sim.close()
+
+
+def test_jvp_through_the_attitude_controller():
+    # PD law with zero-order hold: the held torque's derivative follows the state's
+    sc = W.closed_loop_circle(0, n_steps=200, dx=0.02)
+    sim, ck, u = _setup(sc, lead=20)
+    rng = np.random.default_rng(2)
+    K = 6
+    du = (rng.normal(size=(K, N_STEPS, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(K, 6)) * 0.01
+    r = sim.jvp_rollout(N_STEPS, u, du, sc.theta_ref, dr)
+    un = u.numpy().astype(np.float64)
+    for k in range(K):
+        fw, fr = _oracle_fd(sc, ck, un, du[k].astype(np.float64), dr[k])
+        assert _rel(r["dwrench"][k], fw) <= 5e-3, (k, r["dwrench"][k], fw)
+        assert _rel(r["drigid"][k], fr) <= 1e-3, (k, r["drigid"][k], fr)
+    sim.close()
+
+
+def test_jvp_along_fluid_directions():
+    sc = W.random_tank(11, n_steps=200, n_min=1500, n_max=2000, shape="circle")
+    sim, ck, u = _setup(sc)
+    rng = np.random.default_rng(3)
+    K = 4
+    n = sim.n
+    ds = rng.normal(size=(K, n, 2)) * 1e-3 * sc.dx
+    dw = rng.normal(size=(K, n, 2)) * 1e-3
+    r = sim.jvp_rollout(N_STEPS, u, None, None, np.zeros((K, 6)), ds0=ds, dw0=dw, fluid_tangents=True)
+    un = u.numpy().astype(np.float64)
+    zero_u = np.zeros((N_STEPS, 3))
+    for k in range(K):
+        # the fluid responds nonlinearly beyond ~1e-5 dx: differences at 1e-2 of the direction
+        fw, fr = _oracle_fd(sc, ck, un, zero_u, np.zeros(6), eps=1e-2, ds=ds[k], dw=dw[k])
+        assert _rel(r["dwrench"][k], fw) <= 5e-3, (k, r["dwrench"][k], fw)
+        assert _rel(r["drigid"][k], fr) <= 5e-3, (k, r["drigid"][k], fr)
+    sim.close()
+
+
+def test_jvp_of_the_rigid_body_alone_is_the_closed_form():
+    p = W.Params(h=0.01, h_spiky=0.01, mass=0.1, dt=1e-3, body_mass=10.0, body_inertia=2.0,
+                 domain_min=(-1, -1), domain_max=(1, 1))
+    from paper_2604_12505_amd.sph import Simulator
+    sim = Simulator(p, np.zeros((0, 2), np.float32), np.zeros((0, 2), np.float32),
+                    np.zeros((0, 2), np.float32), np.zeros(6))
+    n = 50
+    K = 4
+    du = np.zeros((K, n, 3), np.float32)
+    du[0, 7, 2] = 1.0          # torque at step 7
+    du[1, 20, 0] = 1.0         # x-force at step 20
+    dr = np.zeros((K, 6))
+    dr[2, 5] = 1.0             # initial theta rate
+    dr[3, 2] = 1.0             # initial theta
+    r = sim.jvp_rollout(n, torch.zeros(n, 3), du, None, dr)
+    dt, J, M = p.dt, p.body_inertia, p.body_mass
+    assert r["drigid"][0][2] == pytest.approx(dt * dt * (n - 7) / J, rel=1e-10)
+    assert r["drigid"][0][5] == pytest.approx(dt / J, rel=1e-10)
+    assert r["drigid"][1][0] == pytest.approx(dt * dt * (n - 20) / M, rel=1e-10)
+    assert r["drigid"][2][2] == pytest.approx(n * dt, rel=1e-10)
+    assert r["drigid"][3][2] == pytest.approx(1.0, rel=1e-12)
+    sim.close()
+
+
+def test_autograd_function_matches_oracle_directional_derivatives():
+    from paper_2604_12505_amd.linearize import FinalWrench
+    sc = W.random_tank(7, n_steps=100, n_min=1500, n_max=2000, shape="rect")
+    sim, ck, _ = _setup(sc, lead=20)
+    n = 12
+    u = torch.as_tensor(sc.u_seq[20:20 + n]).clone().requires_grad_(True)
+    rigid0 = torch.as_tensor(ck[2], dtype=torch.float64).clone().requires_grad_(True)
+    checkpoint = (ck[0], ck[1], ck[3], ck[4])
+    out = FinalWrench.apply(u, rigid0, sim, checkpoint, None)
+    weights = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float64)   # the slosh torque
+    (out * weights).sum().backward()
+    rng = np.random.default_rng(4)
+    un = u.detach().numpy().astype(np.float64)
+    ckn = (ck[0], ck[1], ck[2], ck[3], ck[4])
+    for _ in range(3):
+        du = rng.normal(size=(n, 3)) * 10.0
+        dr = rng.normal(size=6) * 0.01
+        fw, _ = _oracle_fd(sc, ckn, un, du, dr)
+        pred = float((u.grad.numpy().astype(np.float64) * du).sum() + (rigid0.grad.numpy() * dr).sum())
+        assert pred == pytest.approx(fw[2], rel=5e-3, abs=1e-3 * abs(fw).max())
+    sim.close()

@@ -14,6 +14,8 @@
   follows the textbook second-order step response; the zero-order hold keeps
   the torque constant between control instants; the prescribed rotation is
   A sin(2 pi f t).
+* The oracle's central differences (the reference gradient of the
+  linearization tests) reproduce the rigid body's closed-form sensitivities.
 """
 import math
 
@@ -137,6 +139,30 @@ def test_constant_load_gives_the_discrete_closed_form():
     assert st.rigid[0] == pytest.approx(3.0 / p.body_mass * k, rel=1e-12)
     assert st.rigid[1] == pytest.approx(-1.0 / p.body_mass * k, rel=1e-12)
     assert st.rigid[5] == pytest.approx(0.25 / p.body_inertia * n * p.dt, rel=1e-12)
+
+
+def test_oracle_differences_give_the_rigid_sensitivities():
+    # the central differences that serve as the reference gradient of the
+    # linearization tests, on the rigid body alone: d theta_n / d u_k =
+    # dt^2 (n - k) / J and d theta_n / d thetadot_0 = n dt under symplectic Euler
+    p = _rigid_only()
+    n, k, eps = 60, 13, 1e-3
+
+    def final(u, rigid0):
+        st = O.State(np.zeros((0, 2)), np.zeros((0, 2)), np.asarray(rigid0, np.float64))
+        O.rollout(p, st, np.zeros((0, 2)), n, u)
+        return st.rigid
+
+    u0 = np.zeros((n, 3), np.float32)
+    du = np.zeros((n, 3), np.float32)
+    du[k, 2] = 1.0
+    d = (final(u0 + eps * du, np.zeros(6)) - final(u0 - eps * du, np.zeros(6))) / (2 * eps)
+    assert d[2] == pytest.approx(p.dt ** 2 * (n - k) / p.body_inertia, rel=1e-6)
+    assert d[5] == pytest.approx(p.dt / p.body_inertia, rel=1e-6)
+    r = np.zeros(6)
+    r[5] = 1.0
+    d = (final(u0, eps * r) - final(u0, -eps * r)) / (2 * eps)
+    assert d[2] == pytest.approx(n * p.dt, rel=1e-9)
 
 
 def test_pd_attitude_law_tracks_textbook_step_response():

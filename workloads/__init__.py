@@ -309,6 +309,30 @@ def random_tank(seed: int, n_steps: int = 5000, n_min: int = 2000, n_max: int = 
                     shape=shape, tank_size=size)
 
 
+def linearization_tank(seed: int = 0, n_steps: int = 400, n_fluid: int = 8000) -> Scenario:
+    """Rectangular 1.0 x 0.5 m tank, 50 % fill, about n_fluid particles, free
+    spacecraft (m = 1000 kg, J = 500 kg m^2) under a 5-tone multisine torque
+    of amplitude 20 N m: the workload of the linearization measurements."""
+    rng = np.random.default_rng(seed)
+    W_, H = 1.0, 0.5
+    dx = math.sqrt(0.5 * W_ * H / n_fluid)
+    dx = W_ / round(W_ / dx)
+    fill_rows = max(1, int(round(0.5 * H / dx)))
+    fluid, ghosts = rect_tank(W_, H, dx, fill_rows, 3, rng, 0.01)
+    p = _fluid_params(dx)
+    p.motion = MOTION_FREE
+    p.ctrl = CTRL_NONE
+    p.body_mass, p.body_inertia = 1000.0, 500.0
+    pad = 5 * dx
+    p.domain_min = (-W_ / 2 - pad, -H / 2 - pad)
+    p.domain_max = (W_ / 2 + pad, H / 2 + pad)
+    t = np.arange(n_steps) * p.dt
+    u = np.zeros((n_steps, 3), np.float64)
+    u[:, 2] = multisine(rng, 5, 20.0, t)
+    return Scenario("linearization_tank", p, _f32(fluid), np.zeros((fluid.shape[0], 2), np.float32),
+                    _f32(ghosts), np.zeros(6), n_steps, _f32(u), dx=dx, fill=0.5, shape="rect", tank_size=W_)
+
+
 def rect_sweep(k: int, seed: int = 0, n_steps: int = 200) -> Scenario:
     """The rectangular workload refined by 2^k in spacing (N = 1600 * 4^k)."""
     return plain_rect(seed=seed, n_steps=n_steps, dx=0.0125 / (2 ** k))
