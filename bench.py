@@ -185,10 +185,11 @@ def paper_leg(steps: int = 30000):
 
 
 def linearization_leg(n_dir: int = 64, steps: int = 400):
-    """Tangent-linear rollout on a rectangular tank of ~8,000 particles: n_dir
-    directions (input torque sequence and initial rigid state) over `steps`
-    steps.  The gradient of the final slosh torque with respect to all 400
-    torques and the 6 initial rigid-state entries takes 406 directions."""
+    """Linearizations on a rectangular tank of ~8,000 particles over `steps`
+    steps: the tangent-linear rollout along n_dir directions (input torque
+    sequence and initial rigid state; the gradient of the final slosh torque
+    with respect to all 400 torques and 6 initial rigid-state entries would
+    take 406 of them), and the same gradient from one adjoint rollout."""
     import torch
     import workloads as W
     from paper_2604_12505_amd.sph import Simulator
@@ -204,13 +205,20 @@ def linearization_leg(n_dir: int = 64, steps: int = 400):
     t0 = time.perf_counter()
     sim.jvp_rollout(steps, u[40:40 + steps].contiguous(), du, None, dr)
     secs = time.perf_counter() - t0
+    # the whole gradient of the final slosh torque in one adjoint rollout,
+    # the state kept every 20 steps
+    sim.vjp_rollout(8, [0.0, 0.0, 1.0], u[40:48].contiguous(), every=20)   # warm-up
+    t0 = time.perf_counter()
+    sim.vjp_rollout(steps, [0.0, 0.0, 1.0], u[40:40 + steps].contiguous(), every=20)
+    adj = time.perf_counter() - t0
     n = sc.n_fluid
     sim.close()
     return {"workload": f"linearization_tank: rectangle 1.0 x 0.5 m, 50 % fill, {n} fluid + {sc.n_ghost} "
                         f"boundary particles, free body, {steps} steps",
             "directions": n_dir, "seconds": secs,
             "direction_particle_steps_per_s": n_dir * steps * n / secs,
-            "gradient_torques_and_state_s": secs * (steps + 6) / n_dir}
+            "gradient_by_tangents_s": secs * (steps + 6) / n_dir,
+            "adjoint_gradient_s": adj, "adjoint_checkpoint_every": 20}
 
 
 def main() -> int:

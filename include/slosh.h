@@ -257,6 +257,30 @@ int sph_jvp_rollout(sph_handle* h, int32_t n_dir, int32_t n_steps, const float* 
                     size_t ws_bytes, double* wrench, double* dwrench, double* rigid, double* drigid,
                     float* ds_dev, float* dw_dev);
 
+/* ---- linearization: adjoint rollout ------------------------------------ */
+/*
+ * Reverse-mode derivative (the transpose of sph_jvp_rollout) of n_steps
+ * steps from the handle's state: given the adjoint wbar (host [3]) of the
+ * slosh wrench of the last step, optionally rbar (host [6]) of the final
+ * rigid state and sbar_dev / wbar_dev (device [N][2], both or neither) of
+ * the final fluid state, returns the adjoints of the inputs: grad_rigid0
+ * (host [6]) of the initial rigid state, grad_u_dev (device [n_steps][3]) of
+ * the applied force/torque sequence, grad_s0_dev / grad_w0_dev (device
+ * [N][2], caller order) of the initial fluid state; any output may be NULL.
+ * wrench (host [3]) receives the primal wrench of the last step.  The
+ * state is stored every `every` steps on a forward sweep; the reverse sweep
+ * recomputes one segment at a time and reverses its steps.  Inputs as in
+ * sph_jvp_rollout; the handle's state is not changed; single-tank handles
+ * only.  ws_dev: caller-owned, 256-byte aligned, of at least
+ * sph_vjp_workspace_bytes(h, n_steps, every).  Synchronises the stream.
+ */
+int sph_vjp_workspace_bytes(sph_handle* h, int32_t n_steps, int32_t every, size_t* bytes);
+int sph_vjp_rollout(sph_handle* h, int32_t n_steps, int32_t every, const float* u_seq_dev,
+                    const double* theta_ref_dev, int32_t n_ref, const double* wbar, const double* rbar,
+                    const float* sbar_dev, const float* wbar_dev, void* ws_dev, size_t ws_bytes,
+                    double* wrench, double* grad_rigid0, float* grad_u_dev, float* grad_s0_dev,
+                    float* grad_w0_dev);
+
 /* Message for an error code (static storage). */
 const char* sph_strerror(int code);
 

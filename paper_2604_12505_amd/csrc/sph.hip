@@ -48,6 +48,7 @@
 // a tank gives the same bits alone or in a batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -2124,6 +2125,281 @@ __global__ void __launch_bounds__(kBlock) jvp_update(float2* __restrict__ s, flo
   w[i] = wn;
 }
 
+// --------------------------------------------------------------------------
+// adjoint rollout: reverse-mode derivatives of the step
+// --------------------------------------------------------------------------
+//
+// The transpose of the tangent-linear step: given the adjoints of a step's
+// outputs (fluid state, rigid state) and of the wrench it evaluated, the
+// adjoints of its inputs and of its applied force/torque.  The primal of a
+// step is recomputed from its stored input state with the kernels above
+// (no directions), then the step is reversed in the opposite order: fluid
+// update, rigid body (one thread), forces (a gather over each particle's
+// neighbours: a pair term f_ij enters a_i with +m and a_j with -m, so its
+// adjoint is m (abar_i - abar_j) and each particle accumulates the
+// derivatives with respect to its own variables), equation of state and
+// density (a gather with rhobar_i + rhobar_j).
+
+// Reverse of the fluid update x' = (s + dt w', w + dt D).  sb, wb hold the
+// adjoints of (s', w') on entry and those of (s, w) on exit; ab receives
+// the adjoint of a_sph; fpart[block] the sums of the frame adjoints (abx,
+// aby, thetadot, theta'').
+__global__ void __launch_bounds__(kBlock) vjp_update(const float2* __restrict__ s, const float2* __restrict__ w,
+                                                     float2* __restrict__ sb, float2* __restrict__ wb,
+                                                     float2* __restrict__ ab, int n,
+                                                     const float4* __restrict__ frame, float dt,
+                                                     double* __restrict__ fpart) {
+  __shared__ double red[4][kBlock / 64];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
+  if (i < n) {
+    const float4 f = frame[0];
+    const float2 si = s[i], wi = w[i], sbp = sb[i], wbp = wb[i];
+    const float2 wt = make_float2(wbp.x + dt * sbp.x, wbp.y + dt * sbp.y);
+    const float2 Db = make_float2(dt * wt.x, dt * wt.y);
+    ab[i] = Db;
+    const float om2 = f.z * f.z;
+    wb[i] = make_float2(wt.x - 2.0f * f.z * Db.y, wt.y + 2.0f * f.z * Db.x);
+    sb[i] = make_float2(sbp.x - f.w * Db.y + om2 * Db.x, sbp.y + f.w * Db.x + om2 * Db.y);
+    g0 = -Db.x;
+    g1 = -Db.y;
+    g2 = 2.0f * (wi.y * Db.x - wi.x * Db.y) + 2.0f * f.z * (si.x * Db.x + si.y * Db.y);
+    g3 = si.y * Db.x - si.x * Db.y;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const float g[4] = {g0, g1, g2, g3};
+  for (int d = 0; d < 4; ++d) {
+    const double t = wave_sum((double)g[d]);
+    if (lane == 0) red[d][wv] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) t += red[threadIdx.x][q];
+    fpart[4 * blockIdx.x + threadIdx.x] = t;
+  }
+}
+
+// Reverse of the rigid-body step, one thread.  st: the step's input rigid
+// state; F: the wrench the step evaluated; rb [7] (r0, r1, th, rd0, rd1,
+// thd, tau): adjoints of the output state on entry, of the input state on
+// exit; fb [3]: adjoint of the wrench (plus wbar at the last step); ub: the
+// adjoint of the step's applied force/torque.
+__global__ void vjp_rigid(const double* __restrict__ fpart, int nb, const Tank* __restrict__ tanks,
+                          const JvpRigid* __restrict__ st, const double* __restrict__ F,
+                          const float* __restrict__ u, long long n_steps, const double* __restrict__ theta_ref,
+                          int n_ref, double* __restrict__ rb, double* __restrict__ fb,
+                          float* __restrict__ ub, const double* __restrict__ wbar, int last) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const RigidArgs& ra = tanks[0].ra;
+  double fr[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < 4; ++d) fr[d] += fpart[4 * b + d];
+  const long long n = st->step, loc = n - st->step0;
+  double Fb[3] = {0.0, 0.0, 0.0};
+  if (last)
+    for (int d = 0; d < 3; ++d) Fb[d] = wbar[d];
+  if (ra.motion == SPH_MOTION_SINE) {
+    // prescribed motion: the rigid state and the frame depend on time only
+    for (int q = 0; q < kJvpRigidT; ++q) rb[q] = 0.0;
+    for (int d = 0; d < 3; ++d) fb[d] = Fb[d];
+    if (ub && loc >= 0 && loc < n_steps)
+      for (int d = 0; d < 3; ++d) ub[loc * 3 + d] = 0.0f;
+    return;
+  }
+  double uu[3] = {0.0, 0.0, 0.0};
+  if (u && loc >= 0 && loc < n_steps)
+    for (int d = 0; d < 3; ++d) uu[d] = u[loc * 3 + d];
+  const bool sample = ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && n % ra.ctrl_period == 0;
+  double tau = st->tau;
+  if (sample) {
+    double ref = 0.0;
+    if (theta_ref && n_ref > 0) {
+      const long long kk = n / ra.ctrl_period;
+      ref = theta_ref[kk < n_ref ? kk : n_ref - 1];
+    }
+    tau = ra.kp * (ref - st->th) - ra.kd * st->thd;
+  }
+  double sn, cs;
+  sincos(st->th, &sn, &cs);
+  const double M = ra.body_mass, J = ra.body_inertia, dt = ra.dt;
+  const double ax = (cs * F[0] - sn * F[1] + uu[0]) / M;
+  const double ay = (sn * F[0] + cs * F[1] + uu[1]) / M;
+  // output state: r' = r + dt rd', th' = th + dt thd', rd' = rd + dt a, thd' = thd + dt alpha, tau' = tau
+  const double thb = rb[2], thdp = rb[5] + dt * rb[2];
+  const double rd0p = rb[3] + dt * rb[0], rd1p = rb[4] + dt * rb[1];
+  const double alb = dt * thdp + fr[3];
+  double axb = dt * rd0p, ayb = dt * rd1p;
+  // frame: abx = c ax + s ay, aby = -s ax + c ay, thetadot, theta''
+  axb += cs * fr[0] - sn * fr[1];
+  ayb += sn * fr[0] + cs * fr[1];
+  double cb = ax * fr[0] + ay * fr[1], sb = ay * fr[0] - ax * fr[1];
+  // alpha = (F_tau + u_tau + tau) / J
+  Fb[2] += alb / J;
+  const double taub = alb / J + rb[6];
+  // a = (R F + u) / M
+  Fb[0] += (cs * axb + sn * ayb) / M;
+  Fb[1] += (-sn * axb + cs * ayb) / M;
+  cb += (F[0] * axb + F[1] * ayb) / M;
+  sb += (-F[1] * axb + F[0] * ayb) / M;
+  if (ub && loc >= 0 && loc < n_steps) {
+    ub[loc * 3 + 0] = (float)(axb / M);
+    ub[loc * 3 + 1] = (float)(ayb / M);
+    ub[loc * 3 + 2] = (float)(alb / J);
+  }
+  double th_in = thb - sn * cb + cs * sb;
+  double thd_in = thdp + fr[2];
+  double tau_in = taub;
+  if (sample) {
+    th_in -= ra.kp * taub;
+    thd_in -= ra.kd * taub;
+    tau_in = 0.0;
+  }
+  rb[0] = rb[0];
+  rb[1] = rb[1];
+  rb[2] = th_in;
+  rb[3] = rd0p;
+  rb[4] = rd1p;
+  rb[5] = thd_in;
+  rb[6] = tau_in;
+  for (int d = 0; d < 3; ++d) fb[d] = Fb[d];
+}
+
+// Reverse of the forces and wall reactions: accumulates into sb, wb the
+// derivatives with respect to each particle's own position and velocity,
+// and writes rhob = the adjoint of its density (through the pair terms, the
+// wall terms and the equation of state).
+__global__ void __launch_bounds__(kBlock) vjp_force(const float2* __restrict__ s, const float2* __restrict__ w,
+                                                    const float2* __restrict__ rp, const float2* __restrict__ ab,
+                                                    const double* __restrict__ fb, int n,
+                                                    const int* __restrict__ order, const int* __restrict__ cstart,
+                                                    const float2* __restrict__ gpos, const int* __restrict__ gstart,
+                                                    const Tank* __restrict__ tanks, float2* __restrict__ sb,
+                                                    float2* __restrict__ wb, float* __restrict__ rhob) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Tank& tk = tanks[0];
+  const Consts& k = tk.k;
+  const float2 si = s[i], wi = w[i], mi = rp[i], abi = ab[i];
+  const float rho_i = mi.x, pi_i = mi.y;
+  const float Fbx = (float)fb[0], Fby = (float)fb[1], Tb = (float)fb[2];
+  float sbx = 0.f, sby = 0.f, wbx = 0.f, wby = 0.f, rhb = 0.f, pib = 0.f;
+  int cx, cy;
+  cell_of(si, tk.g, cx, cy);
+  for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+    int lo, hi;
+    if (jvp_row(tk, cx, yy, cstart, &lo, &hi))
+      for (int e = lo; e < hi; ++e) {
+        const int j = order[e];
+        const float2 sj = s[j];
+        const float dx = si.x - sj.x, dy = si.y - sj.y, d2 = dist2(dx, dy);
+        if (!(d2 < k.R2 && d2 > 0.0f)) continue;
+        const float2 wj = w[j], mj = rp[j], abj = ab[j];
+        const float fbx = k.mass * (abi.x - abj.x), fby = k.mass * (abi.y - abj.y);
+        const float rn = sqrtf(d2), q = rn * k.inv_h;
+        const float g = cubic_grad_f(q), gW = k.dwc * g;
+        const float vx = wi.x - wj.x, vy = wi.y - wj.y, vr = vx * dx + vy * dy;
+        const float S = rho_i + mj.x, E = d2 + k.eps_h2, D = S * E;
+        const float visc = k.a2h * vr / D, C0 = -(pi_i + mj.y) + visc, coef = C0 * gW;
+        const float coefb = fbx * dx + fby * dy;
+        float rbx = coef * fbx, rby = coef * fby;
+        const float C0b = coefb * gW, gWb = coefb * C0;
+        pib -= C0b;
+        const float vrb = C0b * k.a2h / D, Db = -C0b * visc / D;
+        rhb += Db * E;
+        float d2b = Db * S;
+        wbx += vrb * dx;
+        wby += vrb * dy;
+        rbx += vrb * vx;
+        rby += vrb * vy;
+        const float rnb = gWb * k.dwc * cubic_grad_f_d(q) * k.inv_h;
+        d2b += rnb / (2.0f * rn);
+        sbx += rbx + 2.0f * d2b * dx;
+        sby += rby + 2.0f * d2b * dy;
+      }
+    if (jvp_row(tk, cx, yy, gstart, &lo, &hi))
+      for (int e = lo; e < hi; ++e) {
+        const float2 gp = gpos[e];
+        const float dx = si.x - gp.x, dy = si.y - gp.y, d2 = dist2(dx, dy);
+        if (!(d2 < k.Rs2 && d2 > 0.0f)) continue;
+        // adjoint of the wall term h (acceleration of the fluid particle)
+        const float hbx = abi.x - k.mass * Fbx + k.mass * Tb * gp.y;
+        const float hby = abi.y - k.mass * Fby - k.mass * Tb * gp.x;
+        const float rn = sqrtf(d2), tt = k.hs - rn, gWs = k.dws * tt * tt / rn;
+        const float vr = wi.x * dx + wi.y * dy, mv = fminf(vr, 0.0f);
+        const float vg = k.beta2 / (2.0f * rho_i), E = d2 + k.eps_h2, term = vg * mv / E;
+        const float C0 = -2.0f * pi_i + term, coef = k.mass * C0 * gWs;
+        const float coefb = hbx * dx + hby * dy;
+        float rbx = coef * hbx, rby = coef * hby;
+        const float C0b = coefb * k.mass * gWs, gWsb = coefb * k.mass * C0;
+        pib -= 2.0f * C0b;
+        const float vgb = C0b * mv / E, mvb = C0b * vg / E;
+        float d2b = -C0b * term / E;
+        rhb -= vgb * vg / rho_i;
+        const float vrb = vr < 0.0f ? mvb : 0.0f;
+        wbx += vrb * dx;
+        wby += vrb * dy;
+        rbx += vrb * wi.x;
+        rby += vrb * wi.y;
+        const float ttb = gWsb * k.dws * 2.0f * tt / rn;
+        const float rnb = -gWsb * k.dws * tt * tt / (rn * rn) - ttb;
+        d2b += rnb / (2.0f * rn);
+        sbx += rbx + 2.0f * d2b * dx;
+        sby += rby + 2.0f * d2b * dy;
+      }
+  }
+  float dpi;
+  eos_over_rho2_d(rho_i, k, &dpi);
+  rhob[i] = rhb + dpi * pib;
+  const float2 s0 = sb[i], w0 = wb[i];
+  sb[i] = make_float2(s0.x + sbx, s0.y + sby);
+  wb[i] = make_float2(w0.x + wbx, w0.y + wby);
+}
+
+// Reverse of the density sums: sb_i += m sigma sum_j (rhob_i + rhob_j) dW/dr r_ij / r
+// (+ the ghost terms with rhob_i alone).
+__global__ void __launch_bounds__(kBlock) vjp_density(const float2* __restrict__ s, const float* __restrict__ rhob,
+                                                      int n, const int* __restrict__ order,
+                                                      const int* __restrict__ cstart, const float2* __restrict__ gpos,
+                                                      const int* __restrict__ gstart, const Tank* __restrict__ tanks,
+                                                      float2* __restrict__ sb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Tank& tk = tanks[0];
+  const Consts& k = tk.k;
+  const float2 si = s[i];
+  const float rbi = rhob[i], ms = k.mass * k.wc;
+  float sbx = 0.f, sby = 0.f;
+  int cx, cy;
+  cell_of(si, tk.g, cx, cy);
+  for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+    int lo, hi;
+    if (jvp_row(tk, cx, yy, cstart, &lo, &hi))
+      for (int e = lo; e < hi; ++e) {
+        const int j = order[e];
+        const float2 sj = s[j];
+        const float dx = si.x - sj.x, dy = si.y - sj.y, d2 = dist2(dx, dy);
+        if (!(d2 < k.R2 && d2 > 0.0f)) continue;
+        const float r = sqrtf(d2);
+        const float fac = ms * (rbi + rhob[j]) * cubic_shape_d(r * k.inv_h) * k.inv_h / r;
+        sbx += fac * dx;
+        sby += fac * dy;
+      }
+    if (jvp_row(tk, cx, yy, gstart, &lo, &hi))
+      for (int e = lo; e < hi; ++e) {
+        const float2 gp = gpos[e];
+        const float dx = si.x - gp.x, dy = si.y - gp.y, d2 = dist2(dx, dy);
+        if (!(d2 < k.R2 && d2 > 0.0f)) continue;
+        const float r = sqrtf(d2);
+        const float fac = ms * k.gamma1 * rbi * cubic_shape_d(r * k.inv_h) * k.inv_h / r;
+        sbx += fac * dx;
+        sby += fac * dy;
+      }
+  }
+  const float2 s0 = sb[i];
+  sb[i] = make_float2(s0.x + sbx, s0.y + sby);
+}
+
 }  // namespace
 
 struct sph_handle {
@@ -2954,6 +3230,240 @@ int sph_jvp_rollout(sph_handle* h, int32_t n_dir, int32_t n_steps, const float* 
   if (drigid)
     for (int c = 0; c < n_dir; ++c)
       for (int q = 0; q < 6; ++q) drigid[6 * c + q] = tst[(size_t)c * kJvpRigidT + q];
+  return SPH_OK;
+}
+
+}  // extern "C"
+
+// ---- adjoint rollout: workspace layout and the C entry points ----
+
+namespace {
+
+struct VjpLayout {
+  JvpLayout P;   // primal working arrays (no directions)
+  size_t ck_s, ck_w, ck_st, seg_s, seg_w, seg_st, st_prev, sb, wb, ab, rhob, fpart, rb, fb, wbar, total;
+  int n_ck, every;
+};
+
+VjpLayout vjp_layout(const sph_handle* h, int n_steps, int every) {
+  VjpLayout V;
+  V.P = jvp_layout(h, 0);
+  size_t o = V.P.total;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  const size_t n = (size_t)h->N;
+  V.every = every;
+  V.n_ck = (n_steps + every - 1) / every;
+  V.ck_s = take((size_t)V.n_ck * n * 8);
+  V.ck_w = take((size_t)V.n_ck * n * 8);
+  V.ck_st = take((size_t)V.n_ck * sizeof(JvpRigid));
+  V.seg_s = take((size_t)every * n * 8);
+  V.seg_w = take((size_t)every * n * 8);
+  V.seg_st = take((size_t)every * sizeof(JvpRigid));
+  V.st_prev = take(sizeof(JvpRigid));
+  V.sb = take(n * 8);
+  V.wb = take(n * 8);
+  V.ab = take(n * 8);
+  V.rhob = take(n * 4);
+  V.fpart = take((size_t)V.P.nb * 4 * 8);
+  V.rb = take(kJvpRigidT * 8);
+  V.fb = take(3 * 8);
+  V.wbar = take(3 * 8);
+  V.total = o;
+  return V;
+}
+
+// One primal step of the derivative rollouts (caller order): cell index,
+// density, forces, rigid body (advances the rigid state, writes the frame
+// and the wrench), and, if `update`, the fluid update.
+int derivative_primal_step(sph_handle* h, const JvpLayout& L, char* ws, const float* u, int n_steps,
+                           const double* ref, int n_ref, bool update) {
+  auto at = [&](size_t off) { return reinterpret_cast<void*>(ws + off); };
+  const int n = h->N, nb = L.nb;
+  HIPCHK(hipMemsetAsync(at(L.count), 0, (size_t)h->C * 4, h->stream));
+  if (n > 0)
+    hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s), n, h->at<int>(h->L.owner),
+                       h->at<Tank>(h->L.tanks), (int*)at(L.key), (int*)at(L.count), (int*)at(L.slot));
+  hipLaunchKernelGGL(sph_scan, dim3(1), dim3(kScanThreads), 0, h->stream, (int*)at(L.count), h->at<Tank>(h->L.tanks), 1,
+                     0, (int*)at(L.cstart), h->at<unsigned>(h->L.status));
+  if (n > 0) {
+    hipLaunchKernelGGL(sph_scatter, dim3(nb), dim3(kBlock), 0, h->stream, (const int*)at(L.key),
+                       (const int*)at(L.slot), n, (const int*)at(L.cstart), (int*)at(L.order));
+    hipLaunchKernelGGL(sph_cell_order, dim3(nblocks(h->C)), dim3(kBlock), 0, h->stream, (const int*)at(L.cstart), h->C,
+                       (int*)at(L.order));
+  }
+  hipLaunchKernelGGL(jvp_density<1>, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s), (const float2*)nullptr,
+                     n, 0, 0, (const int*)at(L.order), (const int*)at(L.cstart), h->at<float2>(h->L.gpos),
+                     h->at<int>(h->L.gstart), h->at<Tank>(h->L.tanks), (float2*)at(L.rp), (float2*)nullptr);
+  hipLaunchKernelGGL(jvp_force<1>, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s), (const float2*)at(L.w),
+                     (const float2*)at(L.rp), (const float2*)nullptr, (const float2*)nullptr, (const float2*)nullptr,
+                     n, 0, 0, (const int*)at(L.order), (const int*)at(L.cstart), h->at<float2>(h->L.gpos),
+                     h->at<int>(h->L.gstart), h->at<Tank>(h->L.tanks), (float2*)at(L.a), (float2*)nullptr,
+                     (double*)at(L.part), (double*)nullptr);
+  hipLaunchKernelGGL(jvp_rigid, dim3(1), dim3(kBlock), 0, h->stream, (const double*)at(L.part), (const double*)nullptr,
+                     nb, 0, h->at<Tank>(h->L.tanks), (JvpRigid*)at(L.st), (double*)nullptr, u, (const float*)nullptr,
+                     (long long)n_steps, ref, n_ref, (float4*)at(L.frame), (float4*)nullptr, (double*)at(L.wout),
+                     (double*)nullptr);
+  if (update && n > 0)
+    hipLaunchKernelGGL(jvp_update, dim3(nb), dim3(kBlock), 0, h->stream, (float2*)at(L.s), (float2*)at(L.w),
+                       (const float2*)at(L.a), (float2*)nullptr, (float2*)nullptr, (const float2*)nullptr, n, 0,
+                       (const float4*)at(L.frame), (const float4*)nullptr, (float)h->plan.tanks[0].ra.dt);
+  HIPCHK(hipGetLastError());
+  return SPH_OK;
+}
+
+// The handle's state into the derivative rollouts' primal arrays.
+int derivative_start(sph_handle* h, const JvpLayout& L, char* ws) {
+  auto at = [&](size_t off) { return reinterpret_cast<void*>(ws + off); };
+  const int n = h->N, nb = L.nb;
+  if (n > 0) {
+    hipLaunchKernelGGL(sph_unpermute, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[h->cur]),
+                       h->at<int>(h->L.id[h->ord]), n, (float2*)at(L.s));
+    hipLaunchKernelGGL(sph_unpermute, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.vel[h->cur]),
+                       h->at<int>(h->L.id[h->ord]), n, (float2*)at(L.w));
+  }
+  DevRigid dr;
+  HIPCHK(hipMemcpyAsync(&dr, h->at<DevRigid>(h->L.rigid), sizeof dr, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  JvpRigid js;
+  js.r[0] = dr.r[0];
+  js.r[1] = dr.r[1];
+  js.th = dr.theta;
+  js.rd[0] = dr.rdot[0];
+  js.rd[1] = dr.rdot[1];
+  js.thd = dr.thetadot;
+  js.tau = dr.tau_ctrl;
+  js.step = dr.step;
+  js.step0 = dr.step;
+  HIPCHK(hipMemcpyAsync(at(L.st), &js, sizeof js, hipMemcpyHostToDevice, h->stream));
+  return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_vjp_workspace_bytes(sph_handle* h, int32_t n_steps, int32_t every, size_t* bytes) {
+  if (!h || !bytes || n_steps < 1 || every < 1) return SPH_E_INVAL;
+  *bytes = vjp_layout(h, n_steps, every).total;
+  return SPH_OK;
+}
+
+int sph_vjp_rollout(sph_handle* h, int32_t n_steps, int32_t every, const float* u_seq_dev,
+                    const double* theta_ref_dev, int32_t n_ref, const double* wbar, const double* rbar,
+                    const float* sbar_dev, const float* wbar_dev, void* ws_dev, size_t ws_bytes, double* wrench,
+                    double* grad_rigid0, float* grad_u_dev, float* grad_s0_dev, float* grad_w0_dev) {
+  if (!h || h->T != 1 || n_steps < 1 || every < 1 || n_ref < 0 || !ws_dev || !wbar) return SPH_E_INVAL;
+  if ((sbar_dev == nullptr) != (wbar_dev == nullptr)) return SPH_E_INVAL;
+  const VjpLayout V = vjp_layout(h, n_steps, every);
+  if (ws_bytes < V.total || (reinterpret_cast<uintptr_t>(ws_dev) & 255)) return SPH_E_INVAL;
+  const JvpLayout& L = V.P;
+  char* ws = reinterpret_cast<char*>(ws_dev);
+  auto at = [&](size_t off) { return reinterpret_cast<void*>(ws + off); };
+  const int n = h->N, nb = L.nb;
+  const size_t fb_bytes = (size_t)n * 8;
+  int rc = derivative_start(h, L, ws);
+  if (rc) return rc;
+  // forward sweep, keeping the state every `every` steps
+  for (int k = 0; k < n_steps; ++k) {
+    if (k % every == 0) {
+      const int c = k / every;
+      if (n > 0) {
+        HIPCHK(hipMemcpyAsync(ws + V.ck_s + c * fb_bytes, at(L.s), fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(ws + V.ck_w + c * fb_bytes, at(L.w), fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+      }
+      HIPCHK(hipMemcpyAsync(ws + V.ck_st + c * sizeof(JvpRigid), at(L.st), sizeof(JvpRigid), hipMemcpyDeviceToDevice,
+                            h->stream));
+    }
+    if ((rc = derivative_primal_step(h, L, ws, u_seq_dev, n_steps, theta_ref_dev, n_ref, true)) != SPH_OK) return rc;
+  }
+  std::vector<double> wo(3);
+  HIPCHK(hipMemcpyAsync(wo.data(), at(L.wout), 24, hipMemcpyDeviceToHost, h->stream));
+  // adjoints of the outputs
+  double r7[kJvpRigidT] = {0, 0, 0, 0, 0, 0, 0};
+  if (rbar)
+    for (int q = 0; q < 6; ++q) r7[q] = rbar[q];
+  HIPCHK(hipMemcpyAsync(at(V.rb), r7, sizeof r7, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(at(V.wbar), wbar, 24, hipMemcpyHostToDevice, h->stream));
+  if (n > 0) {
+    if (sbar_dev) {
+      HIPCHK(hipMemcpyAsync(at(V.sb), sbar_dev, fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(at(V.wb), wbar_dev, fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      HIPCHK(hipMemsetAsync(at(V.sb), 0, fb_bytes, h->stream));
+      HIPCHK(hipMemsetAsync(at(V.wb), 0, fb_bytes, h->stream));
+    }
+  }
+  // reverse sweep, one segment at a time: recompute its states, then reverse its steps
+  for (int c = V.n_ck - 1; c >= 0; --c) {
+    const int k0 = c * every, k1 = std::min(n_steps, k0 + every);
+    if (n > 0) {
+      HIPCHK(hipMemcpyAsync(at(L.s), ws + V.ck_s + c * fb_bytes, fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(at(L.w), ws + V.ck_w + c * fb_bytes, fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+    }
+    HIPCHK(hipMemcpyAsync(at(L.st), ws + V.ck_st + c * sizeof(JvpRigid), sizeof(JvpRigid), hipMemcpyDeviceToDevice,
+                          h->stream));
+    for (int k = k0; k < k1; ++k) {
+      const int q = k - k0;
+      if (n > 0) {
+        HIPCHK(hipMemcpyAsync(ws + V.seg_s + q * fb_bytes, at(L.s), fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(ws + V.seg_w + q * fb_bytes, at(L.w), fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+      }
+      HIPCHK(hipMemcpyAsync(ws + V.seg_st + q * sizeof(JvpRigid), at(L.st), sizeof(JvpRigid), hipMemcpyDeviceToDevice,
+                            h->stream));
+      if (k + 1 < k1 &&
+          (rc = derivative_primal_step(h, L, ws, u_seq_dev, n_steps, theta_ref_dev, n_ref, true)) != SPH_OK)
+        return rc;
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const int q = k - k0;
+      if (n > 0) {
+        HIPCHK(hipMemcpyAsync(at(L.s), ws + V.seg_s + q * fb_bytes, fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(at(L.w), ws + V.seg_w + q * fb_bytes, fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+      }
+      HIPCHK(hipMemcpyAsync(at(L.st), ws + V.seg_st + q * sizeof(JvpRigid), sizeof(JvpRigid),
+                            hipMemcpyDeviceToDevice, h->stream));
+      HIPCHK(hipMemcpyAsync(at(V.st_prev), at(L.st), sizeof(JvpRigid), hipMemcpyDeviceToDevice, h->stream));
+      // the step's primal: index, density, forces, wrench, frame (no update)
+      if ((rc = derivative_primal_step(h, L, ws, u_seq_dev, n_steps, theta_ref_dev, n_ref, false)) != SPH_OK)
+        return rc;
+      if (n > 0)
+        hipLaunchKernelGGL(vjp_update, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s),
+                           (const float2*)at(L.w), (float2*)at(V.sb), (float2*)at(V.wb), (float2*)at(V.ab), n,
+                           (const float4*)at(L.frame), (float)h->plan.tanks[0].ra.dt, (double*)at(V.fpart));
+      else
+        HIPCHK(hipMemsetAsync(at(V.fpart), 0, (size_t)nb * 4 * 8, h->stream));
+      hipLaunchKernelGGL(vjp_rigid, dim3(1), dim3(64), 0, h->stream, (const double*)at(V.fpart), nb,
+                         h->at<Tank>(h->L.tanks), (const JvpRigid*)at(V.st_prev), (const double*)at(L.wout),
+                         u_seq_dev, (long long)n_steps, theta_ref_dev, n_ref, (double*)at(V.rb), (double*)at(V.fb),
+                         grad_u_dev, (const double*)at(V.wbar), k == n_steps - 1 ? 1 : 0);
+      if (n > 0) {
+        hipLaunchKernelGGL(vjp_force, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s),
+                           (const float2*)at(L.w), (const float2*)at(L.rp), (const float2*)at(V.ab),
+                           (const double*)at(V.fb), n, (const int*)at(L.order), (const int*)at(L.cstart),
+                           h->at<float2>(h->L.gpos), h->at<int>(h->L.gstart), h->at<Tank>(h->L.tanks),
+                           (float2*)at(V.sb), (float2*)at(V.wb), (float*)at(V.rhob));
+        hipLaunchKernelGGL(vjp_density, dim3(nb), dim3(kBlock), 0, h->stream, (const float2*)at(L.s),
+                           (const float*)at(V.rhob), n, (const int*)at(L.order), (const int*)at(L.cstart),
+                           h->at<float2>(h->L.gpos), h->at<int>(h->L.gstart), h->at<Tank>(h->L.tanks),
+                           (float2*)at(V.sb));
+      }
+      HIPCHK(hipGetLastError());
+    }
+  }
+  if (grad_s0_dev && n > 0)
+    HIPCHK(hipMemcpyAsync(grad_s0_dev, at(V.sb), fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+  if (grad_w0_dev && n > 0)
+    HIPCHK(hipMemcpyAsync(grad_w0_dev, at(V.wb), fb_bytes, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(r7, at(V.rb), sizeof r7, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (wrench)
+    for (int d = 0; d < 3; ++d) wrench[d] = wo[d];
+  if (grad_rigid0)
+    for (int q = 0; q < 6; ++q) grad_rigid0[q] = r7[q];
   return SPH_OK;
 }
 

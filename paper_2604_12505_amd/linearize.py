@@ -4,11 +4,12 @@
 frame) of the last step of an n-step rollout, as a function of the applied
 force/torque sequence u [n, 3] and the initial rigid state [6], from a fixed
 fluid checkpoint.  Its forward runs the library's rollout (``sph_set_state``,
-``sph_rollout``, ``sph_slosh_wrench``); its backward contracts the incoming
-gradient with directional derivatives from ``sph_jvp_rollout`` along every
-input element (forward mode, 64 directions per call), so no intermediate
-states are stored.  Argument marshalling only: every derivative is computed
-by the library's kernels.
+``sph_rollout``, ``sph_slosh_wrench``); its backward is one adjoint rollout
+(``sph_vjp_rollout``: reverse mode, the state kept every 20 steps and each
+segment recomputed).  ``wrench_jacobian`` assembles the full Jacobian from
+the tangent-linear rollout (``sph_jvp_rollout``, forward mode, 64 directions
+per call).  Argument marshalling only: every derivative is computed by the
+library's kernels.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ import numpy as np
 import torch
 
 MAX_DIR = 64
+EVERY = 20   # steps between stored states of the adjoint rollout
 
 
 def input_directions(n_steps: int, first: int, count: int):
@@ -63,10 +65,12 @@ class FinalWrench(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         u_seq, rigid0 = ctx.saved_tensors
+        s, w, tau, step = ctx.checkpoint
         n = int(u_seq.shape[0])
-        jac = wrench_jacobian(ctx.sim, ctx.checkpoint, u_seq.detach(), rigid0.detach().cpu().double().numpy(),
-                              ctx.theta_ref)
-        g = jac.T @ grad_out.detach().cpu().double().numpy()
-        gu = torch.as_tensor(g[:3 * n].reshape(n, 3), dtype=u_seq.dtype, device=u_seq.device)
-        gr = torch.as_tensor(g[3 * n:], dtype=rigid0.dtype, device=rigid0.device)
+        sim = ctx.sim
+        sim.set_state(s, w, rigid0.detach().cpu().double().numpy(), tau, step)
+        g = sim.vjp_rollout(n, grad_out.detach().cpu().double().numpy(), u_seq.detach(), ctx.theta_ref,
+                            every=EVERY)
+        gu = g["u"].to(device=u_seq.device, dtype=u_seq.dtype)
+        gr = torch.as_tensor(g["rigid0"], dtype=rigid0.dtype, device=rigid0.device)
         return gu, gr, None, None, None

@@ -285,6 +285,39 @@ class Simulator:
                 "rigid": np.array(list(rigid)), "drigid": np.array(list(drigid)).reshape(K, 6),
                 "ds": ds, "dw": dw}
 
+    def vjp_rollout(self, n_steps: int, wbar, u_seq=None, theta_ref=None, rbar=None, sbar=None, wbar_fluid=None,
+                    every: int = 20):
+        """sph_vjp_rollout: adjoints of the inputs of n_steps steps from the
+        current state, given the adjoint wbar [3] of the last step's wrench
+        (and optionally rbar [6], sbar / wbar_fluid [N, 2] of the final
+        state).  Returns dict(wrench [3], rigid0 [6], u [n_steps, 3],
+        s0 [N, 2], w0 [N, 2]).  The state is not advanced."""
+        if self.is_batch:
+            raise ValueError("the adjoint rollout takes single-tank handles")
+        u = None if u_seq is None else _dev_f32(u_seq, self.device).reshape(-1, 3)[:n_steps].contiguous()
+        ref = None if theta_ref is None else torch.as_tensor(theta_ref, dtype=torch.float64,
+                                                             device=self.device).reshape(-1).contiguous()
+        wb = (C.c_double * 3)(*[float(x) for x in np.asarray(wbar, np.float64).ravel()])
+        rb = None if rbar is None else (C.c_double * 6)(*[float(x) for x in np.asarray(rbar, np.float64).ravel()])
+        sb = None if sbar is None else _dev_f32(sbar, self.device).reshape(self.n, 2).contiguous()
+        wf = None if wbar_fluid is None else _dev_f32(wbar_fluid, self.device).reshape(self.n, 2).contiguous()
+        nbytes = C.c_size_t()
+        check(self.L.sph_vjp_workspace_bytes(self.h, int(n_steps), int(every), C.byref(nbytes)),
+              "sph_vjp_workspace_bytes")
+        raw = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ws = raw[(-raw.data_ptr()) % 256:]
+        wrench, g_r = (C.c_double * 3)(), (C.c_double * 6)()
+        g_u = torch.zeros(n_steps, 3, device=self.device)
+        g_s = torch.zeros(self.n, 2, device=self.device)
+        g_w = torch.zeros(self.n, 2, device=self.device)
+        self._enter()
+        check(self.L.sph_vjp_rollout(self.h, int(n_steps), int(every), _ptr(u), _ptr(ref),
+                                     0 if ref is None else int(ref.shape[0]), wb, rb, _ptr(sb), _ptr(wf),
+                                     C.c_void_p(ws.data_ptr()), C.c_size_t(nbytes.value), wrench, g_r, _ptr(g_u),
+                                     _ptr(g_s), _ptr(g_w)), "sph_vjp_rollout")
+        self._leave()
+        return {"wrench": np.array(list(wrench)), "rigid0": np.array(list(g_r)), "u": g_u, "s0": g_s, "w0": g_w}
+
     def time_kernels(self, n_steps: int, u_seq=None, theta_ref=None):
         """Mean per-launch microseconds over n_steps directly launched steps:
         bin, scan, place (per rebuild), density, force, wrench (per step)."""

@@ -1,6 +1,8 @@
 """Linearizations of the step: the tangent-linear rollout (sph_jvp_rollout)
-against central differences of the FP64 oracle and of the GPU rollout, and
-the autograd function built on it.
+against central differences of the FP64 oracle and of the GPU rollout; the
+adjoint rollout (sph_vjp_rollout) against the tangent-linear one (the
+transpose identity <ybar, J d> = <J^T ybar, d>), the oracle and the rigid
+body's closed form; and the autograd function built on them.
 
 Tolerances: the oracle's central differences (FP64, eps = 1e-3 times a unit
 direction) agree with themselves at eps = 1e-5 to ~1e-4 of the derivative;
@@ -178,4 +180,105 @@ def test_autograd_function_matches_oracle_directional_derivatives():
         fw, _ = _oracle_fd(sc, ckn, un, du, dr)
         pred = float((u.grad.numpy().astype(np.float64) * du).sum() + (rigid0.grad.numpy() * dr).sum())
         assert pred == pytest.approx(fw[2], rel=5e-3, abs=1e-3 * abs(fw).max())
+    sim.close()
+
+
+def _dot(a, b):
+    return float((np.asarray(a, np.float64) * np.asarray(b, np.float64)).sum())
+
+
+@pytest.mark.parametrize("part", ["wrench", "rigid", "fluid"])
+def test_adjoint_is_the_transpose_of_the_tangent(part):
+    # <ybar, J d> = <J^T ybar, d> for random d and random output adjoints ybar
+    sc = W.random_tank(7, n_steps=200, n_min=1500, n_max=2000, shape="rect")
+    sim, ck, u = _setup(sc)
+    n = sim.n
+    rng = np.random.default_rng({"wrench": 5, "rigid": 6, "fluid": 7}[part])
+    du = (rng.normal(size=(1, N_STEPS, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(1, 6)) * 0.01
+    ds = rng.normal(size=(1, n, 2)) * 1e-3 * sc.dx
+    dw = rng.normal(size=(1, n, 2)) * 1e-3
+    t = sim.jvp_rollout(N_STEPS, u, du, None, dr, ds0=ds, dw0=dw, fluid_tangents=True)
+    wbar = rng.normal(size=3) if part == "wrench" else np.zeros(3)
+    rbar = rng.normal(size=6) if part == "rigid" else None
+    sbar = rng.normal(size=(n, 2)).astype(np.float32) if part == "fluid" else None
+    wfl = rng.normal(size=(n, 2)).astype(np.float32) if part == "fluid" else None
+    g = sim.vjp_rollout(N_STEPS, wbar, u, None, rbar=rbar, sbar=sbar, wbar_fluid=wfl)
+    lhs = _dot(wbar, t["dwrench"][0])
+    if rbar is not None:
+        lhs += _dot(rbar, t["drigid"][0])
+    if sbar is not None:
+        lhs += _dot(sbar, t["ds"][0].cpu().numpy()) + _dot(wfl, t["dw"][0].cpu().numpy())
+    rhs = (_dot(g["rigid0"], dr[0]) + _dot(g["u"].cpu().numpy(), du[0]) + _dot(g["s0"].cpu().numpy(), ds[0])
+           + _dot(g["w0"].cpu().numpy(), dw[0]))
+    print(part, "<ybar, J d>", lhs, "<J^T ybar, d>", rhs)
+    assert rhs == pytest.approx(lhs, rel=1e-3)
+    sim.close()
+
+
+def test_adjoint_matches_oracle_directional_derivatives():
+    sc = W.random_tank(7, n_steps=200, n_min=1500, n_max=2000, shape="rect")
+    sim, ck, u = _setup(sc)
+    g = sim.vjp_rollout(N_STEPS, [0.0, 0.0, 1.0], u)    # gradient of the final slosh torque
+    gu = g["u"].cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(8)
+    un = u.numpy().astype(np.float64)
+    for _ in range(8):
+        du = rng.normal(size=(N_STEPS, 3)) * 10.0
+        dr = rng.normal(size=6) * 0.01
+        fw, _ = _oracle_fd(sc, ck, un, du, dr)
+        pred = _dot(gu, du) + _dot(g["rigid0"], dr)
+        # as for the tangent: within 5e-3 of the largest component of the derivative
+        assert abs(pred - fw[2]) <= 5e-3 * abs(fw).max(), (pred, fw)
+    sim.close()
+
+
+def test_adjoint_through_the_attitude_controller():
+    sc = W.closed_loop_circle(0, n_steps=200, dx=0.02)
+    sim, ck, u = _setup(sc, lead=20)
+    rng = np.random.default_rng(9)
+    du = (rng.normal(size=(1, N_STEPS, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(1, 6)) * 0.01
+    t = sim.jvp_rollout(N_STEPS, u, du, sc.theta_ref, dr)
+    wbar, rbar = rng.normal(size=3), rng.normal(size=6)
+    g = sim.vjp_rollout(N_STEPS, wbar, u, sc.theta_ref, rbar=rbar)
+    lhs = _dot(wbar, t["dwrench"][0]) + _dot(rbar, t["drigid"][0])
+    rhs = _dot(g["rigid0"], dr[0]) + _dot(g["u"].cpu().numpy(), du[0])
+    assert rhs == pytest.approx(lhs, rel=1e-3)
+    sim.close()
+
+
+def test_adjoint_of_the_rigid_body_alone_is_the_closed_form():
+    p = W.Params(h=0.01, h_spiky=0.01, mass=0.1, dt=1e-3, body_mass=10.0, body_inertia=2.0,
+                 domain_min=(-1, -1), domain_max=(1, 1))
+    from paper_2604_12505_amd.sph import Simulator
+    sim = Simulator(p, np.zeros((0, 2), np.float32), np.zeros((0, 2), np.float32),
+                    np.zeros((0, 2), np.float32), np.zeros(6))
+    n = 50
+    rbar = np.zeros(6)
+    rbar[2] = 1.0      # adjoint of the final theta
+    g = sim.vjp_rollout(n, np.zeros(3), torch.zeros(n, 3), rbar=rbar, every=7)
+    dt, J = p.dt, p.body_inertia
+    gu = g["u"].cpu().numpy()
+    for k in (0, 7, 20, 49):
+        assert gu[k, 2] == pytest.approx(dt * dt * (n - k) / J, rel=1e-6)
+    assert g["rigid0"][5] == pytest.approx(n * dt, rel=1e-10)
+    assert g["rigid0"][2] == pytest.approx(1.0, rel=1e-12)
+    sim.close()
+
+
+def test_autograd_backward_equals_the_tangent_jacobian():
+    from paper_2604_12505_amd.linearize import FinalWrench, wrench_jacobian
+    sc = W.random_tank(7, n_steps=100, n_min=1500, n_max=2000, shape="rect")
+    sim, ck, _ = _setup(sc, lead=20)
+    n = 30
+    u = torch.as_tensor(sc.u_seq[20:20 + n]).clone().requires_grad_(True)
+    rigid0 = torch.as_tensor(ck[2], dtype=torch.float64).clone().requires_grad_(True)
+    checkpoint = (ck[0], ck[1], ck[3], ck[4])
+    wt = torch.tensor([0.3, -0.5, 1.0], dtype=torch.float64)
+    (FinalWrench.apply(u, rigid0, sim, checkpoint, None) * wt).sum().backward()
+    jac = wrench_jacobian(sim, checkpoint, u.detach(), ck[2])
+    g = jac.T @ wt.numpy()
+    got = np.concatenate([u.grad.numpy().astype(np.float64).ravel(), rigid0.grad.numpy()])
+    assert np.abs(got - g).max() <= 1e-3 * np.abs(g).max()
     sim.close()
