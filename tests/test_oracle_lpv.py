@@ -1,0 +1,89 @@
+"""Pins of the LPV surrogate oracle (oracle/lpv.py).
+
+* With the scheduling-dependent matrices zero the model is the LTI system
+  (A0, B0, C0, D = 0): its response equals scipy.signal.dlsim's.
+* With A1, B1, C1 nonzero but a scheduling map whose last layer is zero,
+  p_k = b3 is constant: the response equals the LTI system A0 + b3 A1, ...
+* The loss of the exact parameters on their own outputs is the
+  regularization alone; the central-difference gradient of a quadratic
+  special case matches its closed form.
+* BFR is 100 % for an exact fit and 0 % for the mean.
+"""
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import lpv as L
+
+
+def _random_params(rng, scale=0.3):
+    v = rng.normal(size=L.N_PARAM) * scale
+    P = L.unpack(v)
+    P["A0"][:] = 0.5 * np.eye(4) + 0.1 * rng.normal(size=(4, 4))
+    return L.pack(P)
+
+
+def test_parameter_count():
+    assert L.N_THETA == 137 and L.N_PARAM == 141
+
+
+def test_lti_special_case_is_dlsim():
+    rng = np.random.default_rng(0)
+    P = L.unpack(_random_params(rng))
+    for name in ("A1", "B1", "C1"):
+        P[name][:] = 0.0
+    v = L.pack(P)
+    u = rng.normal(size=(60, 3))
+    _, y_ref, _ = signal.dlsim((P["A0"], P["B0"], P["C0"], np.zeros((3, 3)), 1.0), u, x0=P["x0"])
+    assert np.allclose(L.simulate(v, u), y_ref, rtol=1e-12, atol=1e-12)
+
+
+def test_constant_schedule_is_a_shifted_lti_system():
+    rng = np.random.default_rng(1)
+    P = L.unpack(_random_params(rng))
+    P["W3"][:] = 0.0
+    P["b3"][:] = 0.7
+    v = L.pack(P)
+    u = rng.normal(size=(40, 3))
+    A = P["A0"] + 0.7 * P["A1"]
+    B = P["B0"] + 0.7 * P["B1"]
+    Cm = P["C0"] + 0.7 * P["C1"]
+    _, y_ref, _ = signal.dlsim((A, B, Cm, np.zeros((3, 3)), 1.0), u, x0=P["x0"])
+    assert np.allclose(L.simulate(v, u), y_ref, rtol=1e-10, atol=1e-10)
+
+
+def test_loss_of_the_true_parameters_is_the_regularization():
+    rng = np.random.default_rng(2)
+    v = _random_params(rng)
+    u = rng.normal(size=(30, 3))
+    y = L.simulate(v, u)
+    s2, sx = 1e-3, 1e-2
+    expect = 0.5 * s2 * (v[:L.N_THETA] ** 2).sum() + 0.5 * sx * (v[L.N_THETA:] ** 2).sum()
+    assert L.loss(v, u, y, s2, sx) == pytest.approx(expect, rel=1e-12)
+
+
+def test_fd_gradient_of_the_output_map_closed_form():
+    # A = 0, B = 0: y_0 = C0 x0 and y_k = 0 after; J = |y0 - C0 x0|^2 / N
+    rng = np.random.default_rng(3)
+    P = L.unpack(np.zeros(L.N_PARAM))
+    P["C0"][:] = rng.normal(size=(3, 4))
+    P["x0"][:] = rng.normal(size=4)
+    v = L.pack(P)
+    N = 5
+    u = np.zeros((N, 3))
+    y = np.zeros((N, 3))
+    y[0] = rng.normal(size=3)
+    g = L.loss_grad_fd(v, u, y, 0.0, 0.0)
+    r = P["C0"] @ P["x0"] - y[0]
+    gC0 = 2.0 / N * np.outer(r, P["x0"])
+    gx0 = 2.0 / N * P["C0"].T @ r
+    G = L.unpack(g)
+    assert np.allclose(G["C0"], gC0, atol=1e-7)
+    assert np.allclose(G["x0"], gx0, atol=1e-7)
+
+
+def test_bfr_limits():
+    rng = np.random.default_rng(4)
+    y = rng.normal(size=(50, 3))
+    assert np.allclose(L.bfr(y, y), 100.0)
+    assert np.allclose(L.bfr(y, np.tile(y.mean(0), (50, 1))), 0.0)
