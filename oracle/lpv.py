@@ -87,3 +87,139 @@ def bfr(y, yh):
     num = np.sqrt(((y - yh) ** 2).sum(0))
     den = np.sqrt(((y - y.mean(0)) ** 2).sum(0))
     return 100.0 * (1.0 - num / den)
+
+
+# ----------------------------------------------------------------------------
+# loss gradient by reverse-mode automatic differentiation (plain PyTorch CPU
+# ops in FP64: the paper computes its gradients by automatic differentiation,
+# Section 4), and the two optimizers the paper chains (Section 4): Adam
+# (Kingma and Ba, Algorithm 1) and limited-memory BFGS (two-loop recursion,
+# Nocedal and Wright Algorithm 7.4, with a backtracking Armijo line search,
+# Algorithm 3.1).
+# ----------------------------------------------------------------------------
+
+def loss_and_grad(v, u, y, sigma2, sigmax):
+    import torch
+    t = torch.tensor(np.asarray(v, np.float64), dtype=torch.float64, requires_grad=True)
+    U = torch.as_tensor(np.asarray(u, np.float64))
+    Y = torch.as_tensor(np.asarray(y, np.float64))
+    o = 0
+    P = {}
+    for name, shape in SIZES:
+        k = int(np.prod(shape))
+        P[name] = t[o:o + k].reshape(shape)
+        o += k
+    x = t[o:o + NX]
+    err = torch.zeros((), dtype=torch.float64)
+    for k in range(U.shape[0]):
+        z = torch.cat([x, U[k]])
+        h1 = torch.tanh(P["W1"] @ z + P["b1"])
+        h2 = torch.tanh(P["W2"] @ h1 + P["b2"])
+        p = (P["W3"] @ h2 + P["b3"])[0]
+        yh = (P["C0"] + p * P["C1"]) @ x
+        err = err + ((Y[k] - yh) ** 2).sum()
+        x = (P["A0"] + p * P["A1"]) @ x + (P["B0"] + p * P["B1"]) @ U[k]
+    J = err / U.shape[0] + 0.5 * sigma2 * (t[:N_THETA] ** 2).sum() + 0.5 * sigmax * (t[N_THETA:] ** 2).sum()
+    J.backward()
+    return float(J), t.grad.numpy().copy()
+
+
+def lti_mask():
+    """1 for the entries an LTI fit adjusts (A0, B0, C0, x0), 0 elsewhere."""
+    m = np.zeros(N_PARAM)
+    o = 0
+    for name, shape in SIZES:
+        k = int(np.prod(shape))
+        if name in ("A0", "B0", "C0"):
+            m[o:o + k] = 1.0
+        o += k
+    m[N_THETA:] = 1.0
+    return m
+
+
+def adam(v, u, y, sigma2, sigmax, iters, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, mask=None):
+    """Adam from zero moments; returns (parameters, loss at the last evaluated point)."""
+    v = np.array(v, np.float64)
+    m = np.zeros_like(v)
+    s = np.zeros_like(v)
+    f = None
+    for t in range(1, iters + 1):
+        f, g = loss_and_grad(v, u, y, sigma2, sigmax)
+        if mask is not None:
+            g = g * mask
+        m = beta1 * m + (1 - beta1) * g
+        s = beta2 * s + (1 - beta2) * g * g
+        mh = m / (1 - beta1 ** t)
+        sh = s / (1 - beta2 ** t)
+        v = v - lr * mh / (np.sqrt(sh) + eps)
+    return v, f
+
+
+def lbfgs(fun, v, iters, memory=10, c1=1e-4, gtol=1e-10, ftol=1e-13, max_backtracks=40, mask=None):
+    """L-BFGS with a backtracking Armijo line search.
+
+    fun(v) -> (f, g).  Each outer iteration: direction d = -H g by the
+    two-loop recursion over the stored pairs (initial matrix gamma I with
+    gamma = s'y / y'y of the newest pair; steepest descent if the result is
+    not a descent direction, which also clears the memory); trial steps
+    alpha = 1 (1 / max(1, |g|_2) on the first iteration), halved until
+    f(v + alpha d) <= f + c1 alpha g'd.  A pair (s, y) is stored only if
+    s'y > 1e-10 |s| |y|.  Stops after ``iters`` accepted steps, when
+    |g|_inf <= gtol, when the decrease f_old - f <= ftol max(|f_old|, |f|),
+    or when the line search fails.  Returns (v, f, accepted_steps, status):
+    status 1 gtol, 2 ftol, 3 line search failed, 0 iteration limit.
+    """
+    v = np.array(v, np.float64)
+    f, g = fun(v)
+    if mask is not None:
+        g = g * mask
+    S, Y, R = [], [], []
+    k = 0
+    while k < iters:
+        if np.max(np.abs(g)) <= gtol:
+            return v, f, k, 1
+        q = g.copy()
+        alphas = []
+        for s_i, y_i, r_i in zip(reversed(S), reversed(Y), reversed(R)):
+            a = r_i * float(s_i @ q)
+            alphas.append(a)
+            q = q - a * y_i
+        gamma = float(S[-1] @ Y[-1]) / float(Y[-1] @ Y[-1]) if S else 1.0
+        r = gamma * q
+        for (s_i, y_i, r_i), a in zip(zip(S, Y, R), reversed(alphas)):
+            b = r_i * float(y_i @ r)
+            r = r + s_i * (a - b)
+        d = -r
+        gtd = float(g @ d)
+        if not gtd < 0.0:
+            S, Y, R = [], [], []
+            d = -g
+            gtd = -float(g @ g)
+        alpha = 1.0 / max(1.0, float(np.sqrt(g @ g))) if k == 0 else 1.0
+        for _ in range(max_backtracks + 1):
+            vt = v + alpha * d
+            ft, gt = fun(vt)
+            if mask is not None:
+                gt = gt * mask
+            if np.isfinite(ft) and ft <= f + c1 * alpha * gtd:
+                break
+            alpha *= 0.5
+        else:
+            return v, f, k, 3
+        s = vt - v
+        yv = gt - g
+        sy = float(s @ yv)
+        if sy > 1e-10 * float(np.sqrt(s @ s)) * float(np.sqrt(yv @ yv)):
+            S.append(s)
+            Y.append(yv)
+            R.append(1.0 / sy)
+            if len(S) > memory:
+                S.pop(0)
+                Y.pop(0)
+                R.pop(0)
+        f_old = f
+        v, f, g = vt, ft, gt
+        k += 1
+        if f_old - f <= ftol * max(abs(f_old), abs(f)):
+            return v, f, k, 2
+    return v, f, k, 0

@@ -87,3 +87,62 @@ def test_bfr_limits():
     y = rng.normal(size=(50, 3))
     assert np.allclose(L.bfr(y, y), 100.0)
     assert np.allclose(L.bfr(y, np.tile(y.mean(0), (50, 1))), 0.0)
+
+
+def test_autodiff_gradient_matches_central_differences():
+    rng = np.random.default_rng(5)
+    v = _random_params(rng)
+    u = rng.normal(size=(25, 3))
+    y = rng.normal(size=(25, 3))
+    f, g = L.loss_and_grad(v, u, y, 1e-3, 1e-2)
+    assert f == pytest.approx(L.loss(v, u, y, 1e-3, 1e-2), rel=1e-13)
+    fd = L.loss_grad_fd(v, u, y, 1e-3, 1e-2)
+    assert np.max(np.abs(g - fd)) <= 1e-7 * max(1.0, np.max(np.abs(fd)))
+
+
+def test_adam_first_step_is_a_signed_step():
+    # with zero moments the bias-corrected first update is lr g / (|g| + eps)
+    rng = np.random.default_rng(6)
+    v = _random_params(rng)
+    u = rng.normal(size=(10, 3))
+    y = rng.normal(size=(10, 3))
+    _, g = L.loss_and_grad(v, u, y, 0.0, 0.0)
+    v1, _ = L.adam(v, u, y, 0.0, 0.0, 1, lr=1e-2)
+    assert np.allclose(v - v1, 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_mask_freezes_entries():
+    rng = np.random.default_rng(7)
+    v = _random_params(rng)
+    u = rng.normal(size=(10, 3))
+    y = rng.normal(size=(10, 3))
+    m = L.lti_mask()
+    v1, _ = L.adam(v, u, y, 1e-4, 1e-6, 3, mask=m)
+    assert np.array_equal(v1[m == 0], v[m == 0])
+    assert np.all(v1[m == 1] != v[m == 1])
+
+
+def test_lbfgs_solves_a_quadratic():
+    rng = np.random.default_rng(8)
+    Q = rng.normal(size=(12, 12))
+    Q = Q @ Q.T + 12 * np.eye(12)
+    b = rng.normal(size=12)
+
+    def fun(x):
+        return 0.5 * x @ Q @ x - b @ x, Q @ x - b
+
+    # stops on the gradient or when f no longer decreases in FP64
+    x, f, k, status = L.lbfgs(fun, np.zeros(12), 200, gtol=1e-9, ftol=0.0)
+    assert status in (1, 2) and k < 60
+    assert np.allclose(x, np.linalg.solve(Q, b), rtol=1e-8, atol=1e-8)
+
+
+def test_lbfgs_rosenbrock():
+    def fun(x):
+        f = (1 - x[0]) ** 2 + 100 * (x[1] - x[0] ** 2) ** 2
+        g = np.array([-2 * (1 - x[0]) - 400 * x[0] * (x[1] - x[0] ** 2), 200 * (x[1] - x[0] ** 2)])
+        return f, g
+
+    x, f, k, status = L.lbfgs(fun, np.array([-1.2, 1.0]), 500, gtol=1e-9, ftol=0.0)
+    assert status == 1
+    assert np.allclose(x, [1.0, 1.0], atol=1e-6)
