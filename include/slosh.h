@@ -334,6 +334,97 @@ int mlp_make_windows(const float* feat_dev, const float* fill_dev, const float* 
 /* Copies the FP32 master weights to params_dev [231171]. */
 int mlp_get_params(mlp_handle* h, float* params_dev);
 
+/* ---- LPV state-space surrogate (Section 4, Section 5.3) ------------------ */
+/*
+ * The paper's surrogate of the velocity-level dynamics u = [u_x, u_y, tau] ->
+ * y = [rdot_x, rdot_y, thetadot] (Section 5.3): eq. surrogate_form with
+ * n_x = 4, n_u = 3, n_y = 3, one scheduling variable and D = 0,
+ *     p_k     = W3 tanh(W2 tanh(W1 [x_k; u_k] + b1) + b2) + b3   (2 x 4 tanh)
+ *     y_k     = (C0 + p_k C1) x_k
+ *     x_{k+1} = (A0 + p_k A1) x_k + (B0 + p_k B1) u_k            (eq. LPVparametrization)
+ * fitted by minimising eq. pem plus eq. regularization,
+ *     L = (1/n) sum_k |y_k - yhat_k|^2 + sigma2/2 |theta|^2 + sigmax/2 |x0|^2,
+ * with Adam followed by L-BFGS (Section 4).  A model is LPV_N_PARAM FP64
+ * numbers: theta = A0 (4x4), B0 (4x3), C0 (3x4), A1, B1, C1, W1 (4x7: four
+ * state then three input columns), b1 (4), W2 (4x4), b2 (4), W3 (1x4), b3,
+ * each row-major, then the initial state x0 (4).  Data are the caller's
+ * scaled samples: u_dev, y_dev device [n_samples][3] FP64, shared by all
+ * n_models models (independent restarts).  Every entry point enqueues work on
+ * `stream` (a hipStream_t as void*); lpv_lbfgs alone synchronises it (it
+ * polls the per-model status between launches).  Models run one per quad of
+ * lanes, 16 per wave: any n_models >= 1 is accepted and 16 cost the same as 1.
+ */
+#define LPV_N_THETA 137
+#define LPV_N_PARAM 141
+
+typedef struct lpv_opts {
+  double sigma2;         /* weight of |theta|^2 in eq. regularization */
+  double sigmax;         /* weight of |x0|^2 */
+  double lr, beta1, beta2, eps;    /* Adam (Kingma and Ba) */
+  double c1;             /* Armijo constant of the L-BFGS line search */
+  double gtol;           /* L-BFGS stops when max |grad| <= gtol ... */
+  double ftol;           /* ... or when f_old - f <= ftol max(|f_old|, |f|) */
+  int32_t max_backtracks;  /* halvings of the step before the line search fails */
+  int32_t lti_only;      /* 1: only A0, B0, C0 and x0 move (their LTI fit); others keep their values */
+} lpv_opts;
+
+/* Workspace (device, caller-owned, any content) for n_models models over
+ * n_samples samples: the reverse sweep's per-step record and the optimizer
+ * state.  About 8 (4 n_samples + 900) bytes per 4 lanes of a padded model. */
+int lpv_workspace_bytes(int32_t n_models, int32_t n_samples, size_t* bytes);
+
+/* Open-loop simulation: params_dev [n_models][141]; u_dev [n_samples][3]
+ * (u_per_model = 0) or [n_models][n_samples][3] (1); writes yhat to y_dev
+ * [n_models][n_samples][3] and, if p_dev is non-NULL, the scheduling variable
+ * to p_dev [n_models][n_samples].  Starts from each model's x0. */
+int lpv_simulate(const double* params_dev, int32_t n_models, const double* u_dev, int32_t u_per_model,
+                 int32_t n_samples, double* y_dev, double* p_dev, void* stream);
+
+/* Loss L of each model at params_dev to loss_dev [n_models] and, if grad_dev
+ * is non-NULL, its gradient to grad_dev [n_models][141] (reverse sweep;
+ * entries that opts->lti_only freezes get 0; needs the workspace). */
+int lpv_loss_grad(const double* params_dev, int32_t n_models, const double* u_dev, const double* y_dev,
+                  int32_t n_samples, const lpv_opts* opts, double* loss_dev, double* grad_dev, void* ws_dev,
+                  size_t ws_bytes, void* stream);
+
+/* `iters` Adam steps from zero moments on every model; params_dev is updated
+ * in place; loss_dev [n_models] (may be NULL) gets the loss at the last
+ * evaluated point (before the last update). */
+int lpv_adam(double* params_dev, int32_t n_models, const double* u_dev, const double* y_dev, int32_t n_samples,
+             const lpv_opts* opts, int32_t iters, double* loss_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* L-BFGS (memory 10, two-loop recursion, initial matrix gamma I from the
+ * newest pair; steepest descent and a cleared memory when the direction is
+ * not one of descent; trial steps 1, or 1/max(1, |g|_2) on the first
+ * iteration, halved until the Armijo condition holds; a pair is kept only if
+ * s'y > 1e-10 |s| |y|) on every model, from params_dev, updated in place.
+ * Per model (device, each may be NULL): loss_dev the final loss, status_dev
+ * 1 gradient tolerance, 2 no further decrease, 3 line search failed,
+ * 4 max_iter accepted steps; iters_dev the accepted steps.  Synchronises. */
+int lpv_lbfgs(double* params_dev, int32_t n_models, const double* u_dev, const double* y_dev, int32_t n_samples,
+              const lpv_opts* opts, int32_t max_iter, double* loss_dev, int32_t* status_dev, int32_t* iters_dev,
+              void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Closed-loop simulation of the model augmented with position integrators
+ * (Section 5.3) under the sampled attitude law of Section 5.1,
+ * tau_k = kp (ref_k - theta_k) - kd thetadot_k, held for one sample of
+ * length ts.  The law reads the velocity the model predicts while the
+ * previous input is still held, C(eta(x_k, u_{k-1})) x_k (the model's output
+ * map depends on u_k through the scheduling map, so reading the output of
+ * the new input would be an algebraic loop); the integrators advance by ts
+ * C(p_k) x_k with the input applied.  Physical units: force_dev
+ * [n_samples][2] (force_per_model = 0) or [n_models][n_samples][2] world
+ * forces; ref_dev [n_samples] or [n_models][n_samples] angle reference;
+ * scales host [6] = u scales (3) then y scales (3): the model sees u / u_scale
+ * and predicts y / y_scale.  x0_dev [n_models][4] initial model state, or NULL
+ * for zero.  Writes y_dev [n_models][n_samples][6] = r_x, r_y, theta, rdot_x,
+ * rdot_y, thetadot at the start of each sample, and tau_dev
+ * [n_models][n_samples] (may be NULL) the torque applied. */
+int lpv_closed_loop(const double* params_dev, int32_t n_models, const double* x0_dev, const double* force_dev,
+                    int32_t force_per_model, const double* ref_dev, int32_t ref_per_model, int32_t n_samples,
+                    double ts, double kp, double kd, const double* scales, double* y_dev, double* tau_dev,
+                    void* stream);
+
 #ifdef __cplusplus
 }
 #endif

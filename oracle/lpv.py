@@ -80,6 +80,40 @@ def loss_grad_fd(v, u, y, sigma2, sigmax, eps=1e-6):
     return g
 
 
+def closed_loop(v, force, ref, ts, kp, kd, u_scale, y_scale, x0=None):
+    """The velocity model augmented with position integrators (Section 5.3)
+    under the sampled attitude law of Section 5.1 (tau_k = kp (ref_k - theta_k)
+    - kd thetadot_k, held for one sample).  Reading: the law reads the
+    velocity predicted while the previous input is still held,
+    C(eta(x_k, u_{k-1})) x_k with u_{-1} = (first force, zero torque); the
+    integrators advance by ts C(p_k) x_k with the input applied.  Returns
+    [n, 6] = r_x, r_y, theta, rdot_x, rdot_y, thetadot at the start of each
+    sample, and the applied torque [n]."""
+    P = unpack(v)
+    force = np.asarray(force, np.float64)
+    ref = np.asarray(ref, np.float64)
+    us = np.asarray(u_scale, np.float64)
+    ys = np.asarray(y_scale, np.float64)
+    n = force.shape[0]
+    x = np.zeros(NX) if x0 is None else np.asarray(x0, np.float64).copy()
+    pos = np.zeros(3)
+    u_prev = np.array([force[0, 0], force[0, 1], 0.0]) / us
+    out = np.zeros((n, 6))
+    tau = np.zeros(n)
+    for k in range(n):
+        y_meas = (P["C0"] + schedule(P, x, u_prev) * P["C1"]) @ x * ys
+        t = kp * (ref[k] - pos[2]) - kd * y_meas[2]
+        uk = np.array([force[k, 0], force[k, 1], t]) / us
+        p = schedule(P, x, uk)
+        out[k, :3] = pos
+        out[k, 3:] = y_meas
+        tau[k] = t
+        pos = pos + ts * ((P["C0"] + p * P["C1"]) @ x) * ys
+        x = (P["A0"] + p * P["A1"]) @ x + (P["B0"] + p * P["B1"]) @ uk
+        u_prev = uk
+    return out, tau
+
+
 def bfr(y, yh):
     """Best fit rate per output channel, percent (Section 5.3 footnote)."""
     y = np.asarray(y, np.float64)
@@ -167,7 +201,7 @@ def lbfgs(fun, v, iters, memory=10, c1=1e-4, gtol=1e-10, ftol=1e-13, max_backtra
     s'y > 1e-10 |s| |y|.  Stops after ``iters`` accepted steps, when
     |g|_inf <= gtol, when the decrease f_old - f <= ftol max(|f_old|, |f|),
     or when the line search fails.  Returns (v, f, accepted_steps, status):
-    status 1 gtol, 2 ftol, 3 line search failed, 0 iteration limit.
+    status 1 gtol, 2 ftol, 3 line search failed, 4 iteration limit.
     """
     v = np.array(v, np.float64)
     f, g = fun(v)
@@ -222,4 +256,4 @@ def lbfgs(fun, v, iters, memory=10, c1=1e-4, gtol=1e-10, ftol=1e-13, max_backtra
         k += 1
         if f_old - f <= ftol * max(abs(f_old), abs(f)):
             return v, f, k, 2
-    return v, f, k, 0
+    return v, f, k, 4

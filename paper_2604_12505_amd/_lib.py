@@ -36,6 +36,16 @@ SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sp
                "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
                "mlp_make_windows", "mlp_get_params")
+LPV_SYMBOLS = ("lpv_workspace_bytes", "lpv_simulate", "lpv_loss_grad", "lpv_adam", "lpv_lbfgs",
+               "lpv_closed_loop")
+
+
+class LpvOpts(C.Structure):
+    _fields_ = [
+        ("sigma2", C.c_double), ("sigmax", C.c_double), ("lr", C.c_double), ("beta1", C.c_double),
+        ("beta2", C.c_double), ("eps", C.c_double), ("c1", C.c_double), ("gtol", C.c_double),
+        ("ftol", C.c_double), ("max_backtracks", C.c_int32), ("lti_only", C.c_int32),
+    ]
 
 
 def load():
@@ -86,6 +96,16 @@ def load():
         L.mlp_make_windows.argtypes = [p, p, p, i32, i32, i32, p, p, p, p]
         for name in MLP_SYMBOLS:
             getattr(L, name).restype = C.c_int
+    po = P(LpvOpts)
+    L.lpv_workspace_bytes.argtypes = [i32, i32, P(sz)]
+    L.lpv_simulate.argtypes = [p, i32, p, i32, i32, p, p, p]
+    L.lpv_loss_grad.argtypes = [p, i32, p, p, i32, po, p, p, p, sz, p]
+    L.lpv_adam.argtypes = [p, i32, p, p, i32, po, i32, p, p, sz, p]
+    L.lpv_lbfgs.argtypes = [p, i32, p, p, i32, po, i32, p, p, p, p, sz, p]
+    L.lpv_closed_loop.argtypes = [p, i32, p, p, i32, p, i32, i32, C.c_double, C.c_double, C.c_double, p, p, p,
+                                  p]
+    for name in LPV_SYMBOLS:
+        getattr(L, name).restype = C.c_int
     _lib = L
     return L
 

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libslosh.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sph.hip", "mlp.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sph.hip", "mlp.hip", "lpv.hip")]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are kept out of every kernel

@@ -1,0 +1,41 @@
+"""End-to-end identification on a short SPH record (Section 5.3 pipeline at
+reduced size): SPH data -> LTI stand-in for ssest -> LPV fit -> closed loop.
+
+Asserts what holds at any size: the SPH record is the open-loop response
+(the logged torque is the input), the LTI fit explains the velocities, the
+LPV fit is at least as good as the LTI model it starts from (within a small
+margin: its restarts start from it), the selected models behave in closed
+loop as the oracle's closed loop of the same parameters, and the surrogate
+is orders of magnitude faster than the SPH run it replaces.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W  # noqa: E402
+from oracle import lpv as O  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def test_identification_pipeline_short_record():
+    from paper_2604_12505_amd import identify as I
+    n = 240
+    u = W.lpv_input_train(0, n)
+    run = I.sph_run(u, None, relax=(5, 100))
+    assert run["y"].shape == (n, 6)
+    assert np.allclose(run["u"], u, rtol=1e-6, atol=1e-4)
+    res = I.identify(u, run["y"][:, 3:6], n_lti=16, n_restarts=16, adam_iters=200, lbfgs_iters=200,
+                     lti_adam=300, lti_lbfgs=300)
+    print("train BFR LTI", res["lti_bfr"], "LPV", res["lpv_bfr"])
+    assert res["lti_bfr"].mean() > 90.0
+    assert res["lpv_bfr"].mean() >= res["lti_bfr"].mean() - 2.0
+    force, ref = W.manoeuvre_profile(2)
+    force, ref = force[:200], ref[:200]
+    kp, kd = W.lpv_tank(ctrl=True).params.kp, W.lpv_tank(ctrl=True).params.kd
+    y, secs = I.closed_loop(res["lpv"], force, ref, res, kp, kd)
+    y_ref, _ = O.closed_loop(res["lpv"], force, ref, W.LPV_TS, kp, kd, res["u_scale"], res["y_scale"])
+    assert np.allclose(y, y_ref, rtol=1e-10, atol=1e-10 * np.abs(y_ref).max())
+    sph_per_sample = run["sph_seconds"] / n
+    assert sph_per_sample * 200 / secs > 100.0

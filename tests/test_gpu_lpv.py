@@ -1,0 +1,175 @@
+"""LPV surrogate kernels against the FP64 oracle (oracle/lpv.py).
+
+Random stable models on random inputs; sizes span several waves of 16 models
+and model counts that leave a partly filled wave.  Bars: simulation and loss
+to 1e-12 relative (same FP64 arithmetic, different summation order), the
+gradient to 1e-9 of its largest entry, a few Adam and L-BFGS iterations to
+1e-8 (their control flow is the same as long as no decision is a near tie),
+the closed loop to 1e-10.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import lpv as O  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _models(rng, R, scale=0.3):
+    out = []
+    for _ in range(R):
+        P = O.unpack(rng.normal(size=O.N_PARAM) * scale)
+        P["A0"][:] = 0.8 * np.eye(4) + 0.05 * rng.normal(size=(4, 4))
+        P["A1"][:] = 0.05 * rng.normal(size=(4, 4))
+        out.append(O.pack(P))
+    return np.stack(out)
+
+
+def _lpv():
+    from paper_2604_12505_amd import lpv
+    return lpv
+
+
+def test_simulate_matches_oracle():
+    L = _lpv()
+    rng = np.random.default_rng(0)
+    R, n = 21, 300
+    V = _models(rng, R)
+    u = rng.normal(size=(n, 3))
+    y, p = L.simulate(torch.as_tensor(V, device=DEV), torch.as_tensor(u, device=DEV), with_p=True)
+    y = y.cpu().numpy()
+    for r in range(R):
+        ref = O.simulate(V[r], u)
+        assert np.allclose(y[r], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max()), r
+    # per-model inputs
+    U = rng.normal(size=(R, n, 3))
+    y2 = L.simulate(torch.as_tensor(V, device=DEV), torch.as_tensor(U, device=DEV)).cpu().numpy()
+    for r in (0, 7, 20):
+        ref = O.simulate(V[r], U[r])
+        assert np.allclose(y2[r], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max()), r
+
+
+@pytest.mark.parametrize("lti_only", [False, True])
+def test_loss_and_gradient_match_oracle(lti_only):
+    L = _lpv()
+    rng = np.random.default_rng(1)
+    R, n = 18, 120
+    V = _models(rng, R)
+    u = rng.normal(size=(n, 3))
+    y = rng.normal(size=(n, 3))
+    opts = L.Options(sigma2=1e-3, sigmax=1e-2, lti_only=lti_only)
+    loss, g = L.loss_grad(torch.as_tensor(V, device=DEV), torch.as_tensor(u, device=DEV),
+                          torch.as_tensor(y, device=DEV), opts)
+    loss, g = loss.cpu().numpy(), g.cpu().numpy()
+    mask = O.lti_mask() if lti_only else np.ones(O.N_PARAM)
+    for r in range(0, R, 3):
+        f_ref, g_ref = O.loss_and_grad(V[r], u, y, 1e-3, 1e-2)
+        g_ref = g_ref * mask
+        assert loss[r] == pytest.approx(f_ref, rel=1e-12), r
+        assert np.max(np.abs(g[r] - g_ref)) <= 1e-9 * np.max(np.abs(g_ref)), r
+
+
+def test_gradient_on_an_empty_record_is_the_regularization():
+    # one sample: the loss is |y0 - C(p0) x0|^2 plus the regularization; a
+    # zero model has gradient sigma * params exactly where the residual is zero
+    L = _lpv()
+    V = np.zeros((1, O.N_PARAM))
+    u = np.zeros((1, 3))
+    y = np.zeros((1, 3))
+    loss, g = L.loss_grad(torch.as_tensor(V, device=DEV), torch.as_tensor(u, device=DEV),
+                          torch.as_tensor(y, device=DEV), L.Options(sigma2=1.0, sigmax=1.0))
+    assert float(loss[0]) == 0.0
+    assert torch.count_nonzero(g).item() == 0
+
+
+def test_adam_matches_oracle():
+    L = _lpv()
+    rng = np.random.default_rng(2)
+    R, n, K = 3, 60, 6
+    V = _models(rng, R)
+    u = rng.normal(size=(n, 3))
+    y = rng.normal(size=(n, 3))
+    opts = L.Options(sigma2=1e-4, sigmax=1e-6, lr=1e-2)
+    P = torch.as_tensor(V, device=DEV).clone()
+    loss = L.adam(P, torch.as_tensor(u, device=DEV), torch.as_tensor(y, device=DEV), K, opts).cpu().numpy()
+    P = P.cpu().numpy()
+    for r in range(R):
+        v_ref, f_ref = O.adam(V[r], u, y, 1e-4, 1e-6, K, lr=1e-2)
+        assert np.max(np.abs(P[r] - v_ref)) <= 1e-8 * np.max(np.abs(v_ref)), r
+        assert loss[r] == pytest.approx(f_ref, rel=1e-10)
+
+
+def test_adam_lti_only_freezes_the_scheduling_part():
+    L = _lpv()
+    rng = np.random.default_rng(3)
+    V = _models(rng, 2)
+    u = rng.normal(size=(40, 3))
+    y = rng.normal(size=(40, 3))
+    P = torch.as_tensor(V, device=DEV).clone()
+    L.adam(P, torch.as_tensor(u, device=DEV), torch.as_tensor(y, device=DEV), 4, L.Options(lti_only=True))
+    P = P.cpu().numpy()
+    m = O.lti_mask()
+    assert np.array_equal(P[:, m == 0], V[:, m == 0])
+    assert np.all(P[:, m == 1] != V[:, m == 1])
+
+
+def test_lbfgs_matches_oracle():
+    L = _lpv()
+    rng = np.random.default_rng(4)
+    R, n, K = 3, 60, 5
+    V = _models(rng, R)
+    u = rng.normal(size=(n, 3))
+    y = rng.normal(size=(n, 3))
+    opts = L.Options(sigma2=1e-4, sigmax=1e-6)
+    P = torch.as_tensor(V, device=DEV).clone()
+    loss, status, iters = L.lbfgs(P, torch.as_tensor(u, device=DEV), torch.as_tensor(y, device=DEV), K, opts)
+    P = P.cpu().numpy()
+    for r in range(R):
+        v_ref, f_ref, k_ref, st_ref = O.lbfgs(lambda v: O.loss_and_grad(v, u, y, 1e-4, 1e-6), V[r], K)
+        assert int(iters[r]) == k_ref and int(status[r]) == st_ref, r
+        assert float(loss[r]) == pytest.approx(f_ref, rel=1e-9), r
+        assert np.max(np.abs(P[r] - v_ref)) <= 1e-8 * np.max(np.abs(v_ref)), r
+
+
+def test_lbfgs_reaches_a_minimum_of_a_realisable_fit():
+    # data from a teacher model; L-BFGS from a perturbed teacher drives the
+    # loss down to the regularization level and the gradient to near zero
+    L = _lpv()
+    rng = np.random.default_rng(5)
+    teacher = _models(rng, 1, scale=0.2)[0]
+    n = 200
+    u = rng.normal(size=(n, 3))
+    y = O.simulate(teacher, u)
+    R = 16
+    V = teacher[None, :] + 0.02 * rng.normal(size=(R, O.N_PARAM))
+    opts = L.Options(sigma2=0.0, sigmax=0.0, gtol=1e-9, ftol=0.0)
+    P = torch.as_tensor(V, device=DEV).clone()
+    loss, status, iters = L.lbfgs(P, torch.as_tensor(u, device=DEV), torch.as_tensor(y, device=DEV), 400, opts)
+    loss = loss.cpu().numpy()
+    yh = L.simulate(P, torch.as_tensor(u, device=DEV)).cpu().numpy()
+    fits = [O.bfr(y, yh[r]).mean() for r in range(R)]
+    assert np.median(fits) > 99.0, fits
+    assert np.all(loss <= O.loss(V[0], u, y, 0.0, 0.0))
+
+
+def test_closed_loop_matches_oracle():
+    L = _lpv()
+    rng = np.random.default_rng(6)
+    R, n = 5, 250
+    V = _models(rng, R, scale=0.2)
+    force = rng.normal(size=(n, 2)) * 30.0
+    ref = np.where(np.arange(n) > 40, 0.2, 0.0)
+    us, ys = [40.0, 40.0, 10.0], [0.1, 0.1, 0.05]
+    x0 = rng.normal(size=(R, 4)) * 0.1
+    y, tau = L.closed_loop(torch.as_tensor(V, device=DEV), torch.as_tensor(force, device=DEV),
+                           torch.as_tensor(ref, device=DEV), 0.05, 5.0, 3.0, us, ys,
+                           x0=torch.as_tensor(x0, device=DEV), with_tau=True)
+    y, tau = y.cpu().numpy(), tau.cpu().numpy()
+    for r in range(R):
+        out, t = O.closed_loop(V[r], force, ref, 0.05, 5.0, 3.0, us, ys, x0=x0[r])
+        assert np.allclose(y[r], out, rtol=1e-10, atol=1e-10 * np.abs(out).max()), r
+        assert np.allclose(tau[r], t, rtol=1e-10, atol=1e-10 * np.abs(t).max()), r

@@ -146,3 +146,45 @@ def test_lbfgs_rosenbrock():
     x, f, k, status = L.lbfgs(fun, np.array([-1.2, 1.0]), 500, gtol=1e-9, ftol=0.0)
     assert status == 1
     assert np.allclose(x, [1.0, 1.0], atol=1e-6)
+
+
+def test_closed_loop_open_gains_is_the_open_loop_model():
+    # kp = kd = 0 and C1 = 0: the measured velocities are the open-loop
+    # outputs for the input (force, 0), the positions their running sum * ts
+    rng = np.random.default_rng(9)
+    P = L.unpack(_random_params(rng))
+    P["C1"][:] = 0.0
+    v = L.pack(P)
+    n, ts = 50, 0.05
+    force = rng.normal(size=(n, 2))
+    us, ys = np.array([2.0, 3.0, 4.0]), np.array([0.5, 0.25, 2.0])
+    out, tau = L.closed_loop(v, force, np.zeros(n), ts, 0.0, 0.0, us, ys, x0=P["x0"])
+    u = np.concatenate([force, np.zeros((n, 1))], 1) / us
+    y = L.simulate(v, u) * ys
+    assert np.allclose(out[:, 3:], y, rtol=1e-12, atol=1e-12)
+    pos = np.concatenate([np.zeros((1, 3)), ts * np.cumsum(y, 0)[:-1]])
+    assert np.allclose(out[:, :3], pos, rtol=1e-12, atol=1e-12)
+    assert np.all(tau == 0.0)
+
+
+def test_closed_loop_pd_on_a_double_integrator():
+    # an LTI model that is exactly the sampled rigid body (velocity += ts F / m,
+    # thetadot += ts tau / J) under the PD law: the (theta, thetadot) loop is
+    # the linear system [[1, ts], [-ts kp/J, 1 - ts kd/J]] driven by ts kp/J ref
+    ts, m, J = 0.05, 1000.0, 133.84
+    w, xi = 0.2 * np.pi, 0.7
+    kp, kd = J * w * w, 2 * xi * J * w
+    P = L.unpack(np.zeros(L.N_PARAM))
+    P["A0"][:] = np.diag([1.0, 1.0, 1.0, 0.0])
+    P["B0"][:3, :3] = np.diag([ts / m, ts / m, ts / J])
+    P["C0"][:, :3] = np.eye(3)
+    v = L.pack(P)
+    n = 400
+    ref = np.where(np.arange(n) >= 20, 0.3, 0.0)
+    out, tau = L.closed_loop(v, np.zeros((n, 2)), ref, ts, kp, kd, np.ones(3), np.ones(3))
+    A = np.array([[1.0, ts], [-ts * kp / J, 1.0 - ts * kd / J]])
+    B = np.array([[0.0], [ts * kp / J]])
+    _, yy, _ = signal.dlsim((A, B, np.eye(2), np.zeros((2, 1)), ts), ref[:, None])
+    assert np.allclose(out[:, 2], yy[:, 0], rtol=1e-10, atol=1e-12)
+    assert np.allclose(out[:, 5], yy[:, 1], rtol=1e-10, atol=1e-12)
+    assert abs(out[-1, 2] - 0.3) < 1e-3          # the loop settles on the reference

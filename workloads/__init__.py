@@ -369,3 +369,99 @@ def paper_p0(seed: int = 0, n_steps: int = 30000) -> Scenario:
     return Scenario("paper_p0", p, _f32(fluid), np.zeros((fluid.shape[0], 2), np.float32),
                     _f32(ghosts), np.zeros(6), n_steps, np.zeros((n_steps, 3), np.float32),
                     theta_ref=theta_ref, dx=dx, fill=0.6, shape="circle", tank_size=2 * R)
+
+
+# ----------------------------------------------------------------------------
+# LPV identification and validation (Section 5.3 set-up)
+# ----------------------------------------------------------------------------
+
+LPV_TS = 0.05            # sampling time of the surrogate (Section 5.3)
+
+
+def lpv_tank(seed: int = 0, dx: float = 0.01, ctrl: bool = False) -> Scenario:
+    """The paper's spacecraft (Table 1: circular tank r = 0.2 m at the centre
+    of mass, 60 % fill, m = 1010.71 kg, J = 133.84 kg m^2) with this
+    library's fluid model (Tait EOS c0 = 20 m/s, 3 boundary rings, dx = 10 mm,
+    about 750 particles).  dt is the CFL step shortened so that a whole number
+    of steps fills one sample of LPV_TS.  ctrl: PD attitude law with the
+    gains of Section 5.1 (w = 0.2 pi, xi = 0.7), applied once per sample."""
+    rng = np.random.default_rng(seed)
+    R = 0.2
+    fluid, ghosts = circle_tank(R, dx, 0.6, 3, rng, 0.01)
+    p = _fluid_params(dx)
+    steps = int(math.ceil(LPV_TS / p.dt))
+    p.dt = LPV_TS / steps
+    p.motion = MOTION_FREE
+    p.ctrl = CTRL_PD_ZOH if ctrl else CTRL_NONE
+    p.body_mass, p.body_inertia = 1010.71, 133.84
+    w, xi = 0.2 * math.pi, 0.7
+    p.kp = p.body_inertia * w * w
+    p.kd = 2 * xi * p.body_inertia * w
+    p.ctrl_period = steps
+    pad = 5 * dx
+    p.domain_min = (-R - pad, -R - pad)
+    p.domain_max = (R + pad, R + pad)
+    return Scenario("lpv_tank", p, _f32(fluid), np.zeros((fluid.shape[0], 2), np.float32), _f32(ghosts),
+                    np.zeros(6), 0, np.zeros((0, 3), np.float32), theta_ref=np.zeros(1), dx=dx, fill=0.6,
+                    shape="circle", tank_size=2 * R)
+
+
+def lpv_input_train(seed: int = 0, n: int = 2200, force_amp: float = 60.0, torque_amp: float = 10.0,
+                    ts: float = LPV_TS) -> np.ndarray:
+    """Identification input [n, 3] (F_x, F_y world, torque), one value per
+    sample (Section 5.3, Fig. iden_profile): per channel, independently, a
+    random-phase multisine over the whole [0, 2) Hz band on the 0.05 Hz grid
+    (all 39 nonzero tones, equal amplitudes, peak-normalised to a quarter of
+    the channel amplitude) plus a train of pulse doublets: a pulse of
+    U[0.3, 1.2] x amplitude and random sign held for 10-300 samples
+    (0.5-15 s, long enough to reach the velocities of sustained thrust), the
+    opposite pulse right after it (no net impulse), then a gap of 20-100
+    samples."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(n) * ts
+    grid = np.arange(1, 40) * 0.05
+    out = np.zeros((n, 3))
+    for ch, amp in enumerate((force_amp, force_amp, torque_amp)):
+        phi = rng.uniform(0.0, 2 * math.pi, size=grid.size)
+        ms = np.sin(2 * math.pi * grid[None, :] * t[:, None] + phi[None, :]).sum(axis=1)
+        ms *= 0.25 * amp / np.max(np.abs(ms))
+        pulses = np.zeros(n)
+        k = int(rng.integers(10, 60))
+        while k < n:
+            width = int(rng.integers(10, 301))
+            a = amp * float(rng.uniform(0.3, 1.2)) * (1.0 if rng.random() < 0.5 else -1.0)
+            pulses[k:k + width] += a
+            pulses[k + width:k + 2 * width] -= a
+            k += 2 * width + int(rng.integers(20, 101))
+        out[:, ch] = ms + pulses
+    return out
+
+
+def manoeuvre_profile(k: int, ts: float = LPV_TS):
+    """The two closed-loop manoeuvres of Section 5.1, as this library reads
+    their description (their time series are only shown in a figure):
+    profile 1 (60 s): constant thrust F_x = 50 N over 1-21 s, an attitude
+    reference slew from 0 to 20 degrees over 25-27 s (trapezoidal rate, 0.5 s
+    ramps), and a 100 N pulse along y over 40-40.5 s; profile 2 (40 s): a
+    60 N pulse along x and y over 1-5 s, a dwell, and the opposite pulse over
+    15-19 s, reference zero.  Returns (force [n, 2] world, ref [n] rad), one
+    value per sample."""
+    if k == 1:
+        n = int(round(60.0 / ts))
+        t = np.arange(n) * ts
+        force = np.zeros((n, 2))
+        force[(t >= 1.0) & (t < 21.0), 0] = 50.0
+        force[(t >= 40.0) & (t < 40.5), 1] = 100.0
+        ref = trapezoid_slew(math.radians(20.0), 0.5, 1.0, t - 25.0)
+    elif k == 2:
+        n = int(round(40.0 / ts))
+        t = np.arange(n) * ts
+        force = np.zeros((n, 2))
+        on = (t >= 1.0) & (t < 5.0)
+        off = (t >= 15.0) & (t < 19.0)
+        force[on] = 60.0
+        force[off] = -60.0
+        ref = np.zeros(n)
+    else:
+        raise ValueError("profile 1 or 2")
+    return force, ref
