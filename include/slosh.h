@@ -364,7 +364,7 @@ typedef struct lpv_opts {
   double c1;             /* Armijo constant of the L-BFGS line search */
   double gtol;           /* L-BFGS stops when max |grad| <= gtol ... */
   double ftol;           /* ... or when f_old - f <= ftol max(|f_old|, |f|) */
-  int32_t max_backtracks;  /* halvings of the step before the line search fails */
+  int32_t max_backtracks;  /* rejected steps before the line search fails */
   int32_t lti_only;      /* 1: only A0, B0, C0 and x0 move (their LTI fit); others keep their values */
 } lpv_opts;
 
@@ -396,7 +396,9 @@ int lpv_adam(double* params_dev, int32_t n_models, const double* u_dev, const do
 /* L-BFGS (memory 10, two-loop recursion, initial matrix gamma I from the
  * newest pair; steepest descent and a cleared memory when the direction is
  * not one of descent; trial steps 1, or 1/max(1, |g|_2) on the first
- * iteration, halved until the Armijo condition holds; a pair is kept only if
+ * iteration, until the Armijo condition holds, each rejected step replaced by
+ * the minimiser of the interpolating quadratic clamped to [0.1, 0.5] of it
+ * (0.1 after a non-finite loss); a pair is kept only if
  * s'y > 1e-10 |s| |y|) on every model, from params_dev, updated in place.
  * Per model (device, each may be NULL): loss_dev the final loss, status_dev
  * 1 gradient tolerance, 2 no further decrease, 3 line search failed,

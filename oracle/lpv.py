@@ -196,8 +196,10 @@ def lbfgs(fun, v, iters, memory=10, c1=1e-4, gtol=1e-10, ftol=1e-13, max_backtra
     two-loop recursion over the stored pairs (initial matrix gamma I with
     gamma = s'y / y'y of the newest pair; steepest descent if the result is
     not a descent direction, which also clears the memory); trial steps
-    alpha = 1 (1 / max(1, |g|_2) on the first iteration), halved until
-    f(v + alpha d) <= f + c1 alpha g'd.  A pair (s, y) is stored only if
+    alpha = 1 (1 / max(1, |g|_2) on the first iteration) until
+    f(v + alpha d) <= f + c1 alpha g'd, each rejected step replaced by the
+    minimiser of the interpolating quadratic clamped to [0.1, 0.5] alpha
+    (0.1 alpha after a non-finite value).  A pair (s, y) is stored only if
     s'y > 1e-10 |s| |y|.  Stops after ``iters`` accepted steps, when
     |g|_inf <= gtol, when the decrease f_old - f <= ftol max(|f_old|, |f|),
     or when the line search fails.  Returns (v, f, accepted_steps, status):
@@ -237,7 +239,13 @@ def lbfgs(fun, v, iters, memory=10, c1=1e-4, gtol=1e-10, ftol=1e-13, max_backtra
                 gt = gt * mask
             if np.isfinite(ft) and ft <= f + c1 * alpha * gtd:
                 break
-            alpha *= 0.5
+            if np.isfinite(ft):
+                # minimiser of the quadratic through f, g'd and ft (Nocedal
+                # and Wright eq. 3.57), kept within [0.1, 0.5] of the step
+                a_q = -gtd * alpha * alpha / (2.0 * (ft - f - gtd * alpha))
+                alpha = min(max(a_q, 0.1 * alpha), 0.5 * alpha)
+            else:
+                alpha = 0.1 * alpha
         else:
             return v, f, k, 3
         s = vt - v

@@ -456,8 +456,9 @@ __global__ __launch_bounds__(kWave) void lpv_lbfgs_start(FitArgs a, LbfgsOpts o)
 }
 
 // Up to `evals` loss/gradient evaluations of L-BFGS (two-loop recursion,
-// backtracking Armijo line search).  Each pass: every running model picks a
-// trial point (a new direction, or half the last step), all models evaluate
+// backtracking Armijo line search with quadratic interpolation).  Each pass:
+// every running model picks a trial point (a new direction, or the
+// interpolated shorter step), all models evaluate
 // (a finished model evaluates its own point and ignores the result), then
 // each running model accepts or backtracks.  Status: 0 running, 1 gradient
 // tolerance, 2 no further decrease, 3 line search failed, 4 iteration limit,
@@ -546,7 +547,7 @@ __global__ __launch_bounds__(kWave) void lpv_lbfgs_kernel(FitArgs a, LbfgsOpts o
         *cslot(a, cGtd, col) = gtd;
         *cslot(a, cBack, col) = 0.0;
       } else {
-        alpha = 0.5 * *cslot(a, cAlpha, col);
+        alpha = *cslot(a, cAlpha, col);
         gtd = *cslot(a, cGtd, col);
       }
       *cslot(a, cAlpha, col) = alpha;
@@ -595,6 +596,15 @@ __global__ __launch_bounds__(kWave) void lpv_lbfgs_kernel(FitArgs a, LbfgsOpts o
       *cslot(a, cPhase, col) = 0.0;
       lbfgs_accept_checks(a, col, o, f, ft, gmax, iter);
     } else {
+      // next trial: minimiser of the quadratic through f, g'd and ft
+      // (Nocedal and Wright eq. 3.57) within [0.1, 0.5] alpha; 0.1 alpha
+      // after a non-finite value
+      double an = 0.1 * alpha;
+      if (isfinite(ft)) {
+        const double aq = -gtd * alpha * alpha / (2.0 * (ft - f - gtd * alpha));
+        an = fmin(fmax(aq, 0.1 * alpha), 0.5 * alpha);
+      }
+      *cslot(a, cAlpha, col) = an;
       const double back = *cslot(a, cBack, col) + 1.0;
       *cslot(a, cBack, col) = back;
       *cslot(a, cPhase, col) = 1.0;
