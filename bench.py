@@ -158,30 +158,48 @@ def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int, lanes: i
             "roofline": kernel_roofline(kus, n, g, nc)}
 
 
-def paper_leg(steps: int = 30000):
-    """The paper's benchmark parameters (Tables 1-2: 666-particle circular tank,
-    linear EOS, dt = 1 ms, PD attitude law at 0.05 s) for a 30 s simulated run;
-    the paper's manoeuvre inputs are published only as a figure, so the input
-    is zero and the controller holds theta = 0."""
+def paper_leg(relax_cycles: int = 60, relax_steps: int = 50):
+    """The paper's benchmark (Tables 1-2: 666 particles spawned at random in a
+    circular tank, relaxed to rest, linear EOS without tension, dt = 1 ms, PD
+    attitude law at 0.05 s) flying the two reconstructed manoeuvres (60 s and
+    40 s, 60,000 and 40,000 steps), each timed from the relaxed state: the
+    like-for-like counterpart of the SPH rows of the paper's Table 3."""
     import torch
     import workloads as W
-    from paper_2604_12505_amd.sph import Simulator
-    sc = W.paper_p0(seed=0, n_steps=steps)
+    from paper_2604_12505_amd.sph import Simulator, gamma1_estimate
+    from paper_2604_12505_amd.surrogate import _relax
+    sc = W.paper_p0(seed=0, n_steps=1, spawn="random")
     dev = torch.device("cuda:0")
     sim = Simulator.from_scenario(sc, device=dev)
-    ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
-    sim.rollout(256, theta_ref=ref)
-    sim.set_state(torch.as_tensor(sc.pos), torch.as_tensor(sc.vel), sc.rigid0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.rollout(steps, theta_ref=ref, log_stride=50)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    status = sim.status()
+    _relax(sim, relax_cycles, relax_steps)
+    s0, w0, _, _, _ = sim.get_state()
+    g1 = gamma1_estimate(sc.params, s0, sc.ghosts, device=dev)      # eq. gamma1 at the relaxed state
+    per = sc.params.ctrl_period
+    out = {"workload": f"paper Tables 1-2: {sc.n_fluid} fluid + {sc.n_ghost} boundary particles, random spawn "
+                       f"relaxed for {relax_cycles} x {relax_steps} steps, 1 ms steps",
+           "gamma1_estimate_relaxed": g1, "gamma1_used": sc.params.gamma1,
+           "paper_hardware": "i7-13850HX + RTX 2000 Ada laptop, JAX", "profiles": {}}
+    for k, paper_s in ((1, 9.9093), (2, 5.1876)):
+        force, ref = W.manoeuvre_profile(k, ts=per * sc.params.dt)
+        n = force.shape[0] * per
+        u = np.zeros((n, 3), np.float32)
+        u[:, :2] = np.repeat(force, per, axis=0)
+        sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
+        uu = torch.as_tensor(u, device=dev)
+        th = torch.as_tensor(ref, dtype=torch.float64, device=dev)
+        sim.rollout(64, uu[:64].contiguous(), theta_ref=th)        # graphs captured outside the timing
+        sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lg = sim.rollout(n, uu, theta_ref=th, log_stride=per)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        y = lg["y"].cpu().numpy()
+        out["profiles"][str(k)] = {"steps": n, "wall_s": wall, "status": sim.status(), "paper_wall_s": paper_s,
+                                   "final_theta_deg": float(np.degrees(y[-1, 2])),
+                                   "final_rdot": [float(y[-1, 3]), float(y[-1, 4])]}
     sim.close()
-    return {"workload": f"paper Tables 1-2: {sc.n_fluid} fluid + {sc.n_ghost} boundary particles, "
-                        f"{steps} steps of 1 ms", "wall_s": wall, "status": status,
-            "paper_wall_s": 9.9093, "paper_hardware": "i7-13850HX + RTX 2000 Ada laptop, JAX"}
+    return out
 
 
 def linearization_leg(n_dir: int = 64, steps: int = 400):
@@ -323,11 +341,10 @@ def main() -> int:
         "roofline": roofline,
     }
     if not args.no_paper_leg:
-        # timing context only: with the paper's parameters the zero-gravity
-        # fluid develops a tensile instability and particles leave the tank
-        # after a few thousand steps, in the FP64 oracle as well; the status
-        # is reported, not treated as a failure of this run
+        # the paper's own scenario (timing context for its Table 3)
         out["paper_scenario"] = paper_leg()
+        for prof in out["paper_scenario"]["profiles"].values():
+            status |= prof["status"]
     if args.batch_tanks > 0:
         out["batch"] = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
         status |= out["batch"]["status"]

@@ -52,6 +52,7 @@ extern "C" {
 /* ---- method options ----------------------------------------------------- */
 #define SPH_EOS_TAIT 0        /* P = B((rho/rho0)^gamma - 1), B = rho0 c0^2/gamma */
 #define SPH_EOS_LINEAR 1      /* P = k (rho - rho0)  (eq. EOS) */
+#define SPH_EOS_LINEAR_CLAMPED 2  /* P = max(k (rho - rho0), 0): eq. EOS without tension */
 #define SPH_MOTION_FREE 0     /* Newton-Euler rigid body (eq. tankdynamics) */
 #define SPH_MOTION_SINE 1     /* prescribed theta = A sin(2 pi f t), r = 0 */
 #define SPH_CTRL_NONE 0
@@ -228,6 +229,18 @@ int sph_neighbours(sph_handle* h, int32_t max_nbr, int32_t* nbr_dev, int32_t* co
  * with the rigid-body update (these three per step).  Synchronises the stream. */
 int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
                      const double* theta_ref_dev, int32_t n_ref, float* avg_us);
+
+/* Terms of the analytic wall correction (eq. gamma1): for every fluid
+ * particle i of fluid_dev [n_fluid][2] (FP32 positions, body frame) against
+ * ghost_dev [n_ghost][2], num_dev[i] = rho0/m - sum_f W(r_if) (the fluid sum of
+ * the density, self term included) and den_dev[i] = sum_g W(r_ig), FP64,
+ * with the cubic spline and kernel normalisation of p (the printed
+ * denominator index is read as a sum over the ghosts).  gamma1 = num/den is
+ * the value that puts particle i at rest density; the paper evaluates it for
+ * a representative particle next to the wall (Section 3.5).  O(n (n + ng))
+ * set-up work; enqueued on `stream`. */
+int sph_gamma1_terms(const sph_params* p, const float* fluid_dev, int32_t n_fluid, const float* ghost_dev,
+                     int32_t n_ghost, double* num_dev, double* den_dev, void* stream);
 
 /* ---- linearization: tangent-linear rollout ---------------------------- */
 /*

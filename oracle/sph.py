@@ -59,6 +59,8 @@ def lib():
                                         p, i, p]
         L.ora_num_threads.restype = i
         L.ora_num_threads.argtypes = []
+        L.ora_gamma1_terms.restype = None
+        L.ora_gamma1_terms.argtypes = [C.POINTER(OraParams), i, p, p, i, p, p, p, p]
         _lib = L
     return _lib
 
@@ -230,3 +232,18 @@ def rollout_world(prm, x, v, ghosts_body, rigid, n_steps, u_seq=None, theta_ref=
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def gamma1_terms(prm, fluid, ghosts):
+    """(num [n], den [n]) of eq. gamma1 for every fluid particle:
+    num_i = rho0/m - sum_f W_if (self included), den_i = sum_g W_ig."""
+    f = np.ascontiguousarray(fluid, np.float64)
+    g = np.ascontiguousarray(ghosts, np.float64)
+    sx, sy = np.ascontiguousarray(f[:, 0]), np.ascontiguousarray(f[:, 1])
+    gx, gy = np.ascontiguousarray(g[:, 0]), np.ascontiguousarray(g[:, 1])
+    num = np.zeros(f.shape[0])
+    den = np.zeros(f.shape[0])
+    o = make_params(prm)
+    lib().ora_gamma1_terms(C.byref(o), f.shape[0], _ptr(sx), _ptr(sy), g.shape[0], _ptr(gx), _ptr(gy),
+                           _ptr(num), _ptr(den))
+    return num, den

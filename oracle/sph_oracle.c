@@ -17,7 +17,8 @@
  *   density        rho_i = m (sum_f W_cb + gamma1 sum_g W_cb)  (eq. density_update,
  *                  self term included);
  *   pressure       Tait  P = B((rho/rho0)^gamma - 1), B = rho0 c0^2 / gamma,
- *                  or the paper's linear  P = k (rho - rho0)  (eq. EOS);
+ *                  or the paper's linear  P = k (rho - rho0)  (eq. EOS), also
+ *                  in a variant clamped at P >= 0 (no tension);
  *   fluid forces   symmetric pressure (eq. momentum) and artificial viscosity
  *                  (eq. viscous) with grad_i W = W'(r) r_ij / r  (Section 3.1);
  *   wall forces    ghost-to-fluid pressure (eq. pressure_b2f) and Akinci
@@ -62,7 +63,7 @@
 #endif
 
 typedef struct {
-  int32_t eos;          /* 0 Tait, 1 linear */
+  int32_t eos;          /* 0 Tait, 1 linear, 2 linear clamped at zero pressure */
   int32_t motion;       /* 0 free (Newton-Euler), 1 prescribed sine rotation */
   int32_t ctrl;         /* 0 none, 1 PD with zero-order hold */
   int32_t kernel_norm;  /* 0 normalised 5/(14 pi h^2), 1 as printed 15/(14 pi h^2) */
@@ -121,6 +122,10 @@ double ora_dw_spiky(double r, double hs) {
 /* equation of state (eq. EOS; Tait form for the stiffened variant) */
 double ora_eos(const ora_params* p, double rho) {
   if (p->eos == 1) return p->k_lin * (rho - p->rho0);
+  if (p->eos == 2) {              /* the linear law without tension */
+    const double P = p->k_lin * (rho - p->rho0);
+    return P > 0.0 ? P : 0.0;
+  }
   double B = p->rho0 * p->c0 * p->c0 / p->tait_gamma;
   return B * (pow(rho / p->rho0, p->tait_gamma) - 1.0);
 }
@@ -689,4 +694,22 @@ int ora_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* Terms of the analytic wall correction (eq. gamma1, after Koschier et al.):
+ * for every fluid particle i, num_i = rho0 / m - sum_f W(r_if) (the fluid
+ * sum of the density, self term included) and den_i = sum_g W(r_ig) (the
+ * printed denominator index is read as a sum over the ghosts), so that
+ * gamma1 = num_i / den_i makes particle i sit at rest density.  Positions
+ * are separate x and y arrays; O(n (n + ng)), plain loops. */
+void ora_gamma1_terms(const ora_params* p, int n, const double* sx, const double* sy, int ng, const double* gx,
+                      const double* gy, double* num, double* den) {
+  const int pr = p->kernel_norm;
+  for (int i = 0; i < n; ++i) {
+    double sf = 0.0, sg = 0.0;
+    for (int j = 0; j < n; ++j) sf += ora_w_cubic(hypot(sx[i] - sx[j], sy[i] - sy[j]), p->h, pr);
+    for (int k = 0; k < ng; ++k) sg += ora_w_cubic(hypot(sx[i] - gx[k], sy[i] - gy[k]), p->h, pr);
+    num[i] = p->rho0 / p->mass - sf;
+    den[i] = sg;
+  }
 }

@@ -206,8 +206,9 @@ __device__ __forceinline__ float cubic_grad_f(float q) {
 
 __device__ __forceinline__ float eos_over_rho2(float rho, const Consts& k, float* P_out) {
   float P;
-  if (k.eos == SPH_EOS_LINEAR) {
+  if (k.eos != SPH_EOS_TAIT) {
     P = k.k_lin * (rho - k.rho0);
+    if (k.eos == SPH_EOS_LINEAR_CLAMPED) P = fmaxf(P, 0.0f);
   } else {
     float x = rho * k.rho0_inv;
     float xp;
@@ -1548,7 +1549,7 @@ int nblocks(long long threads) { return threads > 0 ? (int)((threads + kBlock - 
 bool params_ok(const sph_params* p) {
   if (!p) return false;
   if (!(p->h > 0 && p->h_spiky > 0 && p->mass > 0 && p->dt > 0 && p->rho0 > 0)) return false;
-  if (p->eos != SPH_EOS_TAIT && p->eos != SPH_EOS_LINEAR) return false;
+  if (p->eos != SPH_EOS_TAIT && p->eos != SPH_EOS_LINEAR && p->eos != SPH_EOS_LINEAR_CLAMPED) return false;
   if (p->eos == SPH_EOS_TAIT && !(p->c0 > 0 && p->tait_gamma > 0)) return false;
   if (p->motion != SPH_MOTION_FREE && p->motion != SPH_MOTION_SINE) return false;
   if (p->ctrl != SPH_CTRL_NONE && p->ctrl != SPH_CTRL_PD_ZOH) return false;
@@ -1742,9 +1743,13 @@ __device__ __forceinline__ float cubic_grad_f_d(float q) {
 // P/rho^2 and its derivative with respect to rho.
 __device__ __forceinline__ float eos_over_rho2_d(float rho, const Consts& k, float* dpi) {
   float P, dP;
-  if (k.eos == SPH_EOS_LINEAR) {
+  if (k.eos != SPH_EOS_TAIT) {
     P = k.k_lin * (rho - k.rho0);
     dP = k.k_lin;
+    if (k.eos == SPH_EOS_LINEAR_CLAMPED && !(P > 0.0f)) {
+      P = 0.0f;
+      dP = 0.0f;
+    }
   } else {
     const float x = rho * k.rho0_inv;
     float xp1;   // x^(gamma - 1)
@@ -3465,6 +3470,60 @@ int sph_vjp_rollout(sph_handle* h, int32_t n_steps, int32_t every, const float* 
   if (grad_rigid0)
     for (int q = 0; q < 6; ++q) grad_rigid0[q] = r7[q];
   return SPH_OK;
+}
+
+}  // extern "C"
+
+// ---- analytic wall correction (eq. gamma1) --------------------------------
+
+namespace {
+
+// Cubic spline shape in FP64: (2-q)^3 - 4(1-q)^3 for q < 1, (2-q)^3 for q < 2.
+__device__ __forceinline__ double cubic_shape_fp64(double q) {
+  if (q >= 2.0) return 0.0;
+  const double a = 2.0 - q;
+  double w = a * a * a;
+  if (q < 1.0) {
+    const double b = 1.0 - q;
+    w -= 4.0 * b * b * b;
+  }
+  return w;
+}
+
+// One thread per fluid particle: num_i = rho0/m - sum_f W_if (self term
+// included, as in the density), den_i = sum_g W_ig, both in FP64 and in
+// particle order.  A one-time set-up computation: plain loops.
+__global__ __launch_bounds__(kBlock) void sph_gamma1_kernel(const float* __restrict__ fluid, int n,
+                                                            const float* __restrict__ ghosts, int ng, double inv_h,
+                                                            double c, double rho0_over_m, double* __restrict__ num,
+                                                            double* __restrict__ den) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double xi = fluid[2 * i], yi = fluid[2 * i + 1];
+  double sf = 0.0, sg = 0.0;
+  for (int j = 0; j < n; ++j)
+    sf += cubic_shape_fp64(hypot(xi - (double)fluid[2 * j], yi - (double)fluid[2 * j + 1]) * inv_h);
+  for (int k = 0; k < ng; ++k)
+    sg += cubic_shape_fp64(hypot(xi - (double)ghosts[2 * k], yi - (double)ghosts[2 * k + 1]) * inv_h);
+  num[i] = rho0_over_m - c * sf;
+  den[i] = c * sg;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_gamma1_terms(const sph_params* p, const float* fluid_dev, int32_t n_fluid, const float* ghost_dev,
+                     int32_t n_ghost, double* num_dev, double* den_dev, void* stream) {
+  if (!p || !(p->h > 0) || !(p->mass > 0) || !(p->rho0 > 0) || n_fluid <= 0 || n_ghost < 0 || !fluid_dev ||
+      (n_ghost > 0 && !ghost_dev) || !num_dev || !den_dev)
+    return SPH_E_INVAL;
+  if (p->kernel_norm != SPH_KNORM_UNIT && p->kernel_norm != SPH_KNORM_PRINTED) return SPH_E_INVAL;
+  const double c = (p->kernel_norm == SPH_KNORM_PRINTED ? 15.0 : 5.0) / (14.0 * M_PI * p->h * p->h);
+  hipLaunchKernelGGL(sph_gamma1_kernel, dim3(nblocks(n_fluid)), dim3(kBlock), 0, (hipStream_t)stream, fluid_dev,
+                     n_fluid, ghost_dev, n_ghost, 1.0 / p->h, c, p->rho0 / p->mass, num_dev, den_dev);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPH_OK : hip_fail(e, "sph_gamma1_terms");
 }
 
 }  // extern "C"

@@ -44,6 +44,33 @@ def _dev_f32(a, device) -> torch.Tensor:
                            dtype=torch.float32, device=device).contiguous()
 
 
+def gamma1_terms(params, fluid, ghosts, device="cuda:0"):
+    """(num [n], den [n]) FP64 device tensors of eq. gamma1 for every fluid
+    particle (``sph_gamma1_terms``)."""
+    L = load()
+    f = _dev_f32(fluid, device)
+    g = _dev_f32(ghosts, device)
+    n = f.shape[0]
+    num = torch.empty(n, dtype=torch.float64, device=device)
+    den = torch.empty(n, dtype=torch.float64, device=device)
+    o = make_params(params)
+    st = C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    check(L.sph_gamma1_terms(C.byref(o), _ptr(f), n, _ptr(g), g.shape[0], _ptr(num), _ptr(den), st),
+          "sph_gamma1_terms")
+    return num, den
+
+
+def gamma1_estimate(params, fluid, ghosts, device="cuda:0", top: float = 0.1) -> float:
+    """A representative eq. gamma1 value: the median of num/den over the
+    fluid particles whose ghost sum is in the top fraction ``top`` (the
+    particles that sit against the wall with a full fluid neighbourhood on
+    the other side, the configuration the paper evaluates it for)."""
+    num, den = gamma1_terms(params, fluid, ghosts, device)
+    k = max(1, int(round(top * int((den > 0).sum().item()))))
+    idx = torch.topk(den, k).indices
+    return float(torch.median(num[idx] / den[idx]).item())
+
+
 class Simulator:
     """One tank or a batch: ``sph_init`` / ``sph_batch_init`` on construction,
     ``sph_destroy`` on close()."""

@@ -49,6 +49,7 @@ SCENARIOS = {
     "plain_rect": lambda: W.plain_rect(0, n_steps=50),
     "closed_loop_circle": lambda: W.closed_loop_circle(0, n_steps=50),
     "paper_p0": lambda: W.paper_p0(0, n_steps=50),
+    "paper_p0_random_literal_eos": lambda: W.paper_p0(1, n_steps=50, spawn="random", eos=W.EOS_LINEAR),
     "random_rect": lambda: W.random_tank(2, n_steps=50, n_min=2000, n_max=4000, shape="rect"),
     "random_circle": lambda: W.random_tank(5, n_steps=50, n_min=2000, n_max=4000, shape="circle"),
 }
@@ -264,3 +265,19 @@ def test_escape_is_flagged():
     sim.set_state(s, w, rig, tau, step)
     assert sim.status() & 1
     sim.close()
+
+
+@pytest.mark.parametrize("name", ["paper_p0", "single_layer_rect"])
+def test_gamma1_terms_match_oracle(name):
+    from paper_2604_12505_amd.sph import gamma1_terms
+    if name == "paper_p0":
+        sc = W.paper_p0(0, n_steps=1, spawn="random")
+        prm, fluid, ghosts = sc.params, sc.pos, sc.ghosts
+    else:
+        fluid, ghosts = W.rect_tank(0.2, 0.1, 0.0125, 8, 1, None, 0.0)
+        prm = W._fluid_params(0.0125)
+        fluid, ghosts = fluid.astype(np.float32), ghosts.astype(np.float32)
+    num, den = gamma1_terms(prm, fluid, ghosts)
+    onum, oden = O.gamma1_terms(prm, fluid.astype(np.float64), ghosts.astype(np.float64))
+    assert np.allclose(num.cpu().numpy(), onum, rtol=1e-12, atol=1e-12 * np.abs(onum).max())
+    assert np.allclose(den.cpu().numpy(), oden, rtol=1e-12, atol=1e-12 * np.abs(oden).max())

@@ -95,7 +95,16 @@ def test_tait_eos_rest_and_sound_speed():
 
 def test_linear_eos_of_the_paper():
     import workloads as W
-    p = W.paper_p0().params
+    p = W.paper_p0(eos=W.EOS_LINEAR).params
     assert O.eos(p, p.rho0) == 0.0
     assert O.eos(p, p.rho0 + 10.0) == pytest.approx(p.k_lin * 10.0, rel=1e-12)
     assert O.eos(p, p.rho0 - 5.0) == pytest.approx(-p.k_lin * 5.0, rel=1e-12)
+
+
+def test_clamped_linear_eos_has_no_tension():
+    import workloads as W
+    p = W.paper_p0().params
+    assert p.eos == W.EOS_LINEAR_CLAMPED
+    assert O.eos(p, p.rho0 + 10.0) == pytest.approx(p.k_lin * 10.0, rel=1e-12)
+    assert O.eos(p, p.rho0 - 5.0) == 0.0
+    assert O.eos(p, p.rho0) == 0.0

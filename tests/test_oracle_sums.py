@@ -157,3 +157,31 @@ def test_wall_viscosity_only_resists_approach():
     assert a_in[1] > 0
     a_out = visc([0.0, 0.5])      # moving away: min(v.r, 0) = 0
     assert np.abs(a_out).max() == 0.0
+
+
+def test_gamma1_estimate_is_one_when_ghosts_fill_the_support():
+    # eq. gamma1 on a lattice whose three boundary layers continue the fluid:
+    # nothing is missing, so the ghost sum must count once
+    p, st, g = _full_lattice()
+    p.rho0 = float(O.rhs(p, st, g)["rho"][0])      # the lattice's own rest density
+    num, den = O.gamma1_terms(p, st.s, g)
+    near = den > 1e-6 * den.max()
+    assert near.sum() > 10
+    assert np.allclose(num[near] / den[near], 1.0, rtol=1e-9)
+
+
+def test_gamma1_estimate_restores_rest_density_next_to_a_single_layer():
+    # with one boundary layer the wall particles miss part of their support;
+    # weighting the ghost sum by the estimate of that particle gives it the
+    # rest density in eq. density_update
+    p, st, g3 = _full_lattice()
+    p.rho0 = float(O.rhs(p, st, g3)["rho"][0])
+    fluid, g1 = W.rect_tank(0.2, 0.1, 0.0125, 8, 1, None, 0.0)
+    num, den = O.gamma1_terms(p, fluid, g1)
+    i = int(np.argmax(den))
+    gamma1 = num[i] / den[i]
+    assert gamma1 > 1.0                           # the single layer must count for more
+    p.gamma1 = gamma1
+    st1 = O.State(fluid.astype(np.float64), np.zeros_like(fluid, dtype=np.float64), np.zeros(6))
+    rho = O.rhs(p, st1, g1)["rho"]
+    assert rho[i] == pytest.approx(p.rho0, rel=1e-12)

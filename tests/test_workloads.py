@@ -27,8 +27,14 @@ def test_paper_p0_matches_tables_1_and_2():
     assert p.ctrl_period * p.dt == pytest.approx(g["time"]["control_dt_s"])
     w, xi = g["controller"]["omega_rad_s"], g["controller"]["xi"]
     assert p.kp == pytest.approx(p.body_inertia * w * w) and p.kd == pytest.approx(2 * xi * p.body_inertia * w)
-    assert sc.n_ghost == pytest.approx(g["fluid"]["n_ghost"], abs=5)
+    assert sc.n_ghost == g["fluid"]["n_ghost"]
     assert sc.n_fluid == pytest.approx(g["fluid"]["n_fluid"], rel=0.06)
+    rnd = W.paper_p0(n_steps=10, spawn="random")
+    assert rnd.n_fluid == g["fluid"]["n_fluid"]
+    r = np.sqrt((rnd.pos.astype(np.float64) ** 2).sum(1))
+    assert r.max() < 0.2 and rnd.pos[:, 1].max() < W.circle_fill_level(0.2, 0.6)
+    d = np.sqrt(((rnd.pos[:, None, :].astype(np.float64) - rnd.pos[None, :, :]) ** 2).sum(-1))
+    assert d[np.triu_indices(rnd.n_fluid, 1)].min() >= 0.6 * rnd.dx * (1 - 1e-6)
 
 
 def test_plain_rect_sizes():

@@ -31,7 +31,7 @@ from typing import Optional
 
 import numpy as np
 
-EOS_TAIT, EOS_LINEAR = 0, 1
+EOS_TAIT, EOS_LINEAR, EOS_LINEAR_CLAMPED = 0, 1, 2
 MOTION_FREE, MOTION_SINE = 0, 1
 CTRL_NONE, CTRL_PD_ZOH = 0, 1
 KNORM_UNIT, KNORM_PRINTED = 0, 1
@@ -338,22 +338,51 @@ def rect_sweep(k: int, seed: int = 0, n_steps: int = 200) -> Scenario:
     return plain_rect(seed=seed, n_steps=n_steps, dx=0.0125 / (2 ** k))
 
 
-def paper_p0(seed: int = 0, n_steps: int = 30000) -> Scenario:
+def _random_fill(rng: np.random.Generator, radius: float, fill: float, n: int, min_dist: float):
+    """n points drawn uniformly from the part of the disk r < radius below the
+    fill level, each at least min_dist from the earlier ones (dart throwing)."""
+    yf = circle_fill_level(radius, fill)
+    pts = np.zeros((0, 2))
+    tries = 0
+    while pts.shape[0] < n:
+        tries += 1
+        if tries > 200 * n:
+            raise RuntimeError("random fill: no room for the requested particles")
+        q = rng.uniform(-radius, radius, size=2)
+        if q[0] * q[0] + q[1] * q[1] >= radius * radius or q[1] >= yf:
+            continue
+        if pts.shape[0] and np.min(((pts - q) ** 2).sum(1)) < min_dist * min_dist:
+            continue
+        pts = np.vstack([pts, q])
+    return pts
+
+
+def paper_p0(seed: int = 0, n_steps: int = 30000, spawn: str = "lattice", eos: int = EOS_LINEAR_CLAMPED) -> Scenario:
     """The paper's benchmark (Tables 1-2): circular tank r = 0.2 m, 60 % fill,
-    6 mm particles, one ring of 5.4 mm ghosts, h = 9.42 mm, linear EOS k = 3,
-    rho0 = 1017, alpha = 8.32e-4, beta = 4e-4, gamma1 = 0.5, dt = 1 ms.
-    The paper spawns particles randomly and relaxes them; here a jittered
-    lattice stands in (timing context only)."""
+    6 mm particles, one ring of 236 ghosts (5.4 mm), h = 9.42 mm, linear EOS
+    k = 3, rho0 = 1017, alpha = 8.32e-4, beta = 4e-4, gamma1 = 0.5,
+    dt = 1 ms, PD attitude law at 0.05 s.  spawn="random" places the paper's
+    666 particles at random in the filled region (at least 0.6 of the mean
+    spacing apart), the initial condition the paper relaxes to rest before
+    its runs (Section 5.1); spawn="lattice" uses a jittered lattice.  eos:
+    EOS_LINEAR_CLAMPED by default (the linear law without tension: with
+    negative pressures the zero-gravity fluid is unstable in this model),
+    EOS_LINEAR for the literal law."""
     rng = np.random.default_rng(seed)
     # 666 particles of mass rho0 (6 mm)^2 at 60 % fill sit on a ~10.6 mm
     # lattice; with the kernel constant as printed this is close to rest density.
-    R, d_part, dg = 0.2, 0.006, 0.0054
+    R, d_part = 0.2, 0.006
     dx = 0.0106
-    fluid, _ = circle_tank(R, dx, 0.6, 1, rng, 0.01)
-    ng = int(round(2 * math.pi * R / dg))
+    if spawn == "random":
+        fluid = _random_fill(rng, R - 0.5 * dx, 0.6, 666, 0.6 * dx)
+    elif spawn == "lattice":
+        fluid, _ = circle_tank(R, dx, 0.6, 1, rng, 0.01)
+    else:
+        raise ValueError("spawn must be 'lattice' or 'random'")
+    ng = 236
     phi = 2 * math.pi * np.arange(ng) / ng
     ghosts = np.stack([R * np.cos(phi), R * np.sin(phi)], axis=1)
-    p = Params(eos=EOS_LINEAR, kernel_norm=KNORM_PRINTED, h=0.00942, h_spiky=0.00942, rho0=1017.0,
+    p = Params(eos=eos, kernel_norm=KNORM_PRINTED, h=0.00942, h_spiky=0.00942, rho0=1017.0,
                mass=1017.0 * d_part * d_part, c0=math.sqrt(3.0), tait_gamma=7.0, k_lin=3.0,
                visc_alpha=8.32e-4, visc_beta=4e-4, eps=0.01, gamma1=0.5, dt=1e-3,
                body_mass=1010.71, body_inertia=133.84, motion=MOTION_FREE, ctrl=CTRL_PD_ZOH)
