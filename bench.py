@@ -184,21 +184,50 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50):
         n = force.shape[0] * per
         u = np.zeros((n, 3), np.float32)
         u[:, :2] = np.repeat(force, per, axis=0)
-        sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
         uu = torch.as_tensor(u, device=dev)
         th = torch.as_tensor(ref, dtype=torch.float64, device=dev)
-        sim.rollout(64, uu[:64].contiguous(), theta_ref=th)        # graphs captured outside the timing
-        sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
+        res = {"steps": n, "paper_wall_s": paper_s}
+        for name, resident in (("multi_kernel", False), ("lds_resident", True)):
+            sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
+            sim.rollout(64, uu[:64].contiguous(), theta_ref=th, resident=resident)   # warm-up, graphs captured
+            sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lg = sim.rollout(n, uu, theta_ref=th, log_stride=per, resident=resident)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            y = lg["y"].cpu().numpy()
+            res[name] = {"wall_s": wall, "status": sim.status(), "final_theta_deg": float(np.degrees(y[-1, 2])),
+                         "final_rdot": [float(y[-1, 3]), float(y[-1, 4])]}
+        res["status"] = res["multi_kernel"]["status"] | res["lds_resident"]["status"]
+        out["profiles"][str(k)] = res
+    sim.close()
+    # many copies of the scenario at once (Monte Carlo use): 256 tanks from
+    # different random spawns, profile 1's first 4,000 steps, both paths
+    n_b, steps_b = 256, 4000
+    scs = [W.paper_p0(seed=s, n_steps=1, spawn="random") for s in range(n_b)]
+    bsim = Simulator.batch(scs, device=dev)
+    _relax(bsim, 10, relax_steps)
+    sb0, wb0, _, _, _ = bsim.get_state()
+    force, ref = W.manoeuvre_profile(1, ts=per * sc.params.dt)
+    u = np.zeros((steps_b, 3), np.float32)
+    u[:, :2] = np.repeat(force, per, axis=0)[:steps_b]
+    ub = torch.as_tensor(np.broadcast_to(u, (n_b, steps_b, 3)).copy(), device=dev)
+    refb = np.broadcast_to(ref, (n_b, ref.size)).copy()
+    n_part = sum(x.n_fluid for x in scs)
+    batch = {"tanks": n_b, "steps": steps_b, "particles": n_part}
+    for name, resident in (("multi_kernel", False), ("lds_resident", True)):
+        bsim.set_state(sb0, wb0, np.zeros((n_b, 6)), 0.0, 0)
+        bsim.rollout(64, ub[:, :64].contiguous(), theta_ref=refb, resident=resident)
+        bsim.set_state(sb0, wb0, np.zeros((n_b, 6)), 0.0, 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lg = sim.rollout(n, uu, theta_ref=th, log_stride=per)
+        bsim.rollout(steps_b, ub, theta_ref=refb, resident=resident)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        y = lg["y"].cpu().numpy()
-        out["profiles"][str(k)] = {"steps": n, "wall_s": wall, "status": sim.status(), "paper_wall_s": paper_s,
-                                   "final_theta_deg": float(np.degrees(y[-1, 2])),
-                                   "final_rdot": [float(y[-1, 3]), float(y[-1, 4])]}
-    sim.close()
+        batch[name] = {"wall_s": wall, "particle_steps_per_s": n_part * steps_b / wall, "status": bsim.status()}
+    bsim.close()
+    out["batch_256_tanks"] = batch
     return out
 
 

@@ -181,6 +181,24 @@ int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
                 float* y_log_dev, float* wrench_log_dev, float* u_log_dev,
                 float* wmean_log_dev);
 
+/* sph_rollout for small tanks, with the same arguments and results: one
+ * workgroup per tank keeps the fluid, the ghosts, a cell list (cells of
+ * side 2h) and the rigid state in LDS and runs up to 4,096 steps per launch,
+ * each step being the same terms as the multi-kernel path (Algorithm "state
+ * transition function": density, EOS, pair and wall forces, wrench, attitude
+ * law, rigid body, symplectic Euler) separated by workgroup barriers.  Needs
+ * every tank to hold at most 2,048 fluid particles, 1,024 ghosts and 2,048
+ * cells of side 2h over its domain box (sph_resident_fits), else returns
+ * SPH_E_CAPACITY without doing anything.  The summation order differs from
+ * sph_rollout's, so the two agree to rounding, not bitwise.  Asynchronous;
+ * ends with a rebuild of the multi-kernel path's cell list. */
+int sph_rollout_resident(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const double* theta_ref_dev,
+                         int32_t n_ref, int32_t log_stride, float* y_log_dev, float* wrench_log_dev,
+                         float* u_log_dev, float* wmean_log_dev);
+
+/* *fits (host) = 1 if every tank of the handle fits sph_rollout_resident. */
+int sph_resident_fits(sph_handle* h, int32_t* fits);
+
 /* The slosh wrench (F_x, F_y, torque) of the fluid on the tank (the reaction
  * sums of eq. tankdynamics, torque about the centre of mass) at the last
  * evaluated state, in SPH_FRAME_BODY or SPH_FRAME_WORLD.  out_dev: device [3]. */

@@ -33,7 +33,7 @@ SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sp
                "sph_neighbours", "sph_time_kernels", "sph_batch_workspace_bytes", "sph_batch_init",
                "sph_num_tanks", "sph_autotune", "sph_set_lanes", "sph_set_near_lists", "sph_get_tuning",
                "sph_jvp_workspace_bytes", "sph_jvp_rollout", "sph_vjp_workspace_bytes", "sph_vjp_rollout",
-               "sph_gamma1_terms", "sph_strerror")
+               "sph_gamma1_terms", "sph_rollout_resident", "sph_resident_fits", "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
                "mlp_make_windows", "mlp_get_params")
 LPV_SYMBOLS = ("lpv_workspace_bytes", "lpv_simulate", "lpv_loss_grad", "lpv_adam", "lpv_lbfgs",
@@ -83,6 +83,8 @@ def load():
     L.sph_vjp_workspace_bytes.argtypes = [p, i32, i32, P(sz)]
     L.sph_vjp_rollout.argtypes = [p, i32, i32, p, p, i32, p, p, p, p, p, sz, p, p, p, p, p]
     L.sph_gamma1_terms.argtypes = [P(SphParams), p, i32, p, i32, p, p, p]
+    L.sph_rollout_resident.argtypes = [p, i32, p, p, i32, i32, p, p, p, p]
+    L.sph_resident_fits.argtypes = [p, P(i32)]
     L.sph_strerror.argtypes = [C.c_int]
     L.sph_strerror.restype = C.c_char_p
     for name in SPH_SYMBOLS[:-1]:

@@ -122,6 +122,7 @@ struct RigidArgs {
 // Everything a kernel needs to know about one tank.
 struct Tank {
   Grid g;
+  Grid g2;        // cells of side 2h (no skin) for the LDS-resident rollout
   Consts k;
   Box box;
   RigidArgs ra;
@@ -1508,6 +1509,340 @@ __global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict_
 }
 
 // --------------------------------------------------------------------------
+// LDS-resident rollout for small tanks.  One workgroup per tank keeps the
+// fluid state, the ghosts, the cell structure (cells of side 2h) and the
+// rigid state in LDS and runs many steps per launch: a step is a few
+// workgroup barriers instead of three launches with their global-memory
+// round trips.  The particles are kept sorted by cell (a stable counting
+// sort after every step, ties in the order of the previous step), so the
+// candidates of a cell row are one contiguous run of LDS and the summation
+// order, and the result, do not depend on timing.  The arithmetic of every
+// term is the multi-kernel path's (density and EOS, pair and wall terms,
+// wrench, rigid step, symplectic update); the wrench is summed per thread in
+// double, then over the waves in a fixed order.
+// --------------------------------------------------------------------------
+
+constexpr int kResThreads = 1024;
+constexpr int kResMaxF = 2048;     // fluid particles per tank
+constexpr int kResMaxG = 1024;     // ghosts per tank
+constexpr int kResMaxC = 2048;     // cells of side 2h per tank
+constexpr int kResPer = kResMaxF / kResThreads;
+constexpr int kResChunk = 4096;    // steps per launch
+
+struct ResLds {
+  float2 s[2][kResMaxF], w[2][kResMaxF];   // cell-sorted state; [par] is current
+  float2 rp[kResMaxF];                     // rho, P / rho^2 of each sorted slot
+  float2 g[kResMaxG];                      // ghosts in cell order
+  unsigned short id[2][kResMaxF];          // slot in the handle's arrays
+  unsigned short ckey[kResMaxF];           // cell of each sorted slot
+  unsigned short key[kResMaxF];            // cell of each slot before sorting
+  unsigned short tmp[kResMaxF];            // a cell's members in arrival order
+  int start[kResMaxC + 1];
+  int cnt[kResMaxC];
+  int gstart[kResMaxC + 1];
+  double red[3][kResThreads / 64];
+  int wsum[kResThreads / 64];
+  DevRigid rb;
+  DevRollout ro;
+  float frame[4];
+  unsigned bad;
+};
+
+// Exclusive workgroup scan: thread t holds v; returns its exclusive prefix
+// and the total.  Ends with a barrier after the totals are read.
+__device__ int res_scan(int v, ResLds& L, int* total) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) L.wsum[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int w = lane < kResThreads / 64 ? L.wsum[lane] : 0;
+    for (int off = 1; off < kResThreads / 64; off <<= 1) {
+      const int y = __shfl_up(w, off, 64);
+      if (lane >= off) w += y;
+    }
+    if (lane < kResThreads / 64) L.wsum[lane] = w;
+  }
+  __syncthreads();
+  const int ex = (wv > 0 ? L.wsum[wv - 1] : 0) + x - v;
+  *total = L.wsum[kResThreads / 64 - 1];
+  __syncthreads();
+  return ex;
+}
+
+// Cell starts from the counts in cnt (thread t owns cells 2t, 2t + 1);
+// leaves cnt zero.
+__device__ void res_starts(ResLds& L, int nc) {
+  const int t = threadIdx.x, c0 = 2 * t, c1 = 2 * t + 1;
+  const int v0 = c0 < nc ? L.cnt[c0] : 0, v1 = c1 < nc ? L.cnt[c1] : 0;
+  int total;
+  const int ex = res_scan(v0 + v1, L, &total);
+  if (c0 < nc) {
+    L.start[c0] = ex;
+    L.cnt[c0] = 0;
+  }
+  if (c1 < nc) {
+    L.start[c1] = ex + v0;
+    L.cnt[c1] = 0;
+  }
+  if (t == 0) L.start[nc] = total;
+  __syncthreads();
+}
+
+// Position of slot i among its cell's members (ascending slot), after every
+// member has been appended to tmp.
+__device__ __forceinline__ int res_rank(const ResLds& L, int i, int c) {
+  const int a = L.start[c], b = L.start[c + 1];
+  int rank = 0;
+  for (int q = a; q < b; ++q) rank += L.tmp[q] < i ? 1 : 0;
+  return a + rank;
+}
+
+// Stable counting sort of the fluid from buffer par into buffer 1 - par by
+// key (counts already in cnt); also writes ckey and the cell starts.
+__device__ void res_sort(ResLds& L, int n, int nc, int par) {
+  res_starts(L, nc);
+  for (int i = threadIdx.x; i < n; i += kResThreads) {
+    const int c = L.key[i];
+    L.tmp[L.start[c] + atomicAdd(&L.cnt[c], 1)] = (unsigned short)i;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kResThreads) {
+    const int c = L.key[i];
+    const int d = res_rank(L, i, c);
+    L.s[1 - par][d] = L.s[par][i];
+    L.w[1 - par][d] = L.w[par][i];
+    L.id[1 - par][d] = L.id[par][i];
+    L.ckey[d] = (unsigned short)c;
+  }
+  for (int c = threadIdx.x; c < nc; c += kResThreads) L.cnt[c] = 0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ int res_key(float2 p, const Grid& g) {
+  int cx, cy;
+  cell_of(p, g, cx, cy);
+  return cy * g.ncx + cx;
+}
+
+// The rigid-body part, kept out of line: thread 0 runs it once per step and
+// its FP64 code would otherwise take registers from the particle loops.
+__device__ __noinline__ void res_rigid_step(DevRigid* rb, const DevRollout* ro, int tank, double F0, double F1,
+                                            double F2, RigidArgs ra, RigidIn in) {
+  const double F[3] = {F0, F1, F2};
+  rigid_step(rb, ro, tank, F, kStep, ra, in);
+}
+
+__global__ void __launch_bounds__(kResThreads) sph_resident(float2* __restrict__ pos, float2* __restrict__ vel,
+                                                            const float2* __restrict__ gpos,
+                                                            const Tank* __restrict__ tanks, DevRigid* rigid,
+                                                            const DevRollout* __restrict__ rollout, int n_steps,
+                                                            unsigned* __restrict__ status) {
+  __shared__ ResLds L;
+  const int tank = blockIdx.x, t = threadIdx.x;
+  const Tank& tk = tanks[tank];
+  const Consts k = tk.k;
+  const Grid g2 = tk.g2;
+  const RigidArgs ra = tk.ra;
+  const int n = tk.n, ng = tk.ng, nc = g2.ncx * g2.ncy;
+  if (t == 0) {
+    L.rb = rigid[tank];
+    L.ro = *rollout;
+    L.bad = 0u;
+  }
+  for (int c = t; c < nc; c += kResThreads) L.cnt[c] = 0;
+  __syncthreads();
+  // ghosts, once: counting sort into L.g (staged in s[1])
+  for (int i = t; i < ng; i += kResThreads) {
+    const float2 p = gpos[tk.q0 + i];
+    L.s[1][i] = p;
+    const int c = res_key(p, g2);
+    L.key[i] = (unsigned short)c;
+    atomicAdd(&L.cnt[c], 1);
+  }
+  __syncthreads();
+  res_starts(L, nc);
+  for (int i = t; i < ng; i += kResThreads) {
+    const int c = L.key[i];
+    L.tmp[L.start[c] + atomicAdd(&L.cnt[c], 1)] = (unsigned short)i;
+  }
+  __syncthreads();
+  for (int i = t; i < ng; i += kResThreads) L.g[res_rank(L, i, L.key[i])] = L.s[1][i];
+  for (int c = t; c <= nc; c += kResThreads) L.gstart[c] = L.start[c];
+  for (int c = t; c < nc; c += kResThreads) L.cnt[c] = 0;
+  __syncthreads();
+  // fluid, sorted into buffer 1
+  for (int i = t; i < n; i += kResThreads) {
+    const float2 p = pos[tk.p0 + i];
+    L.s[0][i] = p;
+    L.w[0][i] = vel[tk.p0 + i];
+    L.id[0][i] = (unsigned short)i;
+    const int c = res_key(p, g2);
+    L.key[i] = (unsigned short)c;
+    atomicAdd(&L.cnt[c], 1);
+  }
+  __syncthreads();
+  res_sort(L, n, nc, 0);
+  int par = 1;
+
+  const int ncx = g2.ncx, ncy = g2.ncy;
+  for (int step = 0; step < n_steps; ++step) {
+    RigidIn in;
+    if (t == 0) in = rigid_inputs(&L.rb, &L.ro, tank, kStep, ra);   // loads in flight during the sums
+    const float2* S = L.s[par];
+    const float2* V = L.w[par];
+    // density and EOS
+#pragma unroll
+    for (int e = 0; e < kResPer; ++e) {
+      const int i = t + e * kResThreads;
+      if (i < n) {
+        const float2 si = S[i];
+        const int c = L.ckey[i], cx = c % ncx, cy = c / ncx;
+        const int xa = cx > 0 ? cx - 1 : 0, xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
+        float sf = 0.0f, sgs = 0.0f;
+        for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+          if (yy < 0 || yy >= ncy) continue;
+          const int row = yy * ncx;
+#pragma unroll 4
+          for (int q = L.start[row + xa], qe = L.start[row + xb + 1]; q < qe; ++q) {
+            const float2 sj = S[q];
+            const float d2 = dist2(si.x - sj.x, si.y - sj.y);
+            if (d2 < k.R2) sf += cubic_shape(fsqrt(d2) * k.inv_h);
+          }
+#pragma unroll 4
+          for (int q = L.gstart[row + xa], qe = L.gstart[row + xb + 1]; q < qe; ++q) {
+            const float2 gj = L.g[q];
+            const float d2 = dist2(si.x - gj.x, si.y - gj.y);
+            if (d2 < k.R2) sgs += cubic_shape(fsqrt(d2) * k.inv_h);
+          }
+        }
+        const float rho = k.mass * k.wc * (sf + k.gamma1 * sgs);
+        L.rp[i] = make_float2(rho, eos_over_rho2(rho, k, nullptr));
+      }
+    }
+    __syncthreads();
+    // pair and wall terms, the tank's reactions
+    float2 acc[kResPer];
+    double F[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kResPer; ++e) {
+      const int i = t + e * kResThreads;
+      acc[e] = make_float2(0.0f, 0.0f);
+      if (i < n) {
+        const float2 s = S[i], w = V[i], me = L.rp[i];
+        const float rho_i = me.x, Pi = me.y;
+        const float visc_g = k.beta2 / (2.0f * rho_i);
+        const int c = L.ckey[i], cx = c % ncx, cy = c / ncx;
+        const int xa = cx > 0 ? cx - 1 : 0, xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
+        float axf = 0.0f, ayf = 0.0f, axg = 0.0f, ayg = 0.0f, fx = 0.0f, fy = 0.0f, tq = 0.0f;
+        for (int yy = cy - 1; yy <= cy + 1; ++yy) {
+          if (yy < 0 || yy >= ncy) continue;
+          const int row = yy * ncx;
+#pragma unroll 2
+          for (int q = L.start[row + xa], qe = L.start[row + xb + 1]; q < qe; ++q) {
+            const float2 sj = S[q];
+            const float dx = s.x - sj.x, dy = s.y - sj.y;
+            const float d2 = dist2(dx, dy);
+            if (d2 < k.R2 && d2 > 0.0f) {
+              const float2 wj = V[q], o = L.rp[q];
+              const float qq = fsqrt(d2) * k.inv_h;
+              const float gW = k.dwc * cubic_grad_f(qq);
+              const float vr = (w.x - wj.x) * dx + (w.y - wj.y) * dy;
+              const float coef = (-(Pi + o.y) + k.a2h * vr * frcp((rho_i + o.x) * (d2 + k.eps_h2))) * gW;
+              axf += coef * dx;
+              ayf += coef * dy;
+            }
+          }
+#pragma unroll 2
+          for (int q = L.gstart[row + xa], qe = L.gstart[row + xb + 1]; q < qe; ++q) {
+            const float2 gj = L.g[q];
+            const float dx = s.x - gj.x, dy = s.y - gj.y;
+            const float d2 = dist2(dx, dy);
+            if (d2 < k.Rs2 && d2 > 0.0f) {
+              const float r = fsqrt(d2);
+              const float tt = k.hs - r;
+              const float gW = k.dws * tt * tt * frcp(r);
+              const float vr = w.x * dx + w.y * dy;
+              const float coef = k.mass * (-2.0f * Pi + visc_g * fminf(vr, 0.0f) * frcp(d2 + k.eps_h2)) * gW;
+              const float ax = coef * dx, ay = coef * dy;
+              axg += ax;
+              ayg += ay;
+              const float Fx = k.mass * ax, Fy = k.mass * ay;
+              fx -= Fx;
+              fy -= Fy;
+              tq -= gj.x * Fy - gj.y * Fx;
+            }
+          }
+        }
+        acc[e] = make_float2(k.mass * axf + axg, k.mass * ayf + ayg);
+        F[0] += (double)fx;
+        F[1] += (double)fy;
+        F[2] += (double)tq;
+      }
+    }
+    const int lane = t & 63, wv = t >> 6;
+    for (int d = 0; d < 3; ++d) {
+      const double v = wave_sum(F[d]);
+      if (lane == 0) L.red[d][wv] = v;
+    }
+    __syncthreads();
+    // the rigid-body part of the step (one thread), then the fluid update
+    if (t == 0) {
+      double Ft[3];
+      for (int d = 0; d < 3; ++d) {
+        double v = 0.0;
+        for (int q = 0; q < kResThreads / 64; ++q) v += L.red[d][q];
+        Ft[d] = v;
+      }
+      res_rigid_step(&L.rb, &L.ro, tank, Ft[0], Ft[1], Ft[2], ra, in);
+      L.frame[0] = L.rb.abx;
+      L.frame[1] = L.rb.aby;
+      L.frame[2] = L.rb.thd;
+      L.frame[3] = L.rb.thdd;
+    }
+    __syncthreads();
+    const Frame fr{L.frame[0], L.frame[1], L.frame[2], L.frame[3]};
+    unsigned bad = 0;
+#pragma unroll
+    for (int e = 0; e < kResPer; ++e) {
+      const int i = t + e * kResThreads;
+      if (i < n) {
+        float2 s = L.s[par][i], w = L.w[par][i];
+        fluid_update(s, w, acc[e], fr, k.dt);
+        L.s[par][i] = s;
+        L.w[par][i] = w;
+        if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) {
+          bad |= SPH_ST_NONFINITE;
+        } else if (!((double)s.x >= tk.box.lo_x && (double)s.x < tk.box.hi_x && (double)s.y >= tk.box.lo_y &&
+                     (double)s.y < tk.box.hi_y)) {
+          bad |= SPH_ST_ESCAPED;
+        }
+        const int c = res_key(s, g2);
+        L.key[i] = (unsigned short)c;
+        atomicAdd(&L.cnt[c], 1);
+      }
+    }
+    if (bad) atomicOr(&L.bad, bad);
+    __syncthreads();
+    res_sort(L, n, nc, par);
+    par = 1 - par;
+  }
+  for (int i = t; i < n; i += kResThreads) {
+    const int slot = L.id[par][i];
+    pos[tk.p0 + slot] = L.s[par][i];
+    vel[tk.p0 + slot] = L.w[par][i];
+  }
+  if (t == 0) {
+    rigid[tank] = L.rb;
+    if (L.bad) atomicOr(status, L.bad);
+  }
+}
+
+// --------------------------------------------------------------------------
 // host side
 // --------------------------------------------------------------------------
 
@@ -1528,8 +1863,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 double support_of(const sph_params* p) { return 2.0 * p->h > p->h_spiky ? 2.0 * p->h : p->h_spiky; }
 
-bool make_grid(const sph_params* p, Grid* g) {
-  double cell = (support_of(p) + kSkinOverH * p->h) * (1.0 + 1e-6);
+bool make_grid(const sph_params* p, Grid* g, double skin_over_h = kSkinOverH) {
+  double cell = (support_of(p) + skin_over_h * p->h) * (1.0 + 1e-6);
   double w = p->domain_max[0] - p->domain_min[0], hh = p->domain_max[1] - p->domain_min[1];
   if (!(w > 0 && hh > 0 && cell > 0)) return false;
   double nx = std::ceil(w / cell), ny = std::ceil(hh / cell);
@@ -1615,7 +1950,7 @@ int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int
     if (!params_ok(p) || n_fluid[t] < 0 || n_ghost[t] < 0) return SPH_E_INVAL;
     Tank& tk = pl->tanks[t];
     memset(&tk, 0, sizeof tk);
-    if (!make_grid(p, &tk.g)) return SPH_E_INVAL;
+    if (!make_grid(p, &tk.g) || !make_grid(p, &tk.g2, 0.0)) return SPH_E_INVAL;
     tk.k = make_consts(p);
     tk.box = Box{p->domain_min[0], p->domain_min[1], p->domain_max[0], p->domain_max[1]};
     tk.ra = RigidArgs{p->dt, p->body_mass, p->body_inertia, p->kp, p->kd, p->sine_amp, p->sine_freq,
@@ -2540,8 +2875,10 @@ void enqueue_steps(sph_handle* h, int n_steps) {
 int sort_fluid(sph_handle* h, const float2* s, const float2* w) {
   const int nb = nblocks(h->N);
   if (h->N > 0) {
-    HIPCHK(hipMemcpyAsync(h->at<float2>(h->L.pos[1]), s, (size_t)h->N * 8, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(h->at<float2>(h->L.vel[1]), w, (size_t)h->N * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (s != h->at<float2>(h->L.pos[1]))
+      HIPCHK(hipMemcpyAsync(h->at<float2>(h->L.pos[1]), s, (size_t)h->N * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (w != h->at<float2>(h->L.vel[1]))
+      HIPCHK(hipMemcpyAsync(h->at<float2>(h->L.vel[1]), w, (size_t)h->N * 8, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipMemsetAsync(h->at<float2>(h->L.acc[0]), 0, (size_t)h->N * 8, h->stream));
   }
   HIPCHK(hipMemsetAsync(h->at<int>(h->L.count), 0, (size_t)h->C * 4, h->stream));
@@ -2634,6 +2971,14 @@ int set_rollout(sph_handle* h, const float* u, const double* ref, int n_ref, int
                      h->at<DevRollout>(h->L.rollout), v, h->at<DevRigid>(h->L.rigid), h->T);
   HIPCHK(hipGetLastError());
   return SPH_OK;
+}
+
+// Every tank fits the LDS-resident rollout.
+bool resident_ok(const sph_handle* h) {
+  for (const Tank& tk : h->plan.tanks)
+    if (tk.n > kResMaxF || tk.ng > kResMaxG || (long long)tk.g2.ncx * tk.g2.ncy > kResMaxC) return false;
+  static_assert(kResMaxF <= 65536 && kResMaxC <= 65536 && 2 * kResThreads >= kResMaxC, "resident sizes");
+  return true;
 }
 
 // Captures kChunk steps starting from (cur, ord) with since_sort == 0 (the
@@ -2831,6 +3176,44 @@ int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const do
   if (left > 0) enqueue_steps(h, left);
   HIPCHK(hipGetLastError());
   return SPH_OK;
+}
+
+int sph_resident_fits(sph_handle* h, int32_t* fits) {
+  if (!h || !fits) return SPH_E_INVAL;
+  *fits = resident_ok(h) ? 1 : 0;
+  return SPH_OK;
+}
+
+int sph_rollout_resident(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const double* theta_ref_dev,
+                         int32_t n_ref, int32_t log_stride, float* y_log_dev, float* wrench_log_dev,
+                         float* u_log_dev, float* wmean_log_dev) {
+  if (!h || n_steps < 0 || log_stride < 0 || n_ref < 0) return SPH_E_INVAL;
+  if (!resident_ok(h)) return SPH_E_CAPACITY;
+  if (n_steps == 0) return SPH_OK;
+  int rc = set_rollout(h, u_seq_dev, theta_ref_dev, n_ref, log_stride, n_steps, y_log_dev, wrench_log_dev,
+                       u_log_dev, wmean_log_dev);
+  if (rc) return rc;
+  // the state of buffer `cur` is integrated between rollouts; the kernel
+  // keeps each particle in its slot
+  for (int s0 = 0; s0 < n_steps; s0 += kResChunk) {
+    const int steps = n_steps - s0 < kResChunk ? n_steps - s0 : kResChunk;
+    hipLaunchKernelGGL(sph_resident, dim3(h->T), dim3(kResThreads), 0, h->stream, h->at<float2>(h->L.pos[h->cur]),
+                       h->at<float2>(h->L.vel[h->cur]), h->at<float2>(h->L.gpos), h->at<Tank>(h->L.tanks),
+                       h->at<DevRigid>(h->L.rigid), h->at<DevRollout>(h->L.rollout), steps,
+                       h->at<unsigned>(h->L.status));
+  }
+  HIPCHK(hipGetLastError());
+  // particles may have crossed many cells of the multi-kernel path's list:
+  // back to caller order in the other buffer, then the general sort
+  const int c = h->cur, other = 1 - c;
+  if (h->N > 0) {
+    hipLaunchKernelGGL(sph_unpermute, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
+                       h->at<float2>(h->L.pos[c]), h->at<int>(h->L.id[h->ord]), h->N, h->at<float2>(h->L.pos[other]));
+    hipLaunchKernelGGL(sph_unpermute, dim3(nblocks(h->N)), dim3(kBlock), 0, h->stream,
+                       h->at<float2>(h->L.vel[c]), h->at<int>(h->L.id[h->ord]), h->N, h->at<float2>(h->L.vel[other]));
+  }
+  h->binned = false;
+  return sort_fluid(h, h->at<float2>(h->L.pos[other]), h->at<float2>(h->L.vel[other]));
 }
 
 int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const double* theta_ref_dev,

@@ -73,7 +73,8 @@ def sph_run(u_samples: np.ndarray, ref: Optional[np.ndarray], seed: int = 0, rel
     (u_samples [n, 3] world forces and torque), the PD law when ref is given.
     Returns y [n, 6] (state at each sample instant), u [n, 3] (applied
     torque includes the law's), the GPU seconds of the rollout (relaxation
-    excluded), steps and particles."""
+    excluded; the LDS-resident rollout when the tank fits it), steps and
+    particles."""
     sc = W.lpv_tank(seed, ctrl=ref is not None)
     steps = sc.params.ctrl_period
     n = u_samples.shape[0]
@@ -83,7 +84,9 @@ def sph_run(u_samples: np.ndarray, ref: Optional[np.ndarray], seed: int = 0, rel
         u = torch.as_tensor(np.repeat(np.asarray(u_samples, np.float32), steps, axis=0), device=device)
         th = None if ref is None else np.asarray(ref, np.float64)
         torch.cuda.synchronize(device)
-        lg, secs = _gpu_seconds(lambda: sim.rollout(n * steps, u, theta_ref=th, log_stride=steps), sim.stream)
+        resident = sim.resident_fits()
+        lg, secs = _gpu_seconds(lambda: sim.rollout(n * steps, u, theta_ref=th, log_stride=steps, resident=resident),
+                                sim.stream)
         st = sim.status()
         if st != 0:
             raise RuntimeError(f"SPH run raised status {st}")

@@ -154,10 +154,18 @@ class Simulator:
         check(self.L.sph_step(self.h, _ptr(u)), "sph_step")
         self._leave()
 
-    def rollout(self, n_steps: int, u_seq=None, theta_ref=None, log_stride: int = 0, logs: bool = True):
+    def resident_fits(self) -> bool:
+        """Every tank fits the LDS-resident rollout (``sph_resident_fits``)."""
+        f = C.c_int32()
+        check(self.L.sph_resident_fits(self.h, C.byref(f)), "sph_resident_fits")
+        return bool(f.value)
+
+    def rollout(self, n_steps: int, u_seq=None, theta_ref=None, log_stride: int = 0, logs: bool = True,
+                resident: bool = False):
         """Runs n_steps; returns a dict of device log tensors (y, wrench, u,
         wrench_mean), [n_log, k] for one tank, [T, n_log, k] for a batch.
-        Batch inputs: u_seq [T, n_steps, 3], theta_ref [T, n_ref]."""
+        Batch inputs: u_seq [T, n_steps, 3], theta_ref [T, n_ref].
+        resident: run them with ``sph_rollout_resident`` (small tanks)."""
         self._enter()
         u = None
         if u_seq is not None:
@@ -178,10 +186,10 @@ class Simulator:
                    "u": torch.zeros(*shape, 3, device=self.device),
                    "wrench_mean": torch.zeros(*shape, 3, device=self.device)}
             self._enter()
-        check(self.L.sph_rollout(self.h, int(n_steps), _ptr(u), _ptr(ref),
-                                 0 if ref is None else int(ref.shape[1]), int(log_stride),
-                                 _ptr(out.get("y")), _ptr(out.get("wrench")), _ptr(out.get("u")),
-                                 _ptr(out.get("wrench_mean"))), "sph_rollout")
+        fn = self.L.sph_rollout_resident if resident else self.L.sph_rollout
+        check(fn(self.h, int(n_steps), _ptr(u), _ptr(ref), 0 if ref is None else int(ref.shape[1]),
+                 int(log_stride), _ptr(out.get("y")), _ptr(out.get("wrench")), _ptr(out.get("u")),
+                 _ptr(out.get("wrench_mean"))), "sph_rollout_resident" if resident else "sph_rollout")
         self._keep = [u, ref]
         self._leave()
         return out
