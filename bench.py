@@ -231,6 +231,52 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50):
     return out
 
 
+def lpv_leg():
+    """The LPV surrogate kernels at the paper's identification size (2,200
+    samples): one loss + gradient evaluation for 8 models (the paper's
+    restart count) and for 4,096 at once, 100 Adam iterations of 8 models,
+    and 16,384 closed-loop runs of manoeuvre 1 in one launch."""
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd import lpv as L
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(0)
+    n = 2200
+    u = torch.as_tensor(W.lpv_input_train(0, n) / 40.0, device=dev)
+    y = torch.as_tensor(rng.normal(size=(n, 3)) * 0.1, device=dev)
+    out = {"workload": f"LPV-SS (n_x 4, n_u 3, n_y 3, 2x4 tanh scheduling), {n} samples"}
+
+    def models(R):
+        V = rng.normal(size=(R, L.N_PARAM)) * 0.1
+        V[:, :16] = np.tile((0.95 * np.eye(4)).ravel(), (R, 1))
+        return torch.as_tensor(V, device=dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    for R in (8, 4096):
+        P = models(R)
+        ws = L.workspace(R, n, dev)
+        out[f"loss_grad_ms_{R}_models"] = 1e3 * timed(lambda: L.loss_grad(P, u, y, ws=ws), 5)
+    P = models(8)
+    ws = L.workspace(8, n, dev)
+    out["adam_ms_per_iteration_8_models"] = 1e3 * timed(lambda: L.adam(P, u, y, 100, ws=ws), 1) / 100
+    force, ref = W.manoeuvre_profile(1)
+    Pc = models(16384)
+    refs = torch.as_tensor(np.broadcast_to(ref, (16384, ref.size)).copy(), device=dev)
+    fc = torch.as_tensor(force, device=dev)
+    secs = timed(lambda: L.closed_loop(Pc, fc, refs, W.LPV_TS, 50.0, 30.0, [40.0] * 3, [0.1] * 3), 3)
+    out["closed_loop_16384_runs_ms"] = 1e3 * secs
+    out["closed_loop_runs_per_s"] = 16384 / secs
+    return out
+
+
 def linearization_leg(n_dir: int = 64, steps: int = 400):
     """Linearizations on a rectangular tank of ~8,000 particles over `steps`
     steps: the tangent-linear rollout along n_dir directions (input torque
@@ -282,6 +328,7 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-paper-leg", action="store_true")
     ap.add_argument("--no-linearization-leg", action="store_true")
+    ap.add_argument("--no-lpv-leg", action="store_true")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes per particle of the closed-loop leg (0: sph_autotune chooses)")
     ap.add_argument("--near-lists", type=int, default=-1,
@@ -379,6 +426,8 @@ def main() -> int:
         status |= out["batch"]["status"]
     if not args.no_linearization_leg:
         out["linearization"] = linearization_leg()
+    if not args.no_lpv_leg:
+        out["lpv"] = lpv_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
     print(json.dumps(out))
