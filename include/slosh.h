@@ -53,6 +53,7 @@ extern "C" {
 #define SPH_EOS_TAIT 0        /* P = B((rho/rho0)^gamma - 1), B = rho0 c0^2/gamma */
 #define SPH_EOS_LINEAR 1      /* P = k (rho - rho0)  (eq. EOS) */
 #define SPH_EOS_LINEAR_CLAMPED 2  /* P = max(k (rho - rho0), 0): eq. EOS without tension */
+#define SPH_EOS_TAIT_CLAMPED 3    /* P = max(B((rho/rho0)^gamma - 1), 0): Tait without tension */
 #define SPH_MOTION_FREE 0     /* Newton-Euler rigid body (eq. tankdynamics) */
 #define SPH_MOTION_SINE 1     /* prescribed theta = A sin(2 pi f t), r = 0 */
 #define SPH_CTRL_NONE 0

@@ -17,8 +17,8 @@
  *   density        rho_i = m (sum_f W_cb + gamma1 sum_g W_cb)  (eq. density_update,
  *                  self term included);
  *   pressure       Tait  P = B((rho/rho0)^gamma - 1), B = rho0 c0^2 / gamma,
- *                  or the paper's linear  P = k (rho - rho0)  (eq. EOS), also
- *                  in a variant clamped at P >= 0 (no tension);
+ *                  or the paper's linear  P = k (rho - rho0)  (eq. EOS), each
+ *                  also in a variant clamped at P >= 0 (no tension);
  *   fluid forces   symmetric pressure (eq. momentum) and artificial viscosity
  *                  (eq. viscous) with grad_i W = W'(r) r_ij / r  (Section 3.1);
  *   wall forces    ghost-to-fluid pressure (eq. pressure_b2f) and Akinci
@@ -63,7 +63,7 @@
 #endif
 
 typedef struct {
-  int32_t eos;          /* 0 Tait, 1 linear, 2 linear clamped at zero pressure */
+  int32_t eos;          /* 0 Tait, 1 linear, 2 linear and 3 Tait clamped at zero pressure */
   int32_t motion;       /* 0 free (Newton-Euler), 1 prescribed sine rotation */
   int32_t ctrl;         /* 0 none, 1 PD with zero-order hold */
   int32_t kernel_norm;  /* 0 normalised 5/(14 pi h^2), 1 as printed 15/(14 pi h^2) */
@@ -127,7 +127,9 @@ double ora_eos(const ora_params* p, double rho) {
     return P > 0.0 ? P : 0.0;
   }
   double B = p->rho0 * p->c0 * p->c0 / p->tait_gamma;
-  return B * (pow(rho / p->rho0, p->tait_gamma) - 1.0);
+  double P = B * (pow(rho / p->rho0, p->tait_gamma) - 1.0);
+  if (p->eos == 3 && !(P > 0.0)) P = 0.0;   /* Tait without tension */
+  return P;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -207,7 +207,7 @@ __device__ __forceinline__ float cubic_grad_f(float q) {
 
 __device__ __forceinline__ float eos_over_rho2(float rho, const Consts& k, float* P_out) {
   float P;
-  if (k.eos != SPH_EOS_TAIT) {
+  if (k.eos == SPH_EOS_LINEAR || k.eos == SPH_EOS_LINEAR_CLAMPED) {
     P = k.k_lin * (rho - k.rho0);
     if (k.eos == SPH_EOS_LINEAR_CLAMPED) P = fmaxf(P, 0.0f);
   } else {
@@ -226,6 +226,7 @@ __device__ __forceinline__ float eos_over_rho2(float rho, const Consts& k, float
       xp = powf(x, k.tgamma_f);
     }
     P = k.B * (xp - 1.0f);
+    if (k.eos == SPH_EOS_TAIT_CLAMPED) P = fmaxf(P, 0.0f);
   }
   if (P_out) *P_out = P;
   return P / (rho * rho);
@@ -1884,8 +1885,10 @@ int nblocks(long long threads) { return threads > 0 ? (int)((threads + kBlock - 
 bool params_ok(const sph_params* p) {
   if (!p) return false;
   if (!(p->h > 0 && p->h_spiky > 0 && p->mass > 0 && p->dt > 0 && p->rho0 > 0)) return false;
-  if (p->eos != SPH_EOS_TAIT && p->eos != SPH_EOS_LINEAR && p->eos != SPH_EOS_LINEAR_CLAMPED) return false;
-  if (p->eos == SPH_EOS_TAIT && !(p->c0 > 0 && p->tait_gamma > 0)) return false;
+  if (p->eos != SPH_EOS_TAIT && p->eos != SPH_EOS_LINEAR && p->eos != SPH_EOS_LINEAR_CLAMPED &&
+      p->eos != SPH_EOS_TAIT_CLAMPED)
+    return false;
+  if ((p->eos == SPH_EOS_TAIT || p->eos == SPH_EOS_TAIT_CLAMPED) && !(p->c0 > 0 && p->tait_gamma > 0)) return false;
   if (p->motion != SPH_MOTION_FREE && p->motion != SPH_MOTION_SINE) return false;
   if (p->ctrl != SPH_CTRL_NONE && p->ctrl != SPH_CTRL_PD_ZOH) return false;
   if (p->kernel_norm != SPH_KNORM_UNIT && p->kernel_norm != SPH_KNORM_PRINTED) return false;
@@ -1911,7 +1914,8 @@ Consts make_consts(const sph_params* p) {
   k.gamma1 = (float)p->gamma1;
   k.rho0 = (float)p->rho0;
   k.rho0_inv = (float)(1.0 / p->rho0);
-  k.B = (float)(p->eos == SPH_EOS_TAIT ? p->rho0 * p->c0 * p->c0 / p->tait_gamma : 0.0);
+  k.B = (float)(p->eos == SPH_EOS_TAIT || p->eos == SPH_EOS_TAIT_CLAMPED ? p->rho0 * p->c0 * p->c0 / p->tait_gamma
+                                                                          : 0.0);
   k.k_lin = (float)p->k_lin;
   k.a2h = (float)(2.0 * p->visc_alpha * h);
   k.beta2 = (float)(2.0 * p->visc_beta);
@@ -2078,7 +2082,7 @@ __device__ __forceinline__ float cubic_grad_f_d(float q) {
 // P/rho^2 and its derivative with respect to rho.
 __device__ __forceinline__ float eos_over_rho2_d(float rho, const Consts& k, float* dpi) {
   float P, dP;
-  if (k.eos != SPH_EOS_TAIT) {
+  if (k.eos == SPH_EOS_LINEAR || k.eos == SPH_EOS_LINEAR_CLAMPED) {
     P = k.k_lin * (rho - k.rho0);
     dP = k.k_lin;
     if (k.eos == SPH_EOS_LINEAR_CLAMPED && !(P > 0.0f)) {
@@ -2096,6 +2100,10 @@ __device__ __forceinline__ float eos_over_rho2_d(float rho, const Consts& k, flo
     }
     P = k.B * (xp1 * x - 1.0f);
     dP = k.B * k.tgamma_f * xp1 * k.rho0_inv;
+    if (k.eos == SPH_EOS_TAIT_CLAMPED && !(P > 0.0f)) {
+      P = 0.0f;
+      dP = 0.0f;
+    }
   }
   const float r2 = rho * rho;
   *dpi = dP / r2 - 2.0f * P / (r2 * rho);

@@ -4,7 +4,8 @@ Orchestration only: every rollout runs in the SPH kernels (``sph_rollout``),
 windows are built by ``mlp_make_windows``, and the network is trained and
 evaluated by the MFMA kernels (``mlp_train_step``, ``mlp_forward``).
 
-Data recipe (the random-tank generator of ``workloads.random_tank``):
+Data recipe (the random-tank generator of ``workloads.random_tank``, with
+the Tait law clamped at zero pressure by default, see ``generate``):
 rectangular or circular tank, fill U[0.2, 0.8], 2k-60k particles, torque a
 5-tone random-phase multisine on the 0.05 Hz grid with amplitude U[0, 50] N m,
 spacecraft m = 1000 kg, J = 500 kg m^2.  Each tank is first brought to rest
@@ -54,10 +55,14 @@ def _relax(sim: Simulator, cycles: int, steps: int) -> None:
 
 def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, relax_cycles: int = 40,
              relax_steps: int = 100, n_min: int = 2000, n_max: int = 60000, device="cuda:0",
-             batch: int = 256, lanes: Optional[int] = None) -> RolloutSet:
+             batch: int = 256, lanes: Optional[int] = None, eos: int = W.EOS_TAIT_CLAMPED,
+             log=None) -> RolloutSet:
     """Runs one relaxed, forced rollout per seed, up to ``batch`` tanks per
     handle (one set of launches).  sph_seconds sums the GPU time of the forced
-    rollouts (relaxation excluded)."""
+    rollouts (relaxation excluded).  eos: the Tait law without tension by
+    default; with the literal one (W.EOS_TAIT) the zero-gravity fluid
+    oscillates by itself (tensile instability) and its wrench does not
+    follow the inputs."""
     dev = torch.device(device)
     R = len(seeds)
     T = (n_steps + log_stride - 1) // log_stride
@@ -68,7 +73,7 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
     sph_seconds = 0.0
     for g0 in range(0, R, batch):
         idx = list(range(g0, min(R, g0 + batch)))
-        scs = [W.random_tank(int(seeds[i]), n_steps=n_steps, n_min=n_min, n_max=n_max) for i in idx]
+        scs = [W.random_tank(int(seeds[i]), n_steps=n_steps, n_min=n_min, n_max=n_max, eos=eos) for i in idx]
         for i, sc in zip(idx, scs):
             n_fluid[i] = sc.n_fluid
             fill[i] = float(sc.fill)
@@ -94,6 +99,8 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
         feat[sl, :, 2] = lg["u"][:, :, 2]
         wrench[sl] = lg["wrench_mean"]
         sim.close()
+        if log is not None:
+            log(f"rollouts {idx[-1] + 1}/{R} done ({sph_seconds:.1f} s of SPH so far)")
     return RolloutSet(feat, fill, wrench, n_fluid, sph_seconds, n_steps)
 
 

@@ -36,6 +36,8 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tanks-per-launch", type=int, default=256)
+    ap.add_argument("--literal-tait", action="store_true",
+                    help="data with the Tait law as written (negative pressures allowed)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
@@ -45,12 +47,14 @@ def main(argv=None) -> int:
     t0 = time.time()
     train_seeds = list(range(1000, 1000 + a.train))
     test_seeds = list(range(900000, 900000 + a.test))
+    import workloads as W
     kw = dict(n_steps=a.steps, log_stride=a.stride, relax_cycles=a.relax_cycles,
-              relax_steps=a.relax_steps, n_min=a.n_min, n_max=a.n_max)
+              relax_steps=a.relax_steps, n_min=a.n_min, n_max=a.n_max,
+              eos=W.EOS_TAIT if a.literal_tait else W.EOS_TAIT_CLAMPED)
     log(f"generating {a.train} training rollouts")
-    tr = S.generate(train_seeds, batch=a.tanks_per_launch, **kw)
+    tr = S.generate(train_seeds, batch=a.tanks_per_launch, log=log, **kw)
     log(f"generating {a.test} held-out rollouts")
-    te = S.generate(test_seeds, batch=a.tanks_per_launch, **kw)
+    te = S.generate(test_seeds, batch=a.tanks_per_launch, log=log, **kw)
     norm = S.norm_from(tr)
     xtr, ytr = S.windows(tr, norm)
     xte, yte = S.windows(te, norm)
@@ -66,6 +70,7 @@ def main(argv=None) -> int:
         t_nn += S.time_inference(net, xte[b:b + 65536].contiguous())
     res = {
         "train_rollouts": a.train, "test_rollouts": a.test, "steps": a.steps, "log_stride": a.stride,
+        "eos": "tait" if a.literal_tait else "tait_clamped",
         "relax": [a.relax_cycles, a.relax_steps], "epochs": a.epochs, "batch": a.batch,
         "train_windows": int(xtr.shape[0]), "test_windows": int(n_win),
         "nrmse": [float(v) for v in err], "nrmse_max": float(np.max(err)),

@@ -52,6 +52,8 @@ SCENARIOS = {
     "paper_p0_random_literal_eos": lambda: W.paper_p0(1, n_steps=50, spawn="random", eos=W.EOS_LINEAR),
     "random_rect": lambda: W.random_tank(2, n_steps=50, n_min=2000, n_max=4000, shape="rect"),
     "random_circle": lambda: W.random_tank(5, n_steps=50, n_min=2000, n_max=4000, shape="circle"),
+    "random_circle_tait_clamped": lambda: W.random_tank(6, n_steps=50, n_min=2000, n_max=4000, shape="circle",
+                                                        eos=W.EOS_TAIT_CLAMPED),
 }
 
 

@@ -10,15 +10,19 @@ random-tank rollouts and judged on held-out rollouts.  What is asserted:
   (the training mean) by more than 10 %.
 
 What is not asserted, and why: a held-out error below the constant
-predictor.  In these zero-gravity rollouts the slosh wrench is dominated by
-a self-excited oscillation of the weakly compressible fluid that grows from
-the relaxed state with or without input (the FP64 oracle shows the same), so
-over a log interval it is uncorrelated with the inputs (theta, omega, input
-torque, fill) and with the previous interval.  The measured per-channel
-NRMSE is printed beside the constant predictor's.
+predictor.  With the Tait law as written (used here) the zero-gravity slosh
+wrench is dominated by a self-excited oscillation of the weakly compressible
+fluid (a tensile instability: negative pressures; the FP64 oracle shows the
+same), so over a log interval it is uncorrelated with the inputs (theta,
+omega, input torque, fill) and with the previous interval.  The data
+generator's default clamps the pressure at zero, which removes the
+oscillation; the full-size training on such data is a separate run.  The
+measured per-channel NRMSE is printed beside the constant predictor's.
 """
 import numpy as np
 import pytest
+
+import workloads as W
 
 torch = pytest.importorskip("torch")
 
@@ -27,7 +31,11 @@ pytestmark = pytest.mark.gpu
 
 def test_surrogate_speedup_and_error():
     from paper_2604_12505_amd import surrogate as S
-    kw = dict(n_steps=1000, log_stride=10, relax_cycles=10, relax_steps=100, n_min=2000, n_max=4000)
+    # the Tait law as written: with 24 short rollouts the clamped law's
+    # wrench (zero until the fluid is compressed, then spiky) gives too few
+    # samples for the statistics of the comparison below
+    kw = dict(n_steps=1000, log_stride=10, relax_cycles=10, relax_steps=100, n_min=2000, n_max=4000,
+              eos=W.EOS_TAIT)
     tr = S.generate(list(range(10, 34)), **kw)
     te = S.generate(list(range(500, 506)), **kw)
     norm = S.norm_from(tr)

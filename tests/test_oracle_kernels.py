@@ -108,3 +108,12 @@ def test_clamped_linear_eos_has_no_tension():
     assert O.eos(p, p.rho0 + 10.0) == pytest.approx(p.k_lin * 10.0, rel=1e-12)
     assert O.eos(p, p.rho0 - 5.0) == 0.0
     assert O.eos(p, p.rho0) == 0.0
+
+
+def test_clamped_tait_eos_has_no_tension():
+    import workloads as W
+    p = W.random_tank(0, n_steps=1, eos=W.EOS_TAIT_CLAMPED).params
+    lit = W.random_tank(0, n_steps=1).params
+    assert O.eos(p, 1.01 * p.rho0) == pytest.approx(O.eos(lit, 1.01 * lit.rho0), rel=1e-15)
+    assert O.eos(lit, 0.99 * lit.rho0) < 0.0
+    assert O.eos(p, 0.99 * p.rho0) == 0.0

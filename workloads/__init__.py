@@ -31,7 +31,7 @@ from typing import Optional
 
 import numpy as np
 
-EOS_TAIT, EOS_LINEAR, EOS_LINEAR_CLAMPED = 0, 1, 2
+EOS_TAIT, EOS_LINEAR, EOS_LINEAR_CLAMPED, EOS_TAIT_CLAMPED = 0, 1, 2, 3
 MOTION_FREE, MOTION_SINE = 0, 1
 CTRL_NONE, CTRL_PD_ZOH = 0, 1
 KNORM_UNIT, KNORM_PRINTED = 0, 1
@@ -269,10 +269,11 @@ def closed_loop_circle(seed: int = 0, n_steps: int = 20000, dx: float = 0.004,
 
 
 def random_tank(seed: int, n_steps: int = 5000, n_min: int = 2000, n_max: int = 60000,
-                shape: Optional[str] = None) -> Scenario:
+                shape: Optional[str] = None, eos: int = EOS_TAIT) -> Scenario:
     """Random tank for the surrogate data set: rectangle 1.0 x 0.5 or circle
     R = 0.5 (equal odds), fill U[0.2, 0.8], particle count U{n_min..n_max},
-    torque a 5-tone multisine with amplitude U[0, 50] N m."""
+    torque a 5-tone multisine with amplitude U[0, 50] N m.  eos: EOS_TAIT
+    (the measured batch configuration) or EOS_TAIT_CLAMPED."""
     rng = np.random.default_rng(seed)
     if shape is None:
         shape = "rect" if rng.random() < 0.5 else "circle"
@@ -294,6 +295,7 @@ def random_tank(seed: int, n_steps: int = 5000, n_min: int = 2000, n_max: int = 
         ext = (R, R)
         size = 2 * R
     p = _fluid_params(dx)
+    p.eos = eos
     p.motion = MOTION_FREE
     p.ctrl = CTRL_NONE
     p.body_mass, p.body_inertia = 1000.0, 500.0
