@@ -55,14 +55,14 @@ SORT_EVERY = 4
 NEIGHBOURS = 20
 FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 
-# HBM traffic of the force kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (per dispatch, scaled by the copy-kernel calibration), valid for the source
-# whose hash is recorded; null once the kernel source changes.
-# Measured on the closed-loop tank with 16 lanes per particle and the full
-# walk (profiles/hbm_traffic_closed_loop_circle.md): 1,705,965 B per plain
-# force launch and 1,901,565 B per binning one (every fourth), averaged.
-TRAFFIC = {"kernel": "sph_force", "lanes": 16, "near_lists": False,
-           "src_sha1": "03120e04d5b06c9bc08891bfdaa386e361609926", "bytes_per_launch": 1754865}
+# HBM traffic per launch of the neighbour kernels from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE (per dispatch, scaled by the copy-kernel
+# calibration, averaged over the plain and the rebuild-step variants in the
+# proportion they run), on the closed-loop tank for the configurations the
+# autotuner picks from (profiles/hbm_traffic_closed_loop_circle.md); valid
+# for the source whose hash is recorded, null once the kernel source changes.
+TRAFFIC = {"src_sha1": "527ba937313bcf3115ef8321b06886b6e73b4e12",
+           "bytes_per_launch": {"sph_force/16/0": 1727258, "sph_density/16/0": 2006377, "sph_force/16/1": 3181284, "sph_density/16/1": 3355478, "sph_force/32/0": 1776759, "sph_density/32/0": 2002287, "sph_force/32/1": 3238322, "sph_density/32/1": 3353623}}
 
 
 def src_hash() -> str:
@@ -97,10 +97,8 @@ def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None):
     alg_bytes = bp * n_fluid + bg * n_ghost + bc * n_cells
     secs = kus[dominant] * 1e-6
     gbs = alg_bytes / secs / 1e9
-    traffic = TRAFFIC["bytes_per_launch"] if (TRAFFIC["src_sha1"] == src_hash()
-                                              and TRAFFIC["kernel"] == "sph_" + dominant
-                                              and TRAFFIC["lanes"] == lanes
-                                              and TRAFFIC["near_lists"] == near) else None
+    key = f"sph_{dominant}/{lanes}/{1 if near else 0}"
+    traffic = TRAFFIC["bytes_per_launch"].get(key) if TRAFFIC["src_sha1"] == src_hash() else None
     hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
            "algorithmic_bytes_per_launch": alg_bytes}
     if dominant in FLOP:
@@ -158,7 +156,7 @@ def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int, lanes: i
             "roofline": kernel_roofline(kus, n, g, nc)}
 
 
-def paper_leg(relax_cycles: int = 60, relax_steps: int = 50):
+def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0):
     """The paper's benchmark (Tables 1-2: 666 particles spawned at random in a
     circular tank, relaxed to rest, linear EOS without tension, dt = 1 ms, PD
     attitude law at 0.05 s) flying the two reconstructed manoeuvres (60 s and
@@ -182,8 +180,10 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50):
     for k, paper_s in ((1, 9.9093), (2, 5.1876)):
         force, ref = W.manoeuvre_profile(k, ts=per * sc.params.dt)
         n = force.shape[0] * per
+        if max_steps > 0:
+            n = min(n, max_steps)
         u = np.zeros((n, 3), np.float32)
-        u[:, :2] = np.repeat(force, per, axis=0)
+        u[:, :2] = np.repeat(force, per, axis=0)[:n]
         uu = torch.as_tensor(u, device=dev)
         th = torch.as_tensor(ref, dtype=torch.float64, device=dev)
         res = {"steps": n, "paper_wall_s": paper_s}
@@ -204,7 +204,7 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50):
     sim.close()
     # many copies of the scenario at once (Monte Carlo use): 256 tanks from
     # different random spawns, profile 1's first 4,000 steps, both paths
-    n_b, steps_b = 256, 4000
+    n_b, steps_b = 256, (min(4000, max_steps) if max_steps > 0 else 4000)
     scs = [W.paper_p0(seed=s, n_steps=1, spawn="random") for s in range(n_b)]
     bsim = Simulator.batch(scs, device=dev)
     _relax(bsim, 10, relax_steps)
@@ -329,6 +329,8 @@ def main() -> int:
     ap.add_argument("--no-paper-leg", action="store_true")
     ap.add_argument("--no-linearization-leg", action="store_true")
     ap.add_argument("--no-lpv-leg", action="store_true")
+    ap.add_argument("--paper-only", action="store_true", help="run only the paper-scenario leg")
+    ap.add_argument("--paper-steps", type=int, default=0, help="cap on the paper leg's steps per run (0: full)")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes per particle of the closed-loop leg (0: sph_autotune chooses)")
     ap.add_argument("--near-lists", type=int, default=-1,
@@ -356,6 +358,11 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    if args.paper_only:
+        res = paper_leg(max_steps=args.paper_steps)
+        print(json.dumps(res))
+        ok = all(p["status"] == 0 for p in res["profiles"].values())
+        return 0 if ok else 1
     if args.batch_only:
         res = batch_leg(args.batch_tanks, args.batch_steps, 16, 16, args.lanes, args.near_lists)
         print(json.dumps(res))
@@ -418,7 +425,7 @@ def main() -> int:
     }
     if not args.no_paper_leg:
         # the paper's own scenario (timing context for its Table 3)
-        out["paper_scenario"] = paper_leg()
+        out["paper_scenario"] = paper_leg(max_steps=args.paper_steps)
         for prof in out["paper_scenario"]["profiles"].values():
             status |= prof["status"]
     if args.batch_tanks > 0:
