@@ -65,6 +65,11 @@ TRAFFIC = {"src_sha1": "527ba937313bcf3115ef8321b06886b6e73b4e12",
            "bytes_per_launch": {"sph_force/16/0": 1727258, "sph_density/16/0": 2006377, "sph_force/16/1": 3181284, "sph_density/16/1": 3355478, "sph_force/32/0": 1776759, "sph_density/32/0": 2002287, "sph_force/32/1": 3238322, "sph_density/32/1": 3353623}}
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (stdout carries the one JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def src_hash() -> str:
     h = hashlib.sha1()
     with open(os.path.join(ROOT, "paper_2604_12505_amd", "csrc", "sph.hip"), "rb") as f:
@@ -423,20 +428,26 @@ def main() -> int:
         "kernel_us": {k: round(v, 3) for k, v in kus.items()},
         "roofline": roofline,
     }
+    progress("closed-loop tank measured")
     if not args.no_paper_leg:
         # the paper's own scenario (timing context for its Table 3)
         out["paper_scenario"] = paper_leg(max_steps=args.paper_steps)
+        progress("paper scenario leg done")
         for prof in out["paper_scenario"]["profiles"].values():
             status |= prof["status"]
     if args.batch_tanks > 0:
         out["batch"] = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
         status |= out["batch"]["status"]
+        progress("batch leg done")
     if not args.no_linearization_leg:
         out["linearization"] = linearization_leg()
+        progress("linearization leg done")
     if not args.no_lpv_leg:
         out["lpv"] = lpv_leg()
+        progress("LPV leg done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+        progress("CPU baseline done")
     print(json.dumps(out))
     return 0 if status == 0 else 1
 
