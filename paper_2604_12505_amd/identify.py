@@ -6,12 +6,13 @@ and its closed-loop validation (Section 5.4), on this library's kernels.
 Steps (orchestration only; every rollout runs in the SPH kernels, every
 simulation, gradient and optimizer step in the LPV kernels):
 
-1. SPH data.  The spacecraft of ``workloads.lpv_tank`` (the paper's Table 1
-   with this library's fluid model), brought to rest first, is driven open
-   loop by the input train of ``workloads.lpv_input_train`` (2,200 samples of
-   0.05 s); the velocities (rdot_x, rdot_y, thetadot) are logged at the
-   sample instants.  The same tank, under the sampled PD attitude law, flies
-   the two manoeuvres of ``workloads.manoeuvre_profile``.
+1. SPH data.  The paper's spacecraft and fuel (Tables 1-2: 666 particles
+   spawned at random and relaxed to rest, dt = 1 ms; ``--tank tait`` takes
+   this library's Tait fluid instead) are driven open loop by the input
+   train of ``workloads.lpv_input_train`` (2,200 samples of 0.05 s); the
+   velocities (rdot_x, rdot_y, thetadot) are logged at the sample instants.
+   The same tank, under the sampled PD attitude law, flies the two
+   manoeuvres of ``workloads.manoeuvre_profile``.
 2. Scaling.  Each input and output channel is divided by its root mean
    square over the training record (zero stays zero, so the model needs no
    offset terms).
@@ -32,6 +33,7 @@ simulation, gradient and optimizer step in the LPV kernels):
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import sys
@@ -67,15 +69,29 @@ def _gpu_seconds(fn, stream):
     return out, e0.elapsed_time(e1) / 1e3
 
 
-def sph_run(u_samples: np.ndarray, ref: Optional[np.ndarray], seed: int = 0, relax=(20, 200),
-            device="cuda:0") -> dict:
-    """One SPH run of the lpv_tank: inputs held for one sample each
-    (u_samples [n, 3] world forces and torque), the PD law when ref is given.
-    Returns y [n, 6] (state at each sample instant), u [n, 3] (applied
-    torque includes the law's), the GPU seconds of the rollout (relaxation
-    excluded; the LDS-resident rollout when the tank fits it), steps and
-    particles."""
-    sc = W.lpv_tank(seed, ctrl=ref is not None)
+def tank_scenario(tank: str, seed: int, ctrl: bool):
+    """'paper': the paper's spacecraft and fluid (Tables 1-2, 666 particles
+    spawned at random, linear EOS without tension, dt = 1 ms); 'tait': the
+    same spacecraft with this library's Tait fluid (``workloads.lpv_tank``)."""
+    if tank == "paper":
+        sc = W.paper_p0(seed, n_steps=1, spawn="random")
+        if not ctrl:
+            sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, ctrl=W.CTRL_NONE))
+        return sc
+    if tank == "tait":
+        return W.lpv_tank(seed, ctrl=ctrl)
+    raise ValueError("tank must be 'paper' or 'tait'")
+
+
+def sph_run(u_samples: np.ndarray, ref: Optional[np.ndarray], seed: int = 0, relax=(60, 50),
+            device="cuda:0", tank: str = "paper") -> dict:
+    """One SPH run: inputs held for one sample each (u_samples [n, 3] world
+    forces and torque), the PD law when ref is given, from the fluid relaxed
+    to rest (relax = cycles x steps of kinetic damping).  Returns y [n, 6]
+    (state at each sample instant), u [n, 3] (applied torque includes the
+    law's), the GPU seconds of the rollout (relaxation excluded; the
+    LDS-resident rollout when the tank fits it), steps and particles."""
+    sc = tank_scenario(tank, seed, ref is not None)
     steps = sc.params.ctrl_period
     n = u_samples.shape[0]
     sim = Simulator.from_scenario(sc, device=device)
@@ -123,11 +139,12 @@ def lti_starts(rng, R: int) -> np.ndarray:
 def lpv_starts(rng, lti: np.ndarray, R: int, m1_std: float = 0.01) -> np.ndarray:
     """M0 and x0 from the LTI model, M1 ~ N(0, m1_std^2), the scheduling
     network by Xavier's uniform rule (bound sqrt(6 / (fan_in + fan_out))),
-    zero biases."""
+    zero biases.  The first start has M1 = 0: it is the LTI model itself, so
+    the best restart is never worse than the model the fit starts from."""
     out = []
-    for _ in range(R):
+    for r in range(R):
         v = lti.copy()
-        v[40:80] = m1_std * rng.normal(size=40)
+        v[40:80] = 0.0 if r == 0 else m1_std * rng.normal(size=40)
         o = 80
         for fan_in, fan_out in ((7, 4), (4, 4), (4, 1)):
             a = math.sqrt(6.0 / (fan_in + fan_out))
@@ -233,6 +250,7 @@ def main(argv=None) -> int:
     ap.add_argument("--lti-adam", type=int, default=2000)
     ap.add_argument("--lti-lbfgs", type=int, default=6000)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tank", default="paper", choices=("paper", "tait"))
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
@@ -242,12 +260,12 @@ def main(argv=None) -> int:
     t0 = time.time()
     u_train = W.lpv_input_train(a.seed, a.samples)
     log(f"SPH identification run: {a.samples} samples")
-    tr = sph_run(u_train, None, seed=a.seed)
+    tr = sph_run(u_train, None, seed=a.seed, tank=a.tank)
     log(f"  {tr['steps']} steps of {tr['n_fluid']} particles in {tr['sph_seconds']:.1f} s")
     y_train = tr["y"][:, 3:6]
     res = identify(u_train, y_train, a.lti_starts, a.restarts, a.adam, a.lbfgs, a.lti_adam, a.lti_lbfgs,
                    seed=a.seed, log=log)
-    out = {"samples": a.samples, "n_fluid": tr["n_fluid"], "sph_train_seconds": tr["sph_seconds"],
+    out = {"tank": a.tank, "samples": a.samples, "n_fluid": tr["n_fluid"], "sph_train_seconds": tr["sph_seconds"],
            "sph_train_steps": tr["steps"], "lti_starts": a.lti_starts, "restarts": a.restarts,
            "adam_iters": a.adam, "lbfgs_max_iters": a.lbfgs,
            "train_bfr_lti": res["lti_bfr"].tolist(), "train_bfr_lpv": res["lpv_bfr"].tolist(),
@@ -259,7 +277,7 @@ def main(argv=None) -> int:
         force, ref = W.manoeuvre_profile(k)
         u = np.concatenate([force, np.zeros((force.shape[0], 1))], 1)
         log(f"SPH manoeuvre {k}: {force.shape[0]} samples")
-        run = sph_run(u, ref, seed=a.seed)
+        run = sph_run(u, ref, seed=a.seed, tank=a.tank)
         prof = {"sph_seconds": run["sph_seconds"], "sph_steps": run["steps"]}
         for name in ("lti", "lpv"):
             y, secs = closed_loop(res[name], force, ref, res, run["kp"], run["kd"])
@@ -270,7 +288,7 @@ def main(argv=None) -> int:
         log(f"  BFR r_x r_y theta rdot_x rdot_y thetadot: LTI {np.round(prof['lti_bfr'], 2).tolist()} "
             f"LPV {np.round(prof['lpv_bfr'], 2).tolist()}; SPH {run['sph_seconds']:.2f} s, "
             f"LPV {prof['lpv_seconds'] * 1e3:.2f} ms")
-    kp, kd = W.lpv_tank(ctrl=True).params.kp, W.lpv_tank(ctrl=True).params.kd
+    kp, kd = tr["kp"], tr["kd"]
     rate, secs = monte_carlo_rate(res["lpv"], res, kp, kd)
     out["monte_carlo_traj_per_s"] = rate
     out["monte_carlo_seconds_16384"] = secs

@@ -23,7 +23,7 @@ def test_identification_pipeline_short_record():
     from paper_2604_12505_amd import identify as I
     n = 240
     u = W.lpv_input_train(0, n)
-    run = I.sph_run(u, None, relax=(5, 100))
+    run = I.sph_run(u, None, relax=(20, 50))
     assert run["y"].shape == (n, 6)
     assert np.allclose(run["u"], u, rtol=1e-6, atol=1e-4)
     res = I.identify(u, run["y"][:, 3:6], n_lti=16, n_restarts=16, adam_iters=200, lbfgs_iters=200,
@@ -33,7 +33,7 @@ def test_identification_pipeline_short_record():
     assert res["lpv_bfr"].mean() >= res["lti_bfr"].mean() - 2.0
     force, ref = W.manoeuvre_profile(2)
     force, ref = force[:200], ref[:200]
-    kp, kd = W.lpv_tank(ctrl=True).params.kp, W.lpv_tank(ctrl=True).params.kd
+    kp, kd = run["kp"], run["kd"]
     y, secs = I.closed_loop(res["lpv"], force, ref, res, kp, kd)
     y_ref, _ = O.closed_loop(res["lpv"], force, ref, W.LPV_TS, kp, kd, res["u_scale"], res["y_scale"])
     assert np.allclose(y, y_ref, rtol=1e-10, atol=1e-10 * np.abs(y_ref).max())
