@@ -2558,16 +2558,11 @@ __global__ void vjp_rigid(const double* __restrict__ fpart, int nb, const Tank* 
   double uu[3] = {0.0, 0.0, 0.0};
   if (u && loc >= 0 && loc < n_steps)
     for (int d = 0; d < 3; ++d) uu[d] = u[loc * 3 + d];
+  // the held torque enters the step linearly, so its reverse needs only
+  // whether this step samples the attitude law, not the torque's value
   const bool sample = ra.ctrl == SPH_CTRL_PD_ZOH && ra.ctrl_period > 0 && n % ra.ctrl_period == 0;
-  double tau = st->tau;
-  if (sample) {
-    double ref = 0.0;
-    if (theta_ref && n_ref > 0) {
-      const long long kk = n / ra.ctrl_period;
-      ref = theta_ref[kk < n_ref ? kk : n_ref - 1];
-    }
-    tau = ra.kp * (ref - st->th) - ra.kd * st->thd;
-  }
+  (void)theta_ref;
+  (void)n_ref;
   double sn, cs;
   sincos(st->th, &sn, &cs);
   const double M = ra.body_mass, J = ra.body_inertia, dt = ra.dt;
@@ -2811,7 +2806,7 @@ int single_n(const sph_handle* h) { return h->T == 1 ? h->N : -1; }
 
 template <int G>
 void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev) {
-  const int c = h->cur, o = h->ord;
+  const int c = h->cur;
   const int nt = (int)h->plan.tiles[v];
   auto mark = [&](int i) {
     if (ev) (void)hipEventRecord(ev[i], h->stream);
