@@ -90,7 +90,7 @@ def cpu_baseline(sc, n_steps: int):
                       f"{dt:.1f} s, FP64 C with OpenMP over particles"}
 
 
-def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None):
+def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None, traffic_workload=None):
     """Roofline position of the kernel that takes the most time per step.
 
     The neighbour kernels are arithmetic-bound, not HBM-bound, by the
@@ -102,8 +102,10 @@ def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None):
     alg_bytes = bp * n_fluid + bg * n_ghost + bc * n_cells
     secs = kus[dominant] * 1e-6
     gbs = alg_bytes / secs / 1e9
+    # measured traffic exists for the closed-loop tank only
     key = f"sph_{dominant}/{lanes}/{1 if near else 0}"
-    traffic = TRAFFIC["bytes_per_launch"].get(key) if TRAFFIC["src_sha1"] == src_hash() else None
+    traffic = (TRAFFIC["bytes_per_launch"].get(key)
+               if traffic_workload == "closed_loop_circle" and TRAFFIC["src_sha1"] == src_hash() else None)
     hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
            "algorithmic_bytes_per_launch": alg_bytes}
     if dominant in FLOP:
@@ -236,6 +238,42 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0)
     return out
 
 
+def sweep_leg(ks=(0, 1, 2, 3, 4, 5, 6), steps: int = 200, warmup: int = 40, kernel_steps: int = 16):
+    """The rectangular tank refined by 2^k in spacing (N = 1,600 x 4^k fluid
+    particles, up to 6.55M at k = 6), prescribed sine rotation, autotuned:
+    particle-steps/s and the roofline of the dominant kernel per size.  At
+    k = 5 the working set still fits the 256 MB last-level cache, at k = 6 it
+    does not."""
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd.sph import Simulator
+    dev = torch.device("cuda:0")
+    rows = []
+    for k in ks:
+        sc = W.rect_sweep(k, seed=0, n_steps=warmup + steps + kernel_steps)
+        sim = Simulator.from_scenario(sc, device=dev)
+        lanes = sim.autotune(reps=3 if k >= 5 else 10)
+        near = sim.tuning()[1]
+        sim.rollout(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.rollout(steps)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kus = sim.time_kernels(kernel_steps)
+        rows.append({"k": k, "n_fluid": sc.n_fluid, "n_ghost": sc.n_ghost, "lanes": lanes, "near_lists": near,
+                     "ms_per_step": ms, "particle_steps_per_s": sc.n_fluid / (ms / 1e3), "status": sim.status(),
+                     "kernel_us": {q: round(v, 2) for q, v in kus.items()},
+                     "roofline": kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc), lanes, near)})
+        sim.close()
+        progress(f"sweep k={k}: {sc.n_fluid} particles, {ms:.3f} ms per step")
+    return {"workload": "rect_sweep: rectangle 1.0 x 0.5 m, 50 % fill, dx = 12.5 mm / 2^k, sine rotation",
+            "steps": steps, "rows": rows}
+
+
 def lpv_leg():
     """The LPV surrogate kernels at the paper's identification size (2,200
     samples): one loss + gradient evaluation for 8 models (the paper's
@@ -334,6 +372,8 @@ def main() -> int:
     ap.add_argument("--no-paper-leg", action="store_true")
     ap.add_argument("--no-linearization-leg", action="store_true")
     ap.add_argument("--no-lpv-leg", action="store_true")
+    ap.add_argument("--no-sweep-leg", action="store_true")
+    ap.add_argument("--sweep-only", action="store_true", help="run only the size sweep")
     ap.add_argument("--paper-only", action="store_true", help="run only the paper-scenario leg")
     ap.add_argument("--paper-steps", type=int, default=0, help="cap on the paper leg's steps per run (0: full)")
     ap.add_argument("--lanes", type=int, default=0,
@@ -363,6 +403,10 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    if args.sweep_only:
+        res = sweep_leg()
+        print(json.dumps(res))
+        return 0 if all(r["status"] == 0 for r in res["rows"]) else 1
     if args.paper_only:
         res = paper_leg(max_steps=args.paper_steps)
         print(json.dumps(res))
@@ -404,7 +448,8 @@ def main() -> int:
     # per-kernel durations, HIP events around each kernel of directly launched steps
     kus = sim.time_kernels(args.kernel_steps, u[args.warmup + args.steps:], ref)
     status |= sim.status()
-    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc), lanes, near)
+    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc), lanes, near,
+                               traffic_workload="closed_loop_circle" if args.dx == 0.004 else None)
     sim.close()
 
     out = {
@@ -445,6 +490,10 @@ def main() -> int:
     if not args.no_lpv_leg:
         out["lpv"] = lpv_leg()
         progress("LPV leg done")
+    if not args.no_sweep_leg:
+        out["size_sweep"] = sweep_leg()
+        for r in out["size_sweep"]["rows"]:
+            status |= r["status"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
         progress("CPU baseline done")

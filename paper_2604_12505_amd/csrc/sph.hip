@@ -341,33 +341,116 @@ __global__ void __launch_bounds__(kBlock) sph_bin(const float2* __restrict__ pos
 // ghosts = 1 scans the ghost layout (base q0, count ng).
 __device__ __forceinline__ int scan_slot(int i) { return i + i / kScanPer; }   // padded: no bank conflicts
 
+constexpr int kChunkCells = kScanThreads * kScanPer;
+
+struct ScanLds {
+  int buf[kChunkCells + kScanThreads];
+  int wsum[kScanThreads / 64];
+};
+
+// One chunk of kChunkCells cells from `base`: exclusive scan of the counts
+// plus `carry` written to start (offset by base0), counts cleared; returns
+// the chunk's total.  A coalesced load into LDS, a sequential scan of
+// kScanPer cells per thread, a workgroup scan of the per-thread sums (wave
+// shuffles, wave totals in LDS), a coalesced write back.
+__device__ int scan_chunk(ScanLds& S, int* __restrict__ count, const Tank& tk, int base, int carry, int base0,
+                          int* __restrict__ start) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int q = 0; q < kScanPer; ++q) {
+    const int i = q * kScanThreads + t;
+    S.buf[scan_slot(i)] = base + i < tk.nc ? count[tk.c0 + base + i] : 0;
+  }
+  __syncthreads();
+  int sum = 0;
+  for (int q = 0; q < kScanPer; ++q) {
+    const int k = scan_slot(t * kScanPer + q);
+    const int v = S.buf[k];
+    S.buf[k] = sum;
+    sum += v;
+  }
+  int x = sum;   // inclusive scan of the per-thread sums
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) S.wsum[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    int w = lane < kScanThreads / 64 ? S.wsum[lane] : 0;
+    for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+      int y = __shfl_up(w, off, 64);
+      if (lane >= off) w += y;
+    }
+    if (lane < kScanThreads / 64) S.wsum[lane] = w;
+  }
+  __syncthreads();
+  const int excl = carry + (wave > 0 ? S.wsum[wave - 1] : 0) + x - sum;
+  for (int q = 0; q < kScanPer; ++q) S.buf[scan_slot(t * kScanPer + q)] += excl;
+  const int total = S.wsum[kScanThreads / 64 - 1];
+  __syncthreads();
+  for (int q = 0; q < kScanPer; ++q) {
+    const int i = q * kScanThreads + t;
+    if (base + i < tk.nc) {
+      start[tk.c0 + base + i] = base0 + S.buf[scan_slot(i)];
+      count[tk.c0 + base + i] = 0;
+    }
+  }
+  __syncthreads();
+  return total;
+}
+
 __global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count,
                                                          const Tank* __restrict__ tanks, int n_tanks,
                                                          int ghosts, int* __restrict__ start,
                                                          unsigned* __restrict__ status) {
-  constexpr int kChunkCells = kScanThreads * kScanPer;
-  __shared__ int buf[kChunkCells + kScanThreads];
-  __shared__ int wsum[kScanThreads / 64];
+  __shared__ ScanLds S;
   const Tank& tk = tanks[blockIdx.x];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int base0 = ghosts ? tk.q0 : tk.p0, expect = ghosts ? tk.ng : tk.n;
   int carry = 0;
-  for (int base = 0; base < tk.nc; base += kChunkCells) {
-    for (int q = 0; q < kScanPer; ++q) {
-      const int i = q * kScanThreads + t;
-      buf[scan_slot(i)] = base + i < tk.nc ? count[tk.c0 + base + i] : 0;
-    }
-    __syncthreads();
-    int sum = 0;
-    for (int q = 0; q < kScanPer; ++q) {
-      const int k = scan_slot(t * kScanPer + q);
-      const int v = buf[k];
-      buf[k] = sum;
-      sum += v;
-    }
-    int x = sum;   // inclusive scan of the per-thread sums
+  for (int base = 0; base < tk.nc; base += kChunkCells) carry += scan_chunk(S, count, tk, base, carry, base0, start);
+  if (threadIdx.x == 0) {
+    // the entry past a tank's last cell is the next tank's first; the last
+    // tank writes the final one
+    if ((int)blockIdx.x == n_tanks - 1) start[tk.c0 + tk.nc] = base0 + carry;
+    if (carry != expect && status) atomicOr(status, SPH_ST_SORT);
+  }
+}
+
+// The same scan for one tank with many cells, in three launches instead of
+// one workgroup walking every chunk: per-chunk totals, an exclusive scan of
+// the totals (part[n_parts] = the grand total), then every chunk's scan
+// from its offset.  The starts are identical to sph_scan's.
+__global__ void __launch_bounds__(kScanThreads) sph_scan_sums(const int* __restrict__ count,
+                                                              const Tank* __restrict__ tanks,
+                                                              int* __restrict__ part) {
+  __shared__ int wsum[kScanThreads / 64];
+  const Tank& tk = tanks[0];
+  const int base = blockIdx.x * kChunkCells;
+  int v = 0;
+  for (int q = 0; q < kScanPer; ++q) {
+    const int i = base + q * kScanThreads + threadIdx.x;
+    if (i < tk.nc) v += count[tk.c0 + i];
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tsum = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) tsum += wsum[w];
+    part[blockIdx.x] = tsum;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) sph_scan_tops(int* __restrict__ part, int n_parts) {
+  __shared__ int wsum[kScanThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int carry = 0;
+  for (int b0 = 0; b0 < n_parts; b0 += kScanThreads) {
+    const int i = b0 + t;
+    const int v = i < n_parts ? part[i] : 0;
+    int x = v;
     for (int off = 1; off < 64; off <<= 1) {
-      int y = __shfl_up(x, off, 64);
+      const int y = __shfl_up(x, off, 64);
       if (lane >= off) x += y;
     }
     if (lane == 63) wsum[wave] = x;
@@ -375,30 +458,34 @@ __global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count
     if (wave == 0) {
       int w = lane < kScanThreads / 64 ? wsum[lane] : 0;
       for (int off = 1; off < kScanThreads / 64; off <<= 1) {
-        int y = __shfl_up(w, off, 64);
+        const int y = __shfl_up(w, off, 64);
         if (lane >= off) w += y;
       }
       if (lane < kScanThreads / 64) wsum[lane] = w;
     }
     __syncthreads();
-    const int excl = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - sum;
-    for (int q = 0; q < kScanPer; ++q) buf[scan_slot(t * kScanPer + q)] += excl;
-    carry += wsum[kScanThreads / 64 - 1];
+    const int ex = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - v;
+    const int tot = wsum[kScanThreads / 64 - 1];
     __syncthreads();
-    for (int q = 0; q < kScanPer; ++q) {
-      const int i = q * kScanThreads + t;
-      if (base + i < tk.nc) {
-        start[tk.c0 + base + i] = base0 + buf[scan_slot(i)];
-        count[tk.c0 + base + i] = 0;
-      }
-    }
-    __syncthreads();
+    if (i < n_parts) part[i] = ex;
+    carry += tot;
   }
-  if (t == 0) {
-    // the entry past a tank's last cell is the next tank's first; the last
-    // tank writes the final one
-    if ((int)blockIdx.x == n_tanks - 1) start[tk.c0 + tk.nc] = base0 + carry;
-    if (carry != expect && status) atomicOr(status, SPH_ST_SORT);
+  if (t == 0) part[n_parts] = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) sph_scan_chunks(int* __restrict__ count,
+                                                                const Tank* __restrict__ tanks, int ghosts,
+                                                                const int* __restrict__ part, int n_parts,
+                                                                int* __restrict__ start,
+                                                                unsigned* __restrict__ status) {
+  __shared__ ScanLds S;
+  const Tank& tk = tanks[0];
+  const int base0 = ghosts ? tk.q0 : tk.p0, expect = ghosts ? tk.ng : tk.n;
+  scan_chunk(S, count, tk, blockIdx.x * kChunkCells, part[blockIdx.x], base0, start);
+  if (threadIdx.x == 0 && (int)blockIdx.x == n_parts - 1) {
+    const int total = part[n_parts];
+    start[tk.c0 + tk.nc] = base0 + total;
+    if (total != expect && status) atomicOr(status, SPH_ST_SORT);
   }
 }
 
@@ -1982,7 +2069,7 @@ int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int
 
 struct Layout {
   size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, near_n, near_f, near_g, key, slot,
-      order, count, gpos,
+      order, count, scanpart, gpos,
       graw, gstart, owner, gowner, cowner, tanks, tiles[kNumVariants], tile0[kNumVariants], partials,
       rigid, rollout, status, total;
 };
@@ -2007,6 +2094,7 @@ Layout make_layout(const Plan& pl) {
     L.cstart[b] = take((nc + 1) * 4);
   }
   L.pos_sort = take(n * 8);
+  L.scanpart = take((nc / kChunkCells + 2) * 4);
   L.rng = take(n * 48);
   L.pkey = take(n * 4);
   L.rp = take(n * 8);
@@ -2767,6 +2855,25 @@ struct sph_handle {
 
 namespace {
 
+// Exclusive scan of the cell counts into start: one workgroup per tank, or,
+// for a single tank with more than four chunks of cells, the three-launch
+// form (same result).
+void enqueue_scan(sph_handle* h, int* start, int ghosts, unsigned* status) {
+  const long long nc = h->plan.tanks[0].nc;
+  if (h->T == 1 && nc > 4LL * kChunkCells) {
+    const int parts = (int)((nc + kChunkCells - 1) / kChunkCells);
+    int* part = h->at<int>(h->L.scanpart);
+    hipLaunchKernelGGL(sph_scan_sums, dim3(parts), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
+                       h->at<Tank>(h->L.tanks), part);
+    hipLaunchKernelGGL(sph_scan_tops, dim3(1), dim3(kScanThreads), 0, h->stream, part, parts);
+    hipLaunchKernelGGL(sph_scan_chunks, dim3(parts), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
+                       h->at<Tank>(h->L.tanks), ghosts, (const int*)part, parts, start, status);
+  } else {
+    hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
+                       h->at<Tank>(h->L.tanks), h->T, ghosts, start, status);
+  }
+}
+
 // Rebuilds the cell list from the current state: key + count, per-tank scan,
 // stable placement into the other buffers.  ev, if given, holds 4 events.
 void enqueue_sort(sph_handle* h, hipEvent_t* ev = nullptr) {
@@ -2782,9 +2889,7 @@ void enqueue_sort(sph_handle* h, hipEvent_t* ev = nullptr) {
   h->binned = false;
   h->near_valid = false;
   mark(1);
-  hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
-                     h->at<Tank>(h->L.tanks), h->T, 0, h->at<int>(h->L.cstart[1 - o]),
-                     h->at<unsigned>(h->L.status));
+  enqueue_scan(h, h->at<int>(h->L.cstart[1 - o]), 0, h->at<unsigned>(h->L.status));
   mark(2);
   hipLaunchKernelGGL(sph_place, dim3(nblocks((long long)h->C * kPlaceGroup)), dim3(kBlock), 0, h->stream,
                      h->at<int>(h->L.key), h->at<int>(h->L.cowner), h->at<Tank>(h->L.tanks), h->C,
@@ -2891,8 +2996,7 @@ int sort_fluid(sph_handle* h, const float2* s, const float2* w) {
   hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1]), h->N,
                      h->at<int>(h->L.owner), h->at<Tank>(h->L.tanks), h->at<int>(h->L.key),
                      h->at<int>(h->L.count), h->at<int>(h->L.slot));
-  hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
-                     h->at<Tank>(h->L.tanks), h->T, 0, h->at<int>(h->L.cstart[0]), h->at<unsigned>(h->L.status));
+  enqueue_scan(h, h->at<int>(h->L.cstart[0]), 0, h->at<unsigned>(h->L.status));
   if (h->N > 0) {
     hipLaunchKernelGGL(sph_scatter, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.key),
                        h->at<int>(h->L.slot), h->N, h->at<int>(h->L.cstart[0]), h->at<int>(h->L.order));
@@ -2919,8 +3023,7 @@ int sort_ghosts(sph_handle* h, const float2* graw) {
   hipLaunchKernelGGL(sph_bin, dim3(nb), dim3(kBlock), 0, h->stream, graw, h->Gh, h->at<int>(h->L.gowner),
                      h->at<Tank>(h->L.tanks), h->at<int>(h->L.key), h->at<int>(h->L.count),
                      h->at<int>(h->L.slot));
-  hipLaunchKernelGGL(sph_scan, dim3(h->T), dim3(kScanThreads), 0, h->stream, h->at<int>(h->L.count),
-                     h->at<Tank>(h->L.tanks), h->T, 1, h->at<int>(h->L.gstart), (unsigned*)nullptr);
+  enqueue_scan(h, h->at<int>(h->L.gstart), 1, (unsigned*)nullptr);
   if (h->Gh > 0) {
     hipLaunchKernelGGL(sph_scatter, dim3(nb), dim3(kBlock), 0, h->stream, h->at<int>(h->L.key),
                        h->at<int>(h->L.slot), h->Gh, h->at<int>(h->L.gstart), h->at<int>(h->L.order));

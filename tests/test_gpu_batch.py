@@ -105,3 +105,30 @@ def test_autotune_picks_a_variant_and_keeps_parity():
     err = np.sqrt(((s[:sc.n_fluid].cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
     assert err <= 1e-3 * sc.tank_size
     batch.close()
+
+
+def test_many_cell_scan_equals_the_per_tank_scan_bitwise():
+    # a single tank with more than four chunks of cells rebuilds its cell list
+    # with the three-launch scan; in a batch the same tank takes the
+    # one-workgroup-per-tank scan; the starts, and so the runs, are identical
+    from paper_2604_12505_amd.sph import Simulator
+    big = W.rect_sweep(4, seed=1, n_steps=24)          # 409,600 particles, ~55,000 cells
+    small = W.plain_rect(2, n_steps=24)
+    n = 24                                             # six rebuilds
+    single = Simulator.from_scenario(big)
+    single.set_lanes(8)
+    single.set_near_lists(False)
+    single.rollout(n)
+    s1, w1, r1, _, _ = single.get_state()
+    assert single.status() == 0
+    batch = Simulator.batch([big, small])
+    batch.set_lanes(8)
+    batch.set_near_lists(False)
+    batch.rollout(n)
+    s2, w2, r2, _, _ = batch.get_state()
+    assert batch.status() == 0
+    nb = big.n_fluid
+    assert torch.equal(s1, s2[:nb]) and torch.equal(w1, w2[:nb])
+    assert np.array_equal(r1, r2[0])
+    single.close()
+    batch.close()
