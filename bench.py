@@ -61,8 +61,8 @@ FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 # proportion they run), on the closed-loop tank for the configurations the
 # autotuner picks from (profiles/hbm_traffic_closed_loop_circle.md); valid
 # for the source whose hash is recorded, null once the kernel source changes.
-TRAFFIC = {"src_sha1": "527ba937313bcf3115ef8321b06886b6e73b4e12",
-           "bytes_per_launch": {"sph_force/16/0": 1727258, "sph_density/16/0": 2006377, "sph_force/16/1": 3181284, "sph_density/16/1": 3355478, "sph_force/32/0": 1776759, "sph_density/32/0": 2002287, "sph_force/32/1": 3238322, "sph_density/32/1": 3353623}}
+TRAFFIC = {"src_sha1": "b7749bff2cdfb8dc063617c9b3e41747b432b303",
+           "bytes_per_launch": {"sph_force/16/0": 1724357, "sph_density/16/0": 1994085, "sph_force/16/1": 3189063, "sph_density/16/1": 3351294, "sph_force/32/0": 1773896, "sph_density/32/0": 2013497, "sph_force/32/1": 3232106, "sph_density/32/1": 3361719}}
 
 
 def progress(msg: str) -> None:
@@ -274,6 +274,34 @@ def sweep_leg(ks=(0, 1, 2, 3, 4, 5, 6), steps: int = 200, warmup: int = 40, kern
             "steps": steps, "rows": rows}
 
 
+def surrogate_leg(n_train: int = 192, n_test: int = 32, steps: int = 2000, epochs: int = 30):
+    """The wrench surrogate end to end at reduced size: relaxed, forced
+    random tanks (2k-8k particles, the Tait law without tension) from the SPH
+    kernels, windows, MFMA training, held-out NRMSE beside the training-mean
+    predictor, and the network's time for the held-out windows against the
+    SPH time that produced them (the full-size run is train_surrogate.py)."""
+    import torch
+    from paper_2604_12505_amd import surrogate as S
+    kw = dict(n_steps=steps, log_stride=25, relax_cycles=10, relax_steps=100, n_min=2000, n_max=8000)
+    tr = S.generate(list(range(1000, 1000 + n_train)), **kw)
+    te = S.generate(list(range(900000, 900000 + n_test)), **kw)
+    norm = S.norm_from(tr)
+    xtr, ytr = S.windows(tr, norm)
+    xte, yte = S.windows(te, norm)
+    net = S.train(xtr, ytr, epochs=epochs, batch=1024, lr=2e-3, lr_final=1e-4)
+    inf = S.inference_net(net, max_batch=65536)
+    err = S.nrmse(S.predict(inf, xte), yte, norm)
+    base = S.nrmse(torch.zeros_like(yte), yte, norm)
+    t_nn = S.time_inference(inf, xte)
+    net.close()
+    inf.close()
+    return {"workload": f"{n_train} training / {n_test} held-out random tanks (2k-8k particles), {steps} steps, "
+                        f"log stride 25, window 32, {epochs} epochs",
+            "nrmse": [float(v) for v in err], "nrmse_mean_predictor": [float(v) for v in base],
+            "heldout_windows": int(xte.shape[0]), "nn_seconds": t_nn, "sph_seconds": te.sph_seconds,
+            "speedup": te.sph_seconds / t_nn}
+
+
 def lpv_leg():
     """The LPV surrogate kernels at the paper's identification size (2,200
     samples): one loss + gradient evaluation for 8 models (the paper's
@@ -373,6 +401,7 @@ def main() -> int:
     ap.add_argument("--no-linearization-leg", action="store_true")
     ap.add_argument("--no-lpv-leg", action="store_true")
     ap.add_argument("--no-sweep-leg", action="store_true")
+    ap.add_argument("--no-surrogate-leg", action="store_true")
     ap.add_argument("--sweep-only", action="store_true", help="run only the size sweep")
     ap.add_argument("--paper-only", action="store_true", help="run only the paper-scenario leg")
     ap.add_argument("--paper-steps", type=int, default=0, help="cap on the paper leg's steps per run (0: full)")
@@ -490,6 +519,9 @@ def main() -> int:
     if not args.no_lpv_leg:
         out["lpv"] = lpv_leg()
         progress("LPV leg done")
+    if not args.no_surrogate_leg:
+        out["surrogate"] = surrogate_leg()
+        progress("surrogate leg done")
     if not args.no_sweep_leg:
         out["size_sweep"] = sweep_leg()
         for r in out["size_sweep"]["rows"]:
