@@ -152,6 +152,21 @@ int sph_set_lanes(sph_handle* h, int32_t lanes);
  * neighbour sets (the sums differ in order only). */
 int sph_set_near_lists(sph_handle* h, int32_t on);
 
+/* Steps between cell-list rebuilds of the multi-kernel path: 1, 2, 4, 8,
+ * 16, 32 or 64 (default 4); anything else is SPH_E_INVAL.  The neighbour sets
+ * are those of an exact search at every step for any interval as long as
+ * every fluid particle stays within skin/2 = h/2 of its position at the last
+ * rebuild; the density kernel checks that bound at every step and latches
+ * SPH_ST_SORT in the status word when it fails, so a run whose status stays
+ * clean computed the same pairs as a rebuild at every step.  A rebuild
+ * reorders the particles, so intervals differ in summation order (rounding)
+ * only.  A change drops the handle's captured graphs; a rebuild that a
+ * shorter interval makes overdue runs at the start of the next rollout. */
+int sph_set_rebuild_interval(sph_handle* h, int32_t steps);
+
+/* The current rebuild interval in steps. */
+int sph_get_rebuild_interval(sph_handle* h, int32_t* steps);
+
 /* The current tuning choices: lanes per particle and near lists (0/1);
  * either pointer may be NULL. */
 int sph_get_tuning(sph_handle* h, int32_t* lanes, int32_t* near_lists);

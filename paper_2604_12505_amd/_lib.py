@@ -32,6 +32,7 @@ SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sp
                "sph_slosh_wrench", "sph_rhs", "sph_get_state", "sph_set_state", "sph_status",
                "sph_neighbours", "sph_time_kernels", "sph_batch_workspace_bytes", "sph_batch_init",
                "sph_num_tanks", "sph_autotune", "sph_set_lanes", "sph_set_near_lists", "sph_get_tuning",
+               "sph_set_rebuild_interval", "sph_get_rebuild_interval",
                "sph_jvp_workspace_bytes", "sph_jvp_rollout", "sph_vjp_workspace_bytes", "sph_vjp_rollout",
                "sph_gamma1_terms", "sph_rollout_resident", "sph_resident_fits", "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
@@ -78,6 +79,8 @@ def load():
     L.sph_set_lanes.argtypes = [p, i32]
     L.sph_set_near_lists.argtypes = [p, i32]
     L.sph_get_tuning.argtypes = [p, P(i32), P(i32)]
+    L.sph_set_rebuild_interval.argtypes = [p, i32]
+    L.sph_get_rebuild_interval.argtypes = [p, P(i32)]
     L.sph_jvp_workspace_bytes.argtypes = [p, i32, P(sz)]
     L.sph_jvp_rollout.argtypes = [p, i32, i32, p, p, p, i32, p, p, p, p, sz, p, p, p, p, p, p]
     L.sph_vjp_workspace_bytes.argtypes = [p, i32, i32, P(sz)]

@@ -37,7 +37,8 @@
 // by sph_autotune (8 by default).
 //
 // Neighbours come from a body-frame cell grid of side (S + skin)(1 + 1e-6),
-// S = max(2h, h_spiky) the widest support, rebuilt every kSortEvery steps by
+// S = max(2h, h_spiky) the widest support, rebuilt every few steps (4 by
+// default, sph_set_rebuild_interval) by
 // a stable counting sort (sph_bin, sph_scan, sph_place) that also rewrites
 // the particle state in cell order.  A particle is searched from the cell it
 // was sorted into; while every particle stays within skin/2 of its position at
@@ -64,8 +65,8 @@ constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;       // cells per thread per scan chunk
 constexpr int kWrenchThreads = 1024;  // one workgroup per tank sums its tile partials
-constexpr int kSortEvery = 4;     // steps between cell-list rebuilds
-constexpr int kChunk = 64;        // steps per captured graph (multiple of kSortEvery, even)
+constexpr int kSortEvery = 4;     // default steps between cell-list rebuilds
+constexpr int kChunk = 64;        // steps per captured graph (a multiple of every rebuild interval, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
 constexpr int kStageF = 640;      // fluid candidates staged in LDS per row segment
 constexpr int kStageG = 512;      // ghost candidates staged in LDS per row segment
@@ -2842,11 +2843,13 @@ struct sph_handle {
   int cur;          // buffer of the current particle state (pos, vel, acc)
   int ord;          // buffer of the current ordering (id, cell starts)
   int since_sort;   // steps since the last cell-list rebuild
+  int sort_every;   // steps between rebuilds, a divisor of kChunk
   bool binned;      // the last force launch computed the keys and counts of the next rebuild
   int variant;      // lanes per particle = kLanes[variant]
   bool near;        // walk near lists (else every candidate of the 3x3 block)
   bool near_valid;  // the near lists belong to the current cell order
-  hipGraphExec_t graph[kNumVariants][2][2][2];   // [variant][near] kChunk steps from (cur, ord)
+  hipGraphExec_t graph[kNumVariants][2][2][2];   // [variant][near] kChunk steps from (cur, ord),
+                                                 // for the current sort_every
   bool graph_ok[kNumVariants][2][2][2];
 
   template <class T_>
@@ -2932,7 +2935,7 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
   if (build) h->near_valid = true;
   mark(1);
   // the step before a scheduled rebuild also bins the particles for it
-  const bool bin = mode == kStep && h->since_sort + 1 >= kSortEvery;
+  const bool bin = mode == kStep && h->since_sort + 1 >= h->sort_every;
   auto force = bin ? sph_force<G, true> : sph_force<G, false>;
   hipLaunchKernelGGL(force, dim3(nt), dim3(kBlock), 0, h->stream, h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<int>(h->L.pkey),
@@ -2972,9 +2975,10 @@ void enqueue_integrate(sph_handle* h) {
 // Steps of a rollout with the rebuild schedule; the state is integrated on
 // entry and on exit.
 void enqueue_steps(sph_handle* h, int n_steps) {
+  if (h->since_sort >= h->sort_every) enqueue_sort(h);   // overdue after a shorter interval was set
   for (int s = 0; s < n_steps; ++s) {
     enqueue_step(h, s > 0, kStep);
-    if (h->since_sort >= kSortEvery) enqueue_sort(h);
+    if (h->since_sort >= h->sort_every) enqueue_sort(h);
   }
   enqueue_integrate(h);
 }
@@ -3170,6 +3174,7 @@ int init_common(int T, const sph_params* params, const int32_t* n_fluid, const f
   h->ws = reinterpret_cast<char*>(ws_dev);
   h->L = L;
   h->cur = h->ord = h->since_sort = 0;
+  h->sort_every = kSortEvery;
   h->binned = false;
   h->variant = kDefaultVariant;
   h->near = false;
@@ -3241,13 +3246,21 @@ int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const fl
   return init_common(1, p, &n_fluid, s0_dev, w0_dev, &n_ghost, g_dev, rigid0, ws_dev, ws_bytes, stream, out);
 }
 
-int sph_destroy(sph_handle* h) {
-  if (!h) return SPH_E_INVAL;
+// Destroys every captured graph of the handle.
+void drop_graphs(sph_handle* h) {
   for (int v = 0; v < kNumVariants; ++v)
     for (int n = 0; n < 2; ++n)
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-          if (h->graph_ok[v][n][a][b]) (void)hipGraphExecDestroy(h->graph[v][n][a][b]);
+          if (h->graph_ok[v][n][a][b]) {
+            (void)hipGraphExecDestroy(h->graph[v][n][a][b]);
+            h->graph_ok[v][n][a][b] = false;
+          }
+}
+
+int sph_destroy(sph_handle* h) {
+  if (!h) return SPH_E_INVAL;
+  drop_graphs(h);
   delete h;
   return SPH_OK;
 }
@@ -3268,7 +3281,8 @@ int sph_rollout(sph_handle* h, int32_t n_steps, const float* u_seq_dev, const do
   }
   int left = n_steps;
   // align to the rebuild schedule so that every graph starts right after a rebuild
-  int lead = (kSortEvery - h->since_sort) % kSortEvery;
+  if (h->since_sort >= h->sort_every) enqueue_sort(h);   // overdue after a shorter interval was set
+  int lead = (h->sort_every - h->since_sort) % h->sort_every;
   if (lead > 0) {
     enqueue_steps(h, lead);
     left -= lead;
@@ -3339,7 +3353,7 @@ int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev, con
       HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
       sum[3 + k] += ms;
     }
-    if (h->since_sort >= kSortEvery) {
+    if (h->since_sort >= h->sort_every) {
       enqueue_sort(h, ev);
       HIPCHK(hipEventSynchronize(ev[3]));
       for (int k = 0; k < 3; ++k) {
@@ -3378,7 +3392,7 @@ int sph_autotune(sph_handle* h, int32_t reps, int32_t* lanes) {
         // one rebuild interval: with near lists, its first step builds them
         h->near_valid = false;
         float ms = 0.f;
-        for (int k = 0; k < kSortEvery; ++k) {
+        for (int k = 0; k < h->sort_every; ++k) {
           h->cur = cur;
           h->ord = ord;
           enqueue_step(h, false, kEval, ev);
@@ -3424,6 +3438,19 @@ int sph_set_near_lists(sph_handle* h, int32_t on) {
   return SPH_OK;
 }
 
+int sph_set_rebuild_interval(sph_handle* h, int32_t steps) {
+  if (!h || steps < 1 || steps > kChunk || kChunk % steps != 0) return SPH_E_INVAL;
+  if (steps != h->sort_every) drop_graphs(h);   // the graphs hold the old schedule
+  h->sort_every = steps;
+  return SPH_OK;
+}
+
+int sph_get_rebuild_interval(sph_handle* h, int32_t* steps) {
+  if (!h || !steps) return SPH_E_INVAL;
+  *steps = h->sort_every;
+  return SPH_OK;
+}
+
 int sph_get_tuning(sph_handle* h, int32_t* lanes, int32_t* near_lists) {
   if (!h) return SPH_E_INVAL;
   if (lanes) *lanes = kLanes[h->variant];
@@ -3442,7 +3469,7 @@ int sph_rhs(sph_handle* h, const float* u_dev, float* rho_dev, float* p_dev, flo
   if (rc) return rc;
   // the cell list and near lists of the last rebuild stay valid until the
   // next scheduled one (the displacement check still runs)
-  if (h->since_sort >= kSortEvery) enqueue_sort(h);
+  if (h->since_sort >= h->sort_every) enqueue_sort(h);
   const int since = h->since_sort;
   enqueue_step(h, false, kEval);
   h->since_sort = since;   // evaluation only: the positions did not move

@@ -270,6 +270,15 @@ class Simulator:
     def set_near_lists(self, on: bool) -> None:
         check(self.L.sph_set_near_lists(self.h, 1 if on else 0), "sph_set_near_lists")
 
+    def set_rebuild_interval(self, steps: int) -> None:
+        """Steps between cell-list rebuilds (1, 2, 4, 8, 16, 32 or 64)."""
+        check(self.L.sph_set_rebuild_interval(self.h, int(steps)), "sph_set_rebuild_interval")
+
+    def rebuild_interval(self) -> int:
+        n = C.c_int32()
+        check(self.L.sph_get_rebuild_interval(self.h, C.byref(n)), "sph_get_rebuild_interval")
+        return int(n.value)
+
     def tuning(self):
         """(lanes per particle, near lists on)."""
         lanes, near = C.c_int32(), C.c_int32()

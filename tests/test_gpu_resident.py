@@ -8,6 +8,8 @@ of the sum of the wall-term magnitudes.  Runs of the same tank are bitwise
 identical, alone or in a batch; a resident rollout hands a consistent state
 to the multi-kernel path and back.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -127,3 +129,45 @@ def test_resident_refuses_a_large_tank():
     sim.rollout(10)   # the multi-kernel path still runs
     assert sim.status() == 0
     sim.close()
+
+
+def _emptied(sc):
+    z = np.zeros((0, 2), np.float32)
+    return dataclasses.replace(sc, name=sc.name + "_empty", pos=z, vel=z)
+
+
+@pytest.mark.parametrize("resident", [False, True], ids=["multi_kernel", "resident"])
+@pytest.mark.parametrize("where", [0, 1, 2], ids=["first", "middle", "last"])
+def test_batch_with_an_empty_tank(where, resident):
+    # a tank with walls and no fluid anywhere in a batch: the other tanks run
+    # bitwise as they do alone, and the empty one flies its rigid body under
+    # its input and attitude law exactly as the oracle's empty tank does
+    from paper_2604_12505_amd.sph import Simulator
+    n = 140   # two graph-replayed chunks on the multi-kernel path
+    scs = [W.paper_p0(0, n_steps=n, spawn="random"), _with_u(W.lpv_tank(1), n, 40.0)]
+    scs.insert(where, _emptied(_with_u(W.paper_p0(2, n_steps=n, spawn="random"), n, 40.0)))
+    n_ref = max(len(sc.theta_ref) for sc in scs)
+    ref = np.stack([np.pad(sc.theta_ref, (0, n_ref - len(sc.theta_ref)), mode="edge") for sc in scs])
+    b = Simulator.batch(scs)
+    assert b.resident_fits()
+    u = torch.stack([torch.as_tensor(sc.u_seq[:n]) for sc in scs])
+    logs = b.rollout(n, u, theta_ref=ref, log_stride=10, resident=resident)
+    s, w, rig, _, step = b.get_state()
+    assert b.status() == 0 and list(step) == [n] * 3
+    o = 0
+    for t, sc in enumerate(scs):
+        one = _sim(sc)
+        one.rollout(n, torch.as_tensor(sc.u_seq[:n]), theta_ref=sc.theta_ref, resident=resident)
+        s1, w1, r1, _, _ = one.get_state()
+        assert one.status() == 0
+        k = sc.n_fluid
+        assert torch.equal(s[o:o + k], s1) and torch.equal(w[o:o + k], w1)
+        assert np.array_equal(rig[t], r1)
+        o += k
+        one.close()
+    e = scs[where]
+    st = O.state_from_scenario(e)
+    O.rollout(e.params, st, e.ghosts.astype(np.float64), n, e.u_seq[:n], e.theta_ref)
+    assert np.allclose(rig[where], st.rigid, rtol=1e-9, atol=1e-12)
+    assert not logs["wrench"][where].any()
+    b.close()

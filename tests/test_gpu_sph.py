@@ -207,6 +207,70 @@ def test_long_rollout_stays_within_the_rebuild_skin_and_tracks_the_oracle(near):
     sim.close()
 
 
+def test_rebuild_interval_tracks_the_oracle():
+    # any interval gives the neighbour sets of an exact search while the
+    # displacement bound holds (status clean); only rounding differs.  In
+    # this tank (fluid speeds up to ~4 m/s at dt = 0.1625 ms) the oracle's
+    # largest displacement over 8-step windows is 0.69 h/2
+    sc = W.plain_rect(3, n_steps=400)
+    st = O.state_from_scenario(sc)
+    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), 400, sc.u_seq)
+    for every, near in ((1, False), (2, False), (8, False), (8, True)):
+        sim = _sim(sc, near)
+        sim.set_rebuild_interval(every)
+        assert sim.rebuild_interval() == every
+        sim.rollout(400, torch.as_tensor(sc.u_seq))
+        s, w, rig, _, step = sim.get_state()
+        assert step == 400 and sim.status() == 0
+        err = np.sqrt(((s.cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
+        print("interval", every, "near", near, "pos err / L", err / sc.tank_size)
+        assert err <= 1e-3 * sc.tank_size
+        assert abs(rig[2] - st.rigid[2]) <= 1e-3
+        sim.close()
+
+
+def test_too_long_rebuild_interval_is_flagged():
+    # 64 steps move particles of the same tank several h/2: the density
+    # kernel's displacement check latches SPH_ST_SORT (the missed pairs then
+    # wreck the run, which the other bits report)
+    sc = W.plain_rect(3, n_steps=400)
+    sim = _sim(sc)
+    sim.set_rebuild_interval(64)
+    sim.rollout(400, torch.as_tensor(sc.u_seq))
+    assert sim.status() & 4   # SPH_ST_SORT
+    sim.close()
+
+
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
+def test_rebuild_interval_graph_equals_direct_and_changes_midrun(near):
+    # a: rollouts (graph chunks of 64 steps + direct tails); c: single steps.
+    # 150 steps at 8, then a shorter interval that makes a rebuild overdue
+    # (150 = 18 * 8 + 6)
+    sc = W.plain_rect(1, n_steps=300)
+    a, c = _sim(sc, near), _sim(sc, near)
+    u = torch.as_tensor(sc.u_seq)
+    for x in (a, c):
+        x.set_rebuild_interval(8)
+    a.rollout(150, u[:150])
+    for k in range(150):
+        c.step(u[k].contiguous())
+    for x in (a, c):
+        x.set_rebuild_interval(4)
+    a.rollout(150, u[150:].contiguous())
+    for k in range(150, 300):
+        c.step(u[k].contiguous())
+    sa, wa, ra, _, ka = a.get_state()
+    sc_, wc, rc_, _, kc = c.get_state()
+    assert ka == kc == 300
+    assert torch.equal(sa, sc_) and torch.equal(wa, wc) and np.array_equal(ra, rc_)
+    assert a.status() == 0 and c.status() == 0
+    for bad in (0, 3, 5, 128):
+        with pytest.raises(RuntimeError):
+            a.set_rebuild_interval(bad)
+    assert a.rebuild_interval() == 4
+    a.close(); c.close()
+
+
 def test_state_roundtrip_and_resume():
     sc = W.plain_rect(2, n_steps=100)
     a = _sim(sc)
