@@ -50,7 +50,7 @@ def lib():
         L.ora_pairs_f32.argtypes = [i, p, p, C.c_float, i, p, p]
         L.ora_rhs.restype = i
         L.ora_rhs.argtypes = [C.POINTER(OraParams), i, p, p, p, p, i, p, p, p, d, i64, p,
-                              p, p, p, p, p, p, p, p, p]
+                              p, p, p, p, p, p, p, p, p, p]
         L.ora_rollout.restype = i
         L.ora_rollout.argtypes = [C.POINTER(OraParams), i, p, p, p, p, i, p, p, p, p, p, i, p, p, i,
                                   i, p, p, p, p]
@@ -161,7 +161,9 @@ def state_from_scenario(sc) -> State:
 
 def rhs(prm, st: State, ghosts, u=(0.0, 0.0, 0.0), use_cells=True):
     """x_dot at the state: dict of rho, P, a_sph [N,2], wdot [N,2], wrench [3], acc [3],
-    and wall_terms [N,3], each particle's term of the wrench sum."""
+    wall_terms [N,3], each particle's term of the wrench sum, and wall_abs
+    [N,3], per particle the sums over its wall pairs of |F_x|, |F_y| and
+    |g_x F_y| + |g_y F_x| (the scale of the rounding of the wrench)."""
     o = make_params(prm, use_cells)
     n = st.s.shape[0]
     g = np.ascontiguousarray(ghosts, np.float64)
@@ -171,13 +173,15 @@ def rhs(prm, st: State, ghosts, u=(0.0, 0.0, 0.0), use_cells=True):
     rho = np.empty(n); P = np.empty(n); ax = np.empty(n); ay = np.empty(n)
     dwx = np.empty(n); dwy = np.empty(n); wrench = np.empty(3); acc = np.empty(3)
     fwall = np.zeros((max(n, 1), 3))
+    fwabs = np.zeros((max(n, 1), 3))
     uu = np.array(u, np.float64)
     rg = np.ascontiguousarray(st.rigid, np.float64)
     lib().ora_rhs(C.byref(o), n, _ptr(sx), _ptr(sy), _ptr(wx), _ptr(wy), g.shape[0], _ptr(gx),
                   _ptr(gy), _ptr(rg), float(st.tau_ctrl), int(st.step), _ptr(uu), _ptr(rho), _ptr(P),
-                  _ptr(ax), _ptr(ay), _ptr(dwx), _ptr(dwy), _ptr(wrench), _ptr(acc), _ptr(fwall))
+                  _ptr(ax), _ptr(ay), _ptr(dwx), _ptr(dwy), _ptr(wrench), _ptr(acc), _ptr(fwall),
+                  _ptr(fwabs))
     return dict(rho=rho, P=P, a_sph=np.stack([ax, ay], 1), wdot=np.stack([dwx, dwy], 1),
-                wrench=wrench, acc=acc, wall_terms=fwall[:n])
+                wrench=wrench, acc=acc, wall_terms=fwall[:n], wall_abs=fwabs[:n])
 
 
 def rollout(prm, st: State, ghosts, n_steps, u_seq=None, theta_ref=None, log_stride=0,

@@ -295,6 +295,8 @@ typedef struct {
   double* ay;
   double wrench[3];  /* force of the fluid on the tank (frame of the inputs) and torque */
   double* fwall;     /* [n][3] or NULL: each particle's reaction on the tank (F_x, F_y, torque) */
+  double* fwall_abs; /* [n][3] or NULL: per particle, the sums over its wall pairs of |F_x|, |F_y|
+                        and |g_x F_y| + |g_y F_x| (the scale of the rounding of the wrench sums) */
 } sums_t;
 
 /* The particle sums.  Positions and velocities are in one frame (the body
@@ -344,6 +346,7 @@ static void particle_sums(const ora_params* p, int n, const double* sx, const do
   double* fwx = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* fwy = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
   double* fwt = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double* fwa = (double*)calloc((size_t)(n > 0 ? n : 1) * 3, sizeof(double));
 #pragma omp parallel
   {
     list_t l = {0, 0, 0};
@@ -370,7 +373,7 @@ static void particle_sums(const ora_params* p, int n, const double* sx, const do
         ay += (-press + visc) * gW * ry;
       }
       /* ghost-to-fluid: F_ik = m^2 (-2 P_i/rho_i^2 + 2 beta/(rho_i+rho_g) min(v.r,0)/(r^2+eps h^2)) grad W_s3 */
-      double fx = 0.0, fy = 0.0, tq = 0.0;
+      double fx = 0.0, fy = 0.0, tq = 0.0, fxa = 0.0, fya = 0.0, tqa = 0.0;
       find_within(&gg, use_cells, sx[i], sy[i], hs, ng, gx, gy, &l);
       for (int t = 0; t < l.n; ++t) {
         int k = l.j[t];
@@ -390,12 +393,18 @@ static void particle_sums(const ora_params* p, int n, const double* sx, const do
         fx -= Fx;
         fy -= Fy;
         tq -= (gx[k] - arm_origin[0]) * Fy - (gy[k] - arm_origin[1]) * Fx;
+        fxa += fabs(Fx);
+        fya += fabs(Fy);
+        tqa += fabs((gx[k] - arm_origin[0]) * Fy) + fabs((gy[k] - arm_origin[1]) * Fx);
       }
       out->ax[i] = ax;
       out->ay[i] = ay;
       fwx[i] = fx;
       fwy[i] = fy;
       fwt[i] = tq;
+      fwa[3 * i] = fxa;
+      fwa[3 * i + 1] = fya;
+      fwa[3 * i + 2] = tqa;
     }
     free(l.j);
   }
@@ -405,6 +414,9 @@ static void particle_sums(const ora_params* p, int n, const double* sx, const do
       out->fwall[3 * i + 1] = fwy[i];
       out->fwall[3 * i + 2] = fwt[i];
     }
+  if (out->fwall_abs)
+    for (int i = 0; i < 3 * n; ++i) out->fwall_abs[i] = fwa[i];
+  free(fwa);
   out->wrench[0] = out->wrench[1] = out->wrench[2] = 0.0;
   for (int i = 0; i < n; ++i) {
     out->wrench[0] += fwx[i];
@@ -471,13 +483,15 @@ static void rigid_accel(const ora_params* p, const ora_rigid* b, const double wr
  * function") without advancing it.  Outputs: rho, P, a_sph and the body-frame
  * fluid acceleration dw/dt [n]; the body-frame slosh wrench [3]; the rigid
  * accelerations (r''_x, r''_y, theta'') [3]; optionally (fwall non-NULL) the
- * per-particle terms of the wrench sum [n][3].  `rigid` = r_x, r_y, theta,
+ * per-particle terms of the wrench sum [n][3], and (fwall_abs non-NULL) per
+ * particle the sums of the magnitudes of its pair terms [n][3].  `rigid` = r_x, r_y, theta,
  * rdot_x, rdot_y, thetadot; tau_ctrl the held controller torque; step n. */
 int ora_rhs(const ora_params* p, int n, const double* sx, const double* sy, const double* wx,
             const double* wy, int ng, const double* gx, const double* gy, const double* rigid,
             double tau_ctrl, int64_t step, const double* u, double* rho, double* P, double* ax,
-            double* ay, double* dwx, double* dwy, double* wrench, double* acc, double* fwall) {
-  sums_t s = {rho, P, ax, ay, {0, 0, 0}, fwall};
+            double* ay, double* dwx, double* dwy, double* wrench, double* acc, double* fwall,
+            double* fwall_abs) {
+  sums_t s = {rho, P, ax, ay, {0, 0, 0}, fwall, fwall_abs};
   double origin[2] = {0.0, 0.0};
   particle_sums(p, n, sx, sy, wx, wy, ng, gx, gy, NULL, NULL, origin, p->use_cells, &s);
   ora_rigid b = {{rigid[0], rigid[1]}, rigid[2], {rigid[3], rigid[4]}, rigid[5], tau_ctrl, step};
@@ -535,7 +549,7 @@ int ora_rollout(const ora_params* p, int n, double* sx, double* sy, double* wx, 
     double rg[6] = {b.r[0], b.r[1], b.theta, b.rdot[0], b.rdot[1], b.thetadot};
     double wrench[3], acc[3];
     ora_rhs(p, n, sx, sy, wx, wy, ng, gx, gy, rg, b.tau_ctrl, b.step, u, rho, P, ax, ay, dwx, dwy,
-            wrench, acc, NULL);
+            wrench, acc, NULL, NULL);
     if (log_stride > 0 && it % log_stride == 0) {
       int k = it / log_stride;
       if (y_log) {
@@ -642,7 +656,7 @@ int ora_rollout_world(const ora_params* p, int n, double* xx, double* xy, double
       gvx[k] = b.rdot[0] - thd * (gy[k] - b.r[1]);
       gvy[k] = b.rdot[1] + thd * (gx[k] - b.r[0]);
     }
-    sums_t sm = {rho, P, ax, ay, {0, 0, 0}, NULL};
+    sums_t sm = {rho, P, ax, ay, {0, 0, 0}, NULL, NULL};
     ora_params q = *p;
     q.use_cells = 0;
     particle_sums(&q, n, xx, xy, vx, vy, ng, gx, gy, gvx, gvy, b.r, 0, &sm);

@@ -68,8 +68,17 @@ constexpr int kWrenchThreads = 1024;  // one workgroup per tank sums its tile pa
 constexpr int kSortEvery = 4;     // default steps between cell-list rebuilds
 constexpr int kChunk = 64;        // steps per captured graph (a multiple of every rebuild interval, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
-constexpr int kStageF = 640;      // fluid candidates staged in LDS per row segment
-constexpr int kStageG = 512;      // ghost candidates staged in LDS per row segment
+// Candidates staged in LDS per row segment: fluid (by tile size) and ghosts.
+// A tile's segment covers its cells of one grid row and the cells around
+// them in three rows: with ~15 particles per cell (cell side 3h at
+// h = 1.3 dx) that is ~320 fluid candidates for 64-particle tiles (at most
+// ~520 in the random tanks, 1 segment in 17,000 above 448) and under 300 for
+// 32 or fewer; ghosts at most ~150.  A larger segment reads its candidates
+// from global memory instead.  Sized so that the 4-lane force kernel fits
+// five workgroups per CU.
+template <int TP>
+constexpr int stage_f() { return TP >= 64 ? 448 : 384; }
+constexpr int kStageG = 192;
 constexpr int kListF = 64;        // in-support fluid neighbours listed per particle and pass
 constexpr int kListG = 32;        // in-support ghost neighbours listed per particle and pass
 // Near lists, built at the first step after each rebuild: for every particle
@@ -949,6 +958,7 @@ __global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__
                                                       unsigned* __restrict__ near_f,
                                                       unsigned* __restrict__ near_g) {
   constexpr int TP = kBlock / G;
+  constexpr int kStageF = stage_f<TP>();
   __shared__ float2 f_pos[kStageF];
   __shared__ float2 f_raw[Build ? kStageF : 1];
   __shared__ float2 g_pos[kStageG];
@@ -1248,6 +1258,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
                                                     const unsigned* __restrict__ near_f,
                                                     const unsigned* __restrict__ near_g) {
   constexpr int TP = kBlock / G;
+  constexpr int kStageF = stage_f<TP>();
   __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
   __shared__ float2 g_pos[kStageG];
   __shared__ unsigned short f_list[TP][kListF], g_list[TP][kListG];
@@ -1540,6 +1551,7 @@ __global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict_
                                                        const Tank* __restrict__ tanks, int max_nbr,
                                                        int* __restrict__ nbr, int* __restrict__ cnt) {
   constexpr int TP = kBlock / G;
+  constexpr int kStageF = stage_f<TP>();
   __shared__ float2 f_pos[kStageF];
   __shared__ int f_id[kStageF];
   __shared__ TileLds<TP> tl;

@@ -142,6 +142,25 @@ def test_wall_pushes_compressed_fluid_away_and_tank_feels_reaction():
     assert np.allclose(p.mass * r["a_sph"][0], -r["wrench"][:2], rtol=1e-12, atol=0)
 
 
+def test_wall_term_magnitudes_bound_the_wall_terms():
+    # one ghost in the support: the magnitude sums are the term's magnitudes
+    # (F_x = 0 above a ghost straight below); many ghosts: the tangential
+    # components cancel in the term but not in the magnitude sum
+    p = _linear_positive_pressure()
+    s = np.array([[0.0, 0.4 * p.h]])
+    one = O.rhs(p, O.State(s, np.zeros_like(s), np.zeros(6)), np.array([[0.0, 0.0]]))
+    F = one["wall_terms"][0]
+    assert F[1] != 0.0 and F[0] == 0.0
+    assert np.array_equal(one["wall_abs"][0, :2], np.abs(F[:2]))
+    g = np.stack([np.linspace(-0.05, 0.05, 21), np.zeros(21)], 1)
+    s = np.array([[0.0013, 0.4 * p.h], [-0.0021, 0.7 * p.h]])
+    many = O.rhs(p, O.State(s, np.zeros_like(s), np.zeros(6)), g)
+    wt, wa = many["wall_terms"], many["wall_abs"]
+    assert (wa >= np.abs(wt)).all()
+    assert (wa[:, 0] > 5 * np.abs(wt[:, 0])).all()          # cancelling tangential sums
+    assert np.allclose(wa[:, 1], np.abs(wt[:, 1]), rtol=1e-12)  # normal terms share a sign
+
+
 def test_wall_viscosity_only_resists_approach():
     p = W._fluid_params(0.01)
     p.domain_min, p.domain_max = (-0.5, -0.5), (0.5, 0.5)
