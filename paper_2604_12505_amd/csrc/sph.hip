@@ -72,13 +72,13 @@ constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between
 // A tile's segment covers its cells of one grid row and the cells around
 // them in three rows: with ~15 particles per cell (cell side 3h at
 // h = 1.3 dx) that is ~320 fluid candidates for 64-particle tiles (at most
-// ~520 in the random tanks, 1 segment in 17,000 above 448) and under 300 for
-// 32 or fewer; ghosts at most ~150.  A larger segment reads its candidates
-// from global memory instead.  Sized so that the 4-lane force kernel fits
-// five workgroups per CU.
+// ~520 in the random tanks, 1 in 1,000 above 385) and under 300 for 32 or
+// fewer; ghosts ~130 at the 99.9th percentile.  A larger segment reads its
+// candidates from global memory instead.  Sized so that the 4-lane force
+// kernel fits six workgroups per CU.
 template <int TP>
-constexpr int stage_f() { return TP >= 64 ? 448 : 384; }
-constexpr int kStageG = 192;
+constexpr int stage_f() { return TP >= 64 ? 416 : 384; }
+constexpr int kStageG = 128;
 constexpr int kListF = 64;        // in-support fluid neighbours listed per particle and pass
 constexpr int kListG = 32;        // in-support ghost neighbours listed per particle and pass
 // Near lists, built at the first step after each rebuild: for every particle
