@@ -132,3 +132,36 @@ def test_many_cell_scan_equals_the_per_tank_scan_bitwise():
     assert np.array_equal(r1, r2[0])
     single.close()
     batch.close()
+
+
+def test_full_256_tank_batch_in_the_bench_configuration_matches_the_oracle():
+    # the batched workload at its full size (256 random tanks, 2k-60k
+    # particles each, 7.7M in all), autotuned and graph-replayed as the bench
+    # runs it; a tank's state is the one it has alone, so sampled tanks (the
+    # largest, the smallest, the first rectangular one and two fixed ones)
+    # are checked against the
+    # oracle run on each of them alone
+    from paper_2604_12505_amd.sph import Simulator
+    n = 80
+    scs = [W.random_tank(seed, n_steps=n) for seed in range(256)]
+    batch = Simulator.batch(scs)
+    lanes = batch.autotune(reps=2)
+    print("autotuned", batch.tuning())
+    u = torch.stack([torch.as_tensor(sc.u_seq) for sc in scs])
+    batch.rollout(n, u)
+    s, _, rig, _, step = batch.get_state()
+    assert batch.status() == 0 and list(step) == [n] * 256
+    sizes = np.array([sc.n_fluid for sc in scs])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    first_rect = next(t for t, sc in enumerate(scs) if sc.shape == "rect")
+    picks = sorted({int(sizes.argmax()), int(sizes.argmin()), 0, 137, first_rect})
+    s = s.cpu().numpy()
+    for t in picks:
+        sc = scs[t]
+        st = O.state_from_scenario(sc)
+        O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n, sc.u_seq[:n])
+        err = np.sqrt(((s[off[t]:off[t + 1]].astype(np.float64) - st.s) ** 2).sum(1)).max()
+        print("tank", t, sc.shape, sc.n_fluid, "lanes", lanes, "pos err / L", err / sc.tank_size)
+        assert err <= 1e-3 * sc.tank_size, (t, err)
+        assert abs(rig[t][2] - st.rigid[2]) <= 1e-3
+    batch.close()

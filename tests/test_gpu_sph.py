@@ -388,3 +388,24 @@ def test_gamma1_terms_match_oracle(name):
     onum, oden = O.gamma1_terms(prm, fluid.astype(np.float64), ghosts.astype(np.float64))
     assert np.allclose(num.cpu().numpy(), onum, rtol=1e-12, atol=1e-12 * np.abs(onum).max())
     assert np.allclose(den.cpu().numpy(), oden, rtol=1e-12, atol=1e-12 * np.abs(oden).max())
+
+
+@pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
+@pytest.mark.parametrize("lanes", [16, 32])
+def test_closed_loop_tank_in_the_bench_configurations(lanes, near):
+    # the closed-loop tank at its full size, in the configurations the
+    # autotuner chooses between for it, through graph-replayed chunks
+    sc = W.closed_loop_circle(0, n_steps=136)
+    sim = _sim(sc, near)
+    sim.set_lanes(lanes)
+    n = 136
+    sim.rollout(n, torch.as_tensor(sc.u_seq), theta_ref=sc.theta_ref)
+    s, w, rig, _, step = sim.get_state()
+    assert step == n and sim.status() == 0
+    st = O.state_from_scenario(sc)
+    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n, sc.u_seq, sc.theta_ref)
+    err = np.sqrt(((s.cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
+    print("closed loop lanes", lanes, "near", near, "pos err / L", err / sc.tank_size)
+    assert err <= 1e-3 * sc.tank_size
+    assert abs(rig[2] - st.rigid[2]) <= 1e-3
+    sim.close()
