@@ -282,3 +282,39 @@ def test_autograd_backward_equals_the_tangent_jacobian():
     got = np.concatenate([u.grad.numpy().astype(np.float64).ravel(), rigid0.grad.numpy()])
     assert np.abs(got - g).max() <= 1e-3 * np.abs(g).max()
     sim.close()
+
+
+def test_adjoint_at_full_size_with_checkpoints():
+    # the adjoint workload at its full size: the ~8,000-particle rectangular
+    # tank, 400 steps, the state kept every 20 steps; the gradient of the
+    # final slosh torque with respect to the input sequence and the initial
+    # rigid state.  Against the tangent-linear rollout on the same binary32
+    # trajectory (the transpose identity, 8 directions, rel 1e-3 as at 100
+    # steps) and against the oracle's central differences (eps = 1e-3, 8
+    # directions).  Binary32 rounding in the linearization grows with the
+    # horizon, so the 100-step bar of 5e-3 of the largest component of the
+    # derivative is scaled by the 4x horizon to 2e-2.
+    steps, lead = 400, 40
+    sc = W.linearization_tank(seed=0, n_steps=steps + lead)
+    from paper_2604_12505_amd.sph import Simulator
+    sim = Simulator.from_scenario(sc)
+    u = torch.as_tensor(sc.u_seq)
+    sim.rollout(lead, u[:lead].contiguous())
+    ck = sim.get_state()
+    uu = u[lead:lead + steps].contiguous()
+    g = sim.vjp_rollout(steps, [0.0, 0.0, 1.0], uu, every=20)
+    gu = g["u"].cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(8)
+    du = (rng.normal(size=(8, steps, 3)) * 10.0).astype(np.float32)
+    dr = rng.normal(size=(8, 6)) * 0.01
+    t = sim.jvp_rollout(steps, uu, du, None, dr)
+    un = uu.numpy().astype(np.float64)
+    worst = 0.0
+    for k in range(8):
+        pred = _dot(gu, du[k]) + _dot(g["rigid0"], dr[k])
+        assert pred == pytest.approx(float(t["dwrench"][k][2]), rel=1e-3, abs=1e-6 * np.abs(t["dwrench"][k]).max())
+        fw, _ = _oracle_fd(sc, ck, un, du[k].astype(np.float64), dr[k])
+        worst = max(worst, abs(pred - fw[2]) / np.abs(fw).max())
+    print("full-size adjoint: worst error / largest derivative component", worst)
+    assert worst <= 2e-2
+    sim.close()

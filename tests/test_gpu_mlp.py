@@ -46,6 +46,23 @@ def test_forward_matches_oracle(B):
     net.close()
 
 
+def test_forward_at_the_inference_batch_size():
+    # the surrogate workload's inference batch, 65,536 windows in one launch:
+    # sampled rows (and the last ones, the ragged end of the grid) against
+    # the oracle
+    G, rng, params, vec = _net(2)
+    B = 65536
+    net = G.Mlp(vec, max_batch=B)
+    x = rng.normal(size=(B, 128)).astype(np.float32)
+    y = net.forward(torch.as_tensor(x)).cpu().numpy().astype(np.float64)
+    rows = np.concatenate([rng.choice(B - 64, 2048, replace=False), np.arange(B - 64, B)])
+    ref, _, _ = M.forward(_rounded_params(vec), _bf16(x[rows]))
+    err = np.abs(y[rows] - ref).max() / np.abs(ref).max()
+    print("forward rel err at B = 65,536", err)
+    assert err < 1e-2
+    net.close()
+
+
 def test_gradients_match_oracle():
     G, rng, params, vec = _net(2)
     B = 256
