@@ -939,8 +939,10 @@ __device__ __forceinline__ int near_pass(NearWords<G, CAP>& nw, int n, int l, co
 // While every particle stays within skin/2 of those positions, every pair
 // closer than the support is listed.  Otherwise a listed particle walks only
 // its near lists.
+// Eight waves per SIMD asked of the register allocator: the 4-lane variant
+// then fits in 64 VGPRs without spilling (72 otherwise, seven waves).
 template <int G, bool Build>
-__global__ void __launch_bounds__(kBlock) sph_density(const float2* __restrict__ pos_in,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) sph_density(const float2* __restrict__ pos_in,
                                                       const float2* __restrict__ vel_in,
                                                       const float2* __restrict__ acc_in, int integrate,
                                                       const float2* __restrict__ pos_sort,
