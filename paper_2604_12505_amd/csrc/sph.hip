@@ -62,6 +62,7 @@ namespace {
 
 constexpr int kBlock = 256;       // threads per workgroup of the particle kernels
 constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
+constexpr int kPlaceAhead = 4;    // source keys per lane loaded ahead in the placement
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;       // cells per thread per scan chunk
 constexpr int kWrenchThreads = 1024;  // one workgroup per tank sums its tile partials
@@ -563,30 +564,47 @@ __global__ void __launch_bounds__(kBlock) sph_place(const int* __restrict__ key,
   const int xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
   int rv[12];
   cell_ranges(tk, cx, cy, start_new, gstart, rv);
-  for (int oy = -1; oy <= 1; ++oy) {
-    int yy = cy + oy;
-    if (yy < 0 || yy >= ncy) continue;
-    int i0 = start_old[tk.c0 + yy * ncx + xa];
-    int i1 = start_old[tk.c0 + yy * ncx + xb + 1];
-    for (int b = i0; b < i1; b += G) {
-      int i = b + l;
-      bool match = i < i1 && key[i] == c;
-      unsigned long long m = __ballot(match);
-      unsigned gm = (unsigned)(m >> shift) & ((1u << G) - 1u);
-      if (match) {
-        int d = dst + __popc(gm & ((1u << l) - 1u));
-        if (d < end) {
-          float2 s = pos_in[i];
-          pos_out[d] = s;
-          vel_out[d] = vel_in[i];
-          acc_out[d] = acc_in[i];
-          id_out[d] = id_in[i];
-          pos_sort[d] = s;
-          pkey[d] = c;
-          store_ranges(rng, d, rv);
-        }
+  // the source rows' bounds, then their keys kPlaceAhead per lane ahead of
+  // the ballots (one memory round trip per row instead of one per pass of
+  // the group); the visiting order, and so the placement, is unchanged
+  int r0[3], r1[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int yy = cy - 1 + r;
+    const bool in = yy >= 0 && yy < ncy;
+    r0[r] = in ? start_old[tk.c0 + yy * ncx + xa] : 0;
+    r1[r] = in ? start_old[tk.c0 + yy * ncx + xb + 1] : 0;
+  }
+  for (int r = 0; r < 3; ++r) {
+    const int i1 = r1[r];
+    for (int b = r0[r]; b < i1; b += kPlaceAhead * G) {
+      int kk[kPlaceAhead];
+#pragma unroll
+      for (int u = 0; u < kPlaceAhead; ++u) {
+        const int i = b + u * G + l;
+        kk[u] = i < i1 ? key[i] : -1;
       }
-      dst += __popc(gm);
+#pragma unroll
+      for (int u = 0; u < kPlaceAhead; ++u) {
+        const int i = b + u * G + l;
+        const bool match = kk[u] == c;   // c >= 0: lanes past the row never match
+        unsigned long long m = __ballot(match);
+        unsigned gm = (unsigned)(m >> shift) & ((1u << G) - 1u);
+        if (match) {
+          int d = dst + __popc(gm & ((1u << l) - 1u));
+          if (d < end) {
+            float2 s = pos_in[i];
+            pos_out[d] = s;
+            vel_out[d] = vel_in[i];
+            acc_out[d] = acc_in[i];
+            id_out[d] = id_in[i];
+            pos_sort[d] = s;
+            pkey[d] = c;
+            store_ranges(rng, d, rv);
+          }
+        }
+        dst += __popc(gm);
+      }
     }
   }
   if (l == 0 && dst != end) atomicOr(status, SPH_ST_SORT);
