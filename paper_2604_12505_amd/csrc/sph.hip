@@ -706,11 +706,22 @@ struct Seg {
   int nf, ng, first, last;
 };
 
+// The row segment that starts at tile slot `first`: the run of slots from
+// `first` in the same grid row, found with one ballot of wavefront 0 (a tile
+// holds at most 64 slots), and its candidate ranges.  Called by the threads
+// of wavefront 0; thread 0 writes sg.
 template <int TP>
 __device__ void make_segment(Seg& sg, const TileLds<TP>& tl, int first) {
+  static_assert(TP <= 64, "one wavefront covers the tile");
+  const int lane = threadIdx.x;   // wavefront 0, all lanes active
   const int row = tl.cy[first];
-  int last = first;
-  while (last + 1 < TP && tl.cy[last + 1] == row) ++last;
+  const unsigned long long same = __ballot(lane < TP && tl.cy[lane] == row);
+  if (lane != 0) return;
+  // slots first, first + 1, ... while the row stays the same (bit 0 of
+  // `from` is slot first itself)
+  const unsigned long long from = same >> first;
+  const int len = ~from == 0ull ? 64 - first : __builtin_ctzll(~from);
+  const int last = first + len - 1;
   int nf = 0, ng = 0;
   for (int r = 0; r < 3; ++r) {
     sg.off[r] = nf;
@@ -1013,7 +1024,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
   int nf_out = kNearNone, ng_out = kNearNone;
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
-    if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
+    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first);
     __syncthreads();
     const bool fst = sg.nf <= kStageF, gst = sg.ng <= kStageG;
     if (fst)
@@ -1312,7 +1323,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   float fx = 0.0f, fy = 0.0f, tq = 0.0f;
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
-    if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
+    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first);
     __syncthreads();
     const bool fst = sg.nf <= kStageF, gst = sg.ng <= kStageG;
     if (fst)
@@ -1585,7 +1596,7 @@ __global__ void __launch_bounds__(kBlock) sph_nbr_list(const float2* __restrict_
   __syncthreads();
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
-    if (threadIdx.x == 0) make_segment<TP>(sg, tl, first);
+    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first);
     __syncthreads();
     const bool fst = sg.nf <= kStageF;
     if (fst)
