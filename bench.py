@@ -61,8 +61,8 @@ FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 # proportion they run), on the closed-loop tank for the configurations the
 # autotuner picks from (profiles/hbm_traffic_closed_loop_circle.md); valid
 # for the source whose hash is recorded, null once the kernel source changes.
-TRAFFIC = {"src_sha1": "f75ee3bb4e48505d823efd378714c5bd31859135",
-           "bytes_per_launch": {"sph_force/16/0": 1725700, "sph_density/16/0": 2001256, "sph_force/16/1": 3182266, "sph_density/16/1": 3354888, "sph_force/32/0": 1766710, "sph_density/32/0": 2012467, "sph_force/32/1": 3222623, "sph_density/32/1": 3351799}}
+TRAFFIC = {"src_sha1": "921bd298df45e88f694fc07033701c1b6e79ebc2",
+           "bytes_per_launch": {"sph_force/16/0": 1725427, "sph_density/16/0": 1993484, "sph_force/16/1": 3191898, "sph_density/16/1": 3351903, "sph_force/32/0": 1785121, "sph_density/32/0": 2013502, "sph_force/32/1": 3244098, "sph_density/32/1": 3361799}}
 
 
 def progress(msg: str) -> None:
