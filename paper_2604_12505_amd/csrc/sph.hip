@@ -270,9 +270,43 @@ __device__ __forceinline__ void fluid_update(float2& s, float2& w, float2 a, con
   s.y += dt * w.y;
 }
 
+// DPP controls of the cross-lane moves (rows of 16 lanes).
+constexpr int kDppQuadXor1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowMirror = 0x140;     // lane i of a row reads lane 15 - i
+constexpr int kDppRowHalfMirror = 0x141; // lane i of a half-row reads lane 7 - i
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+}
+
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  // butterfly inside aligned groups of G lanes with DPP moves (VALU, no trip
+  // through the LDS crossbar): xor 1 and xor 2 inside each quad, then the
+  // mirrored half of the 8-lane half-row and of the 16-lane row; every lane
+  // of the group ends with the same sum (each addition is commutative)
+  v += dpp_f<kDppQuadXor1>(v);
+  v += dpp_f<kDppQuadXor2>(v);
+  if (G >= 8) v += dpp_f<kDppRowHalfMirror>(v);
+  if (G >= 16) v += dpp_f<kDppRowMirror>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
   return v;
 }
 
@@ -283,6 +317,17 @@ __device__ __forceinline__ void flag(unsigned* status, unsigned bits) {
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
+}
+
+// The same wavefront sum, valid in lane 0, in a fixed order with DPP moves
+// inside each 16-lane row and three lane reads across the rows.  Every lane
+// must be active.
+__device__ __forceinline__ double wave_sum0(double v) {
+  v += dpp_d<kDppQuadXor1>(v);
+  v += dpp_d<kDppQuadXor2>(v);
+  v += dpp_d<kDppRowHalfMirror>(v);
+  v += dpp_d<kDppRowMirror>(v);
+  return (v + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Workgroup -> tile, XCD-aware.  The dispatcher deals consecutive
@@ -1452,7 +1497,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   double v[3] = {(double)fx, (double)fy, (double)tq};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int d = 0; d < 3; ++d) {
-    double t = wave_sum(v[d]);
+    double t = wave_sum0(v[d]);
     if (lane == 0) red[d][wv] = t;
   }
   __syncthreads();
@@ -1485,7 +1530,7 @@ __global__ void __launch_bounds__(kWrenchThreads) sph_wrench(const double* __res
   for (int b = threadIdx.x; b < nt; b += kWrenchThreads)
     for (int d = 0; d < 3; ++d) acc3[d] += partials[3 * (t0 + b) + d];
   for (int d = 0; d < 3; ++d) {
-    double t = wave_sum(acc3[d]);
+    double t = wave_sum0(acc3[d]);
     if (lane == 0) red[d][wv] = t;
   }
   __syncthreads();
@@ -1918,7 +1963,7 @@ __global__ void __launch_bounds__(kResThreads) sph_resident(float2* __restrict__
     }
     const int lane = t & 63, wv = t >> 6;
     for (int d = 0; d < 3; ++d) {
-      const double v = wave_sum(F[d]);
+      const double v = wave_sum0(F[d]);
       if (lane == 0) L.red[d][wv] = v;
     }
     __syncthreads();
