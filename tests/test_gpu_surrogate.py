@@ -1,63 +1,55 @@
-"""The trained surrogate against the SPH it replaces (small version of the
-full training run).
+"""The trained surrogate against the SPH it replaces (the reduced-size
+configuration of the benchmark's surrogate leg).
 
 The network is trained by the library's own kernels on relaxed, then forced,
-random-tank rollouts and judged on held-out rollouts.  What is asserted:
+random-tank rollouts (2k-8k particles, the Tait law without tension, the data
+generator's default) and judged on held-out rollouts.  What is asserted:
 
 * the window kernel builds exactly the standardised windows of the logs;
-* the network answers the held-out windows far faster than SPH produced them;
-* its held-out error is no worse than that of the best constant predictor
-  (the training mean) by more than 10 %.
+* the held-out error of every wrench channel is below 0.85 of the best
+  constant predictor's (the training mean); measured about 0.5-0.7 of it;
+* the network answers the held-out windows far faster than SPH produced them.
 
-What is not asserted, and why: a held-out error below the constant
-predictor.  With the Tait law as written (used here) the zero-gravity slosh
-wrench is dominated by a self-excited oscillation of the weakly compressible
-fluid (a tensile instability: negative pressures; the FP64 oracle shows the
-same), so over a log interval it is uncorrelated with the inputs (theta,
-omega, input torque, fill) and with the previous interval.  The data
-generator's default clamps the pressure at zero, which removes the
-oscillation; the full-size training on such data is a separate run.  The
-measured per-channel NRMSE is printed beside the constant predictor's.
+With the Tait law as written the zero-gravity wrench is dominated by a
+self-excited oscillation (a tensile instability from negative pressures,
+which the FP64 oracle shows too): it is then uncorrelated with the inputs,
+and no predictor beats the mean, so such data cannot test learning.
 """
 import numpy as np
 import pytest
-
-import workloads as W
 
 torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
 
-def test_surrogate_speedup_and_error():
+def test_surrogate_learns_the_wrench_and_is_faster_than_sph():
     from paper_2604_12505_amd import surrogate as S
-    # the Tait law as written: with 24 short rollouts the clamped law's
-    # wrench (zero until the fluid is compressed, then spiky) gives too few
-    # samples for the statistics of the comparison below
-    kw = dict(n_steps=1000, log_stride=10, relax_cycles=10, relax_steps=100, n_min=2000, n_max=4000,
-              eos=W.EOS_TAIT)
-    tr = S.generate(list(range(10, 34)), **kw)
-    te = S.generate(list(range(500, 506)), **kw)
+    kw = dict(n_steps=2000, log_stride=25, relax_cycles=10, relax_steps=100, n_min=2000, n_max=8000)
+    tr = S.generate(list(range(1000, 1192)), **kw)
+    te = S.generate(list(range(900000, 900032)), **kw)
     norm = S.norm_from(tr)
     xtr, ytr = S.windows(tr, norm)
     xte, yte = S.windows(te, norm)
-    assert xtr.shape == (24 * (100 - 31), 128)
+    T = 2000 // 25
+    per = T - 31
+    assert xtr.shape == (192 * per, 128)
     # the window kernel against a direct slicing of the logs
     f = tr.feat[3, 5:37].cpu().numpy()
-    x0 = xtr[3 * 69 + 5].reshape(32, 4).cpu().numpy()
+    x0 = xtr[3 * per + 5].reshape(32, 4).cpu().numpy()
     ref = (np.concatenate([f, np.full((32, 1), tr.fill[3].item())], 1) - norm[:4]) / norm[4:8]
     assert np.allclose(x0, ref, rtol=1e-5, atol=1e-5)
     y_ref = (tr.wrench[3, 36].cpu().numpy() - norm[8:11]) / norm[11:14]
-    assert np.allclose(ytr[3 * 69 + 5].cpu().numpy(), y_ref, rtol=1e-5, atol=1e-5)
-    net = S.train(xtr, ytr, epochs=60, batch=256, lr=2e-3, lr_final=1e-4)
-    inf = S.inference_net(net, max_batch=4096)
+    assert np.allclose(ytr[3 * per + 5].cpu().numpy(), y_ref, rtol=1e-5, atol=1e-5)
+    net = S.train(xtr, ytr, epochs=30, batch=1024, lr=2e-3, lr_final=1e-4)
+    inf = S.inference_net(net, max_batch=8192)
     err = S.nrmse(S.predict(inf, xte), yte, norm)
     base = S.nrmse(torch.zeros_like(yte), yte, norm)
     t_nn = S.time_inference(inf, xte)
     speedup = te.sph_seconds / t_nn
     print("held-out NRMSE", err, "constant predictor", base, "speedup", speedup)
     assert np.all(np.isfinite(err))
-    assert np.all(err <= 1.1 * base)
+    assert np.all(err <= 0.85 * base)
     assert speedup > 10.0
     net.close()
     inf.close()
