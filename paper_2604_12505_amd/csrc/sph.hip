@@ -746,40 +746,77 @@ struct TileLds {
 // fluid index j of row r sits at LDS index off[r] + j - lo[r].  The cells of
 // a segment are non-decreasing along the row, so its staged span of row r is
 // [lo of its first particle, hi of its last].
+// The candidates staged for one pass over a tile: the row ranges of one
+// row segment, or of two consecutive ones back to back when both fit in the
+// stage (a tile whose particles span two grid rows then takes one staging
+// round trip and one compute pass instead of two).  Slots first .. split-1
+// use ranges 0-2, slots split .. last ranges 3-5; unused ranges start at nf.
 struct Seg {
-  int lo[3], off[3], glo[3], goff[3];
-  int nf, ng, first, last;
+  int lo[6], off[6], glo[6], goff[6];
+  int nf, ng, first, last, split;
 };
 
 // The row segment that starts at tile slot `first`: the run of slots from
 // `first` in the same grid row, found with one ballot of wavefront 0 (a tile
 // holds at most 64 slots), and its candidate ranges.  Called by the threads
 // of wavefront 0; thread 0 writes sg.
+// Last slot of the run of slots from `first` in first's grid row, found with
+// one ballot (a tile holds at most 64 slots).  All lanes of wavefront 0.
 template <int TP>
-__device__ void make_segment(Seg& sg, const TileLds<TP>& tl, int first) {
+__device__ __forceinline__ int seg_run_end(const TileLds<TP>& tl, int first) {
   static_assert(TP <= 64, "one wavefront covers the tile");
-  const int lane = threadIdx.x;   // wavefront 0, all lanes active
+  const int lane = threadIdx.x;
   const int row = tl.cy[first];
   const unsigned long long same = __ballot(lane < TP && tl.cy[lane] == row);
-  if (lane != 0) return;
   // slots first, first + 1, ... while the row stays the same (bit 0 of
   // `from` is slot first itself)
   const unsigned long long from = same >> first;
   const int len = ~from == 0ull ? 64 - first : __builtin_ctzll(~from);
-  const int last = first + len - 1;
+  return first + len - 1;
+}
+
+// The stage that starts at tile slot `first`: its row segment, and the next
+// one if `merge` and both fit in stage_f fluid / stage_g ghost slots.  Called
+// by the threads of wavefront 0; thread 0 writes sg.
+template <int TP>
+__device__ void make_segment(Seg& sg, const TileLds<TP>& tl, int first, bool merge = false, int stage_f = 0,
+                             int stage_g = 0) {
+  const int last = seg_run_end<TP>(tl, first);
+  const bool more = merge && last + 1 < TP && tl.cy[last + 1] >= 0;   // the same on every lane
+  const int last2 = more ? seg_run_end<TP>(tl, last + 1) : last;
+  if (threadIdx.x != 0) return;
   int nf = 0, ng = 0;
-  for (int r = 0; r < 3; ++r) {
-    sg.off[r] = nf;
-    sg.goff[r] = ng;
-    sg.lo[r] = tl.rng[first][2 * r];
-    sg.glo[r] = tl.rng[first][6 + 2 * r];
-    nf += tl.rng[last][2 * r + 1] - sg.lo[r];
-    ng += tl.rng[last][6 + 2 * r + 1] - sg.glo[r];
+  auto ranges = [&](int a, int b, int r0) {   // slots a .. b of one row into ranges r0 .. r0 + 2
+    for (int r = 0; r < 3; ++r) {
+      sg.off[r0 + r] = nf;
+      sg.goff[r0 + r] = ng;
+      sg.lo[r0 + r] = tl.rng[a][2 * r];
+      sg.glo[r0 + r] = tl.rng[a][6 + 2 * r];
+      nf += tl.rng[b][2 * r + 1] - sg.lo[r0 + r];
+      ng += tl.rng[b][6 + 2 * r + 1] - sg.glo[r0 + r];
+    }
+  };
+  ranges(first, last, 0);
+  const int nf1 = nf, ng1 = ng;
+  int end = last;
+  if (more) {
+    ranges(last + 1, last2, 3);
+    if (nf <= stage_f && ng <= stage_g) end = last2;
+  }
+  if (end == last) {
+    nf = nf1;
+    ng = ng1;
+    for (int r = 3; r < 6; ++r) {
+      sg.off[r] = nf;
+      sg.goff[r] = ng;
+      sg.lo[r] = sg.glo[r] = 0;
+    }
   }
   sg.nf = nf;
   sg.ng = ng;
   sg.first = first;
-  sg.last = last;
+  sg.last = end;
+  sg.split = last + 1;
 }
 
 // Global index of staged element e (row ranges stored back to back).
@@ -787,6 +824,15 @@ __device__ __forceinline__ int seg_src(const int* lo, const int* off, int e) {
   if (e < off[1]) return lo[0] + e - off[0];
   if (e < off[2]) return lo[1] + e - off[1];
   return lo[2] + e - off[2];
+}
+
+// The same over the six ranges of a stage (empty and unused ranges are
+// skipped: a later range that starts at the same offset takes precedence).
+__device__ __forceinline__ int seg_src6(const int* lo, const int* off, int e) {
+  int r = 0;
+#pragma unroll
+  for (int q = 1; q < 6; ++q) r += e >= off[q] ? 1 : 0;
+  return lo[r] + e - off[r];
 }
 
 // The tile a workgroup works on.  A single-tank handle (single_n = its
@@ -1069,12 +1115,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
   int nf_out = kNearNone, ng_out = kNearNone;
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
-    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first);
+    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first, true, kStageF, kStageG);
     __syncthreads();
     const bool fst = sg.nf <= kStageF, gst = sg.ng <= kStageG;
     if (fst)
       for (int e = threadIdx.x; e < sg.nf; e += kBlock) {
-        const int j = seg_src(sg.lo, sg.off, e);
+        const int j = seg_src6(sg.lo, sg.off, e);
         float2 sj = pos_in[j];
         if (Build) f_raw[e] = pos_sort[j];
         if (integrate) {
@@ -1084,15 +1130,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
         f_pos[e] = sj;
       }
     if (gst)
-      for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src(sg.glo, sg.goff, e)];
+      for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src6(sg.glo, sg.goff, e)];
     __syncthreads();
     if (mine && pl >= sg.first && pl <= sg.last) {
+      // this particle's segment's ranges in the stage
+      const int sh = pl < sg.split ? 0 : 3;
+      const int *lo = sg.lo + sh, *off = sg.off + sh, *glo = sg.glo + sh, *goff = sg.goff + sh;
       auto fluid = [&](float2 sj) {
         float d2 = dist2(s.x - sj.x, s.y - sj.y);
         if (d2 < k.R2) sf += cubic_shape(fsqrt(d2) * k.inv_h);
       };
       int total;
-      const OrdMap fm = ord_map<TP>(tl, pl, false, sg.lo, sg.off, &total);
+      const OrdMap fm = ord_map<TP>(tl, pl, false, lo, off, &total);
       const int nlf = tl.near[pl] & 255;
       bool walked = false;
       if (Build && fst && total <= 255) {
@@ -1114,9 +1163,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
       }
       if (!walked) {
         if (fst) {
-          visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int, int e) { fluid(f_pos[e]); });
+          visit<G, TP>(tl, pl, false, lo, off, l, [&](int, int e) { fluid(f_pos[e]); });
         } else {
-          visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) {
+          visit<G, TP>(tl, pl, false, lo, off, l, [&](int j, int) {
             float2 sj = pos_in[j];
             if (integrate) {
               float2 wj = vel_in[j];
@@ -1131,7 +1180,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
         if (d2 < k.R2) sgs += cubic_shape(fsqrt(d2) * k.inv_h);
       };
       int gtotal;
-      const OrdMap gm = ord_map<TP>(tl, pl, true, sg.glo, sg.goff, &gtotal);
+      const OrdMap gm = ord_map<TP>(tl, pl, true, glo, goff, &gtotal);
       const int nlg = (tl.near[pl] >> 8) & 255;
       bool gwalked = false;
       if (Build && gst && gtotal <= 255) {
@@ -1152,9 +1201,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
       }
       if (!gwalked) {
         if (gst)
-          visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int, int e) { ghost(g_pos[e]); });
+          visit<G, TP>(tl, pl, true, glo, goff, l, [&](int, int e) { ghost(g_pos[e]); });
         else
-          visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) { ghost(gpos[j]); });
+          visit<G, TP>(tl, pl, true, glo, goff, l, [&](int j, int) { ghost(gpos[j]); });
       }
     }
     const int next = sg.last + 1;
@@ -1368,20 +1417,23 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   float fx = 0.0f, fy = 0.0f, tq = 0.0f;
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
-    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first);
+    if (threadIdx.x < 64) make_segment<TP>(sg, tl, first, true, kStageF, kStageG);
     __syncthreads();
     const bool fst = sg.nf <= kStageF, gst = sg.ng <= kStageG;
     if (fst)
       for (int e = threadIdx.x; e < sg.nf; e += kBlock) {
-        const int j = seg_src(sg.lo, sg.off, e);
+        const int j = seg_src6(sg.lo, sg.off, e);
         f_pos[e] = pos[j];
         f_vel[e] = vel[j];
         f_rp[e] = rp[j];
       }
     if (gst)
-      for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src(sg.glo, sg.goff, e)];
+      for (int e = threadIdx.x; e < sg.ng; e += kBlock) g_pos[e] = gpos[seg_src6(sg.glo, sg.goff, e)];
     __syncthreads();
     if (mine && pl >= sg.first && pl <= sg.last) {
+      // this particle's segment's ranges in the stage
+      const int sh = pl < sg.split ? 0 : 3;
+      const int *lo = sg.lo + sh, *off = sg.off + sh, *glo = sg.glo + sh, *goff = sg.goff + sh;
       // pair terms of a neighbour inside the support (0 < r < 2h)
       auto fluid = [&](float2 sj, float2 wj, float2 o) {
         float dx = s.x - sj.x, dy = s.y - sj.y;
@@ -1401,7 +1453,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
         // list the neighbours inside the support, then all G lanes work on the list
         unsigned short* lst = f_list[pl];
         int total;
-        const OrdMap fm = ord_map<TP>(tl, pl, false, sg.lo, sg.off, &total);
+        const OrdMap fm = ord_map<TP>(tl, pl, false, lo, off, &total);
         auto inside = [&](int e) {
           const float2 sj = f_pos[e];
           const float d2 = dist2(s.x - sj.x, s.y - sj.y);
@@ -1423,7 +1475,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
           while (c < total) pairs(list_pass<G>(fm, total, l, c, kListF, lst, inside));
         }
       } else {
-        visit<G, TP>(tl, pl, false, sg.lo, sg.off, l, [&](int j, int) { fluid_test(pos[j], vel[j], rp[j]); });
+        visit<G, TP>(tl, pl, false, lo, off, l, [&](int j, int) { fluid_test(pos[j], vel[j], rp[j]); });
       }
       // wall terms of a ghost inside the spiky support (0 < r < h_s)
       auto ghost = [&](float2 gj) {
@@ -1445,7 +1497,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
       if (gst) {
         unsigned short* lst = g_list[pl];
         int total;
-        const OrdMap gm = ord_map<TP>(tl, pl, true, sg.glo, sg.goff, &total);
+        const OrdMap gm = ord_map<TP>(tl, pl, true, glo, goff, &total);
         auto inside = [&](int e) {
           const float2 gj = g_pos[e];
           const float d2 = dist2(s.x - gj.x, s.y - gj.y);
@@ -1464,7 +1516,7 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
           while (c < total) walls(list_pass<G>(gm, total, l, c, kListG, lst, inside));
         }
       } else {
-        visit<G, TP>(tl, pl, true, sg.glo, sg.goff, l, [&](int j, int) {
+        visit<G, TP>(tl, pl, true, glo, goff, l, [&](int j, int) {
           const float2 gj = gpos[j];
           const float d2 = dist2(s.x - gj.x, s.y - gj.y);
           if (d2 < k.Rs2 && d2 > 0.0f) ghost(gj);
