@@ -61,8 +61,8 @@ FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 # proportion they run), on the closed-loop tank for the configurations the
 # autotuner picks from (profiles/hbm_traffic_closed_loop_circle.md); valid
 # for the source whose hash is recorded, null once the kernel source changes.
-TRAFFIC = {"src_sha1": "0c5fb4f831a41d136c51cbff776817fbbf6d892b",
-           "bytes_per_launch": {"sph_force/16/0": 1726661, "sph_density/16/0": 1999224, "sph_force/16/1": 3183295, "sph_density/16/1": 3354388, "sph_force/32/0": 1779002, "sph_density/32/0": 2012470, "sph_force/32/1": 3234648, "sph_density/32/1": 3353872}}
+TRAFFIC = {"src_sha1": "a425062e8f840a7d0c8f4818f19c4a7dc99202e3",
+           "bytes_per_launch": {"sph_force/16/0": 1741341, "sph_density/16/0": 2009451, "sph_force/16/1": 3197587, "sph_density/16/1": 3357636, "sph_force/32/0": 1784934, "sph_density/32/0": 2012494, "sph_force/32/1": 3242387, "sph_density/32/1": 3370210}}
 
 
 def progress(msg: str) -> None:
