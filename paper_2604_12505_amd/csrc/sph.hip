@@ -65,7 +65,7 @@ constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
 constexpr int kPlaceAhead = 4;    // source keys per lane loaded ahead in the placement
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;       // cells per thread per scan chunk
-constexpr int kWrenchThreads = 1024;  // one workgroup per tank sums its tile partials
+constexpr int kWrenchThreads = 256;   // one workgroup per tank sums its tile partials (one wave per SIMD: thread 0's FP64 tail has every register)
 constexpr int kSortEvery = 4;     // default steps between cell-list rebuilds
 constexpr int kChunk = 64;        // steps per captured graph (a multiple of every rebuild interval, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
@@ -404,18 +404,26 @@ struct ScanLds {
   int wsum[kScanThreads / 64];
 };
 
-// One chunk of kChunkCells cells from `base`: exclusive scan of the counts
-// plus `carry` written to start (offset by base0), counts cleared; returns
-// the chunk's total.  A coalesced load into LDS, a sequential scan of
-// kScanPer cells per thread, a workgroup scan of the per-thread sums (wave
-// shuffles, wave totals in LDS), a coalesced write back.
-__device__ int scan_chunk(ScanLds& S, int* __restrict__ count, const Tank& tk, int base, int carry, int base0,
-                          int* __restrict__ start) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+// The counts of the chunk from `base` into registers (coalesced: v[q] is
+// cell base + q * kScanThreads + thread; 0 past the tank's last cell).
+__device__ __forceinline__ void scan_load(int (&v)[kScanPer], const int* __restrict__ count, const Tank& tk,
+                                          int base) {
   for (int q = 0; q < kScanPer; ++q) {
-    const int i = q * kScanThreads + t;
-    S.buf[scan_slot(i)] = base + i < tk.nc ? count[tk.c0 + base + i] : 0;
+    const int i = q * kScanThreads + threadIdx.x;
+    v[q] = base + i < tk.nc ? count[tk.c0 + base + i] : 0;
   }
+}
+
+// One chunk of kChunkCells cells from `base`, its counts v loaded by
+// scan_load: exclusive scan of the counts plus `carry` written to start
+// (offset by base0), counts cleared; returns the chunk's total.  The counts
+// into LDS, a sequential scan of kScanPer cells per thread, a workgroup scan
+// of the per-thread sums (wave shuffles, wave totals in LDS), a coalesced
+// write back.
+__device__ int scan_chunk(ScanLds& S, const int (&v)[kScanPer], int* __restrict__ count, const Tank& tk,
+                          int base, int carry, int base0, int* __restrict__ start) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int q = 0; q < kScanPer; ++q) S.buf[scan_slot(q * kScanThreads + t)] = v[q];
   __syncthreads();
   int sum = 0;
   for (int q = 0; q < kScanPer; ++q) {
@@ -463,7 +471,14 @@ __global__ void __launch_bounds__(kScanThreads) sph_scan(int* __restrict__ count
   const Tank& tk = tanks[blockIdx.x];
   const int base0 = ghosts ? tk.q0 : tk.p0, expect = ghosts ? tk.ng : tk.n;
   int carry = 0;
-  for (int base = 0; base < tk.nc; base += kChunkCells) carry += scan_chunk(S, count, tk, base, carry, base0, start);
+  int v[kScanPer], nx[kScanPer] = {};
+  scan_load(v, count, tk, 0);
+  for (int base = 0; base < tk.nc; base += kChunkCells) {
+    // the next chunk's counts are in flight while this chunk is scanned
+    if (base + kChunkCells < tk.nc) scan_load(nx, count, tk, base + kChunkCells);
+    carry += scan_chunk(S, v, count, tk, base, carry, base0, start);
+    for (int q = 0; q < kScanPer; ++q) v[q] = nx[q];
+  }
   if (threadIdx.x == 0) {
     // the entry past a tank's last cell is the next tank's first; the last
     // tank writes the final one
@@ -537,7 +552,9 @@ __global__ void __launch_bounds__(kScanThreads) sph_scan_chunks(int* __restrict_
   __shared__ ScanLds S;
   const Tank& tk = tanks[0];
   const int base0 = ghosts ? tk.q0 : tk.p0, expect = ghosts ? tk.ng : tk.n;
-  scan_chunk(S, count, tk, blockIdx.x * kChunkCells, part[blockIdx.x], base0, start);
+  int v[kScanPer];
+  scan_load(v, count, tk, blockIdx.x * kChunkCells);
+  scan_chunk(S, v, count, tk, blockIdx.x * kChunkCells, part[blockIdx.x], base0, start);
   if (threadIdx.x == 0 && (int)blockIdx.x == n_parts - 1) {
     const int total = part[n_parts];
     start[tk.c0 + tk.nc] = base0 + total;
@@ -1570,9 +1587,19 @@ __global__ void __launch_bounds__(kWrenchThreads) sph_wrench(const double* __res
                                                      const DevRollout* __restrict__ ro, int mode) {
   __shared__ double red[3][kWrenchThreads / 64];
   const int tank = blockIdx.x;
-  const RigidArgs& ra = tanks[tank].ra;
+  // thread 0's copies of the rigid state, parameters and rollout, loaded
+  // while the partials are summed (reads of them after the barrier would
+  // each wait a memory round trip)
+  DevRigid rb;
+  RigidArgs ra;
+  DevRollout rl;
   RigidIn in;
-  if (threadIdx.x == 0) in = rigid_inputs(&rigid[tank], ro, tank, mode, ra);   // in flight during the sum
+  if (threadIdx.x == 0) {
+    rb = rigid[tank];
+    ra = tanks[tank].ra;
+    rl = *ro;
+    in = rigid_inputs(&rb, &rl, tank, mode, ra);
+  }
   // a single tank's tiles are 0 .. single_nt - 1 (no table load)
   const int t0 = single_nt >= 0 ? 0 : tank_tile0[tank];
   const int nt = single_nt >= 0 ? single_nt : tank_tile0[tank + 1] - t0;
@@ -1593,7 +1620,8 @@ __global__ void __launch_bounds__(kWrenchThreads) sph_wrench(const double* __res
       for (int q = 0; q < kWrenchThreads / 64; ++q) t += red[d][q];
       F[d] = t;
     }
-    rigid_step(&rigid[tank], ro, tank, F, mode, ra, in);
+    rigid_step(&rb, &rl, tank, F, mode, ra, in);
+    rigid[tank] = rb;
   }
 }
 
