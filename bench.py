@@ -61,7 +61,7 @@ FLOP = {"density": NEIGHBOURS * 14, "force": NEIGHBOURS * 28}
 # proportion they run), on the closed-loop tank for the configurations the
 # autotuner picks from (profiles/hbm_traffic_closed_loop_circle.md); valid
 # for the source whose hash is recorded, null once the kernel source changes.
-TRAFFIC = {"src_sha1": "9e38fa988a7a2b2db03389a4cfe354333f0ba90b",
+TRAFFIC = {"src_sha1": "edc4a7216d9360e4305a2ec70cea0791bf63e82e",
            "bytes_per_launch": {"sph_force/16/0": 1735751, "sph_density/16/0": 2017587, "sph_force/16/1": 3199024, "sph_density/16/1": 3367910, "sph_force/32/0": 1792229, "sph_density/32/0": 2024753, "sph_force/32/1": 3245754, "sph_density/32/1": 3372735}}
 
 

@@ -65,7 +65,9 @@ constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
 constexpr int kPlaceAhead = 4;    // source keys per lane loaded ahead in the placement
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;       // cells per thread per scan chunk
-constexpr int kWrenchThreads = 256;   // one workgroup per tank sums its tile partials (one wave per SIMD: thread 0's FP64 tail has every register)
+// one workgroup per tank sums its tile partials; one wave per SIMD, so that
+// thread 0's FP64 tail has every register
+constexpr int kWrenchThreads = 256;
 constexpr int kSortEvery = 4;     // default steps between cell-list rebuilds
 constexpr int kChunk = 64;        // steps per captured graph (a multiple of every rebuild interval, even)
 constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between rebuilds
