@@ -23,16 +23,23 @@ def test_step_jacobian_matches_oracle_differences():
     from paper_2604_12505_amd.eigen import step_jacobian, continuous_eigenvalues
     from paper_2604_12505_amd.sph import Simulator
     sc = W.linearization_tank(0, n_steps=60, n_fluid=100)
+    # the oracle advances the tank 60 steps; the GPU starts from the state it
+    # reaches, rounded to binary32, and the differences are taken around it
+    st = O.state_from_scenario(sc)
+    status, _ = O.rollout(sc.params, st, sc.ghosts.astype(np.float64), 60, sc.u_seq[:60])
+    assert status == 0
+    s = st.s.astype(np.float32)
+    w = st.w.astype(np.float32)
+    rig, step = st.rigid.copy(), st.step
     sim = Simulator.from_scenario(sc)
-    sim.rollout(60, torch.as_tensor(sc.u_seq))
-    s, w, rig, tau, step = sim.get_state()
+    sim.set_state(torch.as_tensor(s), torch.as_tensor(w), rig, st.tau_ctrl, step)
     u = (0.0, 0.0, float(sc.u_seq[-1, 2]))
     J = step_jacobian(sim, u, block=64)
     N = sc.n_fluid
     n = 6 + 4 * N
     assert J.shape == (n, n)
-    s0 = s.cpu().numpy().astype(np.float64)
-    w0 = w.cpu().numpy().astype(np.float64)
+    s0 = s.astype(np.float64)
+    w0 = w.astype(np.float64)
     g = sc.ghosts.astype(np.float64)
     useq = np.array([u], np.float32)
 

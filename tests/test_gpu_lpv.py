@@ -151,7 +151,10 @@ def test_lbfgs_reaches_a_minimum_of_a_realisable_fit():
     loss, status, iters = L.lbfgs(P, torch.as_tensor(u, device=DEV), torch.as_tensor(y, device=DEV), 400, opts)
     loss = loss.cpu().numpy()
     yh = L.simulate(P, torch.as_tensor(u, device=DEV)).cpu().numpy()
-    fits = [O.bfr(y, yh[r]).mean() for r in range(R)]
+    # best fit rate of each fit, percent (Section 5.3), written out here: the
+    # GPU's outputs are scored, not passed to the oracle
+    fits = [100.0 * (1.0 - np.linalg.norm(y - yh[r], axis=0) / np.linalg.norm(y - y.mean(0), axis=0)).mean()
+            for r in range(R)]
     assert np.median(fits) > 99.0, fits
     assert np.all(loss <= O.loss(V[0], u, y, 0.0, 0.0))
 

@@ -35,9 +35,21 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def _state_of(sim):
-    s, w, rig, tau, step = sim.get_state()
-    return O.State(s.cpu().numpy().astype(np.float64), w.cpu().numpy().astype(np.float64), rig, tau, step)
+def _oracle_lead(sc, n, u_seq=None, theta_ref=None):
+    """The scenario advanced n steps by the oracle, positions and velocities
+    rounded to binary32 (what the GPU stores), so that both sides can start
+    from exactly this state."""
+    st = O.state_from_scenario(sc)
+    status, _ = O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n, u_seq, theta_ref)
+    assert status == 0
+    st.s = st.s.astype(np.float32).astype(np.float64)
+    st.w = st.w.astype(np.float32).astype(np.float64)
+    return st
+
+
+def _load(sim, st):
+    sim.set_state(torch.as_tensor(st.s.astype(np.float32)), torch.as_tensor(st.w.astype(np.float32)),
+                  st.rigid, st.tau_ctrl, st.step)
 
 
 def _small_circle(seed=0, n_steps=50):
@@ -94,8 +106,9 @@ def test_neighbour_sets_on_cell_edges():
     sim.close()
 
 
-def _rhs_compare(sc, sim, u=(0.0, 0.0, 0.0), tol=1e-4):
-    st = _state_of(sim)
+def _rhs_compare(sc, sim, st, u=(0.0, 0.0, 0.0), tol=1e-4):
+    # st: the oracle's state, the one sim holds (the scenario's initial state,
+    # or one the oracle advanced and _load gave to sim)
     ut = torch.tensor(u, dtype=torch.float32, device="cuda")
     g = sim.rhs(ut)
     r = O.rhs(sc.params, st, sc.ghosts.astype(np.float64), u)
@@ -126,21 +139,23 @@ def _rhs_compare(sc, sim, u=(0.0, 0.0, 0.0), tol=1e-4):
 def test_rhs_parity_initial_state(name):
     sc = SCENARIOS[name]()
     sim = _sim(sc)
-    _rhs_compare(sc, sim, u=(3.0, -2.0, 5.0))
+    _rhs_compare(sc, sim, O.state_from_scenario(sc), u=(3.0, -2.0, 5.0))
     sim.close()
 
 
 @pytest.mark.parametrize("near", [False, True], ids=["full_walk", "near_lists"])
 @pytest.mark.parametrize("name", ["plain_rect", "closed_loop_circle", "random_rect"])
 def test_rhs_parity_after_evolution(name, near):
+    # the oracle advances the scenario 203 steps and both sides evaluate the
+    # state it reaches (pressures and velocities no longer those of the
+    # lattice); evaluations between rebuilds, on near lists built at earlier
+    # positions, are covered by the trajectory tests
     sc = SCENARIOS[name]()
+    n = 203
+    st = _oracle_lead(sc, n, np.tile(sc.u_seq[:1], (n, 1)) if sc.u_seq is not None else None, sc.theta_ref)
     sim = _sim(sc, near)
-    # 203 steps: the evaluation falls three steps after a rebuild, so it walks
-    # near lists built at positions that have moved since
-    sim.rollout(203, torch.as_tensor(np.tile(sc.u_seq[:1], (203, 1))) if sc.u_seq is not None else None,
-                theta_ref=sc.theta_ref)
-    assert sim.status() == 0
-    _rhs_compare(sc, sim)
+    _load(sim, st)
+    _rhs_compare(sc, sim, st)
     sim.close()
 
 
@@ -299,7 +314,7 @@ def test_dense_cells_take_the_global_paths(lanes, near):
     sc = _dense_rect()
     sim = _sim(sc, near)
     sim.set_lanes(lanes)
-    _rhs_compare(sc, sim)
+    _rhs_compare(sc, sim, O.state_from_scenario(sc))
     n = 50
     sim.rollout(n, torch.as_tensor(sc.u_seq[:n]))
     s, w, rig, _, step = sim.get_state()
@@ -309,6 +324,18 @@ def test_dense_cells_take_the_global_paths(lanes, near):
     err = np.sqrt(((s.cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
     print("dense lanes", lanes, "near", near, "pos err / L", err / sc.tank_size)
     assert err <= 1e-3 * sc.tank_size
+    sim.close()
+
+
+@pytest.mark.parametrize("lanes", [8, 32])
+def test_rhs_parity_on_a_large_tank(lanes):
+    # 409,600 fluid particles in ~55,000 cells: the cell list comes from the
+    # three-launch scan, and each thread of the wrench kernel sums many tile
+    # partials (12,800 tiles at 8 lanes per particle, 51,200 at 32)
+    sc = W.rect_sweep(4, seed=1, n_steps=8)
+    sim = _sim(sc)
+    sim.set_lanes(lanes)
+    _rhs_compare(sc, sim, O.state_from_scenario(sc), u=(3.0, -2.0, 5.0))
     sim.close()
 
 
