@@ -1,24 +1,31 @@
-"""Builds the FP64 oracle library (test infrastructure only) with gcc."""
+"""Builds the FP64 oracle library (test infrastructure only) with gcc.
+
+``python oracle/build.py --sanitize`` builds it with AddressSanitizer and
+UndefinedBehaviorSanitizer instead (host code; run the CPU tests with the
+sanitizer runtimes preloaded, as the design doc describes), and a plain
+``python oracle/build.py`` restores the normal build."""
 from __future__ import annotations
 
 import os
 import subprocess
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "sph_oracle.c")
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, sanitize: bool = False) -> str:
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-           "-shared", "-fPIC", "-Wall", "-o", tmp, SRC, "-lm"]
+           "-shared", "-fPIC", "-Wall", *(SANITIZE if sanitize else []), "-o", tmp, SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(sanitize="--sanitize" in sys.argv[1:]))

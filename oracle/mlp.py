@@ -65,9 +65,16 @@ def loss(params, x, y):
 
 def backward(params, x, y):
     """Gradients of the mean squared error, by the chain rule written out."""
-    out, pre, acts = forward(params, x)
+    out, _, _ = forward(params, x)
     B, D = out.shape
-    g = 2.0 * (out - y) / (B * D)          # dL/d out
+    return backward_from(params, x, 2.0 * (out - y) / (B * D))   # dL/d out of the mean
+
+
+def backward_from(params, x, dy):
+    """Gradients of any loss whose derivative with respect to the output is
+    dy [B, 3], by the chain rule written out."""
+    _, pre, acts = forward(params, x)
+    g = np.asarray(dy, np.float64)
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]

@@ -59,6 +59,10 @@ def lib():
                                         p, i, p]
         L.ora_num_threads.restype = i
         L.ora_num_threads.argtypes = []
+        L.ora_set_num_threads.restype = None
+        L.ora_set_num_threads.argtypes = [i]
+        L.ora_set_round_f32.restype = None
+        L.ora_set_round_f32.argtypes = [i]
         L.ora_gamma1_terms.restype = None
         L.ora_gamma1_terms.argtypes = [C.POINTER(OraParams), i, p, p, i, p, p, p, p]
         _lib = L
@@ -236,6 +240,16 @@ def rollout_world(prm, x, v, ghosts_body, rigid, n_steps, u_seq=None, theta_ref=
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().ora_set_num_threads(int(n))
+
+
+def set_round_f32(on: bool) -> None:
+    """Rollouts round the fluid state to binary32 after every step (off by
+    default): a measure of how much rounding at that precision moves them."""
+    lib().ora_set_round_f32(1 if on else 0)
 
 
 def gamma1_terms(prm, fluid, ghosts):

@@ -83,7 +83,26 @@ typedef struct {
   int64_t step;         /* global step counter n; time t_n = n dt */
 } ora_rigid;
 
-enum { ORA_ESCAPED = 1, ORA_NONFINITE = 2 };
+enum { ORA_ESCAPED = 1, ORA_NONFINITE = 2, ORA_CFL = 4 };
+
+/* Largest Courant number dt (c + |w|) / h a step may reach: twice the 0.2 the
+ * time step is set from (the CFL condition of explicit weakly compressible
+ * SPH; c is the equation of state's sound speed at rest). */
+#define ORA_COURANT_MAX 0.4
+
+/* When set (ora_set_round_f32), ora_rollout rounds the fluid state to
+ * binary32 after every step: a reference for how far rounding at the
+ * precision the GPU stores its state moves a long rollout and its finite
+ * differences.  Off by default. */
+static int g_round_f32 = 0;
+
+void ora_set_round_f32(int on) { g_round_f32 = on ? 1 : 0; }
+
+/* Sound speed at rest: c0 for the Tait law, sqrt(dP/drho) = sqrt(k) for the
+ * linear law (eq. EOS). */
+static double sound_speed(const ora_params* p) {
+  return (p->eos == 1 || p->eos == 2) ? sqrt(p->k_lin) : p->c0;
+}
 
 /* ------------------------------------------------------------------------- */
 /* kernels (eqs. cubicspline, spiky3)                                        */
@@ -521,7 +540,9 @@ int ora_rhs(const ora_params* p, int n, const double* sx, const double* sy, cons
  *            wrench_log [n_log][3] (body frame), u_log [n_log][3] (applied
  *            F_x, F_y, total torque), wrench_mean_log [n_log][3] (mean body-frame
  *            wrench over the steps of the log interval); any may be NULL.
- *   returns: status bits (1 = a particle left the domain, 2 = non-finite value). */
+ *   returns: status bits (1 = a particle left the domain, 2 = non-finite value,
+ *            4 = a particle's Courant number dt (c + |w|) / h exceeded
+ *            ORA_COURANT_MAX after an update). */
 int ora_rollout(const ora_params* p, int n, double* sx, double* sy, double* wx, double* wy,
                 int ng, const double* gx, const double* gy, double* rigid, double* tau_ctrl,
                 int64_t* step, int n_steps, const float* u_seq, const double* theta_ref,
@@ -538,6 +559,7 @@ int ora_rollout(const ora_params* p, int n, double* sx, double* sy, double* wx, 
   ora_rigid b = {{rigid[0], rigid[1]}, rigid[2], {rigid[3], rigid[4]}, rigid[5], *tau_ctrl, *step};
   double mean_acc[3] = {0, 0, 0};
   int mean_cnt = 0;
+  const double c_snd = sound_speed(p);
   for (int it = 0; it < n_steps; ++it) {
     double u[3] = {0, 0, 0};
     if (u_seq) {
@@ -584,11 +606,21 @@ int ora_rollout(const ora_params* p, int n, double* sx, double* sy, double* wx, 
       wy[i] += p->dt * dwy[i];
       sx[i] += p->dt * wx[i];
       sy[i] += p->dt * wy[i];
-      if (!isfinite(sx[i]) || !isfinite(sy[i]) || !isfinite(wx[i]) || !isfinite(wy[i]))
+      if (g_round_f32) {
+        wx[i] = (double)(float)wx[i];
+        wy[i] = (double)(float)wy[i];
+        sx[i] = (double)(float)sx[i];
+        sy[i] = (double)(float)sy[i];
+      }
+      if (!isfinite(sx[i]) || !isfinite(sy[i]) || !isfinite(wx[i]) || !isfinite(wy[i])) {
         status |= ORA_NONFINITE;
-      else if (sx[i] < p->domain_min[0] || sx[i] >= p->domain_max[0] ||
-               sy[i] < p->domain_min[1] || sy[i] >= p->domain_max[1])
-        status |= ORA_ESCAPED;
+      } else {
+        if (sx[i] < p->domain_min[0] || sx[i] >= p->domain_max[0] ||
+            sy[i] < p->domain_min[1] || sy[i] >= p->domain_max[1])
+          status |= ORA_ESCAPED;
+        if (p->dt * (c_snd + sqrt(wx[i] * wx[i] + wy[i] * wy[i])) > ORA_COURANT_MAX * p->h)
+          status |= ORA_CFL;
+      }
     }
     if (p->motion == 1) {
       double th, thd, thdd;
@@ -709,6 +741,16 @@ int ora_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+/* Threads of the parallel loops from now on (timing the oracle on one core
+ * and on all of them). */
+void ora_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }
 
