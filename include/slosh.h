@@ -47,7 +47,11 @@ extern "C" {
 /* ---- device status bits (latched on device, read by sph_status) -------- */
 #define SPH_ST_ESCAPED 1u     /* a fluid particle left the domain box */
 #define SPH_ST_NONFINITE 2u   /* a NaN or Inf position or velocity appeared */
-#define SPH_ST_SORT 4u        /* a particle moved more than one cell in a step */
+#define SPH_ST_SORT 4u        /* a particle moved farther than the cell list's
+                               * skin allows since the last rebuild */
+#define SPH_ST_CFL 8u         /* a fluid particle's speed put the step's Courant
+                               * number dt (c + |w|) / h above 0.4 (c: sound
+                               * speed at rest, c0 or sqrt(k_lin)) */
 
 /* ---- method options ----------------------------------------------------- */
 #define SPH_EOS_TAIT 0        /* P = B((rho/rho0)^gamma - 1), B = rho0 c0^2/gamma */
@@ -93,15 +97,23 @@ typedef struct sph_handle sph_handle;
  * a cell grid above 2^26 cells). */
 int sph_workspace_bytes(const sph_params* p, int32_t n_fluid, int32_t n_ghost, size_t* bytes);
 
-/* Creates a simulator.  s0_dev, w0_dev: [n_fluid][2] body-frame positions and
+/* Creates a simulator of the system of the problem statement (Section 2:
+ * the spacecraft's planar rigid body carrying a partially filled tank, state
+ * x = [r, theta, r_if, rdot, thetadot, rdot_if] of Section 3.4) at its
+ * initial state: the fluid's particles (Section 3.1) and the tank wall's
+ * fixed ghost particles (Section 3.2, which the paper moves with the tank by
+ * eq. kinematicghost and this library keeps static in the tank's body
+ * frame).  s0_dev, w0_dev: [n_fluid][2] body-frame positions and
  * velocities; g_dev: [n_ghost][2] static body-frame ghost positions; rigid0:
  * host [6] = r_x, r_y, theta, rdot_x, rdot_y, thetadot (world frame, double).
  * ws_dev: workspace of at least sph_workspace_bytes, 256-byte aligned, which
  * the caller keeps alive until sph_destroy.  Input arrays are copied and may
  * be freed after the call returns (the call synchronises the stream).
  * Builds the static ghost cell list and sorts the fluid into cells.
- * Returns SPH_E_INVAL on bad sizes/pointers or a particle outside the
- * domain box, SPH_E_CAPACITY if ws_bytes is too small. */
+ * Returns SPH_E_INVAL on bad sizes/pointers, a particle outside the domain
+ * box, or a time step above the Courant limit at rest (dt c > 0.4 h, c the
+ * sound speed of the equation of state, for a tank that holds fluid);
+ * SPH_E_CAPACITY if ws_bytes is too small. */
 int sph_init(const sph_params* p, int32_t n_fluid, const float* s0_dev, const float* w0_dev,
              int32_t n_ghost, const float* g_dev, const double* rigid0, void* ws_dev,
              size_t ws_bytes, void* stream, sph_handle** out);
@@ -181,7 +193,13 @@ int sph_destroy(sph_handle* h);
  * and torque, or NULL for zero.  Asynchronous. */
 int sph_step(sph_handle* h, const float* u_dev);
 
-/* n_steps steps replayed from captured HIP graphs.  u_seq_dev: [n_steps][3]
+/* n_steps steps of the closed-loop simulation of Section 3.5 (each step is
+ * sph_step: Algorithm "state transition function" followed by first-order
+ * symplectic Euler, Section 3.4) under its multi-rate scheme: the SPH state
+ * advances every step, the attitude law of Section 5.1 is sampled and held
+ * every ctrl_period steps (zero-order hold), and the outputs are logged every
+ * log_stride steps.  The steps are replayed from captured HIP graphs.
+ * u_seq_dev: [n_steps][3]
  * inputs or NULL (zero); theta_ref_dev: [n_ref] double angle references at the
  * control instants (global step / ctrl_period) or NULL (zero), used by
  * SPH_CTRL_PD_ZOH.  Every log_stride steps (log_stride > 0) entry k receives
@@ -276,6 +294,19 @@ int sph_time_kernels(sph_handle* h, int32_t n_steps, const float* u_seq_dev,
 int sph_gamma1_terms(const sph_params* p, const float* fluid_dev, int32_t n_fluid, const float* ghost_dev,
                      int32_t n_ghost, double* num_dev, double* den_dev, void* stream);
 
+/* A representative value of eq. gamma1 for a fluid state: the terms of
+ * sph_gamma1_terms (written to the caller's num_dev / den_dev [n_fluid]),
+ * then, on the host, the median of num/den over the fraction `top` (0, 1]
+ * of the particles with a non-zero ghost sum that have the largest ghost
+ * sums (ties by index; of an even count the lower middle value).  Those are
+ * the particles against the wall with a full fluid neighbourhood on the
+ * other side, the configuration the paper evaluates eq. gamma1 for (a
+ * particle next to the wall, Section 3.2).  Synchronises the default stream
+ * (the terms are computed on it); *gamma1 is host memory.  SPH_E_INVAL if no
+ * particle sees a ghost. */
+int sph_gamma1_estimate(const sph_params* p, const float* fluid_dev, int32_t n_fluid, const float* ghost_dev,
+                        int32_t n_ghost, double top, double* num_dev, double* den_dev, double* gamma1);
+
 /* ---- linearization: tangent-linear rollout ---------------------------- */
 /*
  * Forward-mode derivative of the coupled step (the linearization of
@@ -363,6 +394,26 @@ int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev);
 int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, int32_t batch,
                    float lr, float beta1, float beta2, float eps, float* grad_dev,
                    float* loss_dev);
+
+/* Back-propagation of a given output gradient (Section 4 trains its
+ * surrogate by gradient descent on a simulation-error loss; this is the
+ * gradient half of such a step for the network above): the forward pass of
+ * x_dev [B][128] is recomputed with its activations kept, then dy_dev
+ * [B][3] = dL/dy is propagated back through the head and the four GELU
+ * layers.  grads_dev [231171] receives dL/dparams in the packing above
+ * (FP32; BF16 activations and weights, FP32 accumulation).  B is a multiple
+ * of 32 in [32, max_batch]; SPH_E_INVAL otherwise.  The weights do not
+ * change.  Asynchronous. */
+int mlp_backward(mlp_handle* h, const float* x_dev, const float* dy_dev, int32_t batch, float* grads_dev);
+
+/* One Adam step (Kingma and Ba; the optimizer Section 4 starts its fits
+ * with) on the FP32 master weights from grads_dev [231171], bias-corrected
+ * for step t >= 1 (1 - beta^t); moments are kept in the handle and start at
+ * zero; the BF16 copies used by the kernels are refreshed.  The handle's
+ * step counter (used by mlp_train_step) becomes t.  SPH_E_INVAL for t < 1,
+ * lr < 0, betas outside [0, 1) or eps <= 0.  Asynchronous. */
+int mlp_adam_step(mlp_handle* h, const float* grads_dev, float lr, float beta1, float beta2, float eps,
+                  int32_t t);
 
 /* Builds standardised surrogate inputs and targets from rollout logs.
  * feat_dev [n_roll][n_t][3] = theta, thetadot, input torque per log sample;

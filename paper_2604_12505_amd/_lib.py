@@ -34,9 +34,9 @@ SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sp
                "sph_num_tanks", "sph_autotune", "sph_set_lanes", "sph_set_near_lists", "sph_get_tuning",
                "sph_set_rebuild_interval", "sph_get_rebuild_interval",
                "sph_jvp_workspace_bytes", "sph_jvp_rollout", "sph_vjp_workspace_bytes", "sph_vjp_rollout",
-               "sph_gamma1_terms", "sph_rollout_resident", "sph_resident_fits", "sph_strerror")
+               "sph_gamma1_terms", "sph_gamma1_estimate", "sph_rollout_resident", "sph_resident_fits", "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
-               "mlp_make_windows", "mlp_get_params")
+               "mlp_make_windows", "mlp_get_params", "mlp_backward", "mlp_adam_step")
 LPV_SYMBOLS = ("lpv_workspace_bytes", "lpv_simulate", "lpv_loss_grad", "lpv_adam", "lpv_lbfgs",
                "lpv_closed_loop")
 
@@ -86,6 +86,7 @@ def load():
     L.sph_vjp_workspace_bytes.argtypes = [p, i32, i32, P(sz)]
     L.sph_vjp_rollout.argtypes = [p, i32, i32, p, p, i32, p, p, p, p, p, sz, p, p, p, p, p]
     L.sph_gamma1_terms.argtypes = [P(SphParams), p, i32, p, i32, p, p, p]
+    L.sph_gamma1_estimate.argtypes = [P(SphParams), p, i32, p, i32, C.c_double, p, p, P(C.c_double)]
     L.sph_rollout_resident.argtypes = [p, i32, p, p, i32, i32, p, p, p, p]
     L.sph_resident_fits.argtypes = [p, P(i32)]
     L.sph_strerror.argtypes = [C.c_int]
@@ -99,6 +100,8 @@ def load():
         L.mlp_forward.argtypes = [p, p, i32, p]
         L.mlp_train_step.argtypes = [p, p, p, i32, C.c_float, C.c_float, C.c_float, C.c_float, p, p]
         L.mlp_get_params.argtypes = [p, p]
+        L.mlp_backward.argtypes = [p, p, p, i32, p]
+        L.mlp_adam_step.argtypes = [p, p, C.c_float, C.c_float, C.c_float, C.c_float, i32]
         L.mlp_make_windows.argtypes = [p, p, p, i32, i32, i32, p, p, p, p]
         for name in MLP_SYMBOLS:
             getattr(L, name).restype = C.c_int

@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
                                                 const float* __restrict__ b4, int B, float* __restrict__ y,
                                                 const float* __restrict__ target, float* __restrict__ gy,
                                                 float* __restrict__ loss_rows, const float* __restrict__ z4T,
-                                                bf16* __restrict__ g4, bf16* __restrict__ g4T, int ldT) {
+                                                bf16* __restrict__ g4, bf16* __restrict__ g4T, int ldT,
+                                                const float* __restrict__ dy_in) {
   int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (row >= B) return;
@@ -227,16 +228,21 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
   }
   if (lane == 0)
     for (int o = 0; o < kOut; ++o) y[(size_t)row * kOut + o] = out[o];
-  if (!target) return;
+  if (!target && !dy_in) return;
   float g[kOut], l = 0.f;
-  float scale = 2.0f / (float(B) * kOut);
-  for (int o = 0; o < kOut; ++o) {
-    float d = out[o] - target[(size_t)row * kOut + o];
-    g[o] = scale * d;
-    l += d * d;
+  if (dy_in) {
+    // back-propagation of a caller's output gradient dL/dy
+    for (int o = 0; o < kOut; ++o) g[o] = dy_in[(size_t)row * kOut + o];
+  } else {
+    float scale = 2.0f / (float(B) * kOut);
+    for (int o = 0; o < kOut; ++o) {
+      float d = out[o] - target[(size_t)row * kOut + o];
+      g[o] = scale * d;
+      l += d * d;
+    }
   }
   if (lane == 0) {
-    loss_rows[row] = l;
+    if (!dy_in) loss_rows[row] = l;
     for (int o = 0; o < kOut; ++o) gy[(size_t)row * kOut + o] = g[o];
   }
   for (int q = 0; q < 4; ++q) {
@@ -495,16 +501,21 @@ int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev) 
   return SPH_OK;
 }
 
-int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, int32_t batch, float lr,
-                   float beta1, float beta2, float eps, float* grad_dev, float* loss_dev) {
-  if (!h || !x_dev || !target_dev || batch < 32 || batch > h->maxB || batch % 32) return SPH_E_INVAL;
-  const int B = batch, ldT = h->L.ldT;
+}  // extern "C"
+
+namespace {
+
+// Forward with the activations kept, then back-propagation into the
+// handle's gradient buffer, from the mean-squared-error gradient against
+// target (loss rows kept for mlp_loss) or from a given dL/dy.
+void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, const float* dy_dev, int B) {
+  const int ldT = h->L.ldT;
   forward(h, x_dev, B, true);
   float* grad = h->at<float>(h->L.grad);
   hipLaunchKernelGGL(mlp_head, dim3((B + 3) / 4), dim3(256), 0, h->stream, h->at<bf16>(h->L.act[3]),
                      h->at<bf16>(h->L.wb) + kOffW[4], h->at<float>(h->L.master) + kOffB[4], B,
                      h->at<float>(h->L.y), target_dev, h->at<float>(h->L.gy), h->at<float>(h->L.rows),
-                     h->at<float>(h->L.zT[3]), h->at<bf16>(h->L.g[3]), h->at<bf16>(h->L.gT[3]), ldT);
+                     h->at<float>(h->L.zT[3]), h->at<bf16>(h->L.g[3]), h->at<bf16>(h->L.gT[3]), ldT, dy_dev);
   hipLaunchKernelGGL(mlp_head_wgrad, dim3((kOut * (kHid + 1) + 255) / 256), dim3(256), 0, h->stream,
                      h->at<float>(h->L.gy), h->at<bf16>(h->L.actT[3]), ldT, B, grad);
   // hidden layers, top down: g[l] holds dL/dz of hidden layer l (output of W_l)
@@ -528,17 +539,59 @@ int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, i
                          h->at<bf16>(h->L.wT) + (size_t)(l - 1) * kHid * kHid, kHid, B, kHid, kHid, ed);
     }
   }
-  hipLaunchKernelGGL(mlp_loss, dim3(1), dim3(256), 0, h->stream, h->at<float>(h->L.rows), B,
-                     loss_dev ? loss_dev : h->at<float>(h->L.loss));
-  if (grad_dev)
-    MHIP(hipMemcpyAsync(grad_dev, grad, (size_t)MLP_N_PARAMS * 4, hipMemcpyDeviceToDevice, h->stream));
-  h->t += 1;
-  float c1 = 1.0f - powf(beta1, (float)h->t), c2 = 1.0f - powf(beta2, (float)h->t);
+}
+
+// Adam with bias correction at step t on the master weights from grad, then
+// the BF16 copies refreshed.
+void run_adam(mlp_handle* h, const float* grad, float lr, float beta1, float beta2, float eps, long long t) {
+  float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
   hipLaunchKernelGGL(mlp_adam, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
                      h->at<float>(h->L.master), h->at<float>(h->L.m), h->at<float>(h->L.v), grad,
                      MLP_N_PARAMS, lr, beta1, beta2, eps, c1, c2);
   hipLaunchKernelGGL(mlp_refresh, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
                      h->at<float>(h->L.master), h->at<bf16>(h->L.wb), h->at<bf16>(h->L.wT));
+}
+
+bool train_batch_ok(const mlp_handle* h, int batch) {
+  return batch >= 32 && batch <= h->maxB && batch % 32 == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, int32_t batch, float lr,
+                   float beta1, float beta2, float eps, float* grad_dev, float* loss_dev) {
+  if (!h || !x_dev || !target_dev || !train_batch_ok(h, batch)) return SPH_E_INVAL;
+  const int B = batch;
+  run_backward(h, x_dev, target_dev, nullptr, B);
+  float* grad = h->at<float>(h->L.grad);
+  hipLaunchKernelGGL(mlp_loss, dim3(1), dim3(256), 0, h->stream, h->at<float>(h->L.rows), B,
+                     loss_dev ? loss_dev : h->at<float>(h->L.loss));
+  if (grad_dev)
+    MHIP(hipMemcpyAsync(grad_dev, grad, (size_t)MLP_N_PARAMS * 4, hipMemcpyDeviceToDevice, h->stream));
+  h->t += 1;
+  run_adam(h, grad, lr, beta1, beta2, eps, h->t);
+  MHIP(hipGetLastError());
+  return SPH_OK;
+}
+
+int mlp_backward(mlp_handle* h, const float* x_dev, const float* dy_dev, int32_t batch, float* grads_dev) {
+  if (!h || !x_dev || !dy_dev || !grads_dev || !train_batch_ok(h, batch)) return SPH_E_INVAL;
+  run_backward(h, x_dev, nullptr, dy_dev, batch);
+  MHIP(hipMemcpyAsync(grads_dev, h->at<float>(h->L.grad), (size_t)MLP_N_PARAMS * 4, hipMemcpyDeviceToDevice,
+                      h->stream));
+  MHIP(hipGetLastError());
+  return SPH_OK;
+}
+
+int mlp_adam_step(mlp_handle* h, const float* grads_dev, float lr, float beta1, float beta2, float eps,
+                  int32_t t) {
+  if (!h || !grads_dev || t < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return SPH_E_INVAL;
+  run_adam(h, grads_dev, lr, beta1, beta2, eps, t);
+  h->t = t;
   MHIP(hipGetLastError());
   return SPH_OK;
 }

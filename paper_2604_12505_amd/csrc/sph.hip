@@ -119,6 +119,7 @@ struct Consts {
   float half_skin2;         // (skin / 2)^2: allowed squared displacement between rebuilds
   float RL2;                // near-list radius^2 for fluid pairs: (2h + skin)^2, both move
   float RG2;                // near-list radius^2 for ghosts: (S + skin/2)^2, ghosts are fixed
+  float cfl_w2;             // largest squared speed that keeps the step's Courant number within its limit
   int eos, tgamma;          // tgamma > 0: integer Tait exponent
   float tgamma_f;
 };
@@ -1256,6 +1257,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
           (double)s.y < box.hi_y))
       bad |= SPH_ST_ESCAPED;
     if (dist2(s.x - s0.x, s.y - s0.y) > k.half_skin2) bad |= SPH_ST_SORT;
+    if (dist2(w.x, w.y) > k.cfl_w2) bad |= SPH_ST_CFL;
   }
   flag(status, bad);
 }
@@ -1637,11 +1639,15 @@ __global__ void __launch_bounds__(kBlock) sph_integrate(float2* __restrict__ pos
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int t = owner[i];
+  const Consts& k = tanks[t].k;
   float2 s = pos[i], w = vel[i];
-  fluid_update(s, w, acc[i], load_frame(&rigid[t]), tanks[t].k.dt);
+  fluid_update(s, w, acc[i], load_frame(&rigid[t]), k.dt);
   pos[i] = s;
   vel[i] = w;
-  if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) flag(status, SPH_ST_NONFINITE);
+  if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y))
+    flag(status, SPH_ST_NONFINITE);
+  else if (dist2(w.x, w.y) > k.cfl_w2)
+    flag(status, SPH_ST_CFL);
 }
 
 // Outputs of sph_rhs in caller order.
@@ -2076,9 +2082,11 @@ __global__ void __launch_bounds__(kResThreads) sph_resident(float2* __restrict__
         L.w[par][i] = w;
         if (!isfinite(s.x) || !isfinite(s.y) || !isfinite(w.x) || !isfinite(w.y)) {
           bad |= SPH_ST_NONFINITE;
-        } else if (!((double)s.x >= tk.box.lo_x && (double)s.x < tk.box.hi_x && (double)s.y >= tk.box.lo_y &&
-                     (double)s.y < tk.box.hi_y)) {
-          bad |= SPH_ST_ESCAPED;
+        } else {
+          if (!((double)s.x >= tk.box.lo_x && (double)s.x < tk.box.hi_x && (double)s.y >= tk.box.lo_y &&
+                (double)s.y < tk.box.hi_y))
+            bad |= SPH_ST_ESCAPED;
+          if (dist2(w.x, w.y) > k.cfl_w2) bad |= SPH_ST_CFL;
         }
         const int c = res_key(s, g2);
         L.key[i] = (unsigned short)c;
@@ -2121,6 +2129,20 @@ int hip_fail(hipError_t e, const char* what) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 double support_of(const sph_params* p) { return 2.0 * p->h > p->h_spiky ? 2.0 * p->h : p->h_spiky; }
+
+// Courant number of a step: dt (c + |w|) / h, with c the equation of state's
+// sound speed at rest (c0 for the Tait law; sqrt(dP/drho) = sqrt(k) for the
+// linear law of eq. EOS).  The workloads set dt for 0.2 at rest; a step is
+// flagged above twice that.
+constexpr double kCourantMax = 0.4;
+
+double sound_speed(const sph_params* p) {
+  return (p->eos == SPH_EOS_LINEAR || p->eos == SPH_EOS_LINEAR_CLAMPED) ? std::sqrt(p->k_lin) : p->c0;
+}
+
+// The largest particle speed within the limit (not positive: dt is over the
+// limit at rest).
+double cfl_speed(const sph_params* p) { return kCourantMax * p->h / p->dt - sound_speed(p); }
 
 bool make_grid(const sph_params* p, Grid* g, double skin_over_h = kSkinOverH) {
   double cell = (support_of(p) + skin_over_h * p->h) * (1.0 + 1e-6);
@@ -2187,6 +2209,8 @@ Consts make_consts(const sph_params* p) {
   const double rl = (2.0 * h + skin) * (1.0 + 1e-5), rg = (support_of(p) + 0.5 * skin) * (1.0 + 1e-5);
   k.RL2 = (float)(rl * rl);
   k.RG2 = (float)(rg * rg);
+  const double wmax = cfl_speed(p);
+  k.cfl_w2 = wmax > 0.0 ? (float)(wmax * wmax) : 0.0f;
   k.eos = p->eos;
   double gi = std::round(p->tait_gamma);
   k.tgamma = (std::fabs(gi - p->tait_gamma) < 1e-12 && gi >= 1 && gi <= 64) ? (int)gi : 0;
@@ -2210,6 +2234,11 @@ int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int
   for (int t = 0; t < T; ++t) {
     const sph_params* p = &params[t];
     if (!params_ok(p) || n_fluid[t] < 0 || n_ghost[t] < 0) return SPH_E_INVAL;
+    if (n_fluid[t] > 0 && !(cfl_speed(p) > 0.0)) {
+      snprintf(g_err, sizeof g_err, "tank %d: dt (c / h) = %g is above the Courant limit %g", t,
+               p->dt * sound_speed(p) / p->h, kCourantMax);
+      return SPH_E_INVAL;
+    }
     Tank& tk = pl->tanks[t];
     memset(&tk, 0, sizeof tk);
     if (!make_grid(p, &tk.g) || !make_grid(p, &tk.g2, 0.0)) return SPH_E_INVAL;
@@ -4210,6 +4239,30 @@ int sph_gamma1_terms(const sph_params* p, const float* fluid_dev, int32_t n_flui
                      n_fluid, ghost_dev, n_ghost, 1.0 / p->h, c, p->rho0 / p->mass, num_dev, den_dev);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SPH_OK : hip_fail(e, "sph_gamma1_terms");
+}
+
+int sph_gamma1_estimate(const sph_params* p, const float* fluid_dev, int32_t n_fluid, const float* ghost_dev,
+                        int32_t n_ghost, double top, double* num_dev, double* den_dev, double* gamma1) {
+  if (!gamma1 || !(top > 0.0 && top <= 1.0)) return SPH_E_INVAL;
+  int rc = sph_gamma1_terms(p, fluid_dev, n_fluid, ghost_dev, n_ghost, num_dev, den_dev, nullptr);
+  if (rc != SPH_OK) return rc;
+  std::vector<double> num(n_fluid), den(n_fluid);
+  HIPCHK(hipMemcpy(num.data(), num_dev, sizeof(double) * n_fluid, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(den.data(), den_dev, sizeof(double) * n_fluid, hipMemcpyDeviceToHost));
+  // the particles with the largest ghost sums (ties by index), as many as
+  // the fraction `top` of those that see a ghost at all
+  std::vector<int> idx;
+  for (int i = 0; i < n_fluid; ++i)
+    if (den[i] > 0.0) idx.push_back(i);
+  if (idx.empty()) return SPH_E_INVAL;
+  const long long k = std::max(1LL, std::llround(top * (double)idx.size()));
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return den[a] > den[b] || (den[a] == den[b] && a < b); });
+  std::vector<double> ratio(k);
+  for (long long q = 0; q < k; ++q) ratio[q] = num[idx[q]] / den[idx[q]];
+  // median; of an even count the lower of the two middle values
+  std::nth_element(ratio.begin(), ratio.begin() + (k - 1) / 2, ratio.end());
+  *gamma1 = ratio[(k - 1) / 2];
+  return SPH_OK;
 }
 
 }  // extern "C"

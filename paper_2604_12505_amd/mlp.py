@@ -85,6 +85,27 @@ class Mlp:
         self._leave()
         return loss, grad
 
+    def backward(self, x, dy) -> torch.Tensor:
+        """dL/dparams [231171] for the output gradient dy [B, 3] at inputs x."""
+        x = x.to(self.device, torch.float32).contiguous()
+        dy = dy.to(self.device, torch.float32).contiguous()
+        grad = torch.empty(N_PARAMS, device=self.device)
+        self._enter()
+        check(self.L.mlp_backward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(dy.data_ptr()), int(x.shape[0]),
+                                  C.c_void_p(grad.data_ptr())), "mlp_backward")
+        self._keep = [x, dy]
+        self._leave()
+        return grad
+
+    def adam_step(self, grad, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step from grad [231171] with bias correction for step t."""
+        g = grad.to(self.device, torch.float32).contiguous()
+        self._enter()
+        check(self.L.mlp_adam_step(self.h, C.c_void_p(g.data_ptr()), float(lr), float(beta1), float(beta2),
+                                   float(eps), int(t)), "mlp_adam_step")
+        self._keep = [g]
+        self._leave()
+
     def params(self) -> torch.Tensor:
         p = torch.empty(N_PARAMS, device=self.device)
         self._enter()

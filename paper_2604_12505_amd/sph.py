@@ -65,10 +65,18 @@ def gamma1_estimate(params, fluid, ghosts, device="cuda:0", top: float = 0.1) ->
     fluid particles whose ghost sum is in the top fraction ``top`` (the
     particles that sit against the wall with a full fluid neighbourhood on
     the other side, the configuration the paper evaluates it for)."""
-    num, den = gamma1_terms(params, fluid, ghosts, device)
-    k = max(1, int(round(top * int((den > 0).sum().item()))))
-    idx = torch.topk(den, k).indices
-    return float(torch.median(num[idx] / den[idx]).item())
+    L = load()
+    f = _dev_f32(fluid, device)
+    g = _dev_f32(ghosts, device)
+    n = f.shape[0]
+    num = torch.empty(n, dtype=torch.float64, device=device)
+    den = torch.empty(n, dtype=torch.float64, device=device)
+    o = make_params(params)
+    out = C.c_double()
+    torch.cuda.synchronize(device)
+    check(L.sph_gamma1_estimate(C.byref(o), _ptr(f), n, _ptr(g), g.shape[0], float(top), _ptr(num), _ptr(den),
+                                C.byref(out)), "sph_gamma1_estimate")
+    return float(out.value)
 
 
 class Simulator:

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "slosh.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+((?:sph|mlp)_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+((?:sph|mlp|lpv)_\w+)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_the_boundary():

@@ -118,3 +118,47 @@ def test_training_fits_a_smooth_map():
     print("loss", first, "->", last)
     assert last < 0.05 * first
     net.close()
+
+
+def test_backward_of_a_given_output_gradient_matches_oracle():
+    # mlp_backward: any dL/dy, not only the mean-squared-error one; the
+    # weights do not move
+    G, rng, params, vec = _net(5)
+    B = 96
+    net = G.Mlp(vec, max_batch=B)
+    x = rng.normal(size=(B, 128)).astype(np.float32)
+    dy = (rng.normal(size=(B, 3)) / B).astype(np.float32)
+    grad = net.backward(torch.as_tensor(x), torch.as_tensor(dy))
+    ref = M.backward_from(_rounded_params(vec), _bf16(x), dy.astype(np.float64))
+    for li, ((gW, gb), (rW, rb)) in enumerate(zip(G.unpack(grad.cpu().numpy()), ref)):
+        eW = np.abs(gW - rW).max() / np.abs(rW).max()
+        eb = np.abs(gb - rb).max() / np.abs(rb).max()
+        print("layer", li, "dW rel", eW, "db rel", eb)
+        assert eW < 3e-2 and eb < 3e-2
+    assert np.array_equal(net.params().cpu().numpy(), np.asarray(vec, np.float32))
+    # linear in dy: the gradient of 2 dy is twice the gradient of dy, exactly
+    # (scaling by 2 is exact in binary32 and in BF16)
+    grad2 = net.backward(torch.as_tensor(x), torch.as_tensor(2.0 * dy))
+    assert torch.equal(grad2, 2.0 * grad)
+    net.close()
+
+
+def test_split_backward_and_adam_step_match_oracle_adam():
+    # mlp_backward + mlp_adam_step, step by step, against the oracle's Adam on
+    # the same gradients; the bias correction follows the step number given
+    G, rng, params, vec = _net(6)
+    B = 64
+    net = G.Mlp(vec, max_batch=B)
+    x = torch.as_tensor(rng.normal(size=(B, 128)).astype(np.float32))
+    opt = M.Adam(G.unpack(vec), lr=2e-3)
+    cur = G.unpack(vec)
+    for t in (1, 2, 3):
+        dy = torch.as_tensor((rng.normal(size=(B, 3)) / B).astype(np.float32))
+        grad = net.backward(x, dy)
+        net.adam_step(grad, t, lr=2e-3)
+        cur = opt.step(cur, G.unpack(grad.cpu().numpy()))
+    got = net.params().cpu().numpy().astype(np.float64)
+    assert np.abs(got - G.pack(cur).astype(np.float64)).max() < 1e-6
+    with pytest.raises(RuntimeError):
+        net.adam_step(grad, 0)
+    net.close()
