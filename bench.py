@@ -1,18 +1,22 @@
 #!/usr/bin/env python
 """Benchmark of the coupled SPH sloshing step on one MI355X.
 
-Workload: the closed-loop circular-tank run -- tank radius 0.5 m, 30 % fill,
-particle spacing 4 mm (14,542 fluid + 2,385 boundary particles), h = 1.3 dx,
-Tait EOS (gamma 7, c0 = 20 m/s), dt = 0.2 h / c0, spacecraft 1000 kg and
-500 kg m^2 under a PD attitude law (zero-order hold 0.05 s) tracking a
-30-degree trapezoidal-rate slew.  A step is one pass of the whole step
-(cell list, density/EOS, forces, slosh wrench, controller, rigid body,
+Headline workload: 256 independent tanks advanced together in the same
+launches (rectangular 1.0 x 0.5 m or circular R = 0.5 m by the seed, fill
+U[0.2, 0.8], 2k-60k fluid particles each, 7,722,150 fluid + 730,107
+boundary particles in all; Tait EOS, gamma 7, c0 = 20 m/s, h = 1.3 dx,
+dt = 0.2 h / c0 per tank; spacecraft 1000 kg, 500 kg m^2, free body under a
+5-tone random multisine torque).  A step is one pass of the whole step for
+every tank (cell list, density/EOS, forces, slosh wrench, rigid body,
 fictitious accelerations, integrator); the timed region is one rollout of
 --steps steps replayed from HIP graphs, inputs resident in HBM.
 
-Prints one JSON line: particle-steps/s, the roofline position of the
-dominant kernel (HIP-event kernel times measured in this run), and the FP64
-oracle timed on the host on a bounded sample of the same workload.
+Prints one JSON line: fluid particle-steps/s of the batch, the roofline
+position of its dominant kernel (HIP-event kernel times measured in this
+run), the FP64 oracle timed on the host on a bounded sample of the same
+tanks, and the other workloads as extra keys (the batch's full 5,000-step
+run, the closed-loop circular tank and its 44k variant, the paper's
+scenario, the size sweep, linearizations, the LPV and MLP surrogates).
 """
 from __future__ import annotations
 
@@ -65,6 +69,20 @@ TRAFFIC = {"src_sha1": "edc4a7216d9360e4305a2ec70cea0791bf63e82e",
            "bytes_per_launch": {"sph_force/16/0": 1735751, "sph_density/16/0": 2017587, "sph_force/16/1": 3199024, "sph_density/16/1": 3367910, "sph_force/32/0": 1792229, "sph_density/32/0": 2024753, "sph_force/32/1": 3245754, "sph_density/32/1": 3372735}}
 
 
+# The same for the 256-tank batch (4 lanes per particle, near lists: the
+# autotuner's choice there), from the counter runs of
+# profiles/hbm_traffic_batch_256_random_tanks.md.
+TRAFFIC_BATCH = {"src_sha1": None, "bytes_per_launch": {}}
+
+# The binding ceiling of the step (VALU issue, each unordered fluid pair
+# evaluated once): about 590 issue slots per fluid particle-step against
+# 3.93e13 lane-operations/s, 6.7e10 particle-steps/s; the straightforward
+# gather that evaluates every pair from both sides costs about 1,580 slots,
+# 2.5e10 particle-steps/s.
+BINDING_CEILING = 6.7e10
+GATHER_CEILING = 2.5e10
+
+
 def progress(msg: str) -> None:
     """A progress line on stderr (stdout carries the one JSON line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -77,20 +95,57 @@ def src_hash() -> str:
     return h.hexdigest()
 
 
-def cpu_baseline(sc, n_steps: int):
-    """The FP64 oracle, as it stands, on the first n_steps of the workload."""
+def host_info() -> dict:
+    """The host the CPU baseline ran on: logical CPUs, the CPUs this process
+    may use, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "cpu_model": model,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(seeds=(0, 1, 2), n_steps: int = 200, n_steps_1t: int = 20):
+    """The FP64 oracle, as it stands, on a bounded sample of the headline
+    workload: the first tanks of the 256-tank batch (the same generator and
+    seeds), n_steps steps each with OpenMP over particles on every thread it
+    gets, and n_steps_1t steps on one thread."""
+    import workloads as W
     from oracle import sph as O
-    st = O.state_from_scenario(sc)
-    t0 = time.perf_counter()
-    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n_steps, sc.u_seq[:n_steps], sc.theta_ref)
-    dt = time.perf_counter() - t0
-    return {"value": sc.n_fluid * n_steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {n_steps} steps of the same workload ({sc.n_fluid} fluid particles), "
-                      f"{dt:.1f} s, FP64 C with OpenMP over particles"}
+    scs = [W.random_tank(seed, n_steps=n_steps) for seed in seeds]
+    n_part = sum(sc.n_fluid for sc in scs)
+
+    def run(steps):
+        t0 = time.perf_counter()
+        for sc in scs:
+            st = O.state_from_scenario(sc)
+            O.rollout(sc.params, st, sc.ghosts.astype(np.float64), steps, sc.u_seq[:steps])
+        return time.perf_counter() - t0
+
+    threads = O.num_threads()
+    secs = run(n_steps)
+    O.set_num_threads(1)
+    secs_1t = run(n_steps_1t)
+    O.set_num_threads(threads)
+    return {"value": n_part * n_steps / secs, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"tanks {', '.join(str(q) for q in seeds)} of the 256-tank batch ({n_part} fluid particles), "
+                      f"{n_steps} steps each, {secs:.1f} s, FP64 C with OpenMP over particles",
+            "single_thread": {"value": n_part * n_steps_1t / secs_1t, "unit": "particle-steps/s",
+                              "sample": f"the same tanks, {n_steps_1t} steps each, {secs_1t:.1f} s"},
+            "host": host_info()}
 
 
-def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None, traffic_workload=None):
+def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None, traffic_workload=None, rate=None):
     """Roofline position of the kernel that takes the most time per step.
 
     The neighbour kernels are arithmetic-bound, not HBM-bound, by the
@@ -104,16 +159,23 @@ def kernel_roofline(kus, n_fluid, n_ghost, n_cells, lanes=None, near=None, traff
     gbs = alg_bytes / secs / 1e9
     # measured traffic exists for the closed-loop tank only
     key = f"sph_{dominant}/{lanes}/{1 if near else 0}"
-    traffic = (TRAFFIC["bytes_per_launch"].get(key)
-               if traffic_workload == "closed_loop_circle" and TRAFFIC["src_sha1"] == src_hash() else None)
+    table = {"closed_loop_circle": TRAFFIC, "batch_256_random_tanks": TRAFFIC_BATCH}.get(traffic_workload)
+    traffic = table["bytes_per_launch"].get(key) if table and table["src_sha1"] == src_hash() else None
     hbm = {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
            "algorithmic_bytes_per_launch": alg_bytes}
+    binding = None
+    if rate is not None:
+        binding = {"ceiling": BINDING_CEILING, "unit": "particle-steps/s", "frac": rate / BINDING_CEILING,
+                   "gather_ceiling": GATHER_CEILING, "gather_frac": rate / GATHER_CEILING}
     if dominant in FLOP:
         flops = FLOP[dominant] * n_fluid
         tf = flops / secs / 1e12
-        return {"bound": "alu", "achieved": round(tf, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic, "kernel": "sph_" + dominant,
-                "algorithmic_flop_per_launch": flops, "launch_us": kus[dominant], "hbm": hbm}
+        out = {"bound": "alu", "achieved": round(tf, 4), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic, "kernel": "sph_" + dominant,
+               "algorithmic_flop_per_launch": flops, "launch_us": kus[dominant], "hbm": hbm}
+        if binding:
+            out["binding_roofline"] = binding
+        return out
     return {"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": hbm["frac"], "traffic": traffic, "kernel": "sph_" + dominant,
             "algorithmic_bytes_per_launch": alg_bytes, "launch_us": kus[dominant]}
@@ -125,42 +187,114 @@ def n_cells_of(sc):
         int(np.ceil((sc.params.domain_max[1] - sc.params.domain_min[1]) / cell))
 
 
-def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int, lanes: int = 0, near: int = -1):
+def batch_leg(n_tanks: int, steps: int, warmup: int, kernel_steps: int, lanes: int = 0, near: int = -1,
+              full_steps: int = 0):
     """Many random tanks (rectangular or circular, fill U[0.2, 0.8], 2k-60k
-    particles, multisine torque) advanced together in the same launches."""
+    particles, multisine torque) advanced together in the same launches:
+    `steps` steps timed after `warmup`, the kernels timed over
+    `kernel_steps` more, and, if full_steps > 0, a separate timed run of
+    full_steps steps from the initial state (the workload's full length)."""
     import torch
     import workloads as W
     from paper_2604_12505_amd.sph import Simulator
-    total = warmup + steps + kernel_steps
+    total = max(warmup + steps + kernel_steps, full_steps)
     scs = [W.random_tank(seed, n_steps=total) for seed in range(n_tanks)]
     dev = torch.device("cuda:0")
     sim = Simulator.batch(scs, device=dev)
+    s0, w0, r0, _, _ = sim.get_state()
+    s0, w0 = s0.clone(), w0.clone()
     if lanes > 0:
         sim.set_lanes(lanes)
         sim.set_near_lists(near == 1)
     else:
         sim.autotune(reps=5)
     lanes, near = sim.tuning()
+    progress(f"batch: {n_tanks} tanks set up, lanes {lanes}, near lists {near}")
     u = torch.stack([torch.as_tensor(sc.u_seq) for sc in scs]).to(dev)
-    sim.rollout(warmup, u[:, :warmup])
+    sim.rollout(warmup, u[:, :warmup].contiguous())
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(sim.stream)
-    sim.rollout(steps, u[:, warmup:warmup + steps])
+    sim.rollout(steps, u[:, warmup:warmup + steps].contiguous())
     e1.record(sim.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    kus = sim.time_kernels(kernel_steps, u[:, warmup + steps:])
     status = sim.status()
-    sim.close()
+    kus = sim.time_kernels(kernel_steps, u[:, warmup + steps:warmup + steps + kernel_steps].contiguous())
+    status |= sim.status()
     n = sum(sc.n_fluid for sc in scs)
     g = sum(sc.n_ghost for sc in scs)
     nc = sum(n_cells_of(sc) for sc in scs)
-    return {"tanks": n_tanks, "n_fluid": n, "n_ghost": g, "steps": steps, "lanes": lanes, "near_lists": near,
-            "value": n * steps / (ms / 1e3), "unit": "particle-steps/s", "ms_per_step": ms / steps,
-            "status": status, "kernel_us": {k: round(v, 3) for k, v in kus.items()},
-            "roofline": kernel_roofline(kus, n, g, nc)}
+    rate = n * steps / (ms / 1e3)
+    out = {"tanks": n_tanks, "n_fluid": n, "n_ghost": g, "steps": steps, "lanes": lanes, "near_lists": near,
+           "value": rate, "unit": "particle-steps/s", "ms_per_step": ms / steps,
+           "status": status, "kernel_us": {k: round(v, 3) for k, v in kus.items()},
+           "roofline": kernel_roofline(kus, n, g, nc, lanes, near, "batch_256_random_tanks" if n_tanks == 256 else None,
+                                       rate=rate)}
+    progress(f"batch: {steps} steps timed, {ms / steps:.3f} ms per step, status {status}")
+    if full_steps > 0:
+        sim.set_state(s0, w0, r0, 0.0, 0)
+        torch.cuda.synchronize()
+        e0.record(sim.stream)
+        sim.rollout(full_steps, u[:, :full_steps].contiguous())
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        fms = e0.elapsed_time(e1)
+        fst = sim.status()
+        out["full_run"] = {"steps": full_steps, "from": "initial state", "ms_per_step": fms / full_steps,
+                           "value": n * full_steps / (fms / 1e3), "status": fst}
+        out["status"] |= fst
+        progress(f"batch: full run of {full_steps} steps, {fms / full_steps:.3f} ms per step, status {fst}")
+    sim.close()
+    return out
+
+
+def closed_loop_leg(dx: float, steps: int, warmup: int, kernel_steps: int, lanes: int = 0, near: int = -1):
+    """The closed-loop circular tank (R 0.5 m, 30 % fill, spacing dx, PD slew):
+    one rollout of `steps` graph-replayed steps timed after `warmup`."""
+    import torch
+    import workloads as W
+    from paper_2604_12505_amd.sph import Simulator
+    total = warmup + steps + kernel_steps
+    sc = W.closed_loop_circle(seed=0, n_steps=total, dx=dx)
+    dev = torch.device("cuda:0")
+    sim = Simulator.from_scenario(sc, device=dev)
+    u = torch.as_tensor(sc.u_seq, device=dev)
+    ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
+    if lanes > 0:
+        # a fixed choice (profiler runs, where serialised launches would
+        # mislead the autotuner)
+        sim.set_lanes(lanes)
+        sim.set_near_lists(near == 1)
+        lanes, near = sim.tuning()
+    else:
+        lanes = sim.autotune(reps=20)
+        near = sim.tuning()[1]
+    sim.rollout(warmup, u[:warmup], ref)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.rollout(steps, u[warmup:warmup + steps], ref)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    status = sim.status()
+    # per-kernel durations, HIP events around each kernel of directly launched steps
+    kus = sim.time_kernels(kernel_steps, u[warmup + steps:], ref)
+    status |= sim.status()
+    rate = sc.n_fluid * steps / (ms / 1e3)
+    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc), lanes, near,
+                               traffic_workload="closed_loop_circle" if dx == 0.004 else None)
+    sim.close()
+    progress(f"closed loop dx {dx * 1e3:g} mm: {sc.n_fluid} particles, {ms / steps * 1e3:.2f} us per step")
+    return {"workload": f"closed_loop_circle: R 0.5 m, fill 0.3, dx {sc.dx * 1e3:g} mm, "
+                        f"{sc.n_fluid} fluid + {sc.n_ghost} boundary particles, PD slew",
+            "n_fluid": sc.n_fluid, "n_ghost": sc.n_ghost, "dt": sc.params.dt, "steps": steps, "warmup": warmup,
+            "lanes_per_particle": lanes, "near_lists": near, "value": rate, "unit": "particle-steps/s",
+            "ms_per_step": ms / steps, "status": status, "kernel_us": {k: round(v, 3) for k, v in kus.items()},
+            "roofline": roofline}
 
 
 def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0):
@@ -184,16 +318,22 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0)
                        f"relaxed for {relax_cycles} x {relax_steps} steps, 1 ms steps",
            "gamma1_estimate_relaxed": g1, "gamma1_used": sc.params.gamma1,
            "paper_hardware": "i7-13850HX + RTX 2000 Ada laptop, JAX", "profiles": {}}
-    for k, paper_s in ((1, 9.9093), (2, 5.1876)):
+    # profile 1 is timed over the 30 s the paper's Table 3 row covers (its
+    # Section 6: below 10 s for a 30 s simulation), and over the whole
+    # reconstructed 60 s manoeuvre; profile 2 (duration not stated in the
+    # paper) over its reconstructed 40 s
+    for key, k, paper_s, secs in (("1", 1, 9.9093, 30.0), ("1_full", 1, None, None), ("2", 2, 5.1876, None)):
         force, ref = W.manoeuvre_profile(k, ts=per * sc.params.dt)
         n = force.shape[0] * per
+        if secs is not None:
+            n = min(n, int(round(secs / sc.params.dt)))
         if max_steps > 0:
             n = min(n, max_steps)
         u = np.zeros((n, 3), np.float32)
         u[:, :2] = np.repeat(force, per, axis=0)[:n]
         uu = torch.as_tensor(u, device=dev)
         th = torch.as_tensor(ref, dtype=torch.float64, device=dev)
-        res = {"steps": n, "paper_wall_s": paper_s}
+        res = {"steps": n, "simulated_s": n * sc.params.dt, "paper_wall_s": paper_s}
         for name, resident in (("multi_kernel", False), ("lds_resident", True)):
             sim.set_state(s0, w0, np.zeros(6), 0.0, 0)
             sim.rollout(64, uu[:64].contiguous(), theta_ref=th, resident=resident)   # warm-up, graphs captured
@@ -206,8 +346,10 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0)
             y = lg["y"].cpu().numpy()
             res[name] = {"wall_s": wall, "status": sim.status(), "final_theta_deg": float(np.degrees(y[-1, 2])),
                          "final_rdot": [float(y[-1, 3]), float(y[-1, 4])]}
+            if paper_s:
+                res[name]["speedup_vs_paper"] = paper_s / wall
         res["status"] = res["multi_kernel"]["status"] | res["lds_resident"]["status"]
-        out["profiles"][str(k)] = res
+        out["profiles"][key] = res
     sim.close()
     # many copies of the scenario at once (Monte Carlo use): 256 tanks from
     # different random spawns, profile 1's first 4,000 steps, both paths
@@ -302,6 +444,52 @@ def surrogate_leg(n_train: int = 192, n_test: int = 32, steps: int = 2000, epoch
             "speedup": te.sph_seconds / t_nn}
 
 
+# MI355X dense BF16 matrix peak (no sparsity)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+# multiply-adds per row of the surrogate network: 128x256 + 3 x 256x256 + 256x3
+MLP_MACS_PER_ROW = 128 * 256 + 3 * 256 * 256 + 256 * 3
+
+
+def mlp_leg(batch: int = 65536, train_batch: int = 4096, reps: int = 20):
+    """The surrogate network's kernels alone: one fused inference launch on
+    `batch` windows (mlp_forward) and one training step on train_batch
+    (mlp_train_step: forward with activations kept, backward, Adam), each
+    timed with HIP events over `reps` calls on the network's stream, against
+    the BF16 matrix-core peak (2 FLOP per multiply-add; a training step is
+    counted as 3 forward passes)."""
+    import torch
+    from paper_2604_12505_amd import surrogate as S
+    from paper_2604_12505_amd.mlp import Mlp
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    out = {"workload": f"MLP 128-256x4-3 (GELU, BF16 MFMA, FP32 accumulation): inference batch {batch}, "
+                       f"training batch {train_batch}"}
+    for name, B in (("inference", batch), ("train_step", train_batch)):
+        net = Mlp(S.init_params(0), max_batch=B, device=dev)
+        x = torch.randn(B, 128, device=dev, generator=gen)
+        t = torch.randn(B, 3, device=dev, generator=gen)
+        y = torch.empty(B, 3, device=dev)
+        call = (lambda: net.forward(x, out=y)) if name == "inference" else (lambda: net.train_step(x, t, lr=1e-4))
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(reps):
+            call()
+        e1.record(net.stream)
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3 / reps
+        flop = 2.0 * MLP_MACS_PER_ROW * B * (1 if name == "inference" else 3)
+        tf = flop / secs / 1e12
+        out[name] = {"batch": B, "us_per_call": secs * 1e6, "flop_per_call": flop, "tflops": tf,
+                     "mfma_peak_tflops": BF16_MFMA_PEAK_TFLOPS, "frac": tf / BF16_MFMA_PEAK_TFLOPS}
+        net.close()
+    return out
+
+
 def lpv_leg():
     """The LPV surrogate kernels at the paper's identification size (2,200
     samples): one loss + gradient evaluation for 8 models (the paper's
@@ -388,15 +576,18 @@ def linearization_leg(n_dir: int = 64, steps: int = 400):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--cpu-steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=5000, help="timed steps of the 256-tank batch")
+    ap.add_argument("--warmup", type=int, default=100, help="untimed steps before them")
+    ap.add_argument("--kernel-steps", type=int, default=16, help="steps of the per-kernel timing")
+    ap.add_argument("--full-steps", type=int, default=5000,
+                    help="a separate run of the batch over its full length from the initial state (0 skips it)")
+    ap.add_argument("--batch-tanks", type=int, default=256)
+    ap.add_argument("--closed-loop-steps", type=int, default=20000)
+    ap.add_argument("--closed-loop-warmup", type=int, default=1000)
+    ap.add_argument("--dx", type=float, default=0.004, help="spacing of the closed-loop tank")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=200)
-    ap.add_argument("--dx", type=float, default=0.004)
-    ap.add_argument("--batch-tanks", type=int, default=256,
-                    help="tanks of the batched leg (0 skips it)")
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps per sampled tank")
+    ap.add_argument("--no-closed-loop-leg", action="store_true")
     ap.add_argument("--no-paper-leg", action="store_true")
     ap.add_argument("--no-linearization-leg", action="store_true")
     ap.add_argument("--no-lpv-leg", action="store_true")
@@ -406,11 +597,17 @@ def main() -> int:
     ap.add_argument("--paper-only", action="store_true", help="run only the paper-scenario leg")
     ap.add_argument("--paper-steps", type=int, default=0, help="cap on the paper leg's steps per run (0: full)")
     ap.add_argument("--lanes", type=int, default=0,
-                    help="lanes per particle of the closed-loop leg (0: sph_autotune chooses)")
+                    help="lanes per particle of the batch (or, with --closed-loop-only, of the closed-loop tank); "
+                         "0: sph_autotune chooses")
     ap.add_argument("--near-lists", type=int, default=-1,
-                    help="near lists on (1) or off (0) with --lanes (-1: off); with --batch-only they apply to the batch")
+                    help="near lists on (1) or off (0) with --lanes")
     ap.add_argument("--batch-only", action="store_true",
-                    help="run only the batched leg and print its JSON object (profiling)")
+                    help="run only the batch (timed steps and kernel timing) and print its JSON object (profiling)")
+    ap.add_argument("--closed-loop-only", action="store_true",
+                    help="run only the closed-loop tank and print its JSON object (profiling)")
+    ap.add_argument("--mlp-only", action="store_true",
+                    help="run only the surrogate network's kernel timing and print its JSON object (profiling)")
+    ap.add_argument("--no-mlp-leg", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (HBM-counter calibration)")
     args = ap.parse_args()
@@ -420,8 +617,6 @@ def main() -> int:
         return 2
 
     import torch
-    import workloads as W
-    from paper_2604_12505_amd.sph import Simulator
 
     if args.calibrate_copy_mb > 0:
         n = args.calibrate_copy_mb * (1 << 20) // 4
@@ -441,84 +636,66 @@ def main() -> int:
         print(json.dumps(res))
         ok = all(p["status"] == 0 for p in res["profiles"].values())
         return 0 if ok else 1
+    if args.mlp_only:
+        print(json.dumps(mlp_leg()))
+        return 0
+    if args.closed_loop_only:
+        res = closed_loop_leg(args.dx, args.closed_loop_steps, args.closed_loop_warmup, args.kernel_steps,
+                              args.lanes, args.near_lists)
+        print(json.dumps(res))
+        return 0 if res["status"] == 0 else 1
     if args.batch_only:
-        res = batch_leg(args.batch_tanks, args.batch_steps, 16, 16, args.lanes, args.near_lists)
+        res = batch_leg(args.batch_tanks, args.steps, args.warmup, args.kernel_steps, args.lanes, args.near_lists)
         print(json.dumps(res))
         return 0 if res["status"] == 0 else 1
 
-    total = args.warmup + args.steps + args.kernel_steps
-    sc = W.closed_loop_circle(seed=0, n_steps=total, dx=args.dx)
-    dev = torch.device("cuda:0")
-    sim = Simulator.from_scenario(sc, device=dev)
-    u = torch.as_tensor(sc.u_seq, device=dev)
-    ref = torch.as_tensor(sc.theta_ref, dtype=torch.float64, device=dev)
-    if args.lanes > 0:
-        # a fixed choice (profiler runs, where serialised launches would
-        # mislead the autotuner)
-        sim.set_lanes(args.lanes)
-        sim.set_near_lists(args.near_lists == 1)
-        lanes, near = sim.tuning()
-    else:
-        lanes = sim.autotune(reps=20)
-        near = sim.tuning()[1]
-
-    sim.rollout(args.warmup, u[:args.warmup], ref)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(sim.stream)
-    sim.rollout(args.steps, u[args.warmup:args.warmup + args.steps], ref)
-    e1.record(sim.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    status = sim.status()
-    value = sc.n_fluid * args.steps / (ms / 1e3)
-
-    # per-kernel durations, HIP events around each kernel of directly launched steps
-    kus = sim.time_kernels(args.kernel_steps, u[args.warmup + args.steps:], ref)
-    status |= sim.status()
-    roofline = kernel_roofline(kus, sc.n_fluid, sc.n_ghost, n_cells_of(sc), lanes, near,
-                               traffic_workload="closed_loop_circle" if args.dx == 0.004 else None)
-    sim.close()
-
+    b = batch_leg(args.batch_tanks, args.steps, args.warmup, args.kernel_steps, args.lanes, args.near_lists,
+                  full_steps=args.full_steps)
+    status = b["status"]
     out = {
         "metric": "SPH particle-steps/s at 1 GPU (% HBM roofline); NN vs SPH speedup at <=2% err",
-        "value": value,
+        "value": b["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": b["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"closed_loop_circle: R 0.5 m, fill 0.3, dx {sc.dx * 1e3:g} mm, "
-                               f"{sc.n_fluid} fluid + {sc.n_ghost} boundary particles, PD slew",
-                   "n_fluid": sc.n_fluid, "n_ghost": sc.n_ghost, "dt": sc.params.dt,
-                   "lanes_per_particle": lanes, "near_lists": near, "parallelism": "single GPU"},
+        "config": {"workload": f"batch_256_random_tanks: {b['tanks']} tanks in the same launches, rectangular "
+                               f"1.0 x 0.5 m or circular R 0.5 m by seed, fill U[0.2, 0.8], 2k-60k fluid particles "
+                               f"each ({b['n_fluid']} fluid + {b['n_ghost']} boundary), Tait EOS, dt = 0.2 h / c0, "
+                               f"free body under 5-tone multisine torques",
+                   "tanks": b["tanks"], "n_fluid": b["n_fluid"], "n_ghost": b["n_ghost"],
+                   "lanes_per_particle": b["lanes"], "near_lists": b["near_lists"], "parallelism": "single GPU"},
         "status": status,
-        "kernel_us": {k: round(v, 3) for k, v in kus.items()},
-        "roofline": roofline,
+        "kernel_us": b["kernel_us"],
+        "roofline": b["roofline"],
     }
-    progress("closed-loop tank measured")
+    if "full_run" in b:
+        out["batch_full_run"] = b["full_run"]
+    if not args.no_closed_loop_leg:
+        out["closed_loop"] = closed_loop_leg(args.dx, args.closed_loop_steps, args.closed_loop_warmup, 200)
+        out["closed_loop_44k"] = closed_loop_leg(0.002314, args.closed_loop_steps, args.closed_loop_warmup, 200)
+        status |= out["closed_loop"]["status"] | out["closed_loop_44k"]["status"]
     if not args.no_paper_leg:
         # the paper's own scenario (timing context for its Table 3)
         out["paper_scenario"] = paper_leg(max_steps=args.paper_steps)
         progress("paper scenario leg done")
         for prof in out["paper_scenario"]["profiles"].values():
             status |= prof["status"]
-    if args.batch_tanks > 0:
-        out["batch"] = batch_leg(args.batch_tanks, args.batch_steps, 16, 16)
-        status |= out["batch"]["status"]
-        progress("batch leg done")
     if not args.no_linearization_leg:
         out["linearization"] = linearization_leg()
         progress("linearization leg done")
     if not args.no_lpv_leg:
         out["lpv"] = lpv_leg()
         progress("LPV leg done")
+    if not args.no_mlp_leg:
+        out["mlp"] = mlp_leg()
+        progress("MLP kernel leg done")
     if not args.no_surrogate_leg:
         out["surrogate"] = surrogate_leg()
         progress("surrogate leg done")
@@ -527,8 +704,9 @@ def main() -> int:
         for r in out["size_sweep"]["rows"]:
             status |= r["status"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(n_steps=args.cpu_steps)
         progress("CPU baseline done")
+    out["status"] = status
     print(json.dumps(out))
     return 0 if status == 0 else 1
 
