@@ -56,7 +56,7 @@ def _relax(sim: Simulator, cycles: int, steps: int) -> None:
 def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, relax_cycles: int = 40,
              relax_steps: int = 100, n_min: int = 2000, n_max: int = 60000, device="cuda:0",
              batch: int = 256, lanes: Optional[int] = None, eos: int = W.EOS_TAIT_CLAMPED,
-             log=None) -> RolloutSet:
+             log=None, jitter_seed: Optional[int] = None) -> RolloutSet:
     """Runs one relaxed, forced rollout per seed, up to ``batch`` tanks per
     handle (one set of launches).  sph_seconds sums the GPU time of the forced
     rollouts (relaxation excluded).  eos: the Tait law without tension by
@@ -73,7 +73,8 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
     sph_seconds = 0.0
     for g0 in range(0, R, batch):
         idx = list(range(g0, min(R, g0 + batch)))
-        scs = [W.random_tank(int(seeds[i]), n_steps=n_steps, n_min=n_min, n_max=n_max, eos=eos) for i in idx]
+        scs = [W.random_tank(int(seeds[i]), n_steps=n_steps, n_min=n_min, n_max=n_max, eos=eos,
+                             jitter_seed=jitter_seed) for i in idx]
         for i, sc in zip(idx, scs):
             n_fluid[i] = sc.n_fluid
             fill[i] = float(sc.fill)
@@ -189,6 +190,20 @@ def nrmse(pred_std: torch.Tensor, y_std: torch.Tensor, norm: np.ndarray) -> np.n
     t = y_std * std + mean
     err = torch.sqrt(((p - t) ** 2).mean(0))
     ref = torch.sqrt((t ** 2).mean(0))
+    return (err / ref).cpu().numpy()
+
+
+def noise_floor(a: RolloutSet, b: RolloutSet, first: int = WINDOW - 1) -> np.ndarray:
+    """Per-channel RMS(wrench_b - wrench_a) / RMS(wrench_a) of two sets of
+    rollouts of the same tanks and inputs that differ only in the initial
+    jitter, over the samples a window's target can take (from index
+    ``first`` on): how far SPH itself reproduces its wrench.  A predictor
+    that knew the part common to both would reach about this / sqrt(2)
+    against either set when the difference is independent noise."""
+    wa = a.wrench[:, first:].reshape(-1, 3).double()
+    wb = b.wrench[:, first:].reshape(-1, 3).double()
+    err = torch.sqrt(((wb - wa) ** 2).mean(0))
+    ref = torch.sqrt((wa ** 2).mean(0))
     return (err / ref).cpu().numpy()
 
 

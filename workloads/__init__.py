@@ -269,12 +269,16 @@ def closed_loop_circle(seed: int = 0, n_steps: int = 20000, dx: float = 0.004,
 
 
 def random_tank(seed: int, n_steps: int = 5000, n_min: int = 2000, n_max: int = 60000,
-                shape: Optional[str] = None, eos: int = EOS_TAIT) -> Scenario:
+                shape: Optional[str] = None, eos: int = EOS_TAIT, jitter_seed: Optional[int] = None) -> Scenario:
     """Random tank for the surrogate data set: rectangle 1.0 x 0.5 or circle
     R = 0.5 (equal odds), fill U[0.2, 0.8], particle count U{n_min..n_max},
     torque a 5-tone multisine with amplitude U[0, 50] N m.  eos: EOS_TAIT
-    (the measured batch configuration) or EOS_TAIT_CLAMPED."""
+    (the measured batch configuration) or EOS_TAIT_CLAMPED.  jitter_seed:
+    if given, the lattice jitter comes from its own generator, so that tanks
+    of one seed and different jitter seeds share shape, size, fill and input
+    and differ only in the initial jitter."""
     rng = np.random.default_rng(seed)
+    jrng = rng if jitter_seed is None else np.random.default_rng([int(seed), int(jitter_seed)])
     if shape is None:
         shape = "rect" if rng.random() < 0.5 else "circle"
     fill = float(rng.uniform(0.2, 0.8))
@@ -285,13 +289,13 @@ def random_tank(seed: int, n_steps: int = 5000, n_min: int = 2000, n_max: int = 
         dx = W / round(W / dx)            # whole number of columns
         ncy = int(round(H / dx))
         fill_rows = max(1, int(round(fill * ncy)))
-        fluid, ghosts = rect_tank(W, H, dx, fill_rows, 3, rng, 0.01)
+        fluid, ghosts = rect_tank(W, H, dx, fill_rows, 3, jrng, 0.01)
         ext = (W / 2, H / 2)
         size = W
     else:
         R = 0.5
         dx = math.sqrt(fill * math.pi * R * R / n_target)
-        fluid, ghosts = circle_tank(R, dx, fill, 3, rng, 0.01)
+        fluid, ghosts = circle_tank(R, dx, fill, 3, jrng, 0.01)
         ext = (R, R)
         size = 2 * R
     p = _fluid_params(dx)
