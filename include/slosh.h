@@ -485,6 +485,27 @@ int lpv_loss_grad(const double* params_dev, int32_t n_models, const double* u_de
                   int32_t n_samples, const lpv_opts* opts, double* loss_dev, double* grad_dev, void* ws_dev,
                   size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory or hand over a workspace
+ * (code under HIP graph capture, tight serving or fitting loops, harnesses
+ * that forbid allocation): lpv_loss_grad without the workspace arguments.
+ * The reverse sweep's record lives in a fixed array of
+ * LPV_NOALLOC_SCRATCH_BYTES in device memory, one per GPU, reserved when the
+ * library's code is loaded on that GPU and held until the process ends; the
+ * call itself allocates nothing.  It needs n_samples * 4 * 64 *
+ * ceil(n_models / 16) * 8 bytes (16 models share one wave), so 2,200 samples
+ * fit up to 112 models and one wave of 16 models fits 16,384 samples; larger
+ * requests return SPH_E_CAPACITY without launching anything.  The record is
+ * written before it is read, so nothing needs clearing between calls.  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (two streams, or two host threads) race and give undefined results;
+ * calls on one stream are ordered and safe.  Results equal lpv_loss_grad's
+ * bit for bit.  Arguments, outputs and errors are those of lpv_loss_grad;
+ * SPH_E_HIP if the array's device address cannot be obtained. */
+#define LPV_NOALLOC_SCRATCH_BYTES (32u << 20)
+int lpv_loss_grad_noalloc(const double* params_dev, int32_t n_models, const double* u_dev, const double* y_dev,
+                          int32_t n_samples, const lpv_opts* opts, double* loss_dev, double* grad_dev,
+                          void* stream);
+
 /* `iters` Adam steps from zero moments on every model; params_dev is updated
  * in place; loss_dev [n_models] (may be NULL) gets the loss at the last
  * evaluated point (before the last update). */

@@ -38,7 +38,7 @@ SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sp
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
                "mlp_make_windows", "mlp_get_params", "mlp_backward", "mlp_adam_step")
 LPV_SYMBOLS = ("lpv_workspace_bytes", "lpv_simulate", "lpv_loss_grad", "lpv_adam", "lpv_lbfgs",
-               "lpv_closed_loop")
+               "lpv_closed_loop", "lpv_loss_grad_noalloc")
 
 
 class LpvOpts(C.Structure):
@@ -109,6 +109,7 @@ def load():
     L.lpv_workspace_bytes.argtypes = [i32, i32, P(sz)]
     L.lpv_simulate.argtypes = [p, i32, p, i32, i32, p, p, p]
     L.lpv_loss_grad.argtypes = [p, i32, p, p, i32, po, p, p, p, sz, p]
+    L.lpv_loss_grad_noalloc.argtypes = [p, i32, p, p, i32, po, p, p, p]
     L.lpv_adam.argtypes = [p, i32, p, p, i32, po, i32, p, p, sz, p]
     L.lpv_lbfgs.argtypes = [p, i32, p, p, i32, po, i32, p, p, p, p, sz, p]
     L.lpv_closed_loop.argtypes = [p, i32, p, p, i32, p, i32, i32, C.c_double, C.c_double, C.c_double, p, p, p,

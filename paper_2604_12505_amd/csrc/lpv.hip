@@ -32,6 +32,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "slosh.h"
 
@@ -760,6 +761,34 @@ FitArgs fit_args(const lpv_opts* o, int R, const double* u, const double* y, int
 // evaluations per launch: about 2e5 model steps, so one launch stays near 0.1 s
 int evals_per_launch(int n) { return n >= 200000 ? 1 : 200000 / n; }
 
+// Reverse-sweep record of lpv_loss_grad_noalloc: a fixed array in device
+// memory, one copy per GPU, held until the process ends.  Host code never
+// passes `scratch` itself (on the host it names a stand-in, not a device
+// address): it passes the device address that hipGetSymbolAddress returns
+// for the current device, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(LPV_NOALLOC_SCRATCH_BYTES);
+static_assert(kNoAllocScratchBytes % 256 == 0, "scratch size");
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device), or an error code.
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPH_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPH_E_HIP;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return SPH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -789,6 +818,24 @@ int lpv_loss_grad(const double* params_dev, int32_t n_models, const double* u_de
   const FitArgs a = fit_args(opts, n_models, u_dev, y_dev, n_samples, ws_dev);
   const int blocks = (int)(a.sc.cols / kWave);
   hipLaunchKernelGGL(lpv_forward_kernel, dim3(blocks), dim3(kWave), 0, (hipStream_t)stream, a.d, a.sc, n_models,
+                     params_dev, opts->sigma2, opts->sigmax, opts->lti_only, loss_dev, grad_dev, (double*)nullptr,
+                     (double*)nullptr);
+  return hip_rc(hipGetLastError());
+}
+
+int lpv_loss_grad_noalloc(const double* params_dev, int32_t n_models, const double* u_dev, const double* y_dev,
+                          int32_t n_samples, const lpv_opts* opts, double* loss_dev, double* grad_dev,
+                          void* stream) {
+  if (!opts || !params_dev || !valid_data(n_models, n_samples, u_dev, y_dev)) return SPH_E_INVAL;
+  // the record holds x, h1, h2 and p of every lane at every sample
+  if ((size_t)n_samples * 4 * cols_for(n_models) * sizeof(double) > kNoAllocScratchBytes) return SPH_E_CAPACITY;
+  double* traj = nullptr;
+  const int rc = scratch_on_current_device(&traj);
+  if (rc != SPH_OK) return rc;
+  const Data d{u_dev, y_dev, n_samples, 0};
+  const Scratch sc{traj, cols_for(n_models)};
+  const int blocks = (int)(sc.cols / kWave);
+  hipLaunchKernelGGL(lpv_forward_kernel, dim3(blocks), dim3(kWave), 0, (hipStream_t)stream, d, sc, n_models,
                      params_dev, opts->sigma2, opts->sigmax, opts->lti_only, loss_dev, grad_dev, (double*)nullptr,
                      (double*)nullptr);
   return hip_rc(hipGetLastError());

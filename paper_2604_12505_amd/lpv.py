@@ -91,6 +91,24 @@ def loss_grad(params: torch.Tensor, u: torch.Tensor, y: torch.Tensor, opts: Opti
     return loss, g
 
 
+def loss_grad_noalloc(params: torch.Tensor, u: torch.Tensor, y: torch.Tensor, opts: Options = Options(),
+                      grad: bool = True):
+    """loss_grad through lpv_loss_grad_noalloc: no workspace; the library's
+    fixed per-GPU array holds the reverse sweep's record.  Only the outputs
+    are allocated here (by torch, before the call)."""
+    L = load()
+    dev = params.device
+    params = _f64(params, dev).reshape(-1, N_PARAM)
+    u, y = _f64(u, dev), _f64(y, dev)
+    R, n = params.shape[0], u.shape[0]
+    loss = torch.empty(R, dtype=torch.float64, device=dev)
+    g = torch.empty(R, N_PARAM, dtype=torch.float64, device=dev) if grad else None
+    o = opts.c()
+    check(L.lpv_loss_grad_noalloc(_p(params), R, _p(u), _p(y), n, C.byref(o), _p(loss), _p(g), _stream(dev)),
+          "lpv_loss_grad_noalloc")
+    return loss, g
+
+
 def adam(params: torch.Tensor, u: torch.Tensor, y: torch.Tensor, iters: int, opts: Options = Options(),
          ws: Optional[torch.Tensor] = None):
     """Runs `iters` Adam steps in place on params [R, 141]; returns the loss [R]
