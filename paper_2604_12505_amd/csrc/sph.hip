@@ -90,6 +90,11 @@ constexpr int kListG = 32;        // in-support ghost neighbours listed per part
 constexpr int kNearF = 64;        // capacity of a fluid near list
 constexpr int kNearG = 32;        // capacity of a ghost near list
 constexpr int kNearNone = 255;    // list length meaning "not listed: walk all candidates"
+// Marks: for the force kernel of the same step, the density kernel records
+// which listed candidates lie inside the support, one 32-bit word per lane
+// of a particle's group: bit 4q + b for the lane's q-th list word, byte b
+// (fluid list, bits 0-15), bit 16 + 4q + b likewise for the ghost list.
+constexpr int kMarkGhostShift = 16;
 constexpr int kNumVariants = 4;   // lanes per particle: 4, 8, 16, 32
 constexpr int kLanes[kNumVariants] = {4, 8, 16, 32};
 constexpr int kDefaultVariant = 1;
@@ -209,6 +214,14 @@ __device__ __forceinline__ float cubic_shape(float q) {
     w -= 4.0f * b * b * b;
   }
   return w;
+}
+
+// The same shape without a branch: zero unless `in` (the support test);
+// selects, so every candidate costs the same instructions.
+__device__ __forceinline__ float cubic_shape_clamped(float q, bool in) {
+  const float a = 2.0f - q, b = fmaxf(1.0f - q, 0.0f);
+  const float w = a * a * a - 4.0f * (b * b * b);
+  return in ? w : 0.0f;
 }
 
 // (dW/dr)/r of the cubic spline divided by sigma/h^2:
@@ -1034,6 +1047,70 @@ __device__ __forceinline__ void near_visit(NearWords<G, CAP>& nw, int n, int l, 
   }
 }
 
+// Like near_visit, for every entry of lane l's share of the list: calls
+// f(e), which returns whether the candidate lies inside the support, and
+// returns the lane's marks (bit 4q + b for entry 4(l + qG) + b).
+template <int G, int CAP, class F>
+__device__ __forceinline__ unsigned near_visit_marks(NearWords<G, CAP>& nw, int n, int l, const OrdMap& m, F&& f) {
+  unsigned marks = 0u;
+#pragma unroll
+  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
+    unsigned word = nw.pop();
+    const int i0 = 4 * (l + q * G);
+    if (i0 < n)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (i0 + b < n && f(m((int)(word & 255u)))) marks |= 1u << (4 * q + b);
+        word >>= 8;
+      }
+  }
+  return marks;
+}
+
+// The same over a list of n ordinals held in LDS (the list the density
+// kernel just built), in the lanes' word order of NearWords.
+template <int G, int CAP, class F>
+__device__ __forceinline__ unsigned lds_list_marks(const unsigned char* lst, int n, int l, const OrdMap& m, F&& f) {
+  unsigned marks = 0u;
+#pragma unroll
+  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
+    const int i0 = 4 * (l + q * G);
+    if (i0 < n)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (i0 + b < n && f(m((int)lst[i0 + b]))) marks |= 1u << (4 * q + b);
+  }
+  return marks;
+}
+
+// Compacts, from a near list and the marks the density kernel wrote for it
+// at the same positions, the ordinals of the candidates inside the support
+// into lst (in ballot-round order, the order near_pass gives); returns the
+// count, the same on the G lanes.  No candidate is loaded or tested.
+template <int G, int CAP>
+__device__ __forceinline__ int near_pass_marked(NearWords<G, CAP>& nw, unsigned marks, int n, int l,
+                                                unsigned short* lst) {
+  const int base = (int)(threadIdx.x & 63) - l;
+  const unsigned below = (1u << l) - 1u;
+  const int rounds = ((n + 3) / 4 + G - 1) / G;   // the same on the G lanes
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
+    unsigned word = nw.pop();
+    if (q < rounds) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bool in = (marks >> (4 * q + b)) & 1u;
+        const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
+        if (in) lst[cnt + __popc(msk & below)] = (unsigned short)(word & 255u);
+        word >>= 8;
+        cnt += __popc(msk);
+      }
+    }
+  }
+  return cnt;
+}
+
 // Compacts the entries of a near list of n entries that pass `keep` into
 // lst (LDS indices, in ballot-round order); returns the count (<= n), the
 // same on the G lanes.
@@ -1098,7 +1175,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
                                                       unsigned* __restrict__ status,
                                                       int* __restrict__ near_n,
                                                       unsigned* __restrict__ near_f,
-                                                      unsigned* __restrict__ near_g) {
+                                                      unsigned* __restrict__ near_g,
+                                                      unsigned* __restrict__ marks_out) {
   constexpr int TP = kBlock / G;
   constexpr int kStageF = stage_f<TP>();
   __shared__ float2 f_pos[kStageF];
@@ -1132,6 +1210,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
   }
   __syncthreads();
   float sf = 0.0f, sgs = 0.0f;
+  const float inv_h = k.inv_h, R2 = k.R2, Rs2 = k.Rs2;
+  unsigned marks = 0u;
   int nf_out = kNearNone, ng_out = kNearNone;
   int first = 0;
   while (first < TP && tl.cy[first] >= 0) {
@@ -1156,9 +1236,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
       // this particle's segment's ranges in the stage
       const int sh = pl < sg.split ? 0 : 3;
       const int *lo = sg.lo + sh, *off = sg.off + sh, *glo = sg.glo + sh, *goff = sg.goff + sh;
+      // its own updated position as staged (row 1 holds its own cell), so
+      // that it is bit for bit the value its neighbours see: the marks of
+      // the support test must equal the force kernel's test
+      if (fst) s = f_pos[off[1] + p - lo[1]];
       auto fluid = [&](float2 sj) {
-        float d2 = dist2(s.x - sj.x, s.y - sj.y);
-        if (d2 < k.R2) sf += cubic_shape(fsqrt(d2) * k.inv_h);
+        const float d2 = dist2(s.x - sj.x, s.y - sj.y);
+        sf += cubic_shape_clamped(fsqrt(d2) * inv_h, d2 < R2);
+        return d2 < R2 && d2 > 0.0f;
       };
       int total;
       const OrdMap fm = ord_map<TP>(tl, pl, false, lo, off, &total);
@@ -1174,11 +1259,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
         nf_out = cnt <= kNearF ? cnt : kNearNone;
         if (cnt <= kNearF) {
           wave_sync();
-          for (int i = l; i < cnt; i += G) fluid(f_pos[fm(lb[i])]);
+          marks = lds_list_marks<G, kNearF>(lb, cnt, l, fm, [&](int e) { return fluid(f_pos[e]); });
           walked = true;
         }
       } else if (!Build && fst && nlf <= kNearF) {
-        near_visit<G, kNearF>(nwf, nlf, l, fm, [&](int e) { fluid(f_pos[e]); });
+        marks = near_visit_marks<G, kNearF>(nwf, nlf, l, fm, [&](int e) { return fluid(f_pos[e]); });
         walked = true;
       }
       if (!walked) {
@@ -1196,8 +1281,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
         }
       }
       auto ghost = [&](float2 gj) {
-        float d2 = dist2(s.x - gj.x, s.y - gj.y);
-        if (d2 < k.R2) sgs += cubic_shape(fsqrt(d2) * k.inv_h);
+        const float d2 = dist2(s.x - gj.x, s.y - gj.y);
+        sgs += cubic_shape_clamped(fsqrt(d2) * inv_h, d2 < R2);
+        return d2 < Rs2 && d2 > 0.0f;   // inside the spiky support of the wall terms
       };
       int gtotal;
       const OrdMap gm = ord_map<TP>(tl, pl, true, glo, goff, &gtotal);
@@ -1212,11 +1298,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
         ng_out = cnt <= kNearG ? cnt : kNearNone;
         if (cnt <= kNearG) {
           wave_sync();
-          for (int i = l; i < cnt; i += G) ghost(g_pos[gm(lb[i])]);
+          marks |= lds_list_marks<G, kNearG>(lb, cnt, l, gm, [&](int e) { return ghost(g_pos[e]); })
+                   << kMarkGhostShift;
           gwalked = true;
         }
       } else if (!Build && gst && nlg <= kNearG) {
-        near_visit<G, kNearG>(nwg, nlg, l, gm, [&](int e) { ghost(g_pos[e]); });
+        marks |= near_visit_marks<G, kNearG>(nwg, nlg, l, gm, [&](int e) { return ghost(g_pos[e]); })
+                 << kMarkGhostShift;
         gwalked = true;
       }
       if (!gwalked) {
@@ -1241,6 +1329,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
     for (int q = l; q < nwg; q += G) near_g[(size_t)p * (kNearG / 4) + q] = nb_g[pl][q];
     if (l == 0) near_n[p] = nf_out | ng_out << 8;
   }
+  if (marks_out && mine) marks_out[(size_t)p * G + l] = marks;
   if (!mine || l != 0) return;
   const float2 s0 = pos_sort[p];
   float rho = k.mass * k.wc * (sf + k.gamma1 * sgs);
@@ -1389,7 +1478,7 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const d
 //   + sum_g m [-2 P_i/rho_i^2 + (2 beta / (2 rho_i)) min(w_i . s_ig, 0)/(r^2 + eps h^2)] grad_i W_s3
 // The tank receives -m * (wall term) per pair, with torque arm g.
 template <int G, bool Bin>
-__global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ pos,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) sph_force(const float2* __restrict__ pos,
                                                     const float2* __restrict__ vel,
                                                     const float2* __restrict__ rp,
                                                     const int* __restrict__ pkey,
@@ -1402,7 +1491,8 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
                                                     int* __restrict__ key, int* __restrict__ count,
                                                     const int* __restrict__ near_n,
                                                     const unsigned* __restrict__ near_f,
-                                                    const unsigned* __restrict__ near_g) {
+                                                    const unsigned* __restrict__ near_g,
+                                                    const unsigned* __restrict__ marks_in) {
   constexpr int TP = kBlock / G;
   constexpr int kStageF = stage_f<TP>();
   __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
@@ -1422,10 +1512,12 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
   float2 s = make_float2(0.f, 0.f), w = make_float2(0.f, 0.f), me = make_float2(1.f, 0.f);
   NearWords<G, kNearF> nwf;
   NearWords<G, kNearG> nwg;
+  unsigned marks = 0u;
   if (mine) {
     if (near_n) {
       nwf.load(near_f + (size_t)p * (kNearF / 4), l);
       nwg.load(near_g + (size_t)p * (kNearG / 4), l);
+      marks = marks_in[(size_t)p * G + l];
     }
     s = pos[p];
     w = vel[p];
@@ -1490,7 +1582,14 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
         };
         const int nlf = tl.near[pl] & 255;
         if (nlf <= kNearF) {
-          pairs(near_pass<G, kNearF>(nwf, nlf, l, fm, lst, inside));
+          // the density kernel marked the listed candidates inside the support
+          const int cnt = near_pass_marked<G, kNearF>(nwf, marks, nlf, l, lst);
+          wave_sync();
+          for (int q = l; q < cnt; q += G) {
+            const int e = fm(lst[q]);
+            fluid(f_pos[e], f_vel[e], f_rp[e]);
+          }
+          wave_sync();
         } else {
           int c = 0;
           while (c < total) pairs(list_pass<G>(fm, total, l, c, kListF, lst, inside));
@@ -1531,7 +1630,10 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
         };
         const int nlg = (tl.near[pl] >> 8) & 255;
         if (nlg <= kNearG) {
-          walls(near_pass<G, kNearG>(nwg, nlg, l, gm, lst, inside));
+          const int cnt = near_pass_marked<G, kNearG>(nwg, marks >> kMarkGhostShift, nlg, l, lst);
+          wave_sync();
+          for (int q = l; q < cnt; q += G) ghost(g_pos[gm(lst[q])]);
+          wave_sync();
         } else {
           int c = 0;
           while (c < total) walls(list_pass<G>(gm, total, l, c, kListG, lst, inside));
@@ -1566,11 +1668,13 @@ __global__ void __launch_bounds__(kBlock) sph_force(const float2* __restrict__ p
     add_runs<G>(count, kc, mine && l == 0);
   }
 
-  // workgroup reduction of the wrench, in double, fixed order
+  // workgroup reduction of the wrench, in double, fixed order; a wave
+  // without any wall term (all its sums +0) contributes +0 without the sum
   double v[3] = {(double)fx, (double)fy, (double)tq};
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool walls = __ballot(fx != 0.0f || fy != 0.0f || tq != 0.0f) != 0ull;
   for (int d = 0; d < 3; ++d) {
-    double t = wave_sum0(v[d]);
+    double t = walls ? wave_sum0(v[d]) : 0.0;
     if (lane == 0) red[d][wv] = t;
   }
   __syncthreads();
@@ -2268,7 +2372,7 @@ int make_plan(int T, const sph_params* params, const int32_t* n_fluid, const int
 }
 
 struct Layout {
-  size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, near_n, near_f, near_g, key, slot,
+  size_t pos[2], vel[2], acc[2], id[2], cstart[2], pos_sort, rng, pkey, rp, near_n, near_f, near_g, marks, key, slot,
       order, count, scanpart, gpos,
       graw, gstart, owner, gowner, cowner, tanks, tiles[kNumVariants], tile0[kNumVariants], partials,
       rigid, rollout, status, total;
@@ -2301,6 +2405,7 @@ Layout make_layout(const Plan& pl) {
   L.near_n = take(n * 4);
   L.near_f = take(n * kNearF);
   L.near_g = take(n * kNearG);
+  L.marks = take(n * 4 * kLanes[kNumVariants - 1]);
   L.key = take(mx * 4);
   L.slot = take(mx * 4);
   L.order = take(mx * 4);
@@ -3130,7 +3235,8 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
                      h->at<float2>(h->L.gpos), h->at<TileRef>(h->L.tiles[v]), single_n(h),
                      h->at<Tank>(h->L.tanks), h->at<DevRigid>(h->L.rigid), h->at<float2>(h->L.pos[1 - c]),
                      h->at<float2>(h->L.vel[1 - c]), h->at<float2>(h->L.rp), h->at<unsigned>(h->L.status),
-                     near_n, h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
+                     near_n, h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g),
+                     near_n ? h->at<unsigned>(h->L.marks) : nullptr);
   if (build) h->near_valid = true;
   mark(1);
   // the step before a scheduled rebuild also bins the particles for it
@@ -3142,7 +3248,7 @@ void launch_pair(sph_handle* h, int v, bool integrate, int mode, hipEvent_t* ev)
                      single_n(h), h->at<Tank>(h->L.tanks), h->at<float2>(h->L.acc[1 - c]),
                      h->at<double>(h->L.partials),
                      h->at<int>(h->L.key), h->at<int>(h->L.count), near_n,
-                     h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g));
+                     h->at<unsigned>(h->L.near_f), h->at<unsigned>(h->L.near_g), h->at<unsigned>(h->L.marks));
   h->binned = bin;
   mark(2);
   hipLaunchKernelGGL(sph_wrench, dim3(h->T), dim3(kWrenchThreads), 0, h->stream, h->at<double>(h->L.partials),
