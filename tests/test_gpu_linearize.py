@@ -328,30 +328,67 @@ def test_adjoint_at_full_size_against_the_oracle():
     sim.close()
 
 
-def test_adjoint_at_full_size_over_400_steps():
-    # the full 400-step horizon with the state kept every 20 steps.  The
-    # adjoint is the exact transpose of the tangent on the same binary32
-    # trajectory (checked tightly).  Against the oracle, the check is looser:
-    # past ~100 steps this particle system's derivative depends on where the
-    # trajectory goes, and binary32 rounding at every step moves it by a few
-    # percent (measured: errors of 6e-4 to 6e-2 of the largest component over
-    # 8 directions, while one rounding-level perturbation of the start alone
-    # moves the oracle's own derivative by 1e-3; at 100 steps the same
-    # comparison agrees to 5e-4).  So the 8 directional derivatives must
-    # point the same way (cosine >= 0.99) and each lie within 1e-1.
-    steps = 400
-    sc, sim, ck, uu, du, dr, pred = _full_size_adjoint(steps)
+def _golden_directions():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_adjoint_fd.py")
+    spec = importlib.util.spec_from_file_location("make_adjoint_fd", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_adjoint_at_full_size_over_400_steps_on_32_directions():
+    # The adjoint workload at its full specification: ~8,000 particles, 400
+    # steps, state kept every 20, the gradient of the final slosh torque
+    # along 32 random directions of the input sequence and the initial rigid
+    # state, against the FP64 oracle's central differences (eps = 1e-3),
+    # stored with the script that wrote them (tests/golden/make_adjoint_fd.py).
+    #
+    # The bound is derived from the oracle itself.  Past ~100 steps this
+    # particle system's derivative depends on where its trajectory goes: the
+    # golden file holds the same differences from 4 copies of the start
+    # perturbed at binary32 rounding level, and how far those copies'
+    # trajectories end from the unperturbed one.  The binary32 path is one
+    # more such trajectory, ending at its own distance from the oracle's
+    # (measured here).  In the linear regime a derivative's change scales
+    # with the trajectory's, so direction k is allowed
+    #     2 x (GPU distance / mean copy distance) x (largest change of
+    #     derivative k among the copies)  +  5e-3 of its largest component,
+    # the factor 2 for the sampling of 4 copies and the 5e-3 the 100-step bar
+    # (what remains when trajectories do not diverge).
+    from paper_2604_12505_amd.sph import Simulator
+    mod = _golden_directions()
+    gold = np.load(mod.OUT)
+    steps, lead, K = int(gold["steps"]), int(gold["lead"]), mod.K
+    du, dr = mod.directions()
+    assert float(np.abs(du).astype(np.float64).sum()) == float(gold["du_sum"])
+    sc = W.linearization_tank(seed=0, n_steps=steps + lead)
+    assert sc.n_fluid == int(gold["n_fluid"])
+    sim = Simulator.from_scenario(sc)
+    ck = _oracle_lead(sc, lead)
+    sim.set_state(*ck)
+    uu = torch.as_tensor(sc.u_seq)[lead:lead + steps].contiguous()
+    g = sim.vjp_rollout(steps, [0.0, 0.0, 1.0], uu, every=20)
+    pred = np.array([_dot(g["u"].cpu().numpy(), du[k]) + _dot(g["rigid0"], dr[k]) for k in range(K)])
     t = sim.jvp_rollout(steps, uu, du, None, dr)
-    for k in range(8):
+    for k in range(K):      # the adjoint is the tangent's exact transpose on the same trajectory
         assert pred[k] == pytest.approx(float(t["dwrench"][k][2]), rel=1e-3, abs=1e-6 * np.abs(t["dwrench"][k]).max())
-    un = uu.numpy().astype(np.float64)
-    fd = np.zeros(8)
-    worst = 0.0
-    for k in range(8):
-        fw, _ = _oracle_fd(sc, ck, un, du[k].astype(np.float64), dr[k])
-        fd[k] = fw[2]
-        worst = max(worst, abs(pred[k] - fw[2]) / np.abs(fw).max())
-    cos = float(pred @ fd / (np.linalg.norm(pred) * np.linalg.norm(fd)))
-    print("full size, 400 steps: worst error / largest component", worst, "cosine", cos)
-    assert cos >= 0.99 and worst <= 1e-1
+    sim.rollout(steps, uu)
+    s_gpu = sim.get_state()[0].cpu().numpy().astype(np.float64)
     sim.close()
+    rms = lambda a: float(np.sqrt((a ** 2).sum(1).mean()))   # noqa: E731
+    d_gpu = rms(s_gpu - gold["s_final"])
+    d_copy = float(np.mean([rms(m - gold["s_final"]) for m in gold["s_final_members"]]))
+    ratio = d_gpu / d_copy
+    fd = gold["dwrench"]
+    spread = np.abs(gold["dwrench_members"][:, :, 2] - fd[None, :, 2]).max(0)
+    scale = np.abs(fd).max(1)
+    bound = 2.0 * ratio * spread + 5e-3 * scale
+    err = np.abs(pred - fd[:, 2])
+    print(f"400 steps: GPU trajectory {d_gpu:.3e} m from the oracle's, copies {d_copy:.3e} m (ratio {ratio:.1f}); "
+          f"error / largest component: max {np.max(err / scale):.2e}, median {np.median(err / scale):.2e}; "
+          f"error / bound: max {np.max(err / bound):.2f}")
+    assert np.all(err <= bound), np.round(err / bound, 3)
+    cos = float(pred @ fd[:, 2] / (np.linalg.norm(pred) * np.linalg.norm(fd[:, 2])))
+    assert cos >= 0.99
