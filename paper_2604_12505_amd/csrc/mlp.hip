@@ -7,6 +7,7 @@
 //   forward   z_l = a_{l-1} W_l^T + b_l          A = a_{l-1} [B][in],  B = W_l [out][in]
 //   dgrad     g_{l-1} = (g_l W_l) * gelu'(z)     A = g_l [B][out],     B = W_l^T [in][out]
 //   wgrad     dW_l = g_l^T a_{l-1}                A = g_l^T [out][B],   B = a_{l-1}^T [in][B]
+//             (the batch split into up to 16 parts, their results summed in order)
 // so the forward epilogue also writes the transposed activation and the
 // pre-activation, and the dgrad epilogue writes the gradient both ways.  The
 // 3-wide head, the loss, the bias gradients and Adam are small VALU kernels.
@@ -54,6 +55,9 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // column (l % 16) of B for k in [8 (l / 16), 8 (l / 16) + 8) of each 32-wide
 // k step; the result element e of lane l is row 4 (l / 16) + e, column l % 16.
 // Rows m >= M and columns n >= N read zeros and are not stored.  K % 32 == 0.
+// A grid with gridDim.z > 1 splits the k range into gridDim.z equal parts
+// (K % (32 gridDim.z) == 0); part z covers [z K/Z, (z+1) K/Z) and its
+// epilogue sees blockIdx.z (EpiPart stores each part in its own slab).
 // ---------------------------------------------------------------------------
 
 struct EpiFwd {            // hidden forward layer
@@ -87,10 +91,11 @@ struct EpiDgrad {          // g_{l-1} = (g_l W_l) * gelu'(z_{l-1})
   }
 };
 
-struct EpiStore {          // plain FP32 store (weight gradients)
+struct EpiPart {           // k-split part z of a weight gradient, into slab z
   float* c;
   int ldc;
-  __device__ void operator()(int m, int n, float v) const { c[(size_t)m * ldc + n] = v; }
+  size_t slab;
+  __device__ void operator()(int m, int n, float v) const { c[blockIdx.z * slab + (size_t)m * ldc + n] = v; }
 };
 
 template <class Epi>
@@ -107,7 +112,8 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 2; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
   const bf16x8 zero = {};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const int kz = K / (int)gridDim.z, kb = (int)blockIdx.z * kz;
+  for (int k0 = kb; k0 < kb + kz; k0 += 32) {
     bf16x8 a[2], b[2];
     for (int r = 0; r < 2; ++r) {
       int m = m0 + r * 16 + li;
@@ -256,30 +262,47 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
 }
 
 // dW4[o][k] = sum_b gy[b][o] a4[b][k]; db4[o] = sum_b gy[b][o].
-__global__ void mlp_head_wgrad(const float* __restrict__ gy, const bf16* __restrict__ a4T, int ldT,
-                               int B, float* __restrict__ grad) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+// Head weight and bias gradients, dW4[o][k] = sum_b gy[b][o] a4[b][k] and
+// db4[o] = sum_b gy[b][o]: one wavefront per output (k = kHid: the bias),
+// lanes striding over the batch, then a fixed-order wavefront sum.
+__global__ void __launch_bounds__(256) mlp_head_wgrad(const float* __restrict__ gy, const bf16* __restrict__ a4T,
+                                                      int ldT, int B, float* __restrict__ grad) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (t >= kOut * (kHid + 1)) return;
-  int o = t / (kHid + 1), k = t - o * (kHid + 1);
+  const int o = t / (kHid + 1), k = t - o * (kHid + 1);
   float s = 0.f;
   if (k < kHid) {
-    for (int b = 0; b < B; ++b) s += gy[(size_t)b * kOut + o] * (float)a4T[(size_t)k * ldT + b];
-    grad[kOffW[4] + o * kHid + k] = s;
+    for (int b = lane; b < B; b += 64) s += gy[(size_t)b * kOut + o] * (float)a4T[(size_t)k * ldT + b];
   } else {
-    for (int b = 0; b < B; ++b) s += gy[(size_t)b * kOut + o];
-    grad[kOffB[4] + o] = s;
+    for (int b = lane; b < B; b += 64) s += gy[(size_t)b * kOut + o];
   }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) grad[k < kHid ? kOffW[4] + o * kHid + k : kOffB[4] + o] = s;
 }
 
-// db_l[n] = sum_b g_l^T[n][b] (one wave per n, fixed-order reduction).
-__global__ void mlp_bias_grad(const bf16* __restrict__ gT, int ldT, int B, float* __restrict__ db) {
-  int n = blockIdx.x * 4 + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
-  if (n >= kHid) return;
+// Sum of the k-split parts of a weight gradient, slab by slab in order.
+__global__ void mlp_sum_parts(const float* __restrict__ part, int parts, size_t slab, int n,
+                              float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
   float s = 0.f;
-  for (int b = lane; b < B; b += 64) s += (float)gT[(size_t)n * ldT + b];
+  for (int z = 0; z < parts; ++z) s += part[z * slab + i];
+  out[i] = s;
+}
+
+// Bias gradient of a hidden layer, db[n] = sum_b g[b][n]: one workgroup per
+// n, its 256 threads striding over the batch, wavefront sums, then the four
+// wavefronts' sums in order.
+__global__ void __launch_bounds__(256) mlp_bias_grad(const bf16* __restrict__ gT, int ldT, int B,
+                                                     float* __restrict__ db) {
+  __shared__ float red[4];
+  const int n = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float s = 0.f;
+  for (int b = threadIdx.x; b < B; b += 256) s += (float)gT[(size_t)n * ldT + b];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) db[n] = s;
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) db[n] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void mlp_loss(const float* __restrict__ rows, int B, float* __restrict__ out) {
@@ -328,11 +351,15 @@ __global__ void mlp_refresh(const float* __restrict__ w, bf16* __restrict__ wb, 
 // t = w .. w + window - 1 of (theta, omega, input torque) and the fill ratio,
 // each standardised; its target is the wrench at the window's last sample.
 //   x [(r * n_win + w)][t * 4 + c],  y [(r * n_win + w)][3],  n_win = T - window + 1.
+// per-rollout constants in the fourth input channel (fill ratio, tank
+// descriptors), at most this many
+constexpr int kMaxStatic = 8;
+
 struct WinNorm {
-  float in_mean[4], in_inv[4], out_mean[3], out_inv[3];
+  float in_mean[3 + kMaxStatic], in_inv[3 + kMaxStatic], out_mean[3], out_inv[3];
 };
 
-__global__ void mlp_windows(const float* __restrict__ feat, const float* __restrict__ fill,
+__global__ void mlp_windows(const float* __restrict__ feat, const float* __restrict__ stat, int n_static,
                             const float* __restrict__ wrench, int R, int T, int window, WinNorm nm,
                             float* __restrict__ x, float* __restrict__ y) {
   const int n_win = T - window + 1;
@@ -345,8 +372,10 @@ __global__ void mlp_windows(const float* __restrict__ feat, const float* __restr
   int ti = k >> 2, c = k & 3;
   int r = (int)(row / n_win), w = (int)(row - (long long)r * n_win);
   int t = w + ti;
-  float v = c < 3 ? feat[((size_t)r * T + t) * 3 + c] : fill[r];
-  x[e] = (v - nm.in_mean[c]) * nm.in_inv[c];
+  // channel 3 of sample ti carries the rollout's constant ti % n_static
+  const int q = c < 3 ? c : 3 + ti % n_static;
+  float v = c < 3 ? feat[((size_t)r * T + t) * 3 + c] : stat[(size_t)r * n_static + (q - 3)];
+  x[e] = (v - nm.in_mean[q]) * nm.in_inv[q];
   if (y && k < 3) {
     float o = wrench[((size_t)r * T + w + window - 1) * 3 + k];
     y[row * 3 + k] = (o - nm.out_mean[k]) * nm.out_inv[k];
@@ -357,9 +386,20 @@ size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct MlpLayout {
   size_t master, m, v, grad, wb, wT, xb, xT, act[4], actT[4], zT[4], g[4], gT[4], y, gy, rows,
-      loss, total;
+      loss, part, total;
   int ldT;   // leading dimension of the feature-major (transposed) buffers, a multiple of 32
 };
+
+// k-split of the weight gradients: a batch is cut into parts of at least
+// 256 rows, at most kMaxParts of them (the 4x4 or 4x2 output tiles of a
+// layer alone would occupy a few dozen of the 256 CUs)
+constexpr int kMaxParts = 16;
+
+int wgrad_parts(int B) {
+  int z = 1;
+  while (z < kMaxParts && B % (64 * z) == 0 && B / (2 * z) >= 256) z *= 2;
+  return z;
+}
 
 MlpLayout mlp_layout(int maxB) {
   MlpLayout L;
@@ -391,6 +431,7 @@ MlpLayout mlp_layout(int maxB) {
   L.gy = take(B * kOut * 4);
   L.rows = take(B * 4);
   L.loss = take(4);
+  L.part = take((size_t)kMaxParts * kHid * kHid * 4);
   L.total = o;
   return L;
 }
@@ -516,16 +557,20 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
                      h->at<bf16>(h->L.wb) + kOffW[4], h->at<float>(h->L.master) + kOffB[4], B,
                      h->at<float>(h->L.y), target_dev, h->at<float>(h->L.gy), h->at<float>(h->L.rows),
                      h->at<float>(h->L.zT[3]), h->at<bf16>(h->L.g[3]), h->at<bf16>(h->L.gT[3]), ldT, dy_dev);
-  hipLaunchKernelGGL(mlp_head_wgrad, dim3((kOut * (kHid + 1) + 255) / 256), dim3(256), 0, h->stream,
+  hipLaunchKernelGGL(mlp_head_wgrad, dim3((kOut * (kHid + 1) + 3) / 4), dim3(256), 0, h->stream,
                      h->at<float>(h->L.gy), h->at<bf16>(h->L.actT[3]), ldT, B, grad);
   // hidden layers, top down: g[l] holds dL/dz of hidden layer l (output of W_l)
   for (int l = 3; l >= 0; --l) {
     const bf16* aT = l > 0 ? h->at<bf16>(h->L.actT[l - 1]) : h->at<bf16>(h->L.xT);
-    EpiStore es{grad + kOffW[l], kDims[l]};
-    dim3 gw((kDims[l] + 63) / 64, (kHid + 63) / 64);
-    hipLaunchKernelGGL(gemm_tn<EpiStore>, gw, dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]), ldT, aT,
-                       ldT, kHid, kDims[l], B, es);
-    hipLaunchKernelGGL(mlp_bias_grad, dim3(kHid / 4), dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]),
+    const int parts = wgrad_parts(B);
+    const size_t slab = (size_t)kHid * kDims[l];
+    EpiPart ep{h->at<float>(h->L.part), kDims[l], slab};
+    dim3 gw((kDims[l] + 63) / 64, (kHid + 63) / 64, parts);
+    hipLaunchKernelGGL(gemm_tn<EpiPart>, gw, dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]), ldT, aT,
+                       ldT, kHid, kDims[l], B, ep);
+    hipLaunchKernelGGL(mlp_sum_parts, dim3((unsigned)((slab + 255) / 256)), dim3(256), 0, h->stream,
+                       h->at<float>(h->L.part), parts, slab, (int)slab, grad + kOffW[l]);
+    hipLaunchKernelGGL(mlp_bias_grad, dim3(kHid), dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]),
                        ldT, B, grad + kOffB[l]);
     if (l > 0) {
       EpiDgrad ed;
@@ -596,26 +641,29 @@ int mlp_adam_step(mlp_handle* h, const float* grads_dev, float lr, float beta1, 
   return SPH_OK;
 }
 
-int mlp_make_windows(const float* feat_dev, const float* fill_dev, const float* wrench_dev, int32_t n_roll,
-                     int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev, void* stream) {
-  if (!feat_dev || !fill_dev || !norm || !x_dev || n_roll < 1 || window < 1 || n_t < window) return SPH_E_INVAL;
+int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_static, const float* wrench_dev,
+                     int32_t n_roll, int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev,
+                     void* stream) {
+  if (!feat_dev || !static_dev || !norm || !x_dev || n_roll < 1 || window < 1 || n_t < window) return SPH_E_INVAL;
+  if (n_static < 1 || n_static > kMaxStatic || n_static > window) return SPH_E_INVAL;
   if (y_dev && !wrench_dev) return SPH_E_INVAL;
   WinNorm nm;
-  for (int c = 0; c < 4; ++c) {
-    if (!(norm[4 + c] > 0.0f)) return SPH_E_INVAL;
+  const int ni = 3 + n_static;   // input channels with a mean and a std: theta, thetadot, torque, constants
+  for (int c = 0; c < ni; ++c) {
+    if (!(norm[ni + c] > 0.0f)) return SPH_E_INVAL;
     nm.in_mean[c] = norm[c];
-    nm.in_inv[c] = 1.0f / norm[4 + c];
+    nm.in_inv[c] = 1.0f / norm[ni + c];
   }
   for (int c = 0; c < 3; ++c) {
-    if (!(norm[11 + c] > 0.0f)) return SPH_E_INVAL;
-    nm.out_mean[c] = norm[8 + c];
-    nm.out_inv[c] = 1.0f / norm[11 + c];
+    if (!(norm[2 * ni + 3 + c] > 0.0f)) return SPH_E_INVAL;
+    nm.out_mean[c] = norm[2 * ni + c];
+    nm.out_inv[c] = 1.0f / norm[2 * ni + 3 + c];
   }
   long long total = (long long)n_roll * (n_t - window + 1) * window * 4;
   long long blocks = (total + 255) / 256;
   if (blocks > 0x7fffffffLL) return SPH_E_INVAL;
   hipLaunchKernelGGL(mlp_windows, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
-                     feat_dev, fill_dev, wrench_dev, n_roll, n_t, window, nm, x_dev, y_dev);
+                     feat_dev, static_dev, n_static, wrench_dev, n_roll, n_t, window, nm, x_dev, y_dev);
   MHIP(hipGetLastError());
   return SPH_OK;
 }
