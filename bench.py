@@ -417,17 +417,24 @@ def sweep_leg(ks=(0, 1, 2, 3, 4, 5, 6), steps: int = 200, warmup: int = 40, kern
             "steps": steps, "rows": rows}
 
 
-def surrogate_leg(n_train: int = 192, n_test: int = 32, steps: int = 2000, epochs: int = 30):
+def surrogate_leg(n_train: int = 192, n_test: int = 64, steps: int = 2000, epochs: int = 30):
     """The wrench surrogate end to end at reduced size: relaxed, forced
     random tanks (2k-8k particles, the Tait law without tension) from the SPH
-    kernels, windows, MFMA training, held-out NRMSE beside the training-mean
-    predictor, and the network's time for the held-out windows against the
-    SPH time that produced them (the full-size run is train_surrogate.py)."""
+    kernels, windows (theta, thetadot, torque and the tank's fill, shape and
+    spacing), MFMA training, and on held-out tanks simulated twice (differing
+    only in the initial jitter): the network's NRMSE against one set, the SPH
+    noise floor (NRMSE between the two sets), the constant predictor, and the
+    network's time for the held-out windows against the SPH time that
+    produced them.  The speedup at the 2 % error target is reported only if
+    every channel meets it (null otherwise); the speedup at the noise floor
+    when every channel is below it (the full-size run is train_surrogate.py)."""
     import torch
     from paper_2604_12505_amd import surrogate as S
     kw = dict(n_steps=steps, log_stride=25, relax_cycles=10, relax_steps=100, n_min=2000, n_max=8000)
     tr = S.generate(list(range(1000, 1000 + n_train)), **kw)
-    te = S.generate(list(range(900000, 900000 + n_test)), **kw)
+    held = list(range(900000, 900000 + n_test))
+    te = S.generate(held, jitter_seed=1, **kw)
+    te2 = S.generate(held, jitter_seed=2, **kw)
     norm = S.norm_from(tr)
     xtr, ytr = S.windows(tr, norm)
     xte, yte = S.windows(te, norm)
@@ -435,14 +442,19 @@ def surrogate_leg(n_train: int = 192, n_test: int = 32, steps: int = 2000, epoch
     inf = S.inference_net(net, max_batch=65536)
     err = S.nrmse(S.predict(inf, xte), yte, norm)
     base = S.nrmse(torch.zeros_like(yte), yte, norm)
+    floor = S.noise_floor(te, te2)
     t_nn = S.time_inference(inf, xte)
     net.close()
     inf.close()
+    speedup = te.sph_seconds / t_nn
     return {"workload": f"{n_train} training / {n_test} held-out random tanks (2k-8k particles), {steps} steps, "
-                        f"log stride 25, window 32, {epochs} epochs",
-            "nrmse": [float(v) for v in err], "nrmse_mean_predictor": [float(v) for v in base],
+                        f"log stride 25, window 32 (theta, thetadot, torque; fill, shape, dx), {epochs} epochs",
+            "nrmse": [float(v) for v in err], "sph_noise_floor": [float(v) for v in floor],
+            "nrmse_mean_predictor": [float(v) for v in base],
             "heldout_windows": int(xte.shape[0]), "nn_seconds": t_nn, "sph_seconds": te.sph_seconds,
-            "speedup": te.sph_seconds / t_nn}
+            "speedup": speedup,
+            "speedup_at_2pct": speedup if bool(np.all(err <= 0.02)) else None,
+            "speedup_at_noise_floor": speedup if bool(np.all(err <= floor)) else None}
 
 
 # MI355X dense BF16 matrix peak (no sparsity)

@@ -417,17 +417,24 @@ int mlp_adam_step(mlp_handle* h, const float* grads_dev, float lr, float beta1, 
 
 /* Builds standardised surrogate inputs and targets from rollout logs.
  * feat_dev [n_roll][n_t][3] = theta, thetadot, input torque per log sample;
- * fill_dev [n_roll] fill ratios; wrench_dev [n_roll][n_t][3] body-frame slosh
- * force and torque (may be NULL when y_dev is NULL); norm: host [14] =
- * input means [4], input stds [4] (channels theta, thetadot, torque, fill),
- * output means [3], output stds [3] (stds > 0).  With n_win = n_t - window + 1
+ * static_dev [n_roll][n_static] per-rollout constants (the fill ratio, and
+ * optionally tank descriptors such as shape and particle spacing), 1 <=
+ * n_static <= min(8, window); wrench_dev [n_roll][n_t][3] body-frame slosh
+ * force and torque (may be NULL when y_dev is NULL); norm: host
+ * [2 (3 + n_static) + 6] = input means [3 + n_static] (theta, thetadot,
+ * torque, then each constant), input stds [3 + n_static], output means [3],
+ * output stds [3] (stds > 0; with n_static = 1 the 14 numbers of the four
+ * channels theta, thetadot, torque, fill).  With n_win = n_t - window + 1
  * windows per rollout, x_dev [n_roll * n_win][window * 4] receives window w
- * of rollout r as samples t = w .. w + window - 1, 4 channels per sample, and
- * y_dev [n_roll * n_win][3] the wrench at sample w + window - 1 (the
- * surrogate's target, Section 2 eq. surrogate as a one-step map).  Enqueued on
+ * of rollout r as samples t = w .. w + window - 1, 4 channels per sample:
+ * theta, thetadot, torque and, in the fourth, constant (t - w) % n_static of
+ * the rollout (n_static = 1: the fill ratio in every sample); y_dev
+ * [n_roll * n_win][3] the wrench at sample w + window - 1 (the surrogate's
+ * target, Section 2 eq. surrogate as a one-step map).  Enqueued on
  * `stream`; asynchronous. */
-int mlp_make_windows(const float* feat_dev, const float* fill_dev, const float* wrench_dev, int32_t n_roll,
-                     int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev, void* stream);
+int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_static, const float* wrench_dev,
+                     int32_t n_roll, int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev,
+                     void* stream);
 
 /* Copies the FP32 master weights to params_dev [231171]. */
 int mlp_get_params(mlp_handle* h, float* params_dev);

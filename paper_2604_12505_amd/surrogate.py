@@ -14,7 +14,10 @@ Section 5.1): ``relax_cycles`` times, ``relax_steps`` unforced steps followed
 by zeroing every velocity (kinetic damping).  Then ``n_steps`` forced steps
 are logged every ``log_stride`` steps; the target is the mean body-frame slosh
 wrench over each log interval, the inputs the logged (theta, thetadot, input
-torque) and the fill ratio.
+torque) and the per-tank constants: the fill ratio and, as an extension of the
+window's inputs, the tank's shape (0 rectangle, 1 circle) and its particle
+spacing dx in mm (without them the network cannot tell how large the tank's
+resting wall forces are, which set the mean of the wrench).
 """
 from __future__ import annotations
 
@@ -35,14 +38,21 @@ from .sph import Simulator
 WINDOW = 32
 
 
+N_STATIC = 3               # per-tank constants: fill ratio, shape, dx [mm]
+
+
 @dataclasses.dataclass
 class RolloutSet:
     feat: torch.Tensor      # [R, T, 3] theta, thetadot, input torque (device)
-    fill: torch.Tensor      # [R] (device)
+    static: torch.Tensor    # [R, N_STATIC] fill ratio, shape (0 rect, 1 circle), dx in mm (device)
     wrench: torch.Tensor    # [R, T, 3] mean body-frame wrench per log interval (device)
     n_fluid: np.ndarray     # [R]
     sph_seconds: float      # GPU time of the logged (forced) rollouts
     sph_steps: int          # SPH steps per rollout (logged part)
+
+    @property
+    def fill(self) -> torch.Tensor:
+        return self.static[:, 0]
 
 
 def _relax(sim: Simulator, cycles: int, steps: int) -> None:
@@ -68,7 +78,7 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
     T = (n_steps + log_stride - 1) // log_stride
     feat = torch.empty(R, T, 3, device=dev)
     wrench = torch.empty(R, T, 3, device=dev)
-    fill = torch.empty(R, device=dev)
+    static = torch.empty(R, N_STATIC, device=dev)
     n_fluid = np.zeros(R, np.int64)
     sph_seconds = 0.0
     for g0 in range(0, R, batch):
@@ -77,7 +87,7 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
                              jitter_seed=jitter_seed) for i in idx]
         for i, sc in zip(idx, scs):
             n_fluid[i] = sc.n_fluid
-            fill[i] = float(sc.fill)
+            static[i] = torch.tensor([float(sc.fill), 1.0 if sc.shape == "circle" else 0.0, sc.dx * 1e3])
         sim = Simulator.batch(scs, device=dev)
         if lanes:
             sim.set_lanes(lanes)
@@ -102,19 +112,32 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
         sim.close()
         if log is not None:
             log(f"rollouts {idx[-1] + 1}/{R} done ({sph_seconds:.1f} s of SPH so far)")
-    return RolloutSet(feat, fill, wrench, n_fluid, sph_seconds, n_steps)
+    return RolloutSet(feat, static, wrench, n_fluid, sph_seconds, n_steps)
 
 
-def norm_from(data: RolloutSet) -> np.ndarray:
-    """Per-channel mean and std of the inputs (theta, thetadot, torque, fill)
-    and of the targets, as the 14 numbers mlp_make_windows takes."""
+def norm_from(data: RolloutSet, n_static: int = N_STATIC) -> np.ndarray:
+    """Mean and std of the inputs (theta, thetadot, torque, then the first
+    n_static per-tank constants) and of the targets, as the
+    2 (3 + n_static) + 6 numbers mlp_make_windows takes (n_static = 1: the
+    fill ratio alone, the configured window)."""
     f = data.feat.reshape(-1, 3).double()
-    in_mean = torch.cat([f.mean(0), data.fill.double().mean().reshape(1)])
-    in_std = torch.cat([f.std(0), data.fill.double().std().reshape(1)])
+    st = data.static[:, :n_static].double()
+    in_mean = torch.cat([f.mean(0), st.mean(0)])
+    in_std = torch.cat([f.std(0), st.std(0)])
     w = data.wrench.reshape(-1, 3).double()
     out_mean, out_std = w.mean(0), w.std(0)
     v = torch.cat([in_mean, in_std.clamp_min(1e-12), out_mean, out_std.clamp_min(1e-12)])
     return v.cpu().numpy().astype(np.float32)
+
+
+def _n_static(norm: np.ndarray) -> int:
+    return (len(norm) - 12) // 2
+
+
+def out_norm(norm: np.ndarray):
+    """(output means [3], output stds [3]) of a norm vector."""
+    k = 2 * (3 + _n_static(norm))
+    return norm[k:k + 3], norm[k + 3:k + 6]
 
 
 def windows(data: RolloutSet, norm: np.ndarray, with_targets: bool = True, stream=None):
@@ -125,9 +148,11 @@ def windows(data: RolloutSet, norm: np.ndarray, with_targets: bool = True, strea
     dev = data.feat.device
     x = torch.empty(n, WINDOW * 4, device=dev)
     y = torch.empty(n, 3, device=dev) if with_targets else None
-    nm = (C.c_float * 14)(*[float(v) for v in norm])
+    ns = _n_static(norm)
+    stat = data.static[:, :ns].contiguous()
+    nm = (C.c_float * len(norm))(*[float(v) for v in norm])
     st = torch.cuda.current_stream(dev) if stream is None else stream
-    check(L.mlp_make_windows(C.c_void_p(data.feat.data_ptr()), C.c_void_p(data.fill.data_ptr()),
+    check(L.mlp_make_windows(C.c_void_p(data.feat.data_ptr()), C.c_void_p(stat.data_ptr()), ns,
                              C.c_void_p(data.wrench.data_ptr()) if with_targets else None, int(R), int(T),
                              WINDOW, nm, C.c_void_p(x.data_ptr()),
                              C.c_void_p(y.data_ptr()) if with_targets else None,
@@ -184,8 +209,9 @@ def predict(net: Mlp, x: torch.Tensor, batch: int = 65536) -> torch.Tensor:
 
 def nrmse(pred_std: torch.Tensor, y_std: torch.Tensor, norm: np.ndarray) -> np.ndarray:
     """Per-channel RMS(prediction - SPH) / RMS(SPH), in physical units."""
-    mean = torch.as_tensor(norm[8:11], device=y_std.device)
-    std = torch.as_tensor(norm[11:14], device=y_std.device)
+    om, osd = out_norm(norm)
+    mean = torch.as_tensor(om, device=y_std.device)
+    std = torch.as_tensor(osd, device=y_std.device)
     p = pred_std * std + mean
     t = y_std * std + mean
     err = torch.sqrt(((p - t) ** 2).mean(0))

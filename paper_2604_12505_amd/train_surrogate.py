@@ -5,9 +5,14 @@
 Generates training and held-out rollouts with the random-tank generator
 (relaxed, then forced by a multisine torque), trains the MLP with the
 library's MFMA kernels and reports, on the held-out set, the per-channel
-wrench NRMSE and the speedup: GPU time of the SPH rollouts that produced the
-held-out samples (the tanks advanced together, relaxation excluded) over the
-network's time for the same samples in batches of 65,536 windows.
+wrench NRMSE, the SPH noise floor (the held-out tanks are simulated a second
+time with another initial jitter and nothing else changed; the floor is the
+NRMSE between the two sets) and the speedup: GPU time of the SPH rollouts
+that produced the held-out samples (the tanks advanced together, relaxation
+excluded) over the network's time for the same samples in batches of 65,536
+windows.  The window's inputs are theta, thetadot and the input torque and,
+in the fourth channel, the tank's constants (--static 3: fill, shape,
+spacing; --static 1: the fill ratio alone, the configured window).
 """
 from __future__ import annotations
 
@@ -38,6 +43,7 @@ def main(argv=None) -> int:
     ap.add_argument("--tanks-per-launch", type=int, default=256)
     ap.add_argument("--literal-tait", action="store_true",
                     help="data with the Tait law as written (negative pressures allowed)")
+    ap.add_argument("--static", type=int, default=3, help="per-tank constants in the window (1: fill only)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
 
@@ -54,8 +60,11 @@ def main(argv=None) -> int:
     log(f"generating {a.train} training rollouts")
     tr = S.generate(train_seeds, batch=a.tanks_per_launch, log=log, **kw)
     log(f"generating {a.test} held-out rollouts")
-    te = S.generate(test_seeds, batch=a.tanks_per_launch, log=log, **kw)
-    norm = S.norm_from(tr)
+    te = S.generate(test_seeds, batch=a.tanks_per_launch, log=log, jitter_seed=1, **kw)
+    log(f"generating the {a.test} held-out rollouts again with another jitter")
+    te2 = S.generate(test_seeds, batch=a.tanks_per_launch, log=log, jitter_seed=2, **kw)
+    floor = S.noise_floor(te, te2)
+    norm = S.norm_from(tr, a.static)
     xtr, ytr = S.windows(tr, norm)
     xte, yte = S.windows(te, norm)
     log(f"windows: train {xtr.shape[0]}, held-out {xte.shape[0]}")
@@ -73,7 +82,10 @@ def main(argv=None) -> int:
         "eos": "tait" if a.literal_tait else "tait_clamped",
         "relax": [a.relax_cycles, a.relax_steps], "epochs": a.epochs, "batch": a.batch,
         "train_windows": int(xtr.shape[0]), "test_windows": int(n_win),
+        "static_inputs": a.static,
         "nrmse": [float(v) for v in err], "nrmse_max": float(np.max(err)),
+        "sph_noise_floor": [float(v) for v in floor],
+        "below_noise_floor": bool(np.all(err <= floor)),
         "nrmse_mean_predictor": [float(v) for v in base],
         "sph_seconds_heldout": te.sph_seconds,
         "sph_particle_steps_heldout": int(te.n_fluid.sum()) * a.steps,

@@ -1,19 +1,32 @@
 """The trained surrogate against the SPH it replaces (the reduced-size
-configuration of the benchmark's surrogate leg).
+configuration of the benchmark's surrogate leg: random tanks of 2k-8k
+particles, the Tait law without tension, 2,000 forced steps logged every
+25).
 
-The network is trained by the library's own kernels on relaxed, then forced,
-random-tank rollouts (2k-8k particles, the Tait law without tension, the data
-generator's default) and judged on held-out rollouts.  What is asserted:
+The network is trained by the library's own kernels on relaxed, then
+forced, random-tank rollouts and judged on held-out tanks.  Its inputs are
+the configured window (theta, thetadot, input torque) and the tank's
+constants (fill ratio, shape, particle spacing) in the fourth channel.
+
+The bar is SPH's own reproducibility.  The held-out tanks are simulated
+twice with the same shapes, sizes, fills and inputs, differing only in the
+initial lattice jitter (1 % of the spacing): set A and set B.  The
+per-channel NRMSE between A's and B's wrench is the noise floor, how far
+this weakly compressible SPH reproduces its own wrench (measured 0.85 /
+0.32 / 0.35 for F_x / F_y / torque on 64 held-out tanks; 0.34 / 0.14 / 0.16
+at full size, 2k-60k particles over 5,000 steps).  No predictor of the
+wrench from these inputs can do much better than about floor / sqrt(2)
+against one realization.  What is asserted:
 
 * the window kernel builds exactly the standardised windows of the logs;
-* the held-out error of every wrench channel is below 0.85 of the best
-  constant predictor's (the training mean); measured about 0.5-0.7 of it;
-* the network answers the held-out windows far faster than SPH produced them.
+* against set A, every channel's NRMSE is below that channel's floor (the
+  network disagrees with SPH less than SPH disagrees with itself), and
+  below the constant predictor's;
+* the network answers the held-out windows far faster than SPH produced
+  them.
 
-With the Tait law as written the zero-gravity wrench is dominated by a
-self-excited oscillation (a tensile instability from negative pressures,
-which the FP64 oracle shows too): it is then uncorrelated with the inputs,
-and no predictor beats the mean, so such data cannot test learning.
+The 2 % target on the wrench error lies below the floor on every channel,
+so no surrogate of this SPH can be held to it.
 """
 import numpy as np
 import pytest
@@ -23,33 +36,42 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def test_surrogate_learns_the_wrench_and_is_faster_than_sph():
+def test_surrogate_reaches_the_sph_noise_floor_and_is_faster_than_sph():
     from paper_2604_12505_amd import surrogate as S
     kw = dict(n_steps=2000, log_stride=25, relax_cycles=10, relax_steps=100, n_min=2000, n_max=8000)
     tr = S.generate(list(range(1000, 1192)), **kw)
-    te = S.generate(list(range(900000, 900032)), **kw)
+    held = list(range(900000, 900064))
+    te_a = S.generate(held, jitter_seed=1, **kw)
+    te_b = S.generate(held, jitter_seed=2, **kw)
     norm = S.norm_from(tr)
     xtr, ytr = S.windows(tr, norm)
-    xte, yte = S.windows(te, norm)
+    xa, ya = S.windows(te_a, norm)
     T = 2000 // 25
     per = T - 31
     assert xtr.shape == (192 * per, 128)
-    # the window kernel against a direct slicing of the logs
+    # the window kernel against a direct slicing of the logs (fourth
+    # channel: the tank's constants in turn, fill, shape, dx)
+    ns = S.N_STATIC
     f = tr.feat[3, 5:37].cpu().numpy()
     x0 = xtr[3 * per + 5].reshape(32, 4).cpu().numpy()
-    ref = (np.concatenate([f, np.full((32, 1), tr.fill[3].item())], 1) - norm[:4]) / norm[4:8]
+    q = np.arange(32) % ns
+    st = tr.static[3].cpu().numpy()[q]
+    ref = np.concatenate([(f - norm[:3]) / norm[3 + ns:6 + ns], ((st - norm[3 + q]) / norm[6 + ns + q])[:, None]], 1)
     assert np.allclose(x0, ref, rtol=1e-5, atol=1e-5)
-    y_ref = (tr.wrench[3, 36].cpu().numpy() - norm[8:11]) / norm[11:14]
+    om, osd = S.out_norm(norm)
+    y_ref = (tr.wrench[3, 36].cpu().numpy() - om) / osd
     assert np.allclose(ytr[3 * per + 5].cpu().numpy(), y_ref, rtol=1e-5, atol=1e-5)
     net = S.train(xtr, ytr, epochs=30, batch=1024, lr=2e-3, lr_final=1e-4)
     inf = S.inference_net(net, max_batch=8192)
-    err = S.nrmse(S.predict(inf, xte), yte, norm)
-    base = S.nrmse(torch.zeros_like(yte), yte, norm)
-    t_nn = S.time_inference(inf, xte)
-    speedup = te.sph_seconds / t_nn
-    print("held-out NRMSE", err, "constant predictor", base, "speedup", speedup)
+    err = S.nrmse(S.predict(inf, xa), ya, norm)
+    base = S.nrmse(torch.zeros_like(ya), ya, norm)
+    floor = S.noise_floor(te_a, te_b)
+    t_nn = S.time_inference(inf, xa)
+    speedup = te_a.sph_seconds / t_nn
+    print("held-out NRMSE", err, "noise floor", floor, "constant predictor", base, "speedup", speedup)
     assert np.all(np.isfinite(err))
-    assert np.all(err <= 0.85 * base)
+    assert np.all(err <= floor), (err, floor)
+    assert np.all(err < base)
     assert speedup > 10.0
     net.close()
     inf.close()
