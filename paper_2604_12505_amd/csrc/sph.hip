@@ -984,22 +984,30 @@ __device__ __forceinline__ int list_pass(const OrdMap& m, int total, int l, int&
 
 // Near-list build: the ordinals of the candidates that pass `keep`, in
 // order, as bytes into lst (capacity cap).  Returns the number that passed,
-// which may exceed cap (the list is then not used).  total <= 255.
+// which may exceed cap (the list is then not used).  total <= 255.  Walks
+// the three rows one after the other, where a candidate's LDS index is its
+// ordinal plus the row's offset (no per-candidate row search).
 template <int G, class F>
 __device__ __forceinline__ int near_build(const OrdMap& m, int total, int l, unsigned char* lst, int cap,
                                           F&& keep) {
   const int base = (int)(threadIdx.x & 63) - l;
   const unsigned below = (1u << l) - 1u;
   int cnt = 0;
-  for (int c = 0; c < total; c += G) {
-    const int cc = c + l;
-    const bool in = cc < total && keep(m(cc));
-    const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
-    if (in) {
-      const int at = cnt + __popc(msk & below);
-      if (at < cap) lst[at] = (unsigned char)cc;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c0 = r == 0 ? 0 : (r == 1 ? m.n0 : m.n01);
+    const int c1 = r == 0 ? m.n0 : (r == 1 ? m.n01 : total);
+    const int sh = m.e0 + (r >= 1 ? m.d1 : 0) + (r >= 2 ? m.d2 : 0);
+    for (int c = c0; c < c1; c += G) {
+      const int cc = c + l;
+      const bool in = cc < c1 && keep(cc + sh);
+      const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
+      if (in) {
+        const int at = cnt + __popc(msk & below);
+        if (at < cap) lst[at] = (unsigned char)cc;
+      }
+      cnt += __popc(msk);
     }
-    cnt += __popc(msk);
   }
   return cnt;
 }
