@@ -311,6 +311,11 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0)
     sc = W.paper_p0(seed=0, n_steps=1, spawn="random")
     dev = torch.device("cuda:0")
     sim = Simulator.from_scenario(sc, device=dev)
+    # dt = 1 ms moves a particle at 1 m/s by a tenth of h per step: the
+    # multi-kernel path rebuilds its cell list every 2 steps here (every 4 let
+    # a particle outrun the skin late in the 60 s manoeuvre; the LDS-resident
+    # path rebuilds at every step)
+    sim.set_rebuild_interval(2)
     _relax(sim, relax_cycles, relax_steps)
     s0, w0, _, _, _ = sim.get_state()
     g1 = gamma1_estimate(sc.params, s0, sc.ghosts, device=dev)      # eq. gamma1 at the relaxed state
@@ -357,6 +362,7 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0)
     n_b, steps_b = 256, (min(4000, max_steps) if max_steps > 0 else 4000)
     scs = [W.paper_p0(seed=s, n_steps=1, spawn="random") for s in range(n_b)]
     bsim = Simulator.batch(scs, device=dev)
+    bsim.set_rebuild_interval(2)
     _relax(bsim, 10, relax_steps)
     sb0, wb0, _, _, _ = bsim.get_state()
     force, ref = W.manoeuvre_profile(1, ts=per * sc.params.dt)
