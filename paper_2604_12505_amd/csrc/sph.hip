@@ -61,7 +61,7 @@
 namespace {
 
 constexpr int kBlock = 256;       // threads per workgroup of the particle kernels
-constexpr int kPlaceGroup = 16;   // lanes per cell in the placement
+constexpr int kPlaceGroup = 8;    // lanes per cell in the placement
 constexpr int kPlaceAhead = 4;    // source keys per lane loaded ahead in the placement
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;       // cells per thread per scan chunk
@@ -627,24 +627,26 @@ __global__ void __launch_bounds__(kBlock) sph_place(const int* __restrict__ key,
                                                     int* __restrict__ id_out,
                                                     float2* __restrict__ pos_sort,
                                                     unsigned* __restrict__ status) {
-  constexpr int G = kPlaceGroup;
+  constexpr int G = kPlaceGroup, A = kPlaceAhead;
   const int t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int c = t / G, l = t % G;
   if (c >= n_cells) return;
+  int dst = start_new[c];
+  const int end = start_new[c + 1];
+  if (dst == end) return;   // no particle has key c (most cells of the gas region)
   const Tank& tk = tanks[cell_owner[c]];
   const int ncx = tk.g.ncx, ncy = tk.g.ncy;
   const int shift = (threadIdx.x & 63) & ~(G - 1);   // first lane of this group in the wave
   const int lc = c - tk.c0;
   const int cy = lc / ncx, cx = lc - cy * ncx;
-  int dst = start_new[c];
-  const int end = start_new[c + 1];
   const int xa = cx > 0 ? cx - 1 : 0;
   const int xb = cx < ncx - 1 ? cx + 1 : ncx - 1;
   int rv[12];
   cell_ranges(tk, cx, cy, start_new, gstart, rv);
-  // the source rows' bounds, then their keys kPlaceAhead per lane ahead of
-  // the ballots (one memory round trip per row instead of one per pass of
-  // the group); the visiting order, and so the placement, is unchanged
+  // the source rows' bounds, then the first A keys per lane of all three
+  // rows at once (one memory round trip for the common case of rows of at
+  // most A * G particles); longer rows load the rest as they go.  The
+  // visiting order, and so the placement, is that of the rows in turn.
   int r0[3], r1[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -653,36 +655,58 @@ __global__ void __launch_bounds__(kBlock) sph_place(const int* __restrict__ key,
     r0[r] = in ? start_old[tk.c0 + yy * ncx + xa] : 0;
     r1[r] = in ? start_old[tk.c0 + yy * ncx + xb + 1] : 0;
   }
+  int kk[3][A];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int u = 0; u < A; ++u) {
+      const int i = r0[r] + u * G + l;
+      kk[r][u] = i < r1[r] ? key[i] : -1;
+    }
+#pragma unroll
   for (int r = 0; r < 3; ++r) {
     const int i1 = r1[r];
-    for (int b = r0[r]; b < i1; b += kPlaceAhead * G) {
-      int kk[kPlaceAhead];
+    for (int b = r0[r]; b < i1; b += A * G) {
+      if (b != r0[r])
 #pragma unroll
-      for (int u = 0; u < kPlaceAhead; ++u) {
-        const int i = b + u * G + l;
-        kk[u] = i < i1 ? key[i] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < kPlaceAhead; ++u) {
-        const int i = b + u * G + l;
-        const bool match = kk[u] == c;   // c >= 0: lanes past the row never match
-        unsigned long long m = __ballot(match);
-        unsigned gm = (unsigned)(m >> shift) & ((1u << G) - 1u);
-        if (match) {
-          int d = dst + __popc(gm & ((1u << l) - 1u));
-          if (d < end) {
-            float2 s = pos_in[i];
-            pos_out[d] = s;
-            vel_out[d] = vel_in[i];
-            acc_out[d] = acc_in[i];
-            id_out[d] = id_in[i];
-            pos_sort[d] = s;
-            pkey[d] = c;
-            store_ranges(rng, d, rv);
-          }
+        for (int u = 0; u < A; ++u) {
+          const int i = b + u * G + l;
+          kk[r][u] = i < i1 ? key[i] : -1;
         }
+      // destinations of the batch first, then its loads, then its stores
+      int dd[A];
+#pragma unroll
+      for (int u = 0; u < A; ++u) {
+        const bool match = kk[r][u] == c;   // c >= 0: lanes past the row never match
+        const unsigned long long m = __ballot(match);
+        const unsigned gm = (unsigned)(m >> shift) & ((1u << G) - 1u);
+        const int d = dst + __popc(gm & ((1u << l) - 1u));
+        dd[u] = match && d < end ? d : -1;
         dst += __popc(gm);
       }
+      float2 sp[A], sv[A], sa[A];
+      int sid[A];
+#pragma unroll
+      for (int u = 0; u < A; ++u)
+        if (dd[u] >= 0) {
+          const int i = b + u * G + l;
+          sp[u] = pos_in[i];
+          sv[u] = vel_in[i];
+          sa[u] = acc_in[i];
+          sid[u] = id_in[i];
+        }
+#pragma unroll
+      for (int u = 0; u < A; ++u)
+        if (dd[u] >= 0) {
+          const int d = dd[u];
+          pos_out[d] = sp[u];
+          vel_out[d] = sv[u];
+          acc_out[d] = sa[u];
+          id_out[d] = sid[u];
+          pos_sort[d] = sp[u];
+          pkey[d] = c;
+          store_ranges(rng, d, rv);
+        }
     }
   }
   if (l == 0 && dst != end) atomicOr(status, SPH_ST_SORT);
