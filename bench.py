@@ -450,9 +450,20 @@ def surrogate_leg(n_train: int = 192, n_test: int = 64, steps: int = 2000, epoch
     base = S.nrmse(torch.zeros_like(yte), yte, norm)
     floor = S.noise_floor(te, te2)
     t_nn = S.time_inference(inf, xte)
+    # the rigid body driven by the network instead of SPH from the first full
+    # window on, against SPH's trajectories (set te); the mean wrench as the
+    # baseline, the second SPH set as SPH's own spread
+    S.coupled(inf, te, norm)                         # warm-up
+    cpl = S.coupled(inf, te, norm)
+    const = S.constant_net(norm, max_batch=max(64, n_test))
+    e_nn = S.trajectory_nrmse(cpl["y"], te)
+    e_c = S.trajectory_nrmse(S.coupled(const, te, norm)["y"], te)
+    e_b = S.trajectory_nrmse(te2.y, te)
+    const.close()
     net.close()
     inf.close()
     speedup = te.sph_seconds / t_nn
+    ch = S.TRAJ_CHANNELS
     return {"workload": f"{n_train} training / {n_test} held-out random tanks (2k-8k particles), {steps} steps, "
                         f"log stride 25, window 32 (theta, thetadot, torque; fill, shape, dx), {epochs} epochs",
             "nrmse": [float(v) for v in err], "sph_noise_floor": [float(v) for v in floor],
@@ -460,7 +471,15 @@ def surrogate_leg(n_train: int = 192, n_test: int = 64, steps: int = 2000, epoch
             "heldout_windows": int(xte.shape[0]), "nn_seconds": t_nn, "sph_seconds": te.sph_seconds,
             "speedup": speedup,
             "speedup_at_2pct": speedup if bool(np.all(err <= 0.02)) else None,
-            "speedup_at_noise_floor": speedup if bool(np.all(err <= floor)) else None}
+            "speedup_at_noise_floor": speedup if bool(np.all(err <= floor)) else None,
+            "coupled": {"what": "rigid body driven by the network instead of SPH from sample 31 on, same inputs; "
+                                "trajectory NRMSE = RMS(run - SPH) / RMS(SPH - SPH at the hand-over)",
+                        "trajectory_nrmse": dict(zip(ch, (float(v) for v in e_nn))),
+                        "mean_wrench_nrmse": dict(zip(ch, (float(v) for v in e_c))),
+                        "sph_vs_sph_nrmse": dict(zip(ch, (float(v) for v in e_b))),
+                        "out_of_range_rollouts": int((cpl["flags"] & 1).sum().item()),
+                        "seconds": cpl["seconds"], "sph_seconds": te.sph_seconds,
+                        "speedup": te.sph_seconds / cpl["seconds"]}}
 
 
 # MI355X dense BF16 matrix peak (no sparsity)

@@ -436,6 +436,47 @@ int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_s
                      int32_t n_roll, int32_t n_t, int32_t window, const float* norm, float* x_dev, float* y_dev,
                      void* stream);
 
+/* Bit of mlp_coupled_rollout's per-rollout flags: a window input lay further
+ * than z_max standard deviations from the training mean (or was not a
+ * number). */
+#define MLP_FLAG_OUT_OF_RANGE 1u
+
+/* Rigid body driven by the surrogate instead of SPH: the use the paper makes
+ * of its surrogate, standing in for the fluid in the spacecraft's simulation
+ * (Section 4; the closed-loop validation of Section 5.3, Table 3).  For n_roll
+ * rollouts (at most the handle's max_batch) of n_steps steps logged every
+ * log_stride steps (T = ceil(n_steps / log_stride) >= window samples;
+ * window = 32, the network's 128 inputs), for k = window - 1 .. T - 1: the
+ * standardised window of samples k - window + 1 .. k (the layout and norm of
+ * mlp_make_windows, constants from static_dev) goes through the network; its
+ * output, de-standardised, is the mean body-frame slosh wrench over log
+ * interval k (the target sph_rollout logs in wmean_log_dev); the rigid body
+ * integrates the interval's steps with that wrench held and the applied
+ * inputs, by eq. tankdynamics for a free body and the first-order symplectic
+ * Euler of Section 3.4 (sph_rollout's rigid-body update without an attitude
+ * law); then sample k + 1 is logged.
+ * body_dev [n_roll][3] = body mass, inertia, dt; u_seq_dev
+ * [n_roll][n_steps][3] = applied F_x, F_y, torque per step; rigid_dev
+ * [n_roll][6] = r_x, r_y, theta, rdot_x, rdot_y, thetadot, in: the state at
+ * sample window - 1, out: the state after the last step; feat_dev
+ * [n_roll][T][3] = theta, thetadot, input torque per sample, in: samples
+ * 0 .. window - 1 (for instance sph_rollout's logs of the same inputs), out:
+ * samples window .. T - 1; y_log_dev [n_roll][T][6] (sph_rollout's y_log
+ * layout) receives samples window .. T - 1 and wrench_log_dev [n_roll][T][3]
+ * intervals window - 1 .. T - 1 (other rows are left as they are);
+ * flags_dev [n_roll] is cleared, then receives MLP_FLAG_OUT_OF_RANGE for a
+ * rollout any of whose window inputs lay further than z_max standard
+ * deviations from the training mean: it left the data the network was fitted
+ * on, and the caller runs it on SPH instead.  scratch_dev: device,
+ * n_roll * 131 floats.  SPH_E_INVAL for window != 32, n_roll outside
+ * [1, max_batch], T < window, n_static outside mlp_make_windows' range,
+ * z_max <= 0, a std that is not positive or a NULL pointer.  Enqueued on the
+ * handle's stream; asynchronous. */
+int mlp_coupled_rollout(mlp_handle* h, int32_t n_roll, int32_t n_steps, int32_t log_stride, int32_t window,
+                        const double* body_dev, const float* u_seq_dev, const float* static_dev, int32_t n_static,
+                        const float* norm, float z_max, double* rigid_dev, float* feat_dev, float* y_log_dev,
+                        float* wrench_log_dev, uint32_t* flags_dev, float* scratch_dev);
+
 /* Copies the FP32 master weights to params_dev [231171]. */
 int mlp_get_params(mlp_handle* h, float* params_dev);
 

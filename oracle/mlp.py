@@ -109,3 +109,82 @@ class Adam:
                 new.append(p - self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps))
             out.append((new[0], new[1]))
         return out
+
+
+# --------------------------------------------------------------------------
+# The network in place of SPH: rigid body driven by the surrogate's wrench
+# --------------------------------------------------------------------------
+
+def window_input(feat, static, norm, k, window=32):
+    """Standardised input of the window that ends at log sample k, for every
+    rollout: samples k - window + 1 .. k, four channels each (theta,
+    thetadot, input torque, and in the fourth the rollout's constant
+    number (t - first sample) mod n_static), each channel minus its training
+    mean over its training std.  feat [R, T, 3], static [R, n_static], norm as
+    the window kernel takes it (input means, input stds, output means, output
+    stds).  Returns [R, window * 4]."""
+    feat = np.asarray(feat, np.float64)
+    static = np.asarray(static, np.float64)
+    norm = np.asarray(norm, np.float64)
+    R = feat.shape[0]
+    ns = static.shape[1]
+    ni = 3 + ns
+    mean, std = norm[:ni], norm[ni:2 * ni]
+    x = np.empty((R, window, 4))
+    for i in range(window):
+        t = k - window + 1 + i
+        x[:, i, :3] = (feat[:, t, :] - mean[:3]) / std[:3]
+        q = i % ns
+        x[:, i, 3] = (static[:, q] - mean[3 + q]) / std[3 + q]
+    return x.reshape(R, window * 4)
+
+
+def coupled_rollout(params, norm, static, feat0, rigid0, u_seq, body, log_stride, window=32):
+    """The spacecraft simulated with the surrogate standing in for the fluid
+    (the use of the surrogate in Section 4 and in the closed-loop validation
+    of Section 5.3): at every log sample k from window - 1 on, the network's
+    output for the window ending at k, de-standardised, is the mean
+    body-frame slosh wrench over log interval k (steps k log_stride .. (k+1)
+    log_stride - 1); the free rigid body integrates those steps with that
+    wrench and the applied inputs by eq. tankdynamics,
+        m r'' = R(theta) F_body[0:2] + u[0:2],   J theta'' = F_body[2] + u[2],
+    R(theta) = [[cos, -sin], [sin, cos]], with first-order symplectic Euler
+    (Section 3.4: velocities first, positions with the new velocities).
+    Sample k + 1 then records the state and the features of the next window
+    (theta, thetadot, the input torque of the sample's first step).
+
+    params: network weights; norm: the window norm vector; static [R, ns];
+    feat0 [R, window, 3] the first window's features; rigid0 [R, 6] = r_x,
+    r_y, theta, rdot_x, rdot_y, thetadot at sample window - 1; u_seq
+    [R, n_steps, 3]; body [R, 3] = mass, inertia, dt.  Returns dict(y
+    [R, T, 6] with NaN before sample window, wrench [R, T, 3] with NaN before
+    interval window - 1, feat [R, T, 3], rigid [R, 6] after the last step)."""
+    norm = np.asarray(norm, np.float64)
+    u_seq = np.asarray(u_seq, np.float64)
+    body = np.asarray(body, np.float64)
+    R, n_steps, _ = u_seq.shape
+    T = -(-n_steps // log_stride)
+    ni = 3 + np.asarray(static).shape[1]
+    out_mean, out_std = norm[2 * ni:2 * ni + 3], norm[2 * ni + 3:2 * ni + 6]
+    feat = np.zeros((R, T, 3))
+    feat[:, :window] = np.asarray(feat0, np.float64)
+    y = np.full((R, T, 6), np.nan)
+    wrench = np.full((R, T, 3), np.nan)
+    st = np.array(rigid0, np.float64)
+    mass, inertia, dt = body[:, 0], body[:, 1], body[:, 2]
+    for k in range(window - 1, T):
+        out, _, _ = forward(params, window_input(feat, static, norm, k, window))
+        F = out * out_std + out_mean
+        wrench[:, k] = F
+        for n in range(k * log_stride, min((k + 1) * log_stride, n_steps)):
+            u = u_seq[:, n]
+            c, s = np.cos(st[:, 2]), np.sin(st[:, 2])
+            acc = np.stack([(c * F[:, 0] - s * F[:, 1] + u[:, 0]) / mass,
+                            (s * F[:, 0] + c * F[:, 1] + u[:, 1]) / mass,
+                            (F[:, 2] + u[:, 2]) / inertia], axis=1)
+            st[:, 3:6] += dt[:, None] * acc
+            st[:, 0:3] += dt[:, None] * st[:, 3:6]
+        if k + 1 < T:
+            y[:, k + 1] = st
+            feat[:, k + 1] = np.stack([st[:, 2], st[:, 5], u_seq[:, (k + 1) * log_stride, 2]], axis=1)
+    return dict(y=y, wrench=wrench, feat=feat, rigid=st)

@@ -36,7 +36,7 @@ SPH_SYMBOLS = ("sph_workspace_bytes", "sph_init", "sph_destroy", "sph_step", "sp
                "sph_jvp_workspace_bytes", "sph_jvp_rollout", "sph_vjp_workspace_bytes", "sph_vjp_rollout",
                "sph_gamma1_terms", "sph_gamma1_estimate", "sph_rollout_resident", "sph_resident_fits", "sph_strerror")
 MLP_SYMBOLS = ("mlp_workspace_bytes", "mlp_init", "mlp_destroy", "mlp_forward", "mlp_train_step",
-               "mlp_make_windows", "mlp_get_params", "mlp_backward", "mlp_adam_step")
+               "mlp_make_windows", "mlp_get_params", "mlp_backward", "mlp_adam_step", "mlp_coupled_rollout")
 LPV_SYMBOLS = ("lpv_workspace_bytes", "lpv_simulate", "lpv_loss_grad", "lpv_adam", "lpv_lbfgs",
                "lpv_closed_loop", "lpv_loss_grad_noalloc")
 
@@ -103,6 +103,7 @@ def load():
         L.mlp_backward.argtypes = [p, p, p, i32, p]
         L.mlp_adam_step.argtypes = [p, p, C.c_float, C.c_float, C.c_float, C.c_float, i32]
         L.mlp_make_windows.argtypes = [p, p, i32, p, i32, i32, i32, p, p, p, p]
+        L.mlp_coupled_rollout.argtypes = [p, i32, i32, i32, i32, p, p, p, i32, p, C.c_float, p, p, p, p, p, p]
         for name in MLP_SYMBOLS:
             getattr(L, name).restype = C.c_int
     po = P(LpvOpts)

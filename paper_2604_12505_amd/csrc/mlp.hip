@@ -356,7 +356,7 @@ __global__ void mlp_refresh(const float* __restrict__ w, bf16* __restrict__ wb, 
 constexpr int kMaxStatic = 8;
 
 struct WinNorm {
-  float in_mean[3 + kMaxStatic], in_inv[3 + kMaxStatic], out_mean[3], out_inv[3];
+  float in_mean[3 + kMaxStatic], in_inv[3 + kMaxStatic], out_mean[3], out_inv[3], out_std[3];
 };
 
 __global__ void mlp_windows(const float* __restrict__ feat, const float* __restrict__ stat, int n_static,
@@ -380,6 +380,106 @@ __global__ void mlp_windows(const float* __restrict__ feat, const float* __restr
     float o = wrench[((size_t)r * T + w + window - 1) * 3 + k];
     y[row * 3 + k] = (o - nm.out_mean[k]) * nm.out_inv[k];
   }
+}
+
+// The window of each rollout that ends at log sample k, standardised, in
+// mlp_windows' layout; an input further than z_max standard deviations from
+// the training mean (or not a number) sets MLP_FLAG_OUT_OF_RANGE in the
+// rollout's flags: the window lies outside the data the network was fitted on.
+__global__ void mlp_window_at(const float* __restrict__ feat, const float* __restrict__ stat, int n_static,
+                              int R, int T, int window, int k, WinNorm nm, float z_max, float* __restrict__ x,
+                              unsigned* __restrict__ flags) {
+  const int width = window * 4;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)R * width) return;
+  const int r = (int)(e / width), kk = (int)(e - (long long)r * width);
+  const int ti = kk >> 2, c = kk & 3, t = k - window + 1 + ti;
+  const int q = c < 3 ? c : 3 + ti % n_static;
+  const float v = c < 3 ? feat[((size_t)r * T + t) * 3 + c] : stat[(size_t)r * n_static + (q - 3)];
+  const float z = (v - nm.in_mean[q]) * nm.in_inv[q];
+  x[e] = z;
+  if (!(fabsf(z) <= z_max)) atomicOr(&flags[r], MLP_FLAG_OUT_OF_RANGE);
+}
+
+// Rigid body of each rollout over log interval k (steps k stride .. (k+1)
+// stride - 1), driven by the network's body-frame slosh wrench for that
+// interval held over its steps: eq. tankdynamics without an attitude law,
+// first-order symplectic Euler (Section 3.4; velocities first, then
+// positions with the new velocities).  Then log sample k + 1: the state, and
+// the features the next window reads (theta, thetadot, the input torque of
+// the sample's step).  One thread per rollout.
+__global__ void mlp_coupled_interval(const float* __restrict__ ystd, WinNorm nm, const double* __restrict__ body,
+                                     const float* __restrict__ u_seq, int n_steps, int stride, int R, int T, int k,
+                                     double* __restrict__ rigid, float* __restrict__ feat,
+                                     float* __restrict__ y_log, float* __restrict__ w_log) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double F[3];
+  for (int d = 0; d < 3; ++d) {
+    const float f = ystd[3 * r + d] * nm.out_std[d] + nm.out_mean[d];
+    F[d] = (double)f;
+    w_log[((size_t)r * T + k) * 3 + d] = f;
+  }
+  const double mass = body[3 * r], inertia = body[3 * r + 1], dt = body[3 * r + 2];
+  double* st = rigid + 6 * (size_t)r;   // r_x, r_y, theta, rdot_x, rdot_y, thetadot
+  double x0 = st[0], x1 = st[1], th = st[2], v0 = st[3], v1 = st[4], om = st[5];
+  const int n0 = k * stride, n1 = n0 + stride < n_steps ? n0 + stride : n_steps;
+  for (int n = n0; n < n1; ++n) {
+    const float* u = u_seq + ((size_t)r * n_steps + n) * 3;
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const double a0 = (cs * F[0] - sn * F[1] + (double)u[0]) / mass;
+    const double a1 = (sn * F[0] + cs * F[1] + (double)u[1]) / mass;
+    const double a2 = (F[2] + (double)u[2]) / inertia;
+    v0 += dt * a0;
+    v1 += dt * a1;
+    om += dt * a2;
+    x0 += dt * v0;
+    x1 += dt * v1;
+    th += dt * om;
+  }
+  st[0] = x0;
+  st[1] = x1;
+  st[2] = th;
+  st[3] = v0;
+  st[4] = v1;
+  st[5] = om;
+  if (k + 1 < T) {
+    float* y = y_log + ((size_t)r * T + k + 1) * 6;
+    y[0] = (float)x0;
+    y[1] = (float)x1;
+    y[2] = (float)th;
+    y[3] = (float)v0;
+    y[4] = (float)v1;
+    y[5] = (float)om;
+    float* f = feat + ((size_t)r * T + k + 1) * 3;
+    f[0] = (float)th;
+    f[1] = (float)om;
+    f[2] = u_seq[((size_t)r * n_steps + (size_t)(k + 1) * stride) * 3 + 2];
+  }
+}
+
+__global__ void mlp_clear_flags(unsigned* __restrict__ flags, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = 0u;
+}
+
+// The norm vector of mlp_make_windows into kernel form; false if a std is
+// not positive.
+bool win_norm(const float* norm, int n_static, WinNorm* nm) {
+  const int ni = 3 + n_static;   // input channels with a mean and a std: theta, thetadot, torque, constants
+  for (int c = 0; c < ni; ++c) {
+    if (!(norm[ni + c] > 0.0f)) return false;
+    nm->in_mean[c] = norm[c];
+    nm->in_inv[c] = 1.0f / norm[ni + c];
+  }
+  for (int c = 0; c < 3; ++c) {
+    if (!(norm[2 * ni + 3 + c] > 0.0f)) return false;
+    nm->out_mean[c] = norm[2 * ni + c];
+    nm->out_std[c] = norm[2 * ni + 3 + c];
+    nm->out_inv[c] = 1.0f / norm[2 * ni + 3 + c];
+  }
+  return true;
 }
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -648,22 +748,41 @@ int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_s
   if (n_static < 1 || n_static > kMaxStatic || n_static > window) return SPH_E_INVAL;
   if (y_dev && !wrench_dev) return SPH_E_INVAL;
   WinNorm nm;
-  const int ni = 3 + n_static;   // input channels with a mean and a std: theta, thetadot, torque, constants
-  for (int c = 0; c < ni; ++c) {
-    if (!(norm[ni + c] > 0.0f)) return SPH_E_INVAL;
-    nm.in_mean[c] = norm[c];
-    nm.in_inv[c] = 1.0f / norm[ni + c];
-  }
-  for (int c = 0; c < 3; ++c) {
-    if (!(norm[2 * ni + 3 + c] > 0.0f)) return SPH_E_INVAL;
-    nm.out_mean[c] = norm[2 * ni + c];
-    nm.out_inv[c] = 1.0f / norm[2 * ni + 3 + c];
-  }
+  if (!win_norm(norm, n_static, &nm)) return SPH_E_INVAL;
   long long total = (long long)n_roll * (n_t - window + 1) * window * 4;
   long long blocks = (total + 255) / 256;
   if (blocks > 0x7fffffffLL) return SPH_E_INVAL;
   hipLaunchKernelGGL(mlp_windows, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                      feat_dev, static_dev, n_static, wrench_dev, n_roll, n_t, window, nm, x_dev, y_dev);
+  MHIP(hipGetLastError());
+  return SPH_OK;
+}
+
+int mlp_coupled_rollout(mlp_handle* h, int32_t n_roll, int32_t n_steps, int32_t log_stride, int32_t window,
+                        const double* body_dev, const float* u_seq_dev, const float* static_dev, int32_t n_static,
+                        const float* norm, float z_max, double* rigid_dev, float* feat_dev, float* y_log_dev,
+                        float* wrench_log_dev, uint32_t* flags_dev, float* scratch_dev) {
+  if (!h || !body_dev || !u_seq_dev || !static_dev || !norm || !rigid_dev || !feat_dev || !y_log_dev ||
+      !wrench_log_dev || !flags_dev || !scratch_dev)
+    return SPH_E_INVAL;
+  if (window * 4 != kIn || n_roll < 1 || n_roll > h->maxB || log_stride < 1 || n_steps < 1) return SPH_E_INVAL;
+  if (n_static < 1 || n_static > kMaxStatic || n_static > window || !(z_max > 0.0f)) return SPH_E_INVAL;
+  const long long T = ((long long)n_steps + log_stride - 1) / log_stride;
+  if (T < window || (long long)n_roll * T * 6 > 0x7fffffffLL) return SPH_E_INVAL;
+  WinNorm nm;
+  if (!win_norm(norm, n_static, &nm)) return SPH_E_INVAL;
+  float* x = scratch_dev;
+  float* y = scratch_dev + (size_t)n_roll * kIn;
+  const unsigned xb = (unsigned)(((long long)n_roll * kIn + 255) / 256), rb = (unsigned)((n_roll + 63) / 64);
+  hipLaunchKernelGGL(mlp_clear_flags, dim3(rb), dim3(64), 0, h->stream, flags_dev, n_roll);
+  for (int k = window - 1; k < (int)T; ++k) {
+    hipLaunchKernelGGL(mlp_window_at, dim3(xb), dim3(256), 0, h->stream, feat_dev, static_dev, n_static, n_roll,
+                       (int)T, window, k, nm, z_max, x, flags_dev);
+    hipLaunchKernelGGL(mlp_forward_fused, dim3((n_roll + kRows - 1) / kRows), dim3(256), 0, h->stream, x, n_roll,
+                       h->at<bf16>(h->L.wb), h->at<float>(h->L.master), y);
+    hipLaunchKernelGGL(mlp_coupled_interval, dim3(rb), dim3(64), 0, h->stream, y, nm, body_dev, u_seq_dev,
+                       n_steps, log_stride, n_roll, (int)T, k, rigid_dev, feat_dev, y_log_dev, wrench_log_dev);
+  }
   MHIP(hipGetLastError());
   return SPH_OK;
 }

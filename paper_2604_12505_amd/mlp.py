@@ -106,6 +106,42 @@ class Mlp:
         self._keep = [g]
         self._leave()
 
+    def coupled_rollout(self, norm, static, feat0, rigid0, u_seq, body, log_stride: int, z_max: float = 6.0,
+                        window: int = 32):
+        """mlp_coupled_rollout: the rigid body driven by this network's wrench
+        instead of SPH.  static [R, n_static], feat0 [R, window, 3] (theta,
+        thetadot, input torque of the first window's samples), rigid0 [R, 6]
+        (r, theta, rdot, thetadot at sample window - 1), u_seq [R, n_steps, 3],
+        body [R, 3] (mass, inertia, dt).  Returns dict(y [R, T, 6] and wrench
+        [R, T, 3] (NaN where not computed), feat [R, T, 3], rigid [R, 6]
+        float64 after the last step, flags [R] int32)."""
+        dev = self.device
+        u = torch.as_tensor(u_seq, device=dev, dtype=torch.float32).contiguous()
+        R, n_steps, _ = u.shape
+        T = -(-n_steps // int(log_stride))
+        st = torch.as_tensor(static, device=dev, dtype=torch.float32).contiguous()
+        feat = torch.zeros(R, T, 3, device=dev)
+        feat[:, :window] = torch.as_tensor(feat0, device=dev, dtype=torch.float32)
+        rigid = torch.as_tensor(rigid0, device=dev, dtype=torch.float64).contiguous().clone()
+        bd = torch.as_tensor(body, device=dev, dtype=torch.float64).contiguous()
+        y = torch.full((R, T, 6), float("nan"), device=dev)
+        w = torch.full((R, T, 3), float("nan"), device=dev)
+        flags = torch.empty(R, dtype=torch.int32, device=dev)
+        scratch = torch.empty(R * 131, device=dev)
+        nv = np.asarray(norm, np.float32)
+        nm = (C.c_float * len(nv))(*[float(v) for v in nv])
+        self._enter()
+        check(self.L.mlp_coupled_rollout(self.h, int(R), int(n_steps), int(log_stride), int(window),
+                                         C.c_void_p(bd.data_ptr()), C.c_void_p(u.data_ptr()),
+                                         C.c_void_p(st.data_ptr()), int(st.shape[1]), nm, float(z_max),
+                                         C.c_void_p(rigid.data_ptr()), C.c_void_p(feat.data_ptr()),
+                                         C.c_void_p(y.data_ptr()), C.c_void_p(w.data_ptr()),
+                                         C.c_void_p(flags.data_ptr()), C.c_void_p(scratch.data_ptr())),
+              "mlp_coupled_rollout")
+        self._keep = [u, st, feat, rigid, bd, y, w, flags, scratch]
+        self._leave()
+        return dict(y=y, wrench=w, feat=feat, rigid=rigid, flags=flags)
+
     def params(self) -> torch.Tensor:
         p = torch.empty(N_PARAMS, device=self.device)
         self._enter()

@@ -49,6 +49,10 @@ class RolloutSet:
     n_fluid: np.ndarray     # [R]
     sph_seconds: float      # GPU time of the logged (forced) rollouts
     sph_steps: int          # SPH steps per rollout (logged part)
+    y: Optional[torch.Tensor] = None     # [R, T, 6] r, theta, rdot, thetadot per log sample (device)
+    u: Optional[torch.Tensor] = None     # [R, sph_steps, 3] applied force and torque per step (device)
+    body: Optional[torch.Tensor] = None  # [R, 3] body mass, inertia, dt (device, float64)
+    log_stride: int = 0
 
     @property
     def fill(self) -> torch.Tensor:
@@ -79,6 +83,9 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
     feat = torch.empty(R, T, 3, device=dev)
     wrench = torch.empty(R, T, 3, device=dev)
     static = torch.empty(R, N_STATIC, device=dev)
+    y_all = torch.empty(R, T, 6, device=dev)
+    u_all = torch.empty(R, n_steps, 3, device=dev)
+    body = torch.empty(R, 3, device=dev, dtype=torch.float64)
     n_fluid = np.zeros(R, np.int64)
     sph_seconds = 0.0
     for g0 in range(0, R, batch):
@@ -88,6 +95,7 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
         for i, sc in zip(idx, scs):
             n_fluid[i] = sc.n_fluid
             static[i] = torch.tensor([float(sc.fill), 1.0 if sc.shape == "circle" else 0.0, sc.dx * 1e3])
+            body[i] = torch.tensor([sc.params.body_mass, sc.params.body_inertia, sc.params.dt], dtype=torch.float64)
         sim = Simulator.batch(scs, device=dev)
         if lanes:
             sim.set_lanes(lanes)
@@ -109,10 +117,12 @@ def generate(seeds: Sequence[int], n_steps: int = 5000, log_stride: int = 25, re
         feat[sl, :, 1] = lg["y"][:, :, 5]
         feat[sl, :, 2] = lg["u"][:, :, 2]
         wrench[sl] = lg["wrench_mean"]
+        y_all[sl] = lg["y"]
+        u_all[sl] = u
         sim.close()
         if log is not None:
             log(f"rollouts {idx[-1] + 1}/{R} done ({sph_seconds:.1f} s of SPH so far)")
-    return RolloutSet(feat, static, wrench, n_fluid, sph_seconds, n_steps)
+    return RolloutSet(feat, static, wrench, n_fluid, sph_seconds, n_steps, y_all, u_all, body, log_stride)
 
 
 def norm_from(data: RolloutSet, n_static: int = N_STATIC) -> np.ndarray:
@@ -247,3 +257,72 @@ def time_inference(net: Mlp, x: torch.Tensor, reps: int = 20) -> float:
     e1.record(net.stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
+
+
+# The rigid-body channels a coupled run is judged on: r_x, r_y, theta,
+# rdot_x, rdot_y, thetadot.
+TRAJ_CHANNELS = ("r_x", "r_y", "theta", "rdot_x", "rdot_y", "thetadot")
+
+
+def coupled(net: Mlp, data: RolloutSet, norm: np.ndarray, z_max: float = 6.0) -> dict:
+    """The rollouts of `data` again, the rigid body driven by the network
+    instead of SPH from sample WINDOW - 1 on (``mlp_coupled_rollout``): the
+    first window and the state at the hand-over come from SPH's logs, the
+    inputs are the same.  Returns the coupled run's logs, its flags and its
+    GPU seconds (HIP events on the network's stream)."""
+    ns = _n_static(norm)
+    dev = net.device
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record(net.stream)
+    res = net.coupled_rollout(norm, data.static[:, :ns], data.feat[:, :WINDOW], data.y[:, WINDOW - 1].double(),
+                              data.u, data.body, data.log_stride, z_max=z_max, window=WINDOW)
+    e1.record(net.stream)
+    e1.synchronize()
+    res["seconds"] = e0.elapsed_time(e1) / 1e3
+    return res
+
+
+def trajectory_nrmse(y: torch.Tensor, ref: RolloutSet, first: int = WINDOW) -> np.ndarray:
+    """Per rigid-body channel (TRAJ_CHANNELS), RMS(y - SPH) / RMS(SPH - SPH
+    at the hand-over) over the samples from `first` on: the error of a
+    trajectory against SPH's, relative to the motion SPH made after the
+    hand-over at sample WINDOW - 1."""
+    y_ref = ref.y.double()
+    d = (y[:, first:].double() - y_ref[:, first:]).reshape(-1, 6)
+    m = (y_ref[:, first:] - y_ref[:, WINDOW - 1:WINDOW]).reshape(-1, 6)
+    return (torch.sqrt((d ** 2).mean(0)) / torch.sqrt((m ** 2).mean(0))).cpu().numpy()
+
+
+def constant_net(norm: np.ndarray, max_batch: int, device="cuda:0") -> Mlp:
+    """A network whose output is the training-mean wrench for every window
+    (all weights zero): the rigid body with the fluid's mean wrench, the
+    baseline a coupled surrogate must beat."""
+    from .mlp import N_PARAMS
+    return Mlp(np.zeros(N_PARAMS, np.float32), max_batch=max_batch, device=device)
+
+
+def coupled_or_sph(net: Mlp, data: RolloutSet, norm: np.ndarray, scenarios, z_max: float = 6.0,
+                   relax=None) -> dict:
+    """The surrogate with SPH as its fallback: the coupled run of every
+    rollout, then the rollouts whose windows left the training range
+    (MLP_FLAG_OUT_OF_RANGE) simulated again by SPH from the same start;
+    their logs replace the coupled ones.  `scenarios` are the rollouts'
+    workloads.Scenario objects (the SPH fallback needs the tanks), `relax`
+    the relaxation applied before their forced steps, as for the data
+    (cycles, steps).  Returns the merged y [R, T, 6] and wrench [R, T, 3],
+    the flags and the indices that fell back."""
+    res = coupled(net, data, norm, z_max)
+    flags = res["flags"].cpu().numpy()
+    back = [int(i) for i in np.nonzero(flags & 1)[0]]
+    y, w = res["y"].clone(), res["wrench"].clone()
+    if back:
+        sim = Simulator.batch([scenarios[i] for i in back], device=net.device)
+        if relax is not None:
+            _relax(sim, *relax)
+        lg = sim.rollout(data.sph_steps, data.u[back], log_stride=data.log_stride)
+        y[back] = lg["y"]
+        w[back] = lg["wrench_mean"]
+        sim.close()
+    return dict(y=y, wrench=w, flags=res["flags"], fell_back=back, seconds=res["seconds"])

@@ -10,7 +10,11 @@ time with another initial jitter and nothing else changed; the floor is the
 NRMSE between the two sets) and the speedup: GPU time of the SPH rollouts
 that produced the held-out samples (the tanks advanced together, relaxation
 excluded) over the network's time for the same samples in batches of 65,536
-windows.  The window's inputs are theta, thetadot and the input torque and,
+windows.  Then the held-out rollouts again with the rigid body driven by the
+network instead of SPH from the first full window on (the same inputs): the
+trajectory NRMSE against SPH per rigid-body channel, next to the same with
+the fluid's mean wrench and between the two SPH sets, and that run's time
+against SPH's.  The window's inputs are theta, thetadot and the input torque and,
 in the fourth channel, the tank's constants (--static 3: fill, shape,
 spacing; --static 1: the fill ratio alone, the configured window).
 """
@@ -77,6 +81,14 @@ def main(argv=None) -> int:
     t_nn = 0.0
     for b in range(0, n_win, 65536):
         t_nn += S.time_inference(net, xte[b:b + 65536].contiguous())
+    S.coupled(net, te, norm)                                # warm-up
+    cpl = S.coupled(net, te, norm)
+    const = S.constant_net(norm, max_batch=max(64, a.test))
+    e_nn = S.trajectory_nrmse(cpl["y"], te)
+    e_c = S.trajectory_nrmse(S.coupled(const, te, norm)["y"], te)
+    e_b = S.trajectory_nrmse(te2.y, te)
+    const.close()
+    ch = S.TRAJ_CHANNELS
     res = {
         "train_rollouts": a.train, "test_rollouts": a.test, "steps": a.steps, "log_stride": a.stride,
         "eos": "tait" if a.literal_tait else "tait_clamped",
@@ -92,6 +104,11 @@ def main(argv=None) -> int:
         "nn_seconds_heldout": t_nn,
         "speedup": te.sph_seconds / t_nn if t_nn > 0 else None,
         "nn_windows_per_s": n_win / t_nn if t_nn > 0 else None,
+        "coupled": {"trajectory_nrmse": dict(zip(ch, (float(v) for v in e_nn))),
+                    "mean_wrench_nrmse": dict(zip(ch, (float(v) for v in e_c))),
+                    "sph_vs_sph_nrmse": dict(zip(ch, (float(v) for v in e_b))),
+                    "out_of_range_rollouts": int((cpl["flags"] & 1).sum().item()),
+                    "seconds": cpl["seconds"], "speedup": te.sph_seconds / cpl["seconds"]},
         "wall_seconds": time.time() - t0,
     }
     log(json.dumps(res))

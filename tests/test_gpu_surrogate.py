@@ -23,7 +23,13 @@ against one realization.  What is asserted:
   network disagrees with SPH less than SPH disagrees with itself), and
   below the constant predictor's;
 * the network answers the held-out windows far faster than SPH produced
-  them.
+  them;
+* driving the rigid body with the network instead of SPH (from the
+  hand-over at the first full window on, the same inputs), its attitude
+  and rate stay closer to SPH's than with the fluid's mean wrench, and the
+  run is far faster than SPH;
+* with every window declared out of range, the SPH fallback reproduces the
+  SPH logs bit for bit.
 
 The 2 % target on the wrench error lies below the floor on every channel,
 so no surrogate of this SPH can be held to it.
@@ -73,5 +79,29 @@ def test_surrogate_reaches_the_sph_noise_floor_and_is_faster_than_sph():
     assert np.all(err <= floor), (err, floor)
     assert np.all(err < base)
     assert speedup > 10.0
+
+    # the rigid body driven by the network instead of SPH, against SPH
+    # (set A); set B gives SPH's own spread, the mean wrench the baseline
+    cpl = S.coupled(inf, te_a, norm)
+    e_nn = S.trajectory_nrmse(cpl["y"], te_a)
+    const = S.constant_net(norm, max_batch=64)
+    e_c = S.trajectory_nrmse(S.coupled(const, te_a, norm)["y"], te_a)
+    e_b = S.trajectory_nrmse(te_b.y, te_a)
+    speedup_c = te_a.sph_seconds / cpl["seconds"]
+    print("coupled trajectory NRMSE (r_x, r_y, theta, rdot_x, rdot_y, thetadot): network", e_nn,
+          "mean wrench", e_c, "SPH B vs A", e_b, "flagged", int((cpl["flags"] & 1).sum().item()),
+          "coupled speedup", speedup_c)
+    assert np.all(np.isfinite(e_nn))
+    assert e_nn[2] < e_c[2] and e_nn[5] < e_c[5]
+    assert speedup_c > 10.0
+
+    # the fallback: every window out of range, every rollout back on SPH
+    import workloads as W
+    scs = [W.random_tank(sd, n_steps=2000, n_min=2000, n_max=8000, eos=W.EOS_TAIT_CLAMPED, jitter_seed=1)
+           for sd in held]
+    fb = S.coupled_or_sph(inf, te_a, norm, scs, z_max=1e-6, relax=(10, 100))
+    assert fb["fell_back"] == list(range(len(held)))
+    assert torch.equal(fb["y"], te_a.y) and torch.equal(fb["wrench"], te_a.wrench)
+    const.close()
     net.close()
     inf.close()
