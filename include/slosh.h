@@ -467,15 +467,16 @@ int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_s
  * flags_dev [n_roll] is cleared, then receives MLP_FLAG_OUT_OF_RANGE for a
  * rollout any of whose window inputs lay further than z_max standard
  * deviations from the training mean: it left the data the network was fitted
- * on, and the caller runs it on SPH instead.  scratch_dev: device,
- * n_roll * 131 floats.  SPH_E_INVAL for window != 32, n_roll outside
+ * on, and the caller runs it on SPH instead.  One workgroup advances 64
+ * rollouts through every interval in one launch (the last 32 samples in
+ * LDS).  SPH_E_INVAL for window != 32, n_roll outside
  * [1, max_batch], T < window, n_static outside mlp_make_windows' range,
  * z_max <= 0, a std that is not positive or a NULL pointer.  Enqueued on the
  * handle's stream; asynchronous. */
 int mlp_coupled_rollout(mlp_handle* h, int32_t n_roll, int32_t n_steps, int32_t log_stride, int32_t window,
                         const double* body_dev, const float* u_seq_dev, const float* static_dev, int32_t n_static,
                         const float* norm, float z_max, double* rigid_dev, float* feat_dev, float* y_log_dev,
-                        float* wrench_log_dev, uint32_t* flags_dev, float* scratch_dev);
+                        float* wrench_log_dev, uint32_t* flags_dev);
 
 /* Copies the FP32 master weights to params_dev [231171]. */
 int mlp_get_params(mlp_handle* h, float* params_dev);

@@ -103,7 +103,7 @@ def load():
         L.mlp_backward.argtypes = [p, p, p, i32, p]
         L.mlp_adam_step.argtypes = [p, p, C.c_float, C.c_float, C.c_float, C.c_float, i32]
         L.mlp_make_windows.argtypes = [p, p, i32, p, i32, i32, i32, p, p, p, p]
-        L.mlp_coupled_rollout.argtypes = [p, i32, i32, i32, i32, p, p, p, i32, p, C.c_float, p, p, p, p, p, p]
+        L.mlp_coupled_rollout.argtypes = [p, i32, i32, i32, i32, p, p, p, i32, p, C.c_float, p, p, p, p, p]
         for name in MLP_SYMBOLS:
             getattr(L, name).restype = C.c_int
     po = P(LpvOpts)

@@ -38,15 +38,30 @@ static_assert(kOffB[4] + kOut == MLP_N_PARAMS, "packing");
 constexpr float kGeluK = 0.7978845608028654f;  // sqrt(2/pi)
 constexpr float kGeluC = 0.044715f;
 
-__device__ __forceinline__ float gelu(float x) {
-  float t = tanhf(kGeluK * (x + kGeluC * x * x * x));
-  return 0.5f * x * (1.0f + t);
+constexpr float kLog2e = 1.4426950408889634f;
+
+// The logistic function of 2u, 1 / (1 + e^(-2u)), from the hardware base-2
+// exponential and reciprocal (about 1 ulp each; e^(-2u) overflowing to +inf
+// gives 0, underflowing to 0 gives 1).
+__device__ __forceinline__ float sigmoid2(float u) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-2.0f * kLog2e * u));
 }
 
+// The tanh form x/2 (1 + tanh(u)), u = sqrt(2/pi)(x + 0.044715 x^3), written
+// as x s with s = 1 / (1 + e^(-2u)) (1 + tanh(u) = 2 / (1 + e^(-2u))):
+// branch-free, about 8 instructions.
+__device__ __forceinline__ float gelu(float x) {
+  const float u = kGeluK * x * fmaf(kGeluC, x * x, 1.0f);
+  return x * sigmoid2(u);
+}
+
+// Its derivative, s + 2 x s (1 - s) u'(x) (the tanh form's
+// (1 + t)/2 + x (1 - t^2) u'/2 with 1 + t = 2 s, 1 - t^2 = 4 s (1 - s)).
 __device__ __forceinline__ float gelu_grad(float x) {
-  float t = tanhf(kGeluK * (x + kGeluC * x * x * x));
-  float du = kGeluK * (1.0f + 3.0f * kGeluC * x * x);
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * du;
+  const float x2 = x * x;
+  const float sg = sigmoid2(kGeluK * x * fmaf(kGeluC, x2, 1.0f));
+  const float du = kGeluK * fmaf(3.0f * kGeluC, x2, 1.0f);
+  return sg + 2.0f * x * sg * (1.0f - sg) * du;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,20 +162,14 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
 constexpr int kRows = 64;
 constexpr int kLdsStride = kHid + 8;
 
-__global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict__ x, int B,
-                                                         const bf16* __restrict__ wb,
-                                                         const float* __restrict__ master,
-                                                         float* __restrict__ y) {
-  __shared__ __align__(16) bf16 buf[2][kRows * kLdsStride];
-  const int row0 = blockIdx.x * kRows;
+// The network on the kRows rows staged in buf[0] as BF16: the four hidden
+// layers on MFMA (ping-pong between the two buffers), then the head, whose
+// result for row r and output o goes to out(r, o, value) (called by thread
+// 4 r).  All 256 threads; ends without a barrier.
+template <class Out>
+__device__ __forceinline__ void net_rows(bf16 (*buf)[kRows * kLdsStride], const bf16* __restrict__ wb,
+                                         const float* __restrict__ master, Out&& out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < kRows * kIn; e += 256) {
-    int r = e / kIn, k = e - r * kIn;
-    int m = row0 + r;
-    float v = m < B ? x[(size_t)m * kIn + k] : 0.0f;
-    buf[0][r * kLdsStride + k] = (bf16)v;
-  }
-  __syncthreads();
   int cur = 0;
   const int li = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
   const int n0 = wave * 64;
@@ -171,15 +180,21 @@ __global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict
     floatx4 acc[4][4];
     for (int r = 0; r < 4; ++r)
       for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // the weights of the next k step are loaded while this one's products
+    // run (a lone workgroup per CU otherwise waits on every L2 round trip)
+    bf16x8 b[4], bn[4];
+    for (int c = 0; c < 4; ++c) b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + kq);
     for (int k0 = 0; k0 < K; k0 += 32) {
-      bf16x8 a[4], b[4];
+      if (k0 + 32 < K)
+        for (int c = 0; c < 4; ++c)
+          bn[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + 32 + kq);
+      bf16x8 a[4];
       for (int r = 0; r < 4; ++r)
         a[r] = *reinterpret_cast<const bf16x8*>(&buf[cur][(r * 16 + li) * kLdsStride + k0 + kq]);
-      for (int c = 0; c < 4; ++c)
-        b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + kq);
       for (int r = 0; r < 4; ++r)
         for (int c = 0; c < 4; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+      for (int c = 0; c < 4; ++c) b[c] = bn[c];
     }
     for (int c = 0; c < 4; ++c) {
       const int n = n0 + c * 16 + li;
@@ -191,14 +206,54 @@ __global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict
     __syncthreads();
     cur = 1 - cur;
   }
-  if (threadIdx.x < kRows * kOut) {
-    const int r = threadIdx.x / kOut, o = threadIdx.x - r * kOut;
-    const bf16* w4 = wb + kOffW[4] + o * kHid;
-    float s = 0.0f;
-    for (int k = 0; k < kHid; ++k) s += (float)buf[cur][r * kLdsStride + k] * (float)w4[k];
-    const int m = row0 + r;
-    if (m < B) y[(size_t)m * kOut + o] = s + master[kOffB[4] + o];
+  // the head: 4 lanes per row, each over 64 of the 256 inputs for the three
+  // outputs at once, then the sum over the 4 lanes
+  static_assert(kRows * 4 == 256 && kOut == 3, "head layout");
+  const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
+  const bf16* a = &buf[cur][r * kLdsStride + p * 64];
+  const bf16* w4 = wb + kOffW[4] + p * 64;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+  for (int k = 0; k < 64; k += 8) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
+    const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(w4 + k);
+    const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(w4 + kHid + k);
+    const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(w4 + 2 * kHid + k);
+    for (int j = 0; j < 8; ++j) {
+      const float aj = (float)av[j];
+      s0 = fmaf(aj, (float)w0[j], s0);
+      s1 = fmaf(aj, (float)w1[j], s1);
+      s2 = fmaf(aj, (float)w2[j], s2);
+    }
   }
+  for (int off = 1; off < 4; off <<= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+  }
+  if (p == 0) {
+    out(r, 0, s0 + master[kOffB[4]]);
+    out(r, 1, s1 + master[kOffB[4] + 1]);
+    out(r, 2, s2 + master[kOffB[4] + 2]);
+  }
+}
+
+__global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict__ x, int B,
+                                                         const bf16* __restrict__ wb,
+                                                         const float* __restrict__ master,
+                                                         float* __restrict__ y) {
+  __shared__ __align__(16) bf16 buf[2][kRows * kLdsStride];
+  const int row0 = blockIdx.x * kRows;
+  for (int e = threadIdx.x; e < kRows * kIn; e += 256) {
+    int r = e / kIn, k = e - r * kIn;
+    int m = row0 + r;
+    float v = m < B ? x[(size_t)m * kIn + k] : 0.0f;
+    buf[0][r * kLdsStride + k] = (bf16)v;
+  }
+  __syncthreads();
+  net_rows(buf, wb, master, [&](int r, int o, float v) {
+    const int m = row0 + r;
+    if (m < B) y[(size_t)m * kOut + o] = v;
+  });
 }
 
 // FP32 input [B][128] -> BF16 row-major and (training) transposed copies.
@@ -382,86 +437,126 @@ __global__ void mlp_windows(const float* __restrict__ feat, const float* __restr
   }
 }
 
-// The window of each rollout that ends at log sample k, standardised, in
-// mlp_windows' layout; an input further than z_max standard deviations from
-// the training mean (or not a number) sets MLP_FLAG_OUT_OF_RANGE in the
-// rollout's flags: the window lies outside the data the network was fitted on.
-__global__ void mlp_window_at(const float* __restrict__ feat, const float* __restrict__ stat, int n_static,
-                              int R, int T, int window, int k, WinNorm nm, float z_max, float* __restrict__ x,
-                              unsigned* __restrict__ flags) {
-  const int width = window * 4;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)R * width) return;
-  const int r = (int)(e / width), kk = (int)(e - (long long)r * width);
-  const int ti = kk >> 2, c = kk & 3, t = k - window + 1 + ti;
-  const int q = c < 3 ? c : 3 + ti % n_static;
-  const float v = c < 3 ? feat[((size_t)r * T + t) * 3 + c] : stat[(size_t)r * n_static + (q - 3)];
-  const float z = (v - nm.in_mean[q]) * nm.in_inv[q];
-  x[e] = z;
-  if (!(fabsf(z) <= z_max)) atomicOr(&flags[r], MLP_FLAG_OUT_OF_RANGE);
-}
+// Window width of the coupled rollout: the network's 128 inputs are 32
+// samples of 4 channels.
+constexpr int kWin = kIn / 4;
 
-// Rigid body of each rollout over log interval k (steps k stride .. (k+1)
-// stride - 1), driven by the network's body-frame slosh wrench for that
-// interval held over its steps: eq. tankdynamics without an attitude law,
-// first-order symplectic Euler (Section 3.4; velocities first, then
-// positions with the new velocities).  Then log sample k + 1: the state, and
-// the features the next window reads (theta, thetadot, the input torque of
-// the sample's step).  One thread per rollout.
-__global__ void mlp_coupled_interval(const float* __restrict__ ystd, WinNorm nm, const double* __restrict__ body,
-                                     const float* __restrict__ u_seq, int n_steps, int stride, int R, int T, int k,
-                                     double* __restrict__ rigid, float* __restrict__ feat,
-                                     float* __restrict__ y_log, float* __restrict__ w_log) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  double F[3];
-  for (int d = 0; d < 3; ++d) {
-    const float f = ystd[3 * r + d] * nm.out_std[d] + nm.out_mean[d];
-    F[d] = (double)f;
-    w_log[((size_t)r * T + k) * 3 + d] = f;
+// The rigid body of kRows rollouts per workgroup driven by the network, all
+// log intervals in one launch (the rollouts are independent).  Per interval
+// k: the window of samples k - 31 .. k, standardised from a ring of the last
+// 32 samples in LDS (mlp_windows' layout; an input further than z_max
+// standard deviations from the training mean, or not a number, sets
+// MLP_FLAG_OUT_OF_RANGE); the network on MFMA; then thread r integrates its
+// rollout over the interval's steps with the de-standardised wrench held:
+// eq. tankdynamics without an attitude law, first-order symplectic Euler
+// (Section 3.4; velocities first, then positions with the new velocities),
+// and logs sample k + 1 (state; theta, thetadot, the input torque of the
+// sample's step, also into the ring).
+__global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ stat, int n_static, int R, int T,
+                                                   WinNorm nm, float z_max, const double* __restrict__ body,
+                                                   const float* __restrict__ u_seq, int n_steps, int stride,
+                                                   const bf16* __restrict__ wb, const float* __restrict__ master,
+                                                   double* __restrict__ rigid, float* __restrict__ feat,
+                                                   float* __restrict__ y_log, float* __restrict__ w_log,
+                                                   unsigned* __restrict__ flags) {
+  __shared__ __align__(16) bf16 buf[2][kRows * kLdsStride];
+  __shared__ float ring[kRows][kWin][3];
+  __shared__ float hout[kRows * kOut];
+  __shared__ unsigned fl[kRows];
+  const int row0 = blockIdx.x * kRows, t = threadIdx.x;
+  for (int e = t; e < kRows * kWin * 3; e += 256) {
+    const int r = e / (kWin * 3), q = e - r * (kWin * 3);
+    const int m = row0 + r;
+    ring[r][q / 3][q % 3] = m < R ? feat[((size_t)m * T + q / 3) * 3 + q % 3] : 0.0f;
   }
-  const double mass = body[3 * r], inertia = body[3 * r + 1], dt = body[3 * r + 2];
-  double* st = rigid + 6 * (size_t)r;   // r_x, r_y, theta, rdot_x, rdot_y, thetadot
-  double x0 = st[0], x1 = st[1], th = st[2], v0 = st[3], v1 = st[4], om = st[5];
-  const int n0 = k * stride, n1 = n0 + stride < n_steps ? n0 + stride : n_steps;
-  for (int n = n0; n < n1; ++n) {
-    const float* u = u_seq + ((size_t)r * n_steps + n) * 3;
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    const double a0 = (cs * F[0] - sn * F[1] + (double)u[0]) / mass;
-    const double a1 = (sn * F[0] + cs * F[1] + (double)u[1]) / mass;
-    const double a2 = (F[2] + (double)u[2]) / inertia;
-    v0 += dt * a0;
-    v1 += dt * a1;
-    om += dt * a2;
-    x0 += dt * v0;
-    x1 += dt * v1;
-    th += dt * om;
+  if (t < kRows) fl[t] = 0u;
+  const int mine = row0 + t;
+  const bool owner = t < kRows && mine < R;
+  double x0 = 0.0, x1 = 0.0, th = 0.0, v0 = 0.0, v1 = 0.0, om = 0.0, mass = 1.0, inertia = 1.0, dt = 0.0;
+  if (owner) {
+    const double* st = rigid + 6 * (size_t)mine;
+    x0 = st[0];
+    x1 = st[1];
+    th = st[2];
+    v0 = st[3];
+    v1 = st[4];
+    om = st[5];
+    mass = body[3 * (size_t)mine];
+    inertia = body[3 * (size_t)mine + 1];
+    dt = body[3 * (size_t)mine + 2];
   }
-  st[0] = x0;
-  st[1] = x1;
-  st[2] = th;
-  st[3] = v0;
-  st[4] = v1;
-  st[5] = om;
-  if (k + 1 < T) {
-    float* y = y_log + ((size_t)r * T + k + 1) * 6;
-    y[0] = (float)x0;
-    y[1] = (float)x1;
-    y[2] = (float)th;
-    y[3] = (float)v0;
-    y[4] = (float)v1;
-    y[5] = (float)om;
-    float* f = feat + ((size_t)r * T + k + 1) * 3;
-    f[0] = (float)th;
-    f[1] = (float)om;
-    f[2] = u_seq[((size_t)r * n_steps + (size_t)(k + 1) * stride) * 3 + 2];
+  __syncthreads();
+  for (int k = kWin - 1; k < T; ++k) {
+    for (int e = t; e < kRows * kIn; e += 256) {
+      const int r = e / kIn, kk = e - r * kIn;
+      const int ti = kk >> 2, c = kk & 3;
+      const int m = row0 + r;
+      const int q = c < 3 ? c : 3 + ti % n_static;
+      float z = 0.0f;
+      if (m < R) {
+        const float v = c < 3 ? ring[r][(k - kWin + 1 + ti) % kWin][c] : stat[(size_t)m * n_static + (q - 3)];
+        z = (v - nm.in_mean[q]) * nm.in_inv[q];
+        if (!(fabsf(z) <= z_max)) atomicOr(&fl[r], MLP_FLAG_OUT_OF_RANGE);
+      }
+      buf[0][r * kLdsStride + kk] = (bf16)z;
+    }
+    __syncthreads();
+    net_rows(buf, wb, master, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
+    __syncthreads();
+    if (owner) {
+      double F[3];
+      for (int d = 0; d < 3; ++d) {
+        const float f = hout[t * kOut + d] * nm.out_std[d] + nm.out_mean[d];
+        F[d] = (double)f;
+        w_log[((size_t)mine * T + k) * 3 + d] = f;
+      }
+      const int n0 = k * stride, n1 = n0 + stride < n_steps ? n0 + stride : n_steps;
+      for (int n = n0; n < n1; ++n) {
+        const float* u = u_seq + ((size_t)mine * n_steps + n) * 3;
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        const double a0 = (cs * F[0] - sn * F[1] + (double)u[0]) / mass;
+        const double a1 = (sn * F[0] + cs * F[1] + (double)u[1]) / mass;
+        const double a2 = (F[2] + (double)u[2]) / inertia;
+        v0 += dt * a0;
+        v1 += dt * a1;
+        om += dt * a2;
+        x0 += dt * v0;
+        x1 += dt * v1;
+        th += dt * om;
+      }
+      if (k + 1 < T) {
+        float* y = y_log + ((size_t)mine * T + k + 1) * 6;
+        y[0] = (float)x0;
+        y[1] = (float)x1;
+        y[2] = (float)th;
+        y[3] = (float)v0;
+        y[4] = (float)v1;
+        y[5] = (float)om;
+        const float f0 = (float)th, f1 = (float)om;
+        const float f2 = u_seq[((size_t)mine * n_steps + (size_t)(k + 1) * stride) * 3 + 2];
+        float* f = feat + ((size_t)mine * T + k + 1) * 3;
+        f[0] = f0;
+        f[1] = f1;
+        f[2] = f2;
+        float* g = ring[t][(k + 1) % kWin];
+        g[0] = f0;
+        g[1] = f1;
+        g[2] = f2;
+      }
+    }
+    __syncthreads();
   }
-}
-
-__global__ void mlp_clear_flags(unsigned* __restrict__ flags, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = 0u;
+  if (owner) {
+    double* st = rigid + 6 * (size_t)mine;
+    st[0] = x0;
+    st[1] = x1;
+    st[2] = th;
+    st[3] = v0;
+    st[4] = v1;
+    st[5] = om;
+    flags[mine] = fl[t];
+  }
 }
 
 // The norm vector of mlp_make_windows into kernel form; false if a std is
@@ -761,28 +856,21 @@ int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_s
 int mlp_coupled_rollout(mlp_handle* h, int32_t n_roll, int32_t n_steps, int32_t log_stride, int32_t window,
                         const double* body_dev, const float* u_seq_dev, const float* static_dev, int32_t n_static,
                         const float* norm, float z_max, double* rigid_dev, float* feat_dev, float* y_log_dev,
-                        float* wrench_log_dev, uint32_t* flags_dev, float* scratch_dev) {
+                        float* wrench_log_dev, uint32_t* flags_dev) {
   if (!h || !body_dev || !u_seq_dev || !static_dev || !norm || !rigid_dev || !feat_dev || !y_log_dev ||
-      !wrench_log_dev || !flags_dev || !scratch_dev)
+      !wrench_log_dev || !flags_dev)
     return SPH_E_INVAL;
-  if (window * 4 != kIn || n_roll < 1 || n_roll > h->maxB || log_stride < 1 || n_steps < 1) return SPH_E_INVAL;
-  if (n_static < 1 || n_static > kMaxStatic || n_static > window || !(z_max > 0.0f)) return SPH_E_INVAL;
+  if (window != kWin || n_roll < 1 || n_roll > h->maxB || log_stride < 1 || n_steps < 1) return SPH_E_INVAL;
+  if (n_static < 1 || n_static > kMaxStatic || !(z_max > 0.0f)) return SPH_E_INVAL;
   const long long T = ((long long)n_steps + log_stride - 1) / log_stride;
-  if (T < window || (long long)n_roll * T * 6 > 0x7fffffffLL) return SPH_E_INVAL;
+  if (T < window || (long long)n_roll * T * 6 > 0x7fffffffLL || (long long)n_roll * n_steps * 3 > 0x7fffffffLL)
+    return SPH_E_INVAL;
   WinNorm nm;
   if (!win_norm(norm, n_static, &nm)) return SPH_E_INVAL;
-  float* x = scratch_dev;
-  float* y = scratch_dev + (size_t)n_roll * kIn;
-  const unsigned xb = (unsigned)(((long long)n_roll * kIn + 255) / 256), rb = (unsigned)((n_roll + 63) / 64);
-  hipLaunchKernelGGL(mlp_clear_flags, dim3(rb), dim3(64), 0, h->stream, flags_dev, n_roll);
-  for (int k = window - 1; k < (int)T; ++k) {
-    hipLaunchKernelGGL(mlp_window_at, dim3(xb), dim3(256), 0, h->stream, feat_dev, static_dev, n_static, n_roll,
-                       (int)T, window, k, nm, z_max, x, flags_dev);
-    hipLaunchKernelGGL(mlp_forward_fused, dim3((n_roll + kRows - 1) / kRows), dim3(256), 0, h->stream, x, n_roll,
-                       h->at<bf16>(h->L.wb), h->at<float>(h->L.master), y);
-    hipLaunchKernelGGL(mlp_coupled_interval, dim3(rb), dim3(64), 0, h->stream, y, nm, body_dev, u_seq_dev,
-                       n_steps, log_stride, n_roll, (int)T, k, rigid_dev, feat_dev, y_log_dev, wrench_log_dev);
-  }
+  hipLaunchKernelGGL(mlp_coupled, dim3((n_roll + kRows - 1) / kRows), dim3(256), 0, h->stream, static_dev,
+                     n_static, n_roll, (int)T, nm, z_max, body_dev, u_seq_dev, n_steps, log_stride,
+                     h->at<bf16>(h->L.wb), h->at<float>(h->L.master), rigid_dev, feat_dev, y_log_dev,
+                     wrench_log_dev, flags_dev);
   MHIP(hipGetLastError());
   return SPH_OK;
 }

@@ -127,7 +127,6 @@ class Mlp:
         y = torch.full((R, T, 6), float("nan"), device=dev)
         w = torch.full((R, T, 3), float("nan"), device=dev)
         flags = torch.empty(R, dtype=torch.int32, device=dev)
-        scratch = torch.empty(R * 131, device=dev)
         nv = np.asarray(norm, np.float32)
         nm = (C.c_float * len(nv))(*[float(v) for v in nv])
         self._enter()
@@ -136,9 +135,9 @@ class Mlp:
                                          C.c_void_p(st.data_ptr()), int(st.shape[1]), nm, float(z_max),
                                          C.c_void_p(rigid.data_ptr()), C.c_void_p(feat.data_ptr()),
                                          C.c_void_p(y.data_ptr()), C.c_void_p(w.data_ptr()),
-                                         C.c_void_p(flags.data_ptr()), C.c_void_p(scratch.data_ptr())),
+                                         C.c_void_p(flags.data_ptr())),
               "mlp_coupled_rollout")
-        self._keep = [u, st, feat, rigid, bd, y, w, flags, scratch]
+        self._keep = [u, st, feat, rigid, bd, y, w, flags]
         self._leave()
         return dict(y=y, wrench=w, feat=feat, rigid=rigid, flags=flags)
 
