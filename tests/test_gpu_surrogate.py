@@ -12,8 +12,8 @@ The bar is SPH's own reproducibility.  The held-out tanks are simulated
 twice with the same shapes, sizes, fills and inputs, differing only in the
 initial lattice jitter (1 % of the spacing): set A and set B.  The
 per-channel NRMSE between A's and B's wrench is the noise floor, how far
-this weakly compressible SPH reproduces its own wrench (measured 0.85 /
-0.32 / 0.35 for F_x / F_y / torque on 64 held-out tanks; 0.34 / 0.14 / 0.16
+this weakly compressible SPH reproduces its own wrench (measured 0.83 /
+0.32 / 0.35 for F_x / F_y / torque on 64 held-out tanks; 0.29 / 0.12 / 0.14
 at full size, 2k-60k particles over 5,000 steps).  No predictor of the
 wrench from these inputs can do much better than about floor / sqrt(2)
 against one realization.  What is asserted:
