@@ -82,8 +82,19 @@ constexpr double kSkinOverH = 1.0;  // skin = h: a particle may move h/2 between
 template <int TP>
 constexpr int stage_f() { return TP >= 64 ? 416 : 384; }
 constexpr int kStageG = 128;
-constexpr int kListF = 64;        // in-support fluid neighbours listed per particle and pass
-constexpr int kListG = 32;        // in-support ghost neighbours listed per particle and pass
+// In-support neighbours listed per particle and pass in the force kernel's
+// LDS.  With the near-list radius 1.5 times the support, a near list that
+// fits (64) holds about 28 fluid neighbours inside the support at most, and
+// at h_s = h a particle has a few walls inside the wall support; more take
+// the per-lane path over the marked entries (or list in several passes
+// without near lists).
+constexpr int kListF = 48;        // fluid
+constexpr int kListG = 16;        // ghost
+// A variant's list capacity: at least one ballot round of its G lanes
+template <int G>
+constexpr int list_cap_f() { return kListF > G ? kListF : G; }
+template <int G>
+constexpr int list_cap_g() { return kListG > G ? kListG : G; }
 // Near lists, built at the first step after each rebuild: for every particle
 // the ordinals (positions in its candidate enumeration, one byte each) of
 // the candidates that can come within the support before the next rebuild.
@@ -984,9 +995,10 @@ __device__ __forceinline__ OrdMap ord_map(const TileLds<TP>& tl, int pl, bool gh
 // and append the LDS indices of those that pass `keep` to `lst` (ballot
 // compaction, order kept).  Stops before the list could overflow; returns
 // its length and advances c (both the same on the G lanes).
-template <int G, class F>
-__device__ __forceinline__ int list_pass(const OrdMap& m, int total, int l, int& c, int cap, unsigned short* lst,
-                                         F&& keep) {
+template <int G, int CAP, class F>
+__device__ __forceinline__ int list_pass(const OrdMap& m, int total, int l, int& c, unsigned short* lst, F&& keep) {
+  static_assert(CAP >= G, "a pass must hold one ballot round, or it never advances");
+  constexpr int cap = CAP;
   const int base = (int)(threadIdx.x & 63) - l;
   const unsigned below = (1u << l) - 1u;
   int cnt = 0;
@@ -1060,6 +1072,7 @@ struct NearWords {
     w2 = w3;
     return w;
   }
+  __device__ __forceinline__ unsigned word(int q) const { return q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3; }
 };
 
 // Calls f(e) for the staged candidates of lane l's entries of a near list of
@@ -1141,6 +1154,20 @@ __device__ __forceinline__ int near_pass_marked(NearWords<G, CAP>& nw, unsigned 
     }
   }
   return cnt;
+}
+
+// Calls f(e) for each entry of lane l's share of a near list whose mark bit
+// is set (bit 4q + b for entry 4(l + qG) + b), in bit order, with no list in
+// LDS: the path of a particle with more candidates inside the support than
+// its LDS list holds (the words must not have been consumed).
+template <int G, int CAP, class F>
+__device__ __forceinline__ void marked_visit(const NearWords<G, CAP>& nw, unsigned m, const OrdMap& map, F&& f) {
+  while (m) {
+    const int b = __builtin_ctz(m);
+    m &= m - 1u;
+    const unsigned w = nw.word(b >> 2);
+    f(map((int)((w >> (8 * (b & 3))) & 255u)));
+  }
 }
 
 // Compacts the entries of a near list of n entries that pass `keep` into
@@ -1509,6 +1536,10 @@ __device__ void rigid_step(DevRigid* rb, const DevRollout* ro, int tank, const d
 //   + 2 alpha h (w_ij . s_ij) / ((rho_i + rho_j)(r^2 + eps h^2))] grad_i W_ij
 //   + sum_g m [-2 P_i/rho_i^2 + (2 beta / (2 rho_i)) min(w_i . s_ig, 0)/(r^2 + eps h^2)] grad_i W_s3
 // The tank receives -m * (wall term) per pair, with torque arm g.
+// Occupancy: the 4-lane variant's 23 KB of LDS (stages and the in-support
+// lists, sized for the neighbour counts of h = 1.3 dx with room to spare)
+// and 79 VGPRs give six workgroups per CU; a register budget of seven waves
+// spills and was slower.
 template <int G, bool Bin>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) sph_force(const float2* __restrict__ pos,
                                                     const float2* __restrict__ vel,
@@ -1529,7 +1560,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
   constexpr int kStageF = stage_f<TP>();
   __shared__ float2 f_pos[kStageF], f_vel[kStageF], f_rp[kStageF];
   __shared__ float2 g_pos[kStageG];
-  __shared__ unsigned short f_list[TP][kListF], g_list[TP][kListG];
+  constexpr int kLF = list_cap_f<G>(), kLG = list_cap_g<G>();
+  __shared__ unsigned short f_list[TP][kLF], g_list[TP][kLG];
   __shared__ TileLds<TP> tl;
   __shared__ Seg sg;
   __shared__ double red[3][kBlock / 64];
@@ -1615,16 +1647,22 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
         const int nlf = tl.near[pl] & 255;
         if (nlf <= kNearF) {
           // the density kernel marked the listed candidates inside the support
-          const int cnt = near_pass_marked<G, kNearF>(nwf, marks, nlf, l, lst);
-          wave_sync();
-          for (int q = l; q < cnt; q += G) {
-            const int e = fm(lst[q]);
-            fluid(f_pos[e], f_vel[e], f_rp[e]);
+          const unsigned mf = marks & ((1u << kMarkGhostShift) - 1u);
+          const int nin = (int)group_sum<G>((float)__popc(mf));   // the same on the G lanes
+          if (nin <= kLF) {
+            const int cnt = near_pass_marked<G, kNearF>(nwf, marks, nlf, l, lst);
+            wave_sync();
+            for (int q = l; q < cnt; q += G) {
+              const int e = fm(lst[q]);
+              fluid(f_pos[e], f_vel[e], f_rp[e]);
+            }
+            wave_sync();
+          } else {
+            marked_visit<G, kNearF>(nwf, mf, fm, [&](int e) { fluid(f_pos[e], f_vel[e], f_rp[e]); });
           }
-          wave_sync();
         } else {
           int c = 0;
-          while (c < total) pairs(list_pass<G>(fm, total, l, c, kListF, lst, inside));
+          while (c < total) pairs(list_pass<G, kLF>(fm, total, l, c, lst, inside));
         }
       } else {
         visit<G, TP>(tl, pl, false, lo, off, l, [&](int j, int) { fluid_test(pos[j], vel[j], rp[j]); });
@@ -1662,13 +1700,19 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
         };
         const int nlg = (tl.near[pl] >> 8) & 255;
         if (nlg <= kNearG) {
-          const int cnt = near_pass_marked<G, kNearG>(nwg, marks >> kMarkGhostShift, nlg, l, lst);
-          wave_sync();
-          for (int q = l; q < cnt; q += G) ghost(g_pos[gm(lst[q])]);
-          wave_sync();
+          const unsigned mg = marks >> kMarkGhostShift;
+          const int nin = (int)group_sum<G>((float)__popc(mg));   // the same on the G lanes
+          if (nin <= kLG) {
+            const int cnt = near_pass_marked<G, kNearG>(nwg, mg, nlg, l, lst);
+            wave_sync();
+            for (int q = l; q < cnt; q += G) ghost(g_pos[gm(lst[q])]);
+            wave_sync();
+          } else {
+            marked_visit<G, kNearG>(nwg, mg, gm, [&](int e) { ghost(g_pos[e]); });
+          }
         } else {
           int c = 0;
-          while (c < total) walls(list_pass<G>(gm, total, l, c, kListG, lst, inside));
+          while (c < total) walls(list_pass<G, kLG>(gm, total, l, c, lst, inside));
         }
       } else {
         visit<G, TP>(tl, pl, true, glo, goff, l, [&](int j, int) {

@@ -376,6 +376,45 @@ def test_dense_cells_take_the_global_paths(lanes, near):
     sim.close()
 
 
+def _wide_wall(seed=5, layers=6, mult=3.0):
+    """The rectangular tank with the wall kernel's support h_s = 3h and six
+    boundary layers: up to 30 boundary particles inside a particle's wall
+    support while, for most particles by a wall, the boundary near list
+    (radius h_s + skin/2) still holds at most 32 (counted on the CPU: 104 of
+    the 1,600 particles have more than 16 in their support and a near list
+    that fits, 218 more than 8; 16 overflow the near list itself).  The force
+    kernel's LDS list of in-support wall candidates then overflows and its
+    per-lane path over the marked near-list entries runs."""
+    import dataclasses
+    dx = 0.0125
+    sc = W.plain_rect(seed, n_steps=50, dx=dx)
+    rng = np.random.default_rng(seed)
+    fluid, ghosts = W.rect_tank(1.0, 0.5, dx, int(round(0.25 / dx)), layers, rng, 0.01)
+    pad = (layers + 1) * dx
+    p = dataclasses.replace(sc.params, h_spiky=mult * sc.params.h,
+                            domain_min=(-0.5 - pad, -0.25 - pad), domain_max=(0.5 + pad, 0.25 + pad))
+    return dataclasses.replace(sc, name="wide_wall", params=p, pos=fluid.astype(np.float32),
+                               vel=np.zeros_like(fluid, np.float32), ghosts=ghosts.astype(np.float32))
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_wide_wall_support_takes_the_marked_path(lanes):
+    sc = _wide_wall()
+    sim = _sim(sc, True)
+    sim.set_lanes(lanes)
+    _rhs_compare(sc, sim, O.state_from_scenario(sc))
+    n = 50
+    sim.rollout(n, torch.as_tensor(sc.u_seq[:n]))
+    s, w, rig, _, step = sim.get_state()
+    assert step == n and sim.status() == 0
+    st = O.state_from_scenario(sc)
+    O.rollout(sc.params, st, sc.ghosts.astype(np.float64), n, sc.u_seq[:n])
+    err = np.sqrt(((s.cpu().numpy().astype(np.float64) - st.s) ** 2).sum(1)).max()
+    print("wide wall lanes", lanes, "pos err / L", err / sc.tank_size)
+    assert err <= 1e-3 * sc.tank_size
+    sim.close()
+
+
 @pytest.mark.parametrize("lanes", [8, 32])
 def test_rhs_parity_on_a_large_tank(lanes):
     # 409,600 fluid particles in ~55,000 cells: the cell list comes from the
