@@ -1075,26 +1075,11 @@ struct NearWords {
   __device__ __forceinline__ unsigned word(int q) const { return q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3; }
 };
 
-// Calls f(e) for the staged candidates of lane l's entries of a near list of
-// n entries (consumes the words).
-template <int G, int CAP, class F>
-__device__ __forceinline__ void near_visit(NearWords<G, CAP>& nw, int n, int l, const OrdMap& m, F&& f) {
-#pragma unroll
-  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
-    unsigned word = nw.pop();
-    const int i0 = 4 * (l + q * G);
-    if (i0 < n)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (i0 + b < n) f(m((int)(word & 255u)));
-        word >>= 8;
-      }
-  }
-}
-
-// Like near_visit, for every entry of lane l's share of the list: calls
-// f(e), which returns whether the candidate lies inside the support, and
-// returns the lane's marks (bit 4q + b for entry 4(l + qG) + b).
+// For every entry of lane l's share of a near list of n entries (lane l
+// holds words l, l + G, ...; the words are consumed): calls f(e) with the
+// LDS index of the staged candidate, which returns whether the candidate
+// lies inside the support, and returns the lane's marks (bit 4q + b for
+// entry 4(l + qG) + b).
 template <int G, int CAP, class F>
 __device__ __forceinline__ unsigned near_visit_marks(NearWords<G, CAP>& nw, int n, int l, const OrdMap& m, F&& f) {
   unsigned marks = 0u;
@@ -1128,32 +1113,28 @@ __device__ __forceinline__ unsigned lds_list_marks(const unsigned char* lst, int
   return marks;
 }
 
-// Compacts, from a near list and the marks the density kernel wrote for it
-// at the same positions, the ordinals of the candidates inside the support
-// into lst (in ballot-round order, the order near_pass gives); returns the
-// count, the same on the G lanes.  No candidate is loaded or tested.
+// Lists, from a near list and the marks the density kernel wrote for it at
+// the same positions, the ordinals of the candidates inside the support:
+// lane l writes its own marked entries, in bit order, from the sum of the
+// counts of the group's lanes before it on (an exclusive scan over the G
+// lanes); the group's total is the caller's.  No candidate is loaded or
+// tested, and the words are not consumed.
 template <int G, int CAP>
-__device__ __forceinline__ int near_pass_marked(NearWords<G, CAP>& nw, unsigned marks, int n, int l,
-                                                unsigned short* lst) {
-  const int base = (int)(threadIdx.x & 63) - l;
-  const unsigned below = (1u << l) - 1u;
-  const int rounds = ((n + 3) / 4 + G - 1) / G;   // the same on the G lanes
-  int cnt = 0;
+__device__ __forceinline__ void near_list_marked(const NearWords<G, CAP>& nw, unsigned marks, int l,
+                                                 unsigned short* lst) {
+  const int n = __popc(marks);
+  int incl = n;
 #pragma unroll
-  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
-    unsigned word = nw.pop();
-    if (q < rounds) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const bool in = (marks >> (4 * q + b)) & 1u;
-        const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
-        if (in) lst[cnt + __popc(msk & below)] = (unsigned short)(word & 255u);
-        word >>= 8;
-        cnt += __popc(msk);
-      }
-    }
+  for (int off = 1; off < G; off <<= 1) {
+    const int y = __shfl_up(incl, off, G);
+    if (l >= off) incl += y;
   }
-  return cnt;
+  unsigned short* dst = lst + (incl - n);
+  while (marks) {
+    const int b = __builtin_ctz(marks);
+    marks &= marks - 1u;
+    *dst++ = (unsigned short)((nw.word(b >> 2) >> (8 * (b & 3))) & 255u);
+  }
 }
 
 // Calls f(e) for each entry of lane l's share of a near list whose mark bit
@@ -1168,39 +1149,6 @@ __device__ __forceinline__ void marked_visit(const NearWords<G, CAP>& nw, unsign
     const unsigned w = nw.word(b >> 2);
     f(map((int)((w >> (8 * (b & 3))) & 255u)));
   }
-}
-
-// Compacts the entries of a near list of n entries that pass `keep` into
-// lst (LDS indices, in ballot-round order); returns the count (<= n), the
-// same on the G lanes.
-template <int G, int CAP, class F>
-__device__ __forceinline__ int near_pass(NearWords<G, CAP>& nw, int n, int l, const OrdMap& m,
-                                         unsigned short* lst, F&& keep) {
-  const int base = (int)(threadIdx.x & 63) - l;
-  const unsigned below = (1u << l) - 1u;
-  const int rounds = ((n + 3) / 4 + G - 1) / G;   // the same on the G lanes
-  int cnt = 0;
-#pragma unroll
-  for (int q = 0; q < NearWords<G, CAP>::kMaxW; ++q) {
-    unsigned word = nw.pop();
-    if (q < rounds) {
-      const int i0 = 4 * (l + q * G);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int e = 0;
-        bool in = false;
-        if (i0 + b < n) {
-          e = m((int)(word & 255u));
-          in = keep(e);
-        }
-        word >>= 8;
-        const unsigned msk = (unsigned)(__ballot(in) >> base) & group_bits<G>();
-        if (in) lst[cnt + __popc(msk & below)] = (unsigned short)e;
-        cnt += __popc(msk);
-      }
-    }
-  }
-  return cnt;
 }
 
 // --------------------------------------------------------------------------
@@ -1650,9 +1598,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
           const unsigned mf = marks & ((1u << kMarkGhostShift) - 1u);
           const int nin = (int)group_sum<G>((float)__popc(mf));   // the same on the G lanes
           if (nin <= kLF) {
-            const int cnt = near_pass_marked<G, kNearF>(nwf, marks, nlf, l, lst);
+            near_list_marked<G, kNearF>(nwf, mf, l, lst);
             wave_sync();
-            for (int q = l; q < cnt; q += G) {
+            for (int q = l; q < nin; q += G) {
               const int e = fm(lst[q]);
               fluid(f_pos[e], f_vel[e], f_rp[e]);
             }
@@ -1703,9 +1651,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
           const unsigned mg = marks >> kMarkGhostShift;
           const int nin = (int)group_sum<G>((float)__popc(mg));   // the same on the G lanes
           if (nin <= kLG) {
-            const int cnt = near_pass_marked<G, kNearG>(nwg, mg, nlg, l, lst);
+            near_list_marked<G, kNearG>(nwg, mg, l, lst);
             wave_sync();
-            for (int q = l; q < cnt; q += G) ghost(g_pos[gm(lst[q])]);
+            for (int q = l; q < nin; q += G) ghost(g_pos[gm(lst[q])]);
             wave_sync();
           } else {
             marked_visit<G, kNearG>(nwg, mg, gm, [&](int e) { ghost(g_pos[e]); });
