@@ -72,8 +72,8 @@ TRAFFIC = {"src_sha1": "edc4a7216d9360e4305a2ec70cea0791bf63e82e",
 # The same for the 256-tank batch (4 lanes per particle, near lists: the
 # autotuner's choice there), from the counter runs of
 # profiles/hbm_traffic_batch_256_random_tanks.md.
-TRAFFIC_BATCH = {"src_sha1": "2d7d819072c8ee883c1bc2bdf46f0f71aabb47a9",
-                 "bytes_per_launch": {"sph_force/4/1": 1567073647, "sph_density/4/1": 1664810780}}
+TRAFFIC_BATCH = {"src_sha1": "b7ecaf84fe2e8bd058b904413ea6024a5e35a7ba",
+                 "bytes_per_launch": {"sph_force/4/1": 1567141121, "sph_density/4/1": 1664766378}}
 
 # The binding ceiling of the step (VALU issue, each unordered fluid pair
 # evaluated once): about 590 issue slots per fluid particle-step against
