@@ -333,8 +333,9 @@ def paper_leg(relax_cycles: int = 60, relax_steps: int = 50, max_steps: int = 0)
         n = force.shape[0] * per
         if secs is not None:
             n = min(n, int(round(secs / sc.params.dt)))
-        if max_steps > 0:
-            n = min(n, max_steps)
+        if max_steps > 0 and max_steps < n:
+            n = max_steps
+            paper_s = None   # a shortened run is no like-for-like comparison
         u = np.zeros((n, 3), np.float32)
         u[:, :2] = np.repeat(force, per, axis=0)[:n]
         uu = torch.as_tensor(u, device=dev)
