@@ -467,7 +467,7 @@ int mlp_make_windows(const float* feat_dev, const float* static_dev, int32_t n_s
  * flags_dev [n_roll] is cleared, then receives MLP_FLAG_OUT_OF_RANGE for a
  * rollout any of whose window inputs lay further than z_max standard
  * deviations from the training mean: it left the data the network was fitted
- * on, and the caller runs it on SPH instead.  One workgroup advances 64
+ * on, and the caller runs it on SPH instead.  One workgroup advances 16
  * rollouts through every interval in one launch (the last 32 samples in
  * LDS).  SPH_E_INVAL for window != 32, n_roll outside
  * [1, max_batch], T < window, n_static outside mlp_make_windows' range,

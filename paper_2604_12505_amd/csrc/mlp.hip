@@ -162,13 +162,17 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
 constexpr int kRows = 64;
 constexpr int kLdsStride = kHid + 8;
 
-// The network on the kRows rows staged in buf[0] as BF16: the four hidden
-// layers on MFMA (ping-pong between the two buffers), then the head, whose
-// result for row r and output o goes to out(r, o, value) (called by thread
-// 4 r).  All 256 threads; ends without a barrier.
-template <class Out>
-__device__ __forceinline__ void net_rows(bf16 (*buf)[kRows * kLdsStride], const bf16* __restrict__ wb,
+// The network on the ROWS rows (a multiple of 16, at most kRows) staged in
+// buf[0] as BF16: the four hidden layers on MFMA (ping-pong between the two
+// buffers; each of the 4 waves computes ROWS x 64 outputs of a layer as
+// ROWS/16 x 4 MFMA tiles), then the head, whose result for row r and output
+// o goes to out(r, o, value) (called by thread 4 r).  All 256 threads; ends
+// without a barrier.
+template <int ROWS, class Out>
+__device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const bf16* __restrict__ wb,
                                          const float* __restrict__ master, Out&& out) {
+  static_assert(ROWS % 16 == 0 && ROWS <= kRows, "row tiles of 16");
+  constexpr int RT = ROWS / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int cur = 0;
   const int li = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
@@ -177,29 +181,24 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[kRows * kLdsStride], const 
     const int K = kDims[l];
     const bf16* W = wb + kOffW[l];
     const float* bias = master + kOffB[l];
-    floatx4 acc[4][4];
-    for (int r = 0; r < 4; ++r)
+    floatx4 acc[RT][4];
+    for (int r = 0; r < RT; ++r)
       for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // the weights of the next k step are loaded while this one's products
-    // run (a lone workgroup per CU otherwise waits on every L2 round trip)
-    bf16x8 b[4], bn[4];
-    for (int c = 0; c < 4; ++c) b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + kq);
+#pragma unroll 2
     for (int k0 = 0; k0 < K; k0 += 32) {
-      if (k0 + 32 < K)
-        for (int c = 0; c < 4; ++c)
-          bn[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + 32 + kq);
-      bf16x8 a[4];
-      for (int r = 0; r < 4; ++r)
+      bf16x8 a[RT], b[4];
+      for (int r = 0; r < RT; ++r)
         a[r] = *reinterpret_cast<const bf16x8*>(&buf[cur][(r * 16 + li) * kLdsStride + k0 + kq]);
-      for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c)
+        b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + kq);
+      for (int r = 0; r < RT; ++r)
         for (int c = 0; c < 4; ++c)
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
-      for (int c = 0; c < 4; ++c) b[c] = bn[c];
     }
     for (int c = 0; c < 4; ++c) {
       const int n = n0 + c * 16 + li;
       const float bn = bias[n];
-      for (int r = 0; r < 4; ++r)
+      for (int r = 0; r < RT; ++r)
         for (int e = 0; e < 4; ++e)
           buf[1 - cur][(r * 16 + rq + e) * kLdsStride + n] = (bf16)gelu(acc[r][c][e] + bn);
     }
@@ -208,7 +207,8 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[kRows * kLdsStride], const 
   }
   // the head: 4 lanes per row, each over 64 of the 256 inputs for the three
   // outputs at once, then the sum over the 4 lanes
-  static_assert(kRows * 4 == 256 && kOut == 3, "head layout");
+  static_assert(kOut == 3, "head layout");
+  if (threadIdx.x >= 4 * ROWS) return;
   const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
   const bf16* a = &buf[cur][r * kLdsStride + p * 64];
   const bf16* w4 = wb + kOffW[4] + p * 64;
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict
     buf[0][r * kLdsStride + k] = (bf16)v;
   }
   __syncthreads();
-  net_rows(buf, wb, master, [&](int r, int o, float v) {
+  net_rows<kRows>(buf, wb, master, [&](int r, int o, float v) {
     const int m = row0 + r;
     if (m < B) y[(size_t)m * kOut + o] = v;
   });
@@ -441,7 +441,12 @@ __global__ void mlp_windows(const float* __restrict__ feat, const float* __restr
 // samples of 4 channels.
 constexpr int kWin = kIn / 4;
 
-// The rigid body of kRows rollouts per workgroup driven by the network, all
+// Rollouts per workgroup of the coupled rollout: one row tile, so that a few
+// hundred rollouts spread over as many CUs (each interval's network work per
+// wave is a quarter of a 64-row tile's).
+constexpr int kCRows = 16;
+
+// The rigid body of kCRows rollouts per workgroup driven by the network, all
 // log intervals in one launch (the rollouts are independent).  Per interval
 // k: the window of samples k - 31 .. k, standardised from a ring of the last
 // 32 samples in LDS (mlp_windows' layout; an input further than z_max
@@ -459,19 +464,19 @@ __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ sta
                                                    double* __restrict__ rigid, float* __restrict__ feat,
                                                    float* __restrict__ y_log, float* __restrict__ w_log,
                                                    unsigned* __restrict__ flags) {
-  __shared__ __align__(16) bf16 buf[2][kRows * kLdsStride];
-  __shared__ float ring[kRows][kWin][3];
-  __shared__ float hout[kRows * kOut];
-  __shared__ unsigned fl[kRows];
-  const int row0 = blockIdx.x * kRows, t = threadIdx.x;
-  for (int e = t; e < kRows * kWin * 3; e += 256) {
+  __shared__ __align__(16) bf16 buf[2][kCRows * kLdsStride];
+  __shared__ float ring[kCRows][kWin][3];
+  __shared__ float hout[kCRows * kOut];
+  __shared__ unsigned fl[kCRows];
+  const int row0 = blockIdx.x * kCRows, t = threadIdx.x;
+  for (int e = t; e < kCRows * kWin * 3; e += 256) {
     const int r = e / (kWin * 3), q = e - r * (kWin * 3);
     const int m = row0 + r;
     ring[r][q / 3][q % 3] = m < R ? feat[((size_t)m * T + q / 3) * 3 + q % 3] : 0.0f;
   }
-  if (t < kRows) fl[t] = 0u;
+  if (t < kCRows) fl[t] = 0u;
   const int mine = row0 + t;
-  const bool owner = t < kRows && mine < R;
+  const bool owner = t < kCRows && mine < R;
   double x0 = 0.0, x1 = 0.0, th = 0.0, v0 = 0.0, v1 = 0.0, om = 0.0, mass = 1.0, inertia = 1.0, dt = 0.0;
   if (owner) {
     const double* st = rigid + 6 * (size_t)mine;
@@ -487,7 +492,7 @@ __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ sta
   }
   __syncthreads();
   for (int k = kWin - 1; k < T; ++k) {
-    for (int e = t; e < kRows * kIn; e += 256) {
+    for (int e = t; e < kCRows * kIn; e += 256) {
       const int r = e / kIn, kk = e - r * kIn;
       const int ti = kk >> 2, c = kk & 3;
       const int m = row0 + r;
@@ -501,7 +506,7 @@ __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ sta
       buf[0][r * kLdsStride + kk] = (bf16)z;
     }
     __syncthreads();
-    net_rows(buf, wb, master, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
+    net_rows<kCRows>(buf, wb, master, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
     __syncthreads();
     if (owner) {
       double F[3];
@@ -867,7 +872,7 @@ int mlp_coupled_rollout(mlp_handle* h, int32_t n_roll, int32_t n_steps, int32_t 
     return SPH_E_INVAL;
   WinNorm nm;
   if (!win_norm(norm, n_static, &nm)) return SPH_E_INVAL;
-  hipLaunchKernelGGL(mlp_coupled, dim3((n_roll + kRows - 1) / kRows), dim3(256), 0, h->stream, static_dev,
+  hipLaunchKernelGGL(mlp_coupled, dim3((n_roll + kCRows - 1) / kCRows), dim3(256), 0, h->stream, static_dev,
                      n_static, n_roll, (int)T, nm, z_max, body_dev, u_seq_dev, n_steps, log_stride,
                      h->at<bf16>(h->L.wb), h->at<float>(h->L.master), rigid_dev, feat_dev, y_log_dev,
                      wrench_log_dev, flags_dev);
