@@ -1,9 +1,13 @@
 """Builds the FP64 oracle library (test infrastructure only) with gcc.
 
 ``python oracle/build.py --sanitize`` builds it with AddressSanitizer and
-UndefinedBehaviorSanitizer instead (host code; run the CPU tests with the
-sanitizer runtimes preloaded, as the design doc describes), and a plain
-``python oracle/build.py`` restores the normal build."""
+UndefinedBehaviorSanitizer instead (host code).  The CPU tests then run with
+the sanitizer runtimes preloaded into the interpreter:
+
+    LD_PRELOAD="$(gcc -print-file-name=libasan.so) $(gcc -print-file-name=libubsan.so)" \
+    ASAN_OPTIONS=detect_leaks=0 python -m pytest tests -m "not gpu"
+
+and a plain ``python oracle/build.py`` restores the normal build."""
 from __future__ import annotations
 
 import os
