@@ -166,24 +166,28 @@ constexpr int kLdsStride = kHid + 8;
 // buf[0] as BF16: the four hidden layers on MFMA (ping-pong between the two
 // buffers; each of the 4 waves computes ROWS x 64 outputs of a layer as
 // ROWS/16 x 4 MFMA tiles), then the head, whose result for row r and output
-// o goes to out(r, o, value) (called by thread 4 r).  All 256 threads; ends
-// without a barrier.
+// o goes to out(r, o, value) (called by thread 4 r).  w4s is the head's
+// weight matrix (3 x 256) staged in LDS by the caller.  All 256 threads;
+// ends without a barrier.
 template <int ROWS, class Out>
 __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const bf16* __restrict__ wb,
-                                         const float* __restrict__ master, Out&& out) {
+                                         const float* __restrict__ master, const bf16* w4s, Out&& out) {
   static_assert(ROWS % 16 == 0 && ROWS <= kRows, "row tiles of 16");
   constexpr int RT = ROWS / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int cur = 0;
   const int li = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
   const int n0 = wave * 64;
+  // the head's biases, fetched now so that their round trip is hidden
+  const float hb0 = master[kOffB[4]], hb1 = master[kOffB[4] + 1], hb2 = master[kOffB[4] + 2];
   for (int l = 0; l < 4; ++l) {
-    const int K = kDims[l];
     const bf16* W = wb + kOffW[l];
-    const float* bias = master + kOffB[l];
+    float bn[4];   // this lane's four biases, fetched before the products
+    for (int c = 0; c < 4; ++c) bn[c] = master[kOffB[l] + n0 + c * 16 + li];
     floatx4 acc[RT][4];
     for (int r = 0; r < RT; ++r)
       for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int K = kDims[l];
 #pragma unroll 2
     for (int k0 = 0; k0 < K; k0 += 32) {
       bf16x8 a[RT], b[4];
@@ -197,10 +201,9 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
     }
     for (int c = 0; c < 4; ++c) {
       const int n = n0 + c * 16 + li;
-      const float bn = bias[n];
       for (int r = 0; r < RT; ++r)
         for (int e = 0; e < 4; ++e)
-          buf[1 - cur][(r * 16 + rq + e) * kLdsStride + n] = (bf16)gelu(acc[r][c][e] + bn);
+          buf[1 - cur][(r * 16 + rq + e) * kLdsStride + n] = (bf16)gelu(acc[r][c][e] + bn[c]);
     }
     __syncthreads();
     cur = 1 - cur;
@@ -211,7 +214,7 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
   if (threadIdx.x >= 4 * ROWS) return;
   const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
   const bf16* a = &buf[cur][r * kLdsStride + p * 64];
-  const bf16* w4 = wb + kOffW[4] + p * 64;
+  const bf16* w4 = w4s + p * 64;
   float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
   for (int k = 0; k < 64; k += 8) {
     const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
@@ -231,10 +234,18 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
     s2 += __shfl_xor(s2, off, 64);
   }
   if (p == 0) {
-    out(r, 0, s0 + master[kOffB[4]]);
-    out(r, 1, s1 + master[kOffB[4] + 1]);
-    out(r, 2, s2 + master[kOffB[4] + 2]);
+    out(r, 0, s0 + hb0);
+    out(r, 1, s1 + hb1);
+    out(r, 2, s2 + hb2);
   }
+}
+
+// The head's weights (3 x 256 BF16, 96 fragments of 8) into LDS; threads
+// 0-95.  The caller's barrier publishes them.
+__device__ __forceinline__ void stage_head(const bf16* __restrict__ wb, bf16* w4s) {
+  if (threadIdx.x < kOut * kHid / 8)
+    *reinterpret_cast<bf16x8*>(w4s + 8 * threadIdx.x) =
+        *reinterpret_cast<const bf16x8*>(wb + kOffW[4] + 8 * threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict__ x, int B,
@@ -242,15 +253,35 @@ __global__ void __launch_bounds__(256) mlp_forward_fused(const float* __restrict
                                                          const float* __restrict__ master,
                                                          float* __restrict__ y) {
   __shared__ __align__(16) bf16 buf[2][kRows * kLdsStride];
+  __shared__ __align__(16) bf16 w4s[kOut * kHid];
   const int row0 = blockIdx.x * kRows;
-  for (int e = threadIdx.x; e < kRows * kIn; e += 256) {
-    int r = e / kIn, k = e - r * kIn;
-    int m = row0 + r;
-    float v = m < B ? x[(size_t)m * kIn + k] : 0.0f;
-    buf[0][r * kLdsStride + k] = (bf16)v;
+  // the tile's inputs, 4 floats per load and all of a thread's loads issued
+  // before the first is used (rows past B read as zeros)
+  constexpr int kQ = kRows * kIn / 4 / 256;
+  const float* xt = x + (size_t)row0 * kIn;
+  float4 xv[kQ];
+  if (row0 + kRows <= B) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) xv[i] = *reinterpret_cast<const float4*>(xt + 4 * ((int)threadIdx.x + 256 * i));
+  } else {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int e = 4 * ((int)threadIdx.x + 256 * i);
+      xv[i] = row0 + e / kIn < B ? *reinterpret_cast<const float4*>(xt + e) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  stage_head(wb, w4s);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int e = 4 * ((int)threadIdx.x + 256 * i), r = e / kIn, k = e - r * kIn;
+    bf16* d = &buf[0][r * kLdsStride + k];
+    d[0] = (bf16)xv[i].x;
+    d[1] = (bf16)xv[i].y;
+    d[2] = (bf16)xv[i].z;
+    d[3] = (bf16)xv[i].w;
   }
   __syncthreads();
-  net_rows<kRows>(buf, wb, master, [&](int r, int o, float v) {
+  net_rows<kRows>(buf, wb, master, w4s, [&](int r, int o, float v) {
     const int m = row0 + r;
     if (m < B) y[(size_t)m * kOut + o] = v;
   });
@@ -468,7 +499,9 @@ __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ sta
   __shared__ float ring[kCRows][kWin][3];
   __shared__ float hout[kCRows * kOut];
   __shared__ unsigned fl[kCRows];
+  __shared__ __align__(16) bf16 w4s[kOut * kHid];
   const int row0 = blockIdx.x * kCRows, t = threadIdx.x;
+  stage_head(wb, w4s);
   for (int e = t; e < kCRows * kWin * 3; e += 256) {
     const int r = e / (kWin * 3), q = e - r * (kWin * 3);
     const int m = row0 + r;
@@ -506,7 +539,7 @@ __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ sta
       buf[0][r * kLdsStride + kk] = (bf16)z;
     }
     __syncthreads();
-    net_rows<kCRows>(buf, wb, master, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
+    net_rows<kCRows>(buf, wb, master, w4s, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
     __syncthreads();
     if (owner) {
       double F[3];
