@@ -48,11 +48,15 @@ __device__ __forceinline__ float sigmoid2(float u) {
 }
 
 // The tanh form x/2 (1 + tanh(u)), u = sqrt(2/pi)(x + 0.044715 x^3), written
-// as x s with s = 1 / (1 + e^(-2u)) (1 + tanh(u) = 2 / (1 + e^(-2u))):
-// branch-free, about 8 instructions.
+// as x s with s = 1 / (1 + e^(-2u)) (1 + tanh(u) = 2 / (1 + e^(-2u))), and
+// -2u log2(e) = x (A + B x^2): branch-free, 5 instructions and the hardware
+// exponential and reciprocal.
+constexpr float kGeluA = -2.0f * kLog2e * kGeluK;
+constexpr float kGeluB = kGeluA * kGeluC;
+
 __device__ __forceinline__ float gelu(float x) {
-  const float u = kGeluK * x * fmaf(kGeluC, x * x, 1.0f);
-  return x * sigmoid2(u);
+  const float v = x * fmaf(kGeluB, x * x, kGeluA);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(v));
 }
 
 // Its derivative, s + 2 x s (1 - s) u'(x) (the tanh form's
@@ -162,6 +166,89 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
 constexpr int kRows = 64;
 constexpr int kLdsStride = kHid + 8;
 
+// The products of a layer are taken with the weights as the first MFMA
+// operand and the activations as the second, so that acc[r][c] holds, in
+// lane l, outputs n0 + 16 c + rq .. + 3 (rq = 4 (l / 16)) of row 16 r +
+// l % 16: four consecutive outputs of one row, stored as one 8-byte word.
+// Bias + GELU of a layer's ROWS x 64 outputs of this wave into dst (BF16);
+// bn[c] holds the biases of outputs n0 + 16 c + rq .. + 3.
+template <int RT>
+__device__ __forceinline__ void layer_out(const floatx4 (&acc)[RT][4], const float4 (&bn)[4], bf16* dst, int n0,
+                                          int li, int rq) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  for (int c = 0; c < 4; ++c)
+    for (int r = 0; r < RT; ++r) {
+      bf16x4 v;
+      v[0] = (bf16)gelu(acc[r][c][0] + bn[c].x);
+      v[1] = (bf16)gelu(acc[r][c][1] + bn[c].y);
+      v[2] = (bf16)gelu(acc[r][c][2] + bn[c].z);
+      v[3] = (bf16)gelu(acc[r][c][3] + bn[c].w);
+      *reinterpret_cast<bf16x4*>(&dst[(r * 16 + li) * kLdsStride + n0 + c * 16 + rq]) = v;
+    }
+}
+
+// This lane's biases of layer l (see layer_out).
+__device__ __forceinline__ void load_bias(float4 (&bn)[4], const float* __restrict__ master, int l, int n0, int rq) {
+  for (int c = 0; c < 4; ++c) bn[c] = *reinterpret_cast<const float4*>(master + kOffB[l] + n0 + c * 16 + rq);
+}
+
+// The weight fragments of k step ks of a layer with K inputs (W its matrix)
+// for this lane: columns n0 + 16 c + li, inputs 32 ks + kq .. + 7.
+template <int K>
+__device__ __forceinline__ void load_w(bf16x8 (&b)[4], const bf16* __restrict__ W, int ks, int n0, int li, int kq) {
+  for (int c = 0; c < 4; ++c)
+    b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + ks * 32 + kq);
+}
+
+// Weight fragments are requested this many k steps ahead of their use.
+constexpr int kAhead = 2;
+
+template <int L>
+constexpr int layer_in() { return L == 0 ? kIn : kHid; }
+
+// Hidden layer L of a full row tile (kRows rows, RT = 4) with the weight
+// loads software-pipelined: pre holds the fragments of this layer's first
+// kAhead k steps and bn its biases, both requested before the previous
+// layer's epilogue; k step ks requests step ks + kAhead; before this
+// layer's own epilogue the next layer's first steps and biases are
+// requested, so that their round trip overlaps the GELU work.
+template <int L>
+__device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], const bf16* __restrict__ wb,
+                                           const float* __restrict__ master, bf16x8 (&pre)[kAhead][4],
+                                           float4 (&bn)[4], int n0, int li, int kq, int rq) {
+  constexpr int RT = kRows / 16, K = layer_in<L>(), KS = K / 32;
+  static_assert(KS > kAhead, "the prefetch distance fits the layer");
+  const bf16* W = wb + kOffW[L];
+  const bf16* src = buf[L & 1];
+  floatx4 acc[RT][4];
+  for (int r = 0; r < RT; ++r)
+    for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 b[KS][4];
+#pragma unroll
+  for (int s = 0; s < kAhead; ++s)
+    for (int c = 0; c < 4; ++c) b[s][c] = pre[s][c];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks + kAhead < KS) load_w<K>(b[ks + kAhead], W, ks + kAhead, n0, li, kq);
+    bf16x8 a[RT];
+    for (int r = 0; r < RT; ++r)
+      a[r] = *reinterpret_cast<const bf16x8*>(&src[(r * 16 + li) * kLdsStride + ks * 32 + kq]);
+    for (int r = 0; r < RT; ++r)
+      for (int c = 0; c < 4; ++c)
+        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks][c], a[r], acc[r][c], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);   // keep each step's requests in its own step
+  }
+  const float4 bl[4] = {bn[0], bn[1], bn[2], bn[3]};
+  if constexpr (L < 3) {
+    constexpr int KN = layer_in<L + 1>();
+#pragma unroll
+    for (int s = 0; s < kAhead; ++s) load_w<KN>(pre[s], wb + kOffW[L + 1], s, n0, li, kq);
+    load_bias(bn, master, L + 1, n0, rq);
+  }
+  layer_out<RT>(acc, bl, buf[1 - (L & 1)], n0, li, rq);
+  __syncthreads();
+}
+
 // The network on the ROWS rows (a multiple of 16, at most kRows) staged in
 // buf[0] as BF16: the four hidden layers on MFMA (ping-pong between the two
 // buffers; each of the 4 waves computes ROWS x 64 outputs of a layer as
@@ -175,38 +262,50 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
   static_assert(ROWS % 16 == 0 && ROWS <= kRows, "row tiles of 16");
   constexpr int RT = ROWS / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int cur = 0;
   const int li = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
   const int n0 = wave * 64;
   // the head's biases, fetched now so that their round trip is hidden
   const float hb0 = master[kOffB[4]], hb1 = master[kOffB[4] + 1], hb2 = master[kOffB[4] + 2];
-  for (int l = 0; l < 4; ++l) {
-    const bf16* W = wb + kOffW[l];
-    float bn[4];   // this lane's four biases, fetched before the products
-    for (int c = 0; c < 4; ++c) bn[c] = master[kOffB[l] + n0 + c * 16 + li];
-    floatx4 acc[RT][4];
-    for (int r = 0; r < RT; ++r)
-      for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int K = kDims[l];
+  int cur = 0;
+  if constexpr (ROWS == kRows) {
+    // a full tile (inference): the pipelined layers
+    bf16x8 pre[kAhead][4];
+    float4 bn[4];
+#pragma unroll
+    for (int s = 0; s < kAhead; ++s) load_w<kIn>(pre[s], wb + kOffW[0], s, n0, li, kq);
+    load_bias(bn, master, 0, n0, rq);
+    layer_pipe<0>(buf, wb, master, pre, bn, n0, li, kq, rq);
+    layer_pipe<1>(buf, wb, master, pre, bn, n0, li, kq, rq);
+    layer_pipe<2>(buf, wb, master, pre, bn, n0, li, kq, rq);
+    layer_pipe<3>(buf, wb, master, pre, bn, n0, li, kq, rq);
+  } else {
+    // a small row tile inside the coupled rollout's time loop: the weight
+    // fragments are requested per k step (requests made ahead, invariant
+    // over the time loop, would be hoisted out of it into far more
+    // registers than a lane has)
+    for (int l = 0; l < 4; ++l) {
+      const bf16* W = wb + kOffW[l];
+      float4 bn[4];   // this lane's biases, fetched before the products
+      load_bias(bn, master, l, n0, rq);
+      floatx4 acc[RT][4];
+      for (int r = 0; r < RT; ++r)
+        for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int K = kDims[l];
 #pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      bf16x8 a[RT], b[4];
-      for (int r = 0; r < RT; ++r)
-        a[r] = *reinterpret_cast<const bf16x8*>(&buf[cur][(r * 16 + li) * kLdsStride + k0 + kq]);
-      for (int c = 0; c < 4; ++c)
-        b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + kq);
-      for (int r = 0; r < RT; ++r)
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a[RT], b[4];
+        for (int r = 0; r < RT; ++r)
+          a[r] = *reinterpret_cast<const bf16x8*>(&buf[cur][(r * 16 + li) * kLdsStride + k0 + kq]);
         for (int c = 0; c < 4; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+          b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + kq);
+        for (int r = 0; r < RT; ++r)
+          for (int c = 0; c < 4; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[c], a[r], acc[r][c], 0, 0, 0);
+      }
+      layer_out<RT>(acc, bn, buf[1 - cur], n0, li, rq);
+      __syncthreads();
+      cur = 1 - cur;
     }
-    for (int c = 0; c < 4; ++c) {
-      const int n = n0 + c * 16 + li;
-      for (int r = 0; r < RT; ++r)
-        for (int e = 0; e < 4; ++e)
-          buf[1 - cur][(r * 16 + rq + e) * kLdsStride + n] = (bf16)gelu(acc[r][c][e] + bn[c]);
-    }
-    __syncthreads();
-    cur = 1 - cur;
   }
   // the head: 4 lanes per row, each over 64 of the 256 inputs for the three
   // outputs at once, then the sum over the 4 lanes
