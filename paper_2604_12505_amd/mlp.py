@@ -71,6 +71,19 @@ class Mlp:
         self._leave()
         return y
 
+    def launch(self, x: torch.Tensor, out: torch.Tensor) -> None:
+        """forward() without the hand-over between the caller's stream and the
+        network's: enqueues the inference launch on the network's stream only.
+        x (float32, contiguous, on the device) and out must already be ordered
+        on that stream (for example by a previous forward() or a device
+        synchronize); for back-to-back launches on resident data, each of
+        which forward() would bracket with two cross-stream event waits."""
+        B = x.shape[0]
+        if x.dtype != torch.float32 or not x.is_contiguous() or tuple(out.shape) != (B, 3):
+            raise ValueError("launch: x must be contiguous float32 and out of shape (B, 3)")
+        check(self.L.mlp_forward(self.h, C.c_void_p(x.data_ptr()), int(B), C.c_void_p(out.data_ptr())),
+              "mlp_forward")
+
     def train_step(self, x, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_grad=False):
         x = x.to(self.device, torch.float32).contiguous()
         t = target.to(self.device, torch.float32).contiguous()

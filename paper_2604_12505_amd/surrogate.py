@@ -244,8 +244,10 @@ def noise_floor(a: RolloutSet, b: RolloutSet, first: int = WINDOW - 1) -> np.nda
 
 
 def time_inference(net: Mlp, x: torch.Tensor, reps: int = 20) -> float:
-    """Seconds per forward pass of the batch x (HIP events, after a warm-up);
-    x must fit the handle's max_batch."""
+    """Seconds per forward pass of the batch x (HIP events around reps
+    back-to-back launches on the network's stream, after a warm-up); x must
+    fit the handle's max_batch."""
+    x = x.to(torch.float32).contiguous()
     out = torch.empty(x.shape[0], 3, device=x.device)
     net.forward(x, out=out)
     torch.cuda.synchronize()
@@ -253,7 +255,7 @@ def time_inference(net: Mlp, x: torch.Tensor, reps: int = 20) -> float:
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(net.stream)
     for _ in range(reps):
-        net.forward(x, out=out)
+        net.launch(x, out)
     e1.record(net.stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps

@@ -46,6 +46,24 @@ def test_forward_matches_oracle(B):
     net.close()
 
 
+def test_launch_equals_forward():
+    # back-to-back launches on the network's stream (no stream hand-over)
+    # give forward()'s output bit for bit, a ragged last tile included
+    G, rng, params, vec = _net(3)
+    net = G.Mlp(vec, max_batch=1000)
+    x = torch.as_tensor(rng.normal(size=(1000, 128)).astype(np.float32), device="cuda:0")
+    y1 = net.forward(x)
+    y2 = torch.full_like(y1, float("nan"))
+    torch.cuda.synchronize()
+    for _ in range(3):
+        net.launch(x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    with pytest.raises(ValueError):
+        net.launch(x.double(), y2)
+    net.close()
+
+
 def test_forward_at_the_inference_batch_size():
     # the surrogate workload's inference batch, 65,536 windows in one launch:
     # sampled rows (and the last ones, the ragged end of the grid) against
