@@ -13,6 +13,10 @@ SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sph.hip", "mlp.hip", "lpv.hip
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary vector registers: the network
+         # kernels' epilogues then read them without a copy out of the
+         # accumulation registers (the SPH kernels have no MFMA)
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include")]
 
 
