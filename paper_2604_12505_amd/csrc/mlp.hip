@@ -192,60 +192,83 @@ __device__ __forceinline__ void load_bias(float4 (&bn)[4], const float* __restri
   for (int c = 0; c < 4; ++c) bn[c] = *reinterpret_cast<const float4*>(master + kOffB[l] + n0 + c * 16 + rq);
 }
 
-// The weight fragments of k step ks of a layer with K inputs (W its matrix)
-// for this lane: columns n0 + 16 c + li, inputs 32 ks + kq .. + 7.
-template <int K>
-__device__ __forceinline__ void load_w(bf16x8 (&b)[4], const bf16* __restrict__ W, int ks, int n0, int li, int kq) {
-  for (int c = 0; c < 4; ++c)
-    b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + ks * 32 + kq);
-}
-
 // Weight fragments are requested this many k steps ahead of their use.
 constexpr int kAhead = 2;
 
 template <int L>
 constexpr int layer_in() { return L == 0 ? kIn : kHid; }
 
-// Hidden layer L of a full row tile (kRows rows, RT = 4) with the weight
-// loads software-pipelined: pre holds the fragments of this layer's first
-// kAhead k steps and bn its biases, both requested before the previous
-// layer's epilogue; k step ks requests step ks + kAhead; before this
-// layer's own epilogue the next layer's first steps and biases are
-// requested, so that their round trip overlaps the GELU work.
+// Bias + GELU of one 16 x 16 output tile (row tile r, column tile c) of
+// this wave into dst, as in layer_out.
+__device__ __forceinline__ void tile_out(const floatx4& acc, const float4& bn, bf16* dst, int r, int c, int n0,
+                                         int li, int rq) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  bf16x4 v;
+  v[0] = (bf16)gelu(acc[0] + bn.x);
+  v[1] = (bf16)gelu(acc[1] + bn.y);
+  v[2] = (bf16)gelu(acc[2] + bn.z);
+  v[3] = (bf16)gelu(acc[3] + bn.w);
+  *reinterpret_cast<bf16x4*>(&dst[(r * 16 + li) * kLdsStride + n0 + c * 16 + rq]) = v;
+}
+
+// The weight fragments of column tiles 2h and 2h + 1 at k step ks.
+template <int K>
+__device__ __forceinline__ void load_w2(bf16x8 (&b)[2], const bf16* __restrict__ W, int ks, int h, int n0, int li,
+                                        int kq) {
+  for (int c = 0; c < 2; ++c)
+    b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + (2 * h + c) * 16 + li) * K + ks * 32 + kq);
+}
+
+// Hidden layer L of a full row tile (kRows rows, RT = 4), in two halves of
+// the wave's 64 outputs (column tiles 0-1, then 2-3), with the weight loads
+// software-pipelined over the 2 K/32 steps of both halves: pre holds the
+// fragments of the first kAhead steps and bn the biases, both requested
+// before the previous layer's epilogue; step s requests step s + kAhead.
+// The first half's epilogue is interleaved with the second half's products
+// (one 16 x 16 tile per step or two), so that the matrix cores and the
+// vector unit of a wave work at once; before the second half's epilogue the
+// next layer's first steps and biases are requested.
 template <int L>
 __device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], const bf16* __restrict__ wb,
-                                           const float* __restrict__ master, bf16x8 (&pre)[kAhead][4],
+                                           const float* __restrict__ master, bf16x8 (&pre)[kAhead][2],
                                            float4 (&bn)[4], int n0, int li, int kq, int rq) {
-  constexpr int RT = kRows / 16, K = layer_in<L>(), KS = K / 32;
-  static_assert(KS > kAhead, "the prefetch distance fits the layer");
+  constexpr int RT = kRows / 16, K = layer_in<L>(), KS = K / 32, S = 2 * KS;
+  constexpr int GPS = 2 * RT / KS;   // epilogue tiles of the first half per step of the second
+  static_assert(KS > kAhead && GPS * KS == 2 * RT, "steps and tiles");
   const bf16* W = wb + kOffW[L];
   const bf16* src = buf[L & 1];
+  bf16* dst = buf[1 - (L & 1)];
   floatx4 acc[RT][4];
   for (int r = 0; r < RT; ++r)
     for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  bf16x8 b[KS][4];
+  bf16x8 b[S][2];
 #pragma unroll
   for (int s = 0; s < kAhead; ++s)
-    for (int c = 0; c < 4; ++c) b[s][c] = pre[s][c];
+    for (int c = 0; c < 2; ++c) b[s][c] = pre[s][c];
+  const float4 bl[4] = {bn[0], bn[1], bn[2], bn[3]};
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    if (ks + kAhead < KS) load_w<K>(b[ks + kAhead], W, ks + kAhead, n0, li, kq);
+  for (int s = 0; s < S; ++s) {
+    const int h = s / KS, ks = s % KS;
+    if (s + kAhead < S) load_w2<K>(b[s + kAhead], W, (s + kAhead) % KS, (s + kAhead) / KS, n0, li, kq);
+    if (h == 1 && ks == KS - 1 && L < 3) {
+      // the next layer's first steps and biases
+      constexpr int KN = layer_in<(L < 3 ? L + 1 : L)>();
+#pragma unroll
+      for (int t = 0; t < kAhead; ++t) load_w2<KN>(pre[t], wb + kOffW[L < 3 ? L + 1 : L], t, 0, n0, li, kq);
+      load_bias(bn, master, L < 3 ? L + 1 : L, n0, rq);
+    }
     bf16x8 a[RT];
     for (int r = 0; r < RT; ++r)
       a[r] = *reinterpret_cast<const bf16x8*>(&src[(r * 16 + li) * kLdsStride + ks * 32 + kq]);
     for (int r = 0; r < RT; ++r)
-      for (int c = 0; c < 4; ++c)
-        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[ks][c], a[r], acc[r][c], 0, 0, 0);
-    __builtin_amdgcn_sched_barrier(0);   // keep each step's requests in its own step
+      for (int c = 0; c < 2; ++c)
+        acc[r][2 * h + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[s][c], a[r], acc[r][2 * h + c], 0, 0, 0);
+    if (h == 1)
+      for (int g = ks * GPS; g < ks * GPS + GPS; ++g) tile_out(acc[g >> 1][g & 1], bl[g & 1], dst, g >> 1, g & 1, n0, li, rq);
+    __builtin_amdgcn_sched_barrier(0);   // keep each step's requests and epilogue tiles in its own step
   }
-  const float4 bl[4] = {bn[0], bn[1], bn[2], bn[3]};
-  if constexpr (L < 3) {
-    constexpr int KN = layer_in<L + 1>();
-#pragma unroll
-    for (int s = 0; s < kAhead; ++s) load_w<KN>(pre[s], wb + kOffW[L + 1], s, n0, li, kq);
-    load_bias(bn, master, L + 1, n0, rq);
-  }
-  layer_out<RT>(acc, bl, buf[1 - (L & 1)], n0, li, rq);
+  for (int r = 0; r < RT; ++r)
+    for (int c = 2; c < 4; ++c) tile_out(acc[r][c], bl[c], dst, r, c, n0, li, rq);
   __syncthreads();
 }
 
@@ -269,10 +292,10 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
   int cur = 0;
   if constexpr (ROWS == kRows) {
     // a full tile (inference): the pipelined layers
-    bf16x8 pre[kAhead][4];
+    bf16x8 pre[kAhead][2];
     float4 bn[4];
 #pragma unroll
-    for (int s = 0; s < kAhead; ++s) load_w<kIn>(pre[s], wb + kOffW[0], s, n0, li, kq);
+    for (int s = 0; s < kAhead; ++s) load_w2<kIn>(pre[s], wb + kOffW[0], s, 0, n0, li, kq);
     load_bias(bn, master, 0, n0, rq);
     layer_pipe<0>(buf, wb, master, pre, bn, n0, li, kq, rq);
     layer_pipe<1>(buf, wb, master, pre, bn, n0, li, kq, rq);
