@@ -170,21 +170,29 @@ constexpr int kLdsStride = kHid + 8;
 // operand and the activations as the second, so that acc[r][c] holds, in
 // lane l, outputs n0 + 16 c + rq .. + 3 (rq = 4 (l / 16)) of row 16 r +
 // l % 16: four consecutive outputs of one row, stored as one 8-byte word.
-// Bias + GELU of a layer's ROWS x 64 outputs of this wave into dst (BF16);
-// bn[c] holds the biases of outputs n0 + 16 c + rq .. + 3.
+// The accumulators start from the biases (bias_acc), so a layer's output
+// is GELU of the accumulator.  GELU of a layer's ROWS x 64 outputs of this
+// wave into dst (BF16).
 template <int RT>
-__device__ __forceinline__ void layer_out(const floatx4 (&acc)[RT][4], const float4 (&bn)[4], bf16* dst, int n0,
-                                          int li, int rq) {
+__device__ __forceinline__ void layer_out(const floatx4 (&acc)[RT][4], bf16* dst, int n0, int li, int rq) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   for (int c = 0; c < 4; ++c)
     for (int r = 0; r < RT; ++r) {
       bf16x4 v;
-      v[0] = (bf16)gelu(acc[r][c][0] + bn[c].x);
-      v[1] = (bf16)gelu(acc[r][c][1] + bn[c].y);
-      v[2] = (bf16)gelu(acc[r][c][2] + bn[c].z);
-      v[3] = (bf16)gelu(acc[r][c][3] + bn[c].w);
+      v[0] = (bf16)gelu(acc[r][c][0]);
+      v[1] = (bf16)gelu(acc[r][c][1]);
+      v[2] = (bf16)gelu(acc[r][c][2]);
+      v[3] = (bf16)gelu(acc[r][c][3]);
       *reinterpret_cast<bf16x4*>(&dst[(r * 16 + li) * kLdsStride + n0 + c * 16 + rq]) = v;
     }
+}
+
+// Accumulators of a layer set to this lane's biases: bn[c] holds the biases
+// of outputs n0 + 16 c + rq .. + 3, the outputs acc[r][c] holds.
+template <int RT>
+__device__ __forceinline__ void bias_acc(floatx4 (&acc)[RT][4], const float4 (&bn)[4]) {
+  for (int r = 0; r < RT; ++r)
+    for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{bn[c].x, bn[c].y, bn[c].z, bn[c].w};
 }
 
 // This lane's biases of layer l (see layer_out).
@@ -198,16 +206,15 @@ constexpr int kAhead = 2;
 template <int L>
 constexpr int layer_in() { return L == 0 ? kIn : kHid; }
 
-// Bias + GELU of one 16 x 16 output tile (row tile r, column tile c) of
-// this wave into dst, as in layer_out.
-__device__ __forceinline__ void tile_out(const floatx4& acc, const float4& bn, bf16* dst, int r, int c, int n0,
-                                         int li, int rq) {
+// GELU of one 16 x 16 output tile (row tile r, column tile c) of this wave
+// into dst, as in layer_out.
+__device__ __forceinline__ void tile_out(const floatx4& acc, bf16* dst, int r, int c, int n0, int li, int rq) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   bf16x4 v;
-  v[0] = (bf16)gelu(acc[0] + bn.x);
-  v[1] = (bf16)gelu(acc[1] + bn.y);
-  v[2] = (bf16)gelu(acc[2] + bn.z);
-  v[3] = (bf16)gelu(acc[3] + bn.w);
+  v[0] = (bf16)gelu(acc[0]);
+  v[1] = (bf16)gelu(acc[1]);
+  v[2] = (bf16)gelu(acc[2]);
+  v[3] = (bf16)gelu(acc[3]);
   *reinterpret_cast<bf16x4*>(&dst[(r * 16 + li) * kLdsStride + n0 + c * 16 + rq]) = v;
 }
 
@@ -239,13 +246,11 @@ __device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], cons
   const bf16* src = buf[L & 1];
   bf16* dst = buf[1 - (L & 1)];
   floatx4 acc[RT][4];
-  for (int r = 0; r < RT; ++r)
-    for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  bias_acc<RT>(acc, bn);
   bf16x8 b[S][2];
 #pragma unroll
   for (int s = 0; s < kAhead; ++s)
     for (int c = 0; c < 2; ++c) b[s][c] = pre[s][c];
-  const float4 bl[4] = {bn[0], bn[1], bn[2], bn[3]};
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int h = s / KS, ks = s % KS;
@@ -264,11 +269,11 @@ __device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], cons
       for (int c = 0; c < 2; ++c)
         acc[r][2 * h + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[s][c], a[r], acc[r][2 * h + c], 0, 0, 0);
     if (h == 1)
-      for (int g = ks * GPS; g < ks * GPS + GPS; ++g) tile_out(acc[g >> 1][g & 1], bl[g & 1], dst, g >> 1, g & 1, n0, li, rq);
+      for (int g = ks * GPS; g < ks * GPS + GPS; ++g) tile_out(acc[g >> 1][g & 1], dst, g >> 1, g & 1, n0, li, rq);
     __builtin_amdgcn_sched_barrier(0);   // keep each step's requests and epilogue tiles in its own step
   }
   for (int r = 0; r < RT; ++r)
-    for (int c = 2; c < 4; ++c) tile_out(acc[r][c], bl[c], dst, r, c, n0, li, rq);
+    for (int c = 2; c < 4; ++c) tile_out(acc[r][c], dst, r, c, n0, li, rq);
   __syncthreads();
 }
 
@@ -276,9 +281,9 @@ __device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], cons
 // buf[0] as BF16: the four hidden layers on MFMA (ping-pong between the two
 // buffers; each of the 4 waves computes ROWS x 64 outputs of a layer as
 // ROWS/16 x 4 MFMA tiles), then the head, whose result for row r and output
-// o goes to out(r, o, value) (called by thread 4 r).  w4s is the head's
-// weight matrix (3 x 256) staged in LDS by the caller.  All 256 threads;
-// ends without a barrier.
+// o goes to out(r, o, value) (called by one lane of the row's wave).  w4s
+// is the head's weight matrix (3 x 256) staged in LDS by the caller.  All
+// 256 threads; ends without a barrier.
 template <int ROWS, class Out>
 __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const bf16* __restrict__ wb,
                                          const float* __restrict__ master, const bf16* w4s, Out&& out) {
@@ -311,8 +316,7 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
       float4 bn[4];   // this lane's biases, fetched before the products
       load_bias(bn, master, l, n0, rq);
       floatx4 acc[RT][4];
-      for (int r = 0; r < RT; ++r)
-        for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+      bias_acc<RT>(acc, bn);
       const int K = kDims[l];
 #pragma unroll 2
       for (int k0 = 0; k0 < K; k0 += 32) {
@@ -325,40 +329,28 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
           for (int c = 0; c < 4; ++c)
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[c], a[r], acc[r][c], 0, 0, 0);
       }
-      layer_out<RT>(acc, bn, buf[1 - cur], n0, li, rq);
+      layer_out<RT>(acc, buf[1 - cur], n0, li, rq);
       __syncthreads();
       cur = 1 - cur;
     }
   }
-  // the head: 4 lanes per row, each over 64 of the 256 inputs for the three
-  // outputs at once, then the sum over the 4 lanes
+  // the head on MFMA: wave w takes row tile w, its 3 outputs padded to a
+  // 16-wide tile with zero weights; lane l < 16 ends with outputs 0-2 of
+  // row 16 w + l (the accumulator starts from the head's biases)
   static_assert(kOut == 3, "head layout");
-  if (threadIdx.x >= 4 * ROWS) return;
-  const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
-  const bf16* a = &buf[cur][r * kLdsStride + p * 64];
-  const bf16* w4 = w4s + p * 64;
-  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-  for (int k = 0; k < 64; k += 8) {
-    const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
-    const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(w4 + k);
-    const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(w4 + kHid + k);
-    const bf16x8 w2 = *reinterpret_cast<const bf16x8*>(w4 + 2 * kHid + k);
-    for (int j = 0; j < 8; ++j) {
-      const float aj = (float)av[j];
-      s0 = fmaf(aj, (float)w0[j], s0);
-      s1 = fmaf(aj, (float)w1[j], s1);
-      s2 = fmaf(aj, (float)w2[j], s2);
-    }
+  if (wave >= RT) return;
+  floatx4 h = rq == 0 ? floatx4{hb0, hb1, hb2, 0.f} : floatx4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = {};
+#pragma unroll
+  for (int ks = 0; ks < kHid / 32; ++ks) {
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(&buf[cur][(wave * 16 + li) * kLdsStride + ks * 32 + kq]);
+    const bf16x8 b = li < kOut ? *reinterpret_cast<const bf16x8*>(&w4s[li * kHid + ks * 32 + kq]) : zero;
+    h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a, h, 0, 0, 0);
   }
-  for (int off = 1; off < 4; off <<= 1) {
-    s0 += __shfl_xor(s0, off, 64);
-    s1 += __shfl_xor(s1, off, 64);
-    s2 += __shfl_xor(s2, off, 64);
-  }
-  if (p == 0) {
-    out(r, 0, s0 + hb0);
-    out(r, 1, s1 + hb1);
-    out(r, 2, s2 + hb2);
+  if (lane < 16) {
+    out(wave * 16 + li, 0, h[0]);
+    out(wave * 16 + li, 1, h[1]);
+    out(wave * 16 + li, 2, h[2]);
   }
 }
 
