@@ -161,8 +161,8 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
 // Inference: the whole network for a tile of kRows rows in one workgroup.
 // Activations stay in LDS (two BF16 buffers, rows padded by 16 bytes); each of
 // the 4 waves computes kRows x 64 outputs of a layer as 4 x 4 MFMA tiles with
-// the weights read from L2; bias + GELU are applied in the epilogue; the
-// 3-wide head is a dot product per (row, output).
+// the weights read from L2 (accumulators starting from the biases); GELU is
+// applied in the epilogue; the 3-wide head is one MFMA tile per 16 rows.
 constexpr int kRows = 64;
 constexpr int kLdsStride = kHid + 8;
 
