@@ -72,7 +72,9 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // gemm_tn: 256 threads = 4 waves in a 2x2 arrangement, 64x64 output tile, each
 // wave 32x32 = 2x2 MFMA tiles of 16x16.  Lane l holds row (l % 16) of A and
 // column (l % 16) of B for k in [8 (l / 16), 8 (l / 16) + 8) of each 32-wide
-// k step; the result element e of lane l is row 4 (l / 16) + e, column l % 16.
+// k step; the result element e of lane l is row 4 (l / 16) + e, column
+// l % 16, or, for an epilogue that asks for B as the first MFMA operand
+// (kBFirst), row l % 16, column 4 (l / 16) + e.
 // Rows m >= M and columns n >= N read zeros and are not stored.  K % 32 == 0.
 // A grid with gridDim.z > 1 splits the k range into gridDim.z equal parts
 // (K % (32 gridDim.z) == 0); part z covers [z K/Z, (z+1) K/Z) and its
@@ -80,6 +82,7 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // ---------------------------------------------------------------------------
 
 struct EpiFwd {            // hidden forward layer
+  static constexpr bool kBFirst = true;   // two of its three stores are transposed
   const float* bias;       // [N]
   bf16* act;               // [M][ld_act] row-major, next layer's A
   int ld_act;
@@ -98,6 +101,7 @@ struct EpiFwd {            // hidden forward layer
 };
 
 struct EpiDgrad {          // g_{l-1} = (g_l W_l) * gelu'(z_{l-1})
+  static constexpr bool kBFirst = false;
   const float* zT;         // [N][ldT] pre-activation of the layer below
   bf16* g;                 // [M][ld_g] row-major or null
   int ld_g;
@@ -111,6 +115,7 @@ struct EpiDgrad {          // g_{l-1} = (g_l W_l) * gelu'(z_{l-1})
 };
 
 struct EpiPart {           // k-split part z of a weight gradient, into slab z
+  static constexpr bool kBFirst = false;
   float* c;
   int ldc;
   size_t slab;
@@ -144,18 +149,21 @@ __global__ void __launch_bounds__(256) gemm_tn(const bf16* __restrict__ A, int l
     }
     for (int r = 0; r < 2; ++r)
       for (int c = 0; c < 2; ++c)
-        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+        acc[r][c] = Epi::kBFirst ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[c], a[r], acc[r][c], 0, 0, 0)
+                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
   }
-  const int rq = (lane >> 4) * 4;
+  const int q4 = (lane >> 4) * 4;
   for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c) {
-      int n = n0 + c * 16 + li;
-      if (n >= N) continue;
+    for (int c = 0; c < 2; ++c)
       for (int e = 0; e < 4; ++e) {
-        int m = m0 + r * 16 + rq + e;
-        if (m < M) epi(m, n, acc[r][c][e]);
+        // B first: element e of lane l is row 16 r + l % 16, column
+        // 16 c + 4 (l / 16) + e (the lanes of a store hold consecutive rows,
+        // so transposed stores are contiguous); A first: row 16 r + 4 (l / 16)
+        // + e, column 16 c + l % 16 (row-major stores are)
+        const int m = m0 + r * 16 + (Epi::kBFirst ? li : q4 + e);
+        const int n = n0 + c * 16 + (Epi::kBFirst ? q4 + e : li);
+        if (m < M && n < N) epi(m, n, acc[r][c][e]);
       }
-    }
 }
 
 // Inference: the whole network for a tile of kRows rows in one workgroup.
