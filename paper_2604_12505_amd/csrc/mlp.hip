@@ -314,6 +314,9 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
     layer_pipe<1>(buf, wb, master, pre, bn, n0, li, kq, rq);
     layer_pipe<2>(buf, wb, master, pre, bn, n0, li, kq, rq);
     layer_pipe<3>(buf, wb, master, pre, bn, n0, li, kq, rq);
+    // layer L writes buf[1 - (L & 1)]: the last hidden layer's outputs are
+    // in buf[0], so cur stays 0 for the head
+    static_assert(((4 - 1) & 1) == 1, "an even number of hidden layers ends in buf[0]");
   } else {
     // a small row tile inside the coupled rollout's time loop: the weight
     // fragments are requested per k step (requests made ahead, invariant
