@@ -243,13 +243,12 @@ __device__ __forceinline__ void load_w2(bf16x8 (&b)[2], const bf16* __restrict__
 // (one 16 x 16 tile per step or two), so that the matrix cores and the
 // vector unit of a wave work at once; before the second half's epilogue the
 // next layer's first steps and biases are requested.
-template <int L>
-__device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], const bf16* __restrict__ wb,
+template <int L, int ROWS>
+__device__ __forceinline__ void layer_pipe(bf16 (*buf)[ROWS * kLdsStride], const bf16* __restrict__ wb,
                                            const float* __restrict__ master, bf16x8 (&pre)[kAhead][2],
                                            float4 (&bn)[4], int n0, int li, int kq, int rq) {
-  constexpr int RT = kRows / 16, K = layer_in<L>(), KS = K / 32, S = 2 * KS;
-  constexpr int GPS = 2 * RT / KS;   // epilogue tiles of the first half per step of the second
-  static_assert(KS > kAhead && GPS * KS == 2 * RT, "steps and tiles");
+  constexpr int RT = ROWS / 16, K = layer_in<L>(), KS = K / 32, S = 2 * KS;
+  static_assert(KS > kAhead, "the prefetch distance fits the layer");
   const bf16* W = wb + kOffW[L];
   const bf16* src = buf[L & 1];
   bf16* dst = buf[1 - (L & 1)];
@@ -276,8 +275,9 @@ __device__ __forceinline__ void layer_pipe(bf16 (*buf)[kRows * kLdsStride], cons
     for (int r = 0; r < RT; ++r)
       for (int c = 0; c < 2; ++c)
         acc[r][2 * h + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[s][c], a[r], acc[r][2 * h + c], 0, 0, 0);
-    if (h == 1)
-      for (int g = ks * GPS; g < ks * GPS + GPS; ++g) tile_out(acc[g >> 1][g & 1], dst, g >> 1, g & 1, n0, li, rq);
+    if (h == 1)   // the first half's tiles g (2 RT of them) spread over the KS steps
+      for (int g = 0; g < 2 * RT; ++g)
+        if (g * KS / (2 * RT) == ks) tile_out(acc[g >> 1][g & 1], dst, g >> 1, g & 1, n0, li, rq);
     __builtin_amdgcn_sched_barrier(0);   // keep each step's requests and epilogue tiles in its own step
   }
   for (int r = 0; r < RT; ++r)
@@ -302,49 +302,19 @@ __device__ __forceinline__ void net_rows(bf16 (*buf)[ROWS * kLdsStride], const b
   const int n0 = wave * 64;
   // the head's biases, fetched now so that their round trip is hidden
   const float hb0 = master[kOffB[4]], hb1 = master[kOffB[4] + 1], hb2 = master[kOffB[4] + 2];
-  int cur = 0;
-  if constexpr (ROWS == kRows) {
-    // a full tile (inference): the pipelined layers
-    bf16x8 pre[kAhead][2];
-    float4 bn[4];
+  // the pipelined layers; layer L writes buf[1 - (L & 1)], so the last
+  // hidden layer's outputs are in buf[0]
+  bf16x8 pre[kAhead][2];
+  float4 bn[4];
 #pragma unroll
-    for (int s = 0; s < kAhead; ++s) load_w2<kIn>(pre[s], wb + kOffW[0], s, 0, n0, li, kq);
-    load_bias(bn, master, 0, n0, rq);
-    layer_pipe<0>(buf, wb, master, pre, bn, n0, li, kq, rq);
-    layer_pipe<1>(buf, wb, master, pre, bn, n0, li, kq, rq);
-    layer_pipe<2>(buf, wb, master, pre, bn, n0, li, kq, rq);
-    layer_pipe<3>(buf, wb, master, pre, bn, n0, li, kq, rq);
-    // layer L writes buf[1 - (L & 1)]: the last hidden layer's outputs are
-    // in buf[0], so cur stays 0 for the head
-    static_assert(((4 - 1) & 1) == 1, "an even number of hidden layers ends in buf[0]");
-  } else {
-    // a small row tile inside the coupled rollout's time loop: the weight
-    // fragments are requested per k step (requests made ahead, invariant
-    // over the time loop, would be hoisted out of it into far more
-    // registers than a lane has)
-    for (int l = 0; l < 4; ++l) {
-      const bf16* W = wb + kOffW[l];
-      float4 bn[4];   // this lane's biases, fetched before the products
-      load_bias(bn, master, l, n0, rq);
-      floatx4 acc[RT][4];
-      bias_acc<RT>(acc, bn);
-      const int K = kDims[l];
-#pragma unroll 2
-      for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 a[RT], b[4];
-        for (int r = 0; r < RT; ++r)
-          a[r] = *reinterpret_cast<const bf16x8*>(&buf[cur][(r * 16 + li) * kLdsStride + k0 + kq]);
-        for (int c = 0; c < 4; ++c)
-          b[c] = *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + c * 16 + li) * K + k0 + kq);
-        for (int r = 0; r < RT; ++r)
-          for (int c = 0; c < 4; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[c], a[r], acc[r][c], 0, 0, 0);
-      }
-      layer_out<RT>(acc, buf[1 - cur], n0, li, rq);
-      __syncthreads();
-      cur = 1 - cur;
-    }
-  }
+  for (int s = 0; s < kAhead; ++s) load_w2<kIn>(pre[s], wb + kOffW[0], s, 0, n0, li, kq);
+  load_bias(bn, master, 0, n0, rq);
+  layer_pipe<0, ROWS>(buf, wb, master, pre, bn, n0, li, kq, rq);
+  layer_pipe<1, ROWS>(buf, wb, master, pre, bn, n0, li, kq, rq);
+  layer_pipe<2, ROWS>(buf, wb, master, pre, bn, n0, li, kq, rq);
+  layer_pipe<3, ROWS>(buf, wb, master, pre, bn, n0, li, kq, rq);
+  static_assert(((4 - 1) & 1) == 1, "an even number of hidden layers ends in buf[0]");
+  constexpr int cur = 0;
   // the head on MFMA: wave w takes row tile w, its 3 outputs padded to a
   // 16-wide tile with zero weights; lane l < 16 ends with outputs 0-2 of
   // row 16 w + l (the accumulator starts from the head's biases)
@@ -613,6 +583,14 @@ constexpr int kCRows = 16;
 // (Section 3.4; velocities first, then positions with the new velocities),
 // and logs sample k + 1 (state; theta, thetadot, the input torque of the
 // sample's step, also into the ring).
+// The network on a 16-row tile, out of line: inlined into the coupled
+// rollout's time loop, its weight requests made ahead took every register
+// and spilled (512 registers a lane and 412 B of scratch); as a call, 134.
+__device__ __attribute__((noinline)) void net16(bf16 (*buf)[kCRows * kLdsStride], const bf16* __restrict__ wb,
+                                              const float* __restrict__ master, const bf16* w4s, float* hout) {
+  net_rows<kCRows>(buf, wb, master, w4s, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
+}
+
 __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ stat, int n_static, int R, int T,
                                                    WinNorm nm, float z_max, const double* __restrict__ body,
                                                    const float* __restrict__ u_seq, int n_steps, int stride,
@@ -664,7 +642,7 @@ __global__ void __launch_bounds__(256) mlp_coupled(const float* __restrict__ sta
       buf[0][r * kLdsStride + kk] = (bf16)z;
     }
     __syncthreads();
-    net_rows<kCRows>(buf, wb, master, w4s, [&](int r, int o, float v) { hout[r * kOut + o] = v; });
+    net16(buf, wb, master, w4s, hout);
     __syncthreads();
     if (owner) {
       double F[3];
