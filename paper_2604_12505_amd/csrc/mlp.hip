@@ -461,29 +461,42 @@ __global__ void __launch_bounds__(256) mlp_head_wgrad(const float* __restrict__ 
   if (lane == 0) grad[k < kHid ? kOffW[4] + o * kHid + k : kOffB[4] + o] = s;
 }
 
-// Sum of the k-split parts of a weight gradient, slab by slab in order.
-__global__ void mlp_sum_parts(const float* __restrict__ part, int parts, size_t slab, int n,
-                              float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.f;
-  for (int z = 0; z < parts; ++z) s += part[z * slab + i];
-  out[i] = s;
-}
+// The weight- and bias-gradient reductions of the four hidden layers in one
+// launch.  Blocks [0, blk0[4]) sum the k-split parts of the weight
+// gradients, slab by slab in order (256 elements a block, the layers' blocks
+// back to back from blk0[l]); the next 4 kHid blocks each sum one hidden
+// bias gradient, db_l[n] = sum_b g_l[b][n]: 256 threads striding over the
+// batch, wavefront sums, then the four wavefronts' sums in order.
+struct GradReduce {
+  float* part[4];          // layer l's parts, slab[l] floats each (written by gemm_tn<EpiPart>)
+  int slab[4];
+  int blk0[5];
+  const bf16* gT[4];       // dL/dz of hidden layer l, feature-major
+  int parts;
+};
 
-// Bias gradient of a hidden layer, db[n] = sum_b g[b][n]: one workgroup per
-// n, its 256 threads striding over the batch, wavefront sums, then the four
-// wavefronts' sums in order.
-__global__ void __launch_bounds__(256) mlp_bias_grad(const bf16* __restrict__ gT, int ldT, int B,
-                                                     float* __restrict__ db) {
+__global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, int B, float* __restrict__ grad) {
+  const int blk = blockIdx.x;
+  if (blk < a.blk0[4]) {   // the same branch for the whole block
+    int l = 0;
+    while (l < 3 && blk >= a.blk0[l + 1]) ++l;
+    const int i = (blk - a.blk0[l]) * 256 + (int)threadIdx.x;
+    if (i >= a.slab[l]) return;
+    float s = 0.f;
+    for (int z = 0; z < a.parts; ++z) s += a.part[l][(size_t)z * a.slab[l] + i];
+    grad[kOffW[l] + i] = s;
+    return;
+  }
   __shared__ float red[4];
-  const int n = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = blk - a.blk0[4], l = q / kHid, n = q - l * kHid;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bf16* g = a.gT[l] + (size_t)n * ldT;
   float s = 0.f;
-  for (int b = threadIdx.x; b < B; b += 256) s += (float)gT[(size_t)n * ldT + b];
+  for (int b = threadIdx.x; b < B; b += 256) s += (float)g[b];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) red[wave] = s;
   __syncthreads();
-  if (threadIdx.x == 0) db[n] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) grad[kOffB[l] + n] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void mlp_loss(const float* __restrict__ rows, int B, float* __restrict__ out) {
@@ -767,7 +780,7 @@ MlpLayout mlp_layout(int maxB) {
   L.gy = take(B * kOut * 4);
   L.rows = take(B * 4);
   L.loss = take(4);
-  L.part = take((size_t)kMaxParts * kHid * kHid * 4);
+  L.part = take((size_t)kMaxParts * kHid * (kIn + 3 * kHid) * 4);   // every hidden layer's parts
   L.total = o;
   return L;
 }
@@ -895,19 +908,27 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
                      h->at<float>(h->L.zT[3]), h->at<bf16>(h->L.g[3]), h->at<bf16>(h->L.gT[3]), ldT, dy_dev);
   hipLaunchKernelGGL(mlp_head_wgrad, dim3((kOut * (kHid + 1) + 3) / 4), dim3(256), 0, h->stream,
                      h->at<float>(h->L.gy), h->at<bf16>(h->L.actT[3]), ldT, B, grad);
-  // hidden layers, top down: g[l] holds dL/dz of hidden layer l (output of W_l)
+  // hidden layers, top down: g[l] holds dL/dz of hidden layer l (output of
+  // W_l); each layer's weight gradient in k-split parts, reduced with the
+  // bias gradients in one launch at the end
+  const int parts = wgrad_parts(B);
+  GradReduce gr;
+  gr.parts = parts;
+  gr.blk0[0] = 0;
+  size_t off = 0;
+  for (int l = 0; l < 4; ++l) {
+    gr.slab[l] = kHid * kDims[l];
+    gr.part[l] = h->at<float>(h->L.part) + off;
+    gr.gT[l] = h->at<bf16>(h->L.gT[l]);
+    gr.blk0[l + 1] = gr.blk0[l] + (gr.slab[l] + 255) / 256;
+    off += (size_t)kMaxParts * gr.slab[l];
+  }
   for (int l = 3; l >= 0; --l) {
     const bf16* aT = l > 0 ? h->at<bf16>(h->L.actT[l - 1]) : h->at<bf16>(h->L.xT);
-    const int parts = wgrad_parts(B);
-    const size_t slab = (size_t)kHid * kDims[l];
-    EpiPart ep{h->at<float>(h->L.part), kDims[l], slab};
+    EpiPart ep{gr.part[l], kDims[l], (size_t)gr.slab[l]};
     dim3 gw((kDims[l] + 63) / 64, (kHid + 63) / 64, parts);
     hipLaunchKernelGGL(gemm_tn<EpiPart>, gw, dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]), ldT, aT,
                        ldT, kHid, kDims[l], B, ep);
-    hipLaunchKernelGGL(mlp_sum_parts, dim3((unsigned)((slab + 255) / 256)), dim3(256), 0, h->stream,
-                       h->at<float>(h->L.part), parts, slab, (int)slab, grad + kOffW[l]);
-    hipLaunchKernelGGL(mlp_bias_grad, dim3(kHid), dim3(256), 0, h->stream, h->at<bf16>(h->L.gT[l]),
-                       ldT, B, grad + kOffB[l]);
     if (l > 0) {
       EpiDgrad ed;
       ed.zT = h->at<float>(h->L.zT[l - 1]);
@@ -920,6 +941,7 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
                          h->at<bf16>(h->L.wT) + (size_t)(l - 1) * kHid * kHid, kHid, B, kHid, kHid, ed);
     }
   }
+  hipLaunchKernelGGL(mlp_grad_reduce, dim3(gr.blk0[4] + 4 * kHid), dim3(256), 0, h->stream, gr, ldT, B, grad);
 }
 
 // Adam with bias correction at step t on the master weights from grad, then
