@@ -443,36 +443,22 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
 }
 
 // dW4[o][k] = sum_b gy[b][o] a4[b][k]; db4[o] = sum_b gy[b][o].
-// Head weight and bias gradients, dW4[o][k] = sum_b gy[b][o] a4[b][k] and
-// db4[o] = sum_b gy[b][o]: one wavefront per output (k = kHid: the bias),
-// lanes striding over the batch, then a fixed-order wavefront sum.
-__global__ void __launch_bounds__(256) mlp_head_wgrad(const float* __restrict__ gy, const bf16* __restrict__ a4T,
-                                                      int ldT, int B, float* __restrict__ grad) {
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (t >= kOut * (kHid + 1)) return;
-  const int o = t / (kHid + 1), k = t - o * (kHid + 1);
-  float s = 0.f;
-  if (k < kHid) {
-    for (int b = lane; b < B; b += 64) s += gy[(size_t)b * kOut + o] * (float)a4T[(size_t)k * ldT + b];
-  } else {
-    for (int b = lane; b < B; b += 64) s += gy[(size_t)b * kOut + o];
-  }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) grad[k < kHid ? kOffW[4] + o * kHid + k : kOffB[4] + o] = s;
-}
-
-// The weight- and bias-gradient reductions of the four hidden layers in one
-// launch.  Blocks [0, blk0[4]) sum the k-split parts of the weight
-// gradients, slab by slab in order (256 elements a block, the layers' blocks
-// back to back from blk0[l]); the next 4 kHid blocks each sum one hidden
-// bias gradient, db_l[n] = sum_b g_l[b][n]: 256 threads striding over the
-// batch, wavefront sums, then the four wavefronts' sums in order.
+// The gradient reductions of back-propagation in one launch.  Blocks
+// [0, blk0[4]) sum the k-split parts of the hidden layers' weight gradients,
+// slab by slab in order (256 elements a block, the layers' blocks back to
+// back from blk0[l]); the next 4 kHid blocks each sum one hidden bias
+// gradient, db_l[n] = sum_b g_l[b][n]; the last 3 (kHid + 1) blocks one of
+// the head's, dW4[o][k] = sum_b gy[b][o] a4[b][k] (k = kHid: db4[o] =
+// sum_b gy[b][o]).  A sum over the batch: 256 threads striding over it,
+// wavefront sums, then the four wavefronts' sums in order.
 struct GradReduce {
   float* part[4];          // layer l's parts, slab[l] floats each (written by gemm_tn<EpiPart>)
   int slab[4];
   int blk0[5];
   const bf16* gT[4];       // dL/dz of hidden layer l, feature-major
   int parts;
+  const float* gy;         // dL/dy [B][3]
+  const bf16* a4T;         // last hidden activations, feature-major
 };
 
 __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, int B, float* __restrict__ grad) {
@@ -488,15 +474,29 @@ __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, in
     return;
   }
   __shared__ float red[4];
-  const int q = blk - a.blk0[4], l = q / kHid, n = q - l * kHid;
+  const int q = blk - a.blk0[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bf16* g = a.gT[l] + (size_t)n * ldT;
   float s = 0.f;
-  for (int b = threadIdx.x; b < B; b += 256) s += (float)g[b];
+  int dst;
+  if (q < 4 * kHid) {
+    const int l = q / kHid, n = q - l * kHid;
+    const bf16* g = a.gT[l] + (size_t)n * ldT;
+    for (int b = threadIdx.x; b < B; b += 256) s += (float)g[b];
+    dst = kOffB[l] + n;
+  } else {
+    const int t = q - 4 * kHid, o = t / (kHid + 1), k = t - o * (kHid + 1);
+    if (k < kHid) {
+      const bf16* x = a.a4T + (size_t)k * ldT;
+      for (int b = threadIdx.x; b < B; b += 256) s += a.gy[(size_t)b * kOut + o] * (float)x[b];
+    } else {
+      for (int b = threadIdx.x; b < B; b += 256) s += a.gy[(size_t)b * kOut + o];
+    }
+    dst = k < kHid ? kOffW[4] + o * kHid + k : kOffB[4] + o;
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) red[wave] = s;
   __syncthreads();
-  if (threadIdx.x == 0) grad[kOffB[l] + n] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) grad[dst] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void mlp_loss(const float* __restrict__ rows, int B, float* __restrict__ out) {
@@ -513,32 +513,42 @@ __global__ void mlp_loss(const float* __restrict__ rows, int B, float* __restric
 }
 
 // Adam with bias correction on FP32 masters, then the BF16 copies.
+// Parameter i's BF16 copies from its FP32 value: the row-major copy of all
+// parameters and, for W1..W3, the transposed copy.
+__device__ __forceinline__ void refresh_one(int i, float w, bf16* __restrict__ wb, bf16* __restrict__ wT) {
+  const bf16 v = (bf16)w;
+  wb[i] = v;
+  for (int l = 1; l <= 3; ++l) {
+    const int off = kOffW[l];
+    if (i >= off && i < off + kHid * kHid) {
+      const int r = (i - off) / kHid, c = (i - off) % kHid;     // W_l[r][c], r = out, c = in
+      wT[(size_t)(l - 1) * kHid * kHid + (size_t)c * kHid + r] = v;
+    }
+  }
+}
+
+// Adam with bias correction on the FP32 master weights, then their BF16
+// copies (one pass over the parameters).
 __global__ void mlp_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
-                         const float* __restrict__ g, int n, float lr, float b1, float b2, float eps,
-                         float c1, float c2) {
+                         const float* __restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2,
+                         bf16* __restrict__ wb, bf16* __restrict__ wT) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= MLP_N_PARAMS) return;
   float gi = g[i];
   float mi = b1 * m[i] + (1.0f - b1) * gi;
   float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  refresh_one(i, wi, wb, wT);
 }
 
-// BF16 row-major copy of all parameters, and transposed copies of W1..W3.
+// The BF16 copies of all parameters (after they are set).
 __global__ void mlp_refresh(const float* __restrict__ w, bf16* __restrict__ wb, bf16* __restrict__ wT) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= MLP_N_PARAMS) return;
-  bf16 v = (bf16)w[i];
-  wb[i] = v;
-  for (int l = 1; l <= 3; ++l) {
-    int off = kOffW[l];
-    if (i >= off && i < off + kHid * kHid) {
-      int r = (i - off) / kHid, c = (i - off) % kHid;     // W_l[r][c], r = out, c = in
-      wT[(size_t)(l - 1) * kHid * kHid + (size_t)c * kHid + r] = v;
-    }
-  }
+  refresh_one(i, w[i], wb, wT);
 }
 
 // Surrogate inputs from rollout logs: window w of rollout r holds samples
@@ -906,14 +916,14 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
                      h->at<bf16>(h->L.wb) + kOffW[4], h->at<float>(h->L.master) + kOffB[4], B,
                      h->at<float>(h->L.y), target_dev, h->at<float>(h->L.gy), h->at<float>(h->L.rows),
                      h->at<float>(h->L.zT[3]), h->at<bf16>(h->L.g[3]), h->at<bf16>(h->L.gT[3]), ldT, dy_dev);
-  hipLaunchKernelGGL(mlp_head_wgrad, dim3((kOut * (kHid + 1) + 3) / 4), dim3(256), 0, h->stream,
-                     h->at<float>(h->L.gy), h->at<bf16>(h->L.actT[3]), ldT, B, grad);
   // hidden layers, top down: g[l] holds dL/dz of hidden layer l (output of
   // W_l); each layer's weight gradient in k-split parts, reduced with the
   // bias gradients in one launch at the end
   const int parts = wgrad_parts(B);
   GradReduce gr;
   gr.parts = parts;
+  gr.gy = h->at<float>(h->L.gy);
+  gr.a4T = h->at<bf16>(h->L.actT[3]);
   gr.blk0[0] = 0;
   size_t off = 0;
   for (int l = 0; l < 4; ++l) {
@@ -941,7 +951,8 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
                          h->at<bf16>(h->L.wT) + (size_t)(l - 1) * kHid * kHid, kHid, B, kHid, kHid, ed);
     }
   }
-  hipLaunchKernelGGL(mlp_grad_reduce, dim3(gr.blk0[4] + 4 * kHid), dim3(256), 0, h->stream, gr, ldT, B, grad);
+  hipLaunchKernelGGL(mlp_grad_reduce, dim3(gr.blk0[4] + 4 * kHid + kOut * (kHid + 1)), dim3(256), 0, h->stream, gr,
+                     ldT, B, grad);
 }
 
 // Adam with bias correction at step t on the master weights from grad, then
@@ -949,10 +960,8 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
 void run_adam(mlp_handle* h, const float* grad, float lr, float beta1, float beta2, float eps, long long t) {
   float c1 = 1.0f - powf(beta1, (float)t), c2 = 1.0f - powf(beta2, (float)t);
   hipLaunchKernelGGL(mlp_adam, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
-                     h->at<float>(h->L.master), h->at<float>(h->L.m), h->at<float>(h->L.v), grad,
-                     MLP_N_PARAMS, lr, beta1, beta2, eps, c1, c2);
-  hipLaunchKernelGGL(mlp_refresh, dim3((MLP_N_PARAMS + 255) / 256), dim3(256), 0, h->stream,
-                     h->at<float>(h->L.master), h->at<bf16>(h->L.wb), h->at<bf16>(h->L.wT));
+                     h->at<float>(h->L.master), h->at<float>(h->L.m), h->at<float>(h->L.v), grad, lr, beta1,
+                     beta2, eps, c1, c2, h->at<bf16>(h->L.wb), h->at<bf16>(h->L.wT));
 }
 
 bool train_batch_ok(const mlp_handle* h, int batch) {
