@@ -443,14 +443,31 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
 }
 
 // dW4[o][k] = sum_b gy[b][o] a4[b][k]; db4[o] = sum_b gy[b][o].
+// The batch loss, the mean of the per-row squared errors over B rows and
+// the 3 outputs: 256 threads striding over the rows, then a tree in LDS.
+// All 256 threads of a block.
+__device__ void loss_sum(const float* __restrict__ rows, int B, float* __restrict__ out) {
+  __shared__ float part[256];
+  float s = 0.f;
+  for (int b = threadIdx.x; b < B; b += 256) s += rows[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0] / (float(B) * kOut);
+}
+
 // The gradient reductions of back-propagation in one launch.  Blocks
 // [0, blk0[4]) sum the k-split parts of the hidden layers' weight gradients,
 // slab by slab in order (256 elements a block, the layers' blocks back to
 // back from blk0[l]); the next 4 kHid blocks each sum one hidden bias
 // gradient, db_l[n] = sum_b g_l[b][n]; the last 3 (kHid + 1) blocks one of
 // the head's, dW4[o][k] = sum_b gy[b][o] a4[b][k] (k = kHid: db4[o] =
-// sum_b gy[b][o]).  A sum over the batch: 256 threads striding over it,
-// wavefront sums, then the four wavefronts' sums in order.
+// sum_b gy[b][o]); with rows, one more block the batch loss (loss_sum).
+// A sum over the batch: 256 threads striding over it, wavefront sums, then
+// the four wavefronts' sums in order.
 struct GradReduce {
   float* part[4];          // layer l's parts, slab[l] floats each (written by gemm_tn<EpiPart>)
   int slab[4];
@@ -459,6 +476,8 @@ struct GradReduce {
   int parts;
   const float* gy;         // dL/dy [B][3]
   const bf16* a4T;         // last hidden activations, feature-major
+  const float* rows;       // per-row squared errors, or null (no loss)
+  float* loss;             // the batch loss (mean squared error), if rows
 };
 
 __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, int B, float* __restrict__ grad) {
@@ -473,8 +492,12 @@ __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, in
     grad[kOffW[l] + i] = s;
     return;
   }
-  __shared__ float red[4];
   const int q = blk - a.blk0[4];
+  if (q == 4 * kHid + kOut * (kHid + 1)) {   // the loss block (launched only with rows)
+    loss_sum(a.rows, B, a.loss);
+    return;
+  }
+  __shared__ float red[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float s = 0.f;
   int dst;
@@ -499,20 +522,7 @@ __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, in
   if (threadIdx.x == 0) grad[dst] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void mlp_loss(const float* __restrict__ rows, int B, float* __restrict__ out) {
-  __shared__ float part[256];
-  float s = 0.f;
-  for (int b = threadIdx.x; b < B; b += 256) s += rows[b];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = part[0] / (float(B) * kOut);
-}
 
-// Adam with bias correction on FP32 masters, then the BF16 copies.
 // Parameter i's BF16 copies from its FP32 value: the row-major copy of all
 // parameters and, for W1..W3, the transposed copy.
 __device__ __forceinline__ void refresh_one(int i, float w, bf16* __restrict__ wb, bf16* __restrict__ wT) {
@@ -907,8 +917,9 @@ namespace {
 
 // Forward with the activations kept, then back-propagation into the
 // handle's gradient buffer, from the mean-squared-error gradient against
-// target (loss rows kept for mlp_loss) or from a given dL/dy.
-void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, const float* dy_dev, int B) {
+// target (the batch loss into loss_dev, if given) or from a given dL/dy.
+void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, const float* dy_dev, int B,
+                  float* loss_dev = nullptr) {
   const int ldT = h->L.ldT;
   forward(h, x_dev, B, true);
   float* grad = h->at<float>(h->L.grad);
@@ -924,6 +935,8 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
   gr.parts = parts;
   gr.gy = h->at<float>(h->L.gy);
   gr.a4T = h->at<bf16>(h->L.actT[3]);
+  gr.rows = loss_dev ? h->at<float>(h->L.rows) : nullptr;
+  gr.loss = loss_dev;
   gr.blk0[0] = 0;
   size_t off = 0;
   for (int l = 0; l < 4; ++l) {
@@ -951,8 +964,8 @@ void run_backward(mlp_handle* h, const float* x_dev, const float* target_dev, co
                          h->at<bf16>(h->L.wT) + (size_t)(l - 1) * kHid * kHid, kHid, B, kHid, kHid, ed);
     }
   }
-  hipLaunchKernelGGL(mlp_grad_reduce, dim3(gr.blk0[4] + 4 * kHid + kOut * (kHid + 1)), dim3(256), 0, h->stream, gr,
-                     ldT, B, grad);
+  hipLaunchKernelGGL(mlp_grad_reduce, dim3(gr.blk0[4] + 4 * kHid + kOut * (kHid + 1) + (loss_dev ? 1 : 0)), dim3(256),
+                     0, h->stream, gr, ldT, B, grad);
 }
 
 // Adam with bias correction at step t on the master weights from grad, then
@@ -976,10 +989,8 @@ int mlp_train_step(mlp_handle* h, const float* x_dev, const float* target_dev, i
                    float beta1, float beta2, float eps, float* grad_dev, float* loss_dev) {
   if (!h || !x_dev || !target_dev || !train_batch_ok(h, batch)) return SPH_E_INVAL;
   const int B = batch;
-  run_backward(h, x_dev, target_dev, nullptr, B);
+  run_backward(h, x_dev, target_dev, nullptr, B, loss_dev ? loss_dev : h->at<float>(h->L.loss));
   float* grad = h->at<float>(h->L.grad);
-  hipLaunchKernelGGL(mlp_loss, dim3(1), dim3(256), 0, h->stream, h->at<float>(h->L.rows), B,
-                     loss_dev ? loss_dev : h->at<float>(h->L.loss));
   if (grad_dev)
     MHIP(hipMemcpyAsync(grad_dev, grad, (size_t)MLP_N_PARAMS * 4, hipMemcpyDeviceToDevice, h->stream));
   h->t += 1;
