@@ -384,7 +384,9 @@ int mlp_init(const float* params_dev, int32_t max_batch, void* ws_dev, size_t ws
 int mlp_destroy(mlp_handle* h);
 
 /* y_dev [B][3] FP32 = net(x_dev [B][128] FP32), inputs rounded to BF16; one
- * fused kernel (activations stay on chip).  Asynchronous. */
+ * fused kernel (activations stay on chip).  Asynchronous.  x_dev must be
+ * 16-byte aligned (here and in mlp_train_step and mlp_backward), else
+ * SPH_E_INVAL. */
 int mlp_forward(mlp_handle* h, const float* x_dev, int32_t batch, float* y_dev);
 
 /* One training step on the mean squared error: forward, backward (gradients

@@ -64,6 +64,23 @@ def test_launch_equals_forward():
     net.close()
 
 
+def test_misaligned_input_is_refused():
+    # the input rows are read four floats at a time: an input pointer that
+    # is not 16-byte aligned is refused with SPH_E_INVAL, nothing launched
+    import ctypes as C
+    G, rng, params, vec = _net(4)
+    net = G.Mlp(vec, max_batch=256)
+    x = torch.zeros(129 * 128, device="cuda:0")
+    y = torch.zeros(128, 3, device="cuda:0")
+    t = torch.zeros(128, 3, device="cuda:0")
+    bad = C.c_void_p(x.data_ptr() + 4)
+    assert net.L.mlp_forward(net.h, bad, 128, C.c_void_p(y.data_ptr())) < 0
+    assert net.L.mlp_train_step(net.h, bad, C.c_void_p(t.data_ptr()), 128, 1e-3, 0.9, 0.999, 1e-8, None, None) < 0
+    assert net.L.mlp_forward(net.h, C.c_void_p(x.data_ptr()), 128, C.c_void_p(y.data_ptr())) == 0
+    torch.cuda.synchronize()
+    net.close()
+
+
 def test_forward_at_the_inference_batch_size():
     # the surrogate workload's inference batch, 65,536 windows in one launch:
     # sampled rows (and the last ones, the ragged end of the grid) against
