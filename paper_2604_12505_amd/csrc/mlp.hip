@@ -180,21 +180,7 @@ constexpr int kLdsStride = kHid + 8;
 // lane l, outputs n0 + 16 c + rq .. + 3 (rq = 4 (l / 16)) of row 16 r +
 // l % 16: four consecutive outputs of one row, stored as one 8-byte word.
 // The accumulators start from the biases (bias_acc), so a layer's output
-// is GELU of the accumulator.  GELU of a layer's ROWS x 64 outputs of this
-// wave into dst (BF16).
-template <int RT>
-__device__ __forceinline__ void layer_out(const floatx4 (&acc)[RT][4], bf16* dst, int n0, int li, int rq) {
-  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-  for (int c = 0; c < 4; ++c)
-    for (int r = 0; r < RT; ++r) {
-      bf16x4 v;
-      v[0] = (bf16)gelu(acc[r][c][0]);
-      v[1] = (bf16)gelu(acc[r][c][1]);
-      v[2] = (bf16)gelu(acc[r][c][2]);
-      v[3] = (bf16)gelu(acc[r][c][3]);
-      *reinterpret_cast<bf16x4*>(&dst[(r * 16 + li) * kLdsStride + n0 + c * 16 + rq]) = v;
-    }
-}
+// is GELU of the accumulator (tile_out).
 
 // Accumulators of a layer set to this lane's biases: bn[c] holds the biases
 // of outputs n0 + 16 c + rq .. + 3, the outputs acc[r][c] holds.
@@ -204,7 +190,7 @@ __device__ __forceinline__ void bias_acc(floatx4 (&acc)[RT][4], const float4 (&b
     for (int c = 0; c < 4; ++c) acc[r][c] = floatx4{bn[c].x, bn[c].y, bn[c].z, bn[c].w};
 }
 
-// This lane's biases of layer l (see layer_out).
+// This lane's biases of layer l (the outputs bias_acc gives them to).
 __device__ __forceinline__ void load_bias(float4 (&bn)[4], const float* __restrict__ master, int l, int n0, int rq) {
   for (int c = 0; c < 4; ++c) bn[c] = *reinterpret_cast<const float4*>(master + kOffB[l] + n0 + c * 16 + rq);
 }
@@ -216,7 +202,8 @@ template <int L>
 constexpr int layer_in() { return L == 0 ? kIn : kHid; }
 
 // GELU of one 16 x 16 output tile (row tile r, column tile c) of this wave
-// into dst, as in layer_out.
+// into dst (BF16): the lane's four consecutive outputs of one row as one
+// 8-byte word.
 __device__ __forceinline__ void tile_out(const floatx4& acc, bf16* dst, int r, int c, int n0, int li, int rq) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   bf16x4 v;
