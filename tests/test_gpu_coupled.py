@@ -57,7 +57,8 @@ def _gpu(vec, R, *args, **kw):
     return out
 
 
-@pytest.mark.parametrize("R,n_steps,stride", [(16, 41 * 10 + 3, 10), (70, 40 * 25, 25)])
+# log strides 10, 25 and 70 (a ragged last interval in each)
+@pytest.mark.parametrize("R,n_steps,stride", [(16, 41 * 10 + 3, 10), (70, 40 * 25, 25), (20, 35 * 70 + 11, 70)])
 def test_constant_network_integration_matches_oracle(R, n_steps, stride):
     from paper_2604_12505_amd import mlp as G
     static, feat0, u, body, rigid0, norm = _case(R, n_steps, stride, seed=R)
