@@ -427,10 +427,28 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
   const int row0 = blockIdx.x * kHeadRows, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nr = B - row0 < kHeadRows ? B - row0 : kHeadRows;
   const bool train = target || dy_in;
-  for (int rr = wave; rr < nr; rr += 4) {
+  // every load of the kernel requested up front: the wave's rows of a4 and
+  // this thread's pre-activations of the g4 part (kHeadRows consecutive rows
+  // of a feature per kHeadRows threads)
+  constexpr int kRowsPerWave = kHeadRows / 4, kZPer = kHeadRows * kHid / 256;
+  float av[kRowsPerWave][4];
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) {
+    const int rr = wave + 4 * j;
+    for (int q = 0; q < 4; ++q) av[j][q] = rr < nr ? (float)a4[(size_t)(row0 + rr) * kHid + lane * 4 + q] : 0.f;
+  }
+  float zv[kZPer];
+#pragma unroll
+  for (int j = 0; j < kZPer; ++j) {
+    const int i = threadIdx.x + 256 * j, k = i / kHeadRows, rr = i - k * kHeadRows;
+    zv[j] = train && rr < nr ? z4T[(size_t)k * ldT + row0 + rr] : 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) {
+    const int rr = wave + 4 * j;
+    if (rr >= nr) break;
     const int row = row0 + rr;
-    float a[4];
-    for (int q = 0; q < 4; ++q) a[q] = (float)a4[(size_t)row * kHid + lane * 4 + q];
+    const float* a = av[j];
     float out[kOut];
     for (int o = 0; o < kOut; ++o) {
       float s = 0.f;
@@ -463,12 +481,13 @@ __global__ void __launch_bounds__(256) mlp_head(const bf16* __restrict__ a4, con
   }
   if (!train) return;
   __syncthreads();
-  for (int i = threadIdx.x; i < kHeadRows * kHid; i += 256) {
-    const int k = i / kHeadRows, rr = i - k * kHeadRows;
+#pragma unroll
+  for (int j = 0; j < kZPer; ++j) {
+    const int i = threadIdx.x + 256 * j, k = i / kHeadRows, rr = i - k * kHeadRows;
     if (rr >= nr) continue;
     float s = 0.f;
     for (int o = 0; o < kOut; ++o) s += gs[rr][o] * (float)W4[o * kHid + k];
-    const bf16 v = (bf16)(s * gelu_grad(z4T[(size_t)k * ldT + row0 + rr]));
+    const bf16 v = (bf16)(s * gelu_grad(zv[j]));
     g4T[(size_t)k * ldT + row0 + rr] = v;
     tile[rr][k] = v;
   }
