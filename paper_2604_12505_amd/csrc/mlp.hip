@@ -544,6 +544,7 @@ __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, in
     const int i = (blk - a.blk0[l]) * 256 + (int)threadIdx.x;
     if (i >= a.slab[l]) return;
     float s = 0.f;
+#pragma unroll 4
     for (int z = 0; z < a.parts; ++z) s += a.part[l][(size_t)z * a.slab[l] + i];
     grad[kOffW[l] + i] = s;
     return;
@@ -560,14 +561,17 @@ __global__ void __launch_bounds__(256) mlp_grad_reduce(GradReduce a, int ldT, in
   if (q < 4 * kHid) {
     const int l = q / kHid, n = q - l * kHid;
     const bf16* g = a.gT[l] + (size_t)n * ldT;
+#pragma unroll 4
     for (int b = threadIdx.x; b < B; b += 256) s += (float)g[b];
     dst = kOffB[l] + n;
   } else {
     const int t = q - 4 * kHid, o = t / (kHid + 1), k = t - o * (kHid + 1);
     if (k < kHid) {
       const bf16* x = a.a4T + (size_t)k * ldT;
+#pragma unroll 4
       for (int b = threadIdx.x; b < B; b += 256) s += a.gy[(size_t)b * kOut + o] * (float)x[b];
     } else {
+#pragma unroll 4
       for (int b = threadIdx.x; b < B; b += 256) s += a.gy[(size_t)b * kOut + o];
     }
     dst = k < kHid ? kOffW[4] + o * kHid + k : kOffB[4] + o;
